@@ -1,0 +1,195 @@
+"""FTLE oracle -- TEST INFRASTRUCTURE ONLY.
+
+Python face of ``ftle_oracle.c``: a plain double-precision CPU implementation
+of the per-point FTLE computation (least-squares flow-map gradient over the
+mesh neighbours, Cauchy-Green tensor, largest eigenvalue, ln sqrt(lambda)/|T|)
+and of its adjoint.  It exists to check the GPU library; only the tests, the
+smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
+code with the GPU library and does not import it.
+
+Parity status of each function (what pins it) is listed in the test module
+``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ftle_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def compile_source(src: str, out: str) -> str:
+    """gcc -O2, OpenMP, no FMA contraction; writes the shared library atomically."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+                           "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle library next to its source."""
+    if force or not os.path.exists(_LIB):
+        compile_source(_SRC, _LIB)
+    return _LIB
+
+
+def source_path() -> str:
+    return _SRC
+
+
+class _Lib:
+    """ctypes bindings of one compiled oracle library."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        i64, vp = ctypes.c_int64, ctypes.c_void_p
+        lib.oracle_ring1_bound.restype = i64
+        lib.oracle_ring1_bound.argtypes = [ctypes.c_int, i64]
+        lib.oracle_ring1.restype = i64
+        lib.oracle_ring1.argtypes = [ctypes.c_int, i64, i64, vp, vp, vp]
+        lib.oracle_axis.restype = None
+        lib.oracle_axis.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
+        lib.oracle_ftle.restype = None
+        lib.oracle_ftle.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, ctypes.c_double,
+                                    i64, vp, vp, vp, vp]
+        lib.oracle_ftle_grad.restype = None
+        lib.oracle_ftle_grad.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, ctypes.c_double,
+                                         vp, vp]
+        lib.oracle_jacobi_eig3.restype = None
+        lib.oracle_jacobi_eig3.argtypes = [vp, vp, vp]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_max_threads.argtypes = []
+        self.c = lib
+        self.path = path
+
+
+def load_library(path: str):
+    """Load another build of the oracle (used by the tests that plant mistakes)."""
+    return _Lib(path)
+
+
+def _load(lib=None):
+    global _lib
+    if lib is not None:
+        return lib.c
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = _Lib(_LIB)
+    return _lib.c
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+class Stencil:
+    """CSR stencil in the caller's point order: row_ptr (n+1, int64), col (nnz, int32).
+
+    Entries equal to -1 stand for an absent neighbour and are skipped.
+    """
+
+    def __init__(self, row_ptr, col):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+
+    @property
+    def n(self):
+        return self.row_ptr.shape[0] - 1
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+
+def ring1(dim: int, n: int, cells, lib=None) -> Stencil:
+    """Every vertex sharing a cell with i (excluding i), deduplicated, ascending."""
+    lib = _load(lib)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    ncells = cells.shape[0]
+    assert cells.shape[1] == dim + 1
+    cap = int(lib.oracle_ring1_bound(dim, ncells))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(cap, 1), dtype=np.int32)
+    nnz = lib.oracle_ring1(dim, n, ncells, _p(cells), _p(row_ptr), _p(col))
+    if nnz < 0:
+        raise ValueError("cell references a point outside [0, n)")
+    return Stencil(row_ptr, col[:nnz].copy())
+
+
+def axis(dim: int, coords, st: Stencil, lib=None) -> Stencil:
+    """The paper's fixed-width list: 2*dim slots per point, -1 where absent."""
+    lib = _load(lib)
+    x = _f64(coords)
+    n = x.shape[0]
+    slots = np.full(n * 2 * dim, -1, dtype=np.int32)
+    lib.oracle_axis(dim, n, _p(x), _p(st.row_ptr), _p(st.col), _p(slots))
+    return Stencil(np.arange(n + 1, dtype=np.int64) * 2 * dim, slots)
+
+
+def ftle(dim: int, coords, flow, st: Stencil, T: float, sel=None, diagnostics: bool = False, lib=None):
+    """FTLE per point (float64).  sel: optional point indices to evaluate.
+
+    With diagnostics=True also returns (gap, detratio): the relative gap
+    (lam1 - lam2)/lam1 of C's top eigenvalue and det M / (tr M / D)^D.
+    """
+    lib = _load(lib)
+    x, f = _f64(coords), _f64(flow)
+    n = x.shape[0]
+    assert x.shape == (n, dim) and f.shape == (n, dim) and st.n == n
+    if sel is None:
+        cnt, selp = n, None
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        cnt, selp = sel.shape[0], _p(sel)
+    out = np.empty(cnt, dtype=np.float64)
+    gap = np.empty(cnt, dtype=np.float64) if diagnostics else None
+    det = np.empty(cnt, dtype=np.float64) if diagnostics else None
+    lib.oracle_ftle(dim, n, _p(x), _p(f), _p(st.row_ptr), _p(st.col), float(T),
+                    cnt, selp, _p(out), _p(gap) if diagnostics else None,
+                    _p(det) if diagnostics else None)
+    if diagnostics:
+        return out, gap, det
+    return out
+
+
+def ftle_grad(dim: int, coords, flow, st: Stencil, T: float, g, lib=None):
+    """dL/dflow (n x dim, float64) for L = sum_i g_i FTLE_i."""
+    lib = _load(lib)
+    x, f, gg = _f64(coords), _f64(flow), _f64(g)
+    n = x.shape[0]
+    grad = np.empty((n, dim), dtype=np.float64)
+    lib.oracle_ftle_grad(dim, n, _p(x), _p(f), _p(st.row_ptr), _p(st.col), float(T),
+                         _p(gg), _p(grad))
+    return grad
+
+
+def jacobi_eig3(m, lib=None):
+    """Eigenvalues (ascending) and unit eigenvectors (columns) of a symmetric 3x3."""
+    lib = _load(lib)
+    m = _f64(m).reshape(3, 3)
+    vals = np.empty(3)
+    vecs = np.empty((3, 3))
+    lib.oracle_jacobi_eig3(_p(m), _p(vals), _p(vecs))
+    return vals, vecs

@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+@pytest.fixture(scope="session")
+def small_2d_workload():
+    from workloads import configs
+    return configs.small_2d()
+
+
+@pytest.fixture(scope="session")
+def abc16_workload():
+    from workloads import configs
+    return configs.abc3d(16, 10.0, "f64")
