@@ -1,0 +1,242 @@
+"""Benchmark of the FTLE hot path on one MI355X.
+
+Headline: forward FTLE on the 2048x2048 jittered triangulated double-gyre
+mesh (4,194,304 points, float32), points/s.  Also measured in the same run
+and reported under "variants": the 160^3 ABC tetrahedral forward, the 96^3
+forward+adjoint, and the 48-mesh batched forward.
+
+Every timed step reads inputs already resident in HBM.  Each workload is held
+in several independent copies (mesh records, coordinates, flow map, output)
+and consecutive steps rotate through them, so a step never finds its inputs
+in the 256 MB Infinity Cache left there by the previous step.
+
+Algorithmic bytes per launch (each array touched once, 32-bit CSR):
+  forward  B = 4 (N + 1) + 4 nnz + 2 D s N + s N
+  adjoint  B = 4 (N + 1) + 4 nnz + 3 D s N + s N     (x, flow, grad; g)
+with s the storage bytes (4).  "format_bytes" is what this library's own
+layout (tile records with 16-bit local indices) holds for the same launch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def alg_bytes_fwd(n, nnz, dim, s=4):
+    return 4 * (n + 1) + 4 * nnz + 2 * dim * s * n + s * n
+
+
+def alg_bytes_bwd(n, nnz, dim, s=4):
+    return 4 * (n + 1) + 4 * nnz + 3 * dim * s * n + s * n
+
+
+def format_bytes_fwd(mesh, dim, s=4):
+    st = mesh.tile_stats()
+    return st["record_bytes"] + 2 * dim * s * mesh.n + s * mesh.n
+
+
+def time_steps(fns, steps, warmup, torch):
+    """Run warmup untimed steps, then exactly `steps` timed ones; ms per step."""
+    for i in range(warmup):
+        fns[i % len(fns)]()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        fns[i % len(fns)]()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def roofline(alg_bytes, ms):
+    gbps = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None}
+
+
+def cpu_baseline(w, threads):
+    """The FP64 oracle, as it stands, on the headline workload (per-point loop only)."""
+    import numpy as np
+
+    import oracle
+    oracle.set_threads(threads)
+    st = oracle.ring1(w.dim, w.n, w.cells)
+    x = w.coords.astype(np.float64)
+    phi = w.flow_numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.ftle(w.dim, x, phi, st, w.T)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= 2.0 or reps >= 20:
+            break
+    return {"value": round(w.n * reps / el, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {w.n} points of the 2048^2 workload x{reps} passes, per-point loop only "
+                      f"(stencil built beforehand), float64, OpenMP {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--copies", type=int, default=3, help="input copies rotated between steps")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of: fwd2d,fwd3d,fwdbwd,batched")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the FTLE hot path is "
+              "built and measured on a single MI355X; see DESIGN.md for how it would shard.", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2408_02758_amd as F
+    from workloads import configs
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    only = set(filter(None, args.only.split(",")))
+    want = lambda k: (not only) or (k in only)  # noqa: E731
+    R = max(1, args.copies)
+    result = {}
+    variants = {}
+
+    # ---- headline: 2D forward at 2048^2 ------------------------------------
+    log("generating 2048^2 double-gyre workload (RK4 on the GPU)")
+    w2 = configs.scale_2d(dev)
+    log("building meshes")
+    meshes2 = [F.Mesh(w2.coords, w2.cells, "f32") for _ in range(R)]
+    nnz2 = meshes2[0].info()["nnz"]
+    flows2 = [w2.flow.to(dev).clone().contiguous() for _ in range(R)]
+    outs2 = [torch.empty(w2.n, dtype=torch.float32, device=dev) for _ in range(R)]
+    fns = [lambda k=k: meshes2[k].forward(flows2[k], w2.T, out=outs2[k]) for k in range(R)]
+    log("timing 2D forward")
+    ms = time_steps(fns, args.steps, args.warmup, torch)
+    B = alg_bytes_fwd(w2.n, nnz2, 2)
+    pts = w2.n / (ms * 1e-3)
+    rl = roofline(B, ms)
+    rl["alg_bytes_per_launch"] = B
+    rl["format_bytes_per_launch"] = format_bytes_fwd(meshes2[0], 2)
+    rl["format_frac"] = round(rl["format_bytes_per_launch"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    nan = int(torch.isnan(outs2[0]).sum().item())
+    result.update({
+        "metric": "FTLE points/s (fwd, fwd+bwd, batched) + % HBM roofline at stated err vs FP64",
+        "value": round(pts, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2D plain FTLE forward, 2048x2048 jittered triangulated grid, double gyre "
+                               "(A=0.1, eps=0.25, omega=2pi/10), RK4 dt=0.01, T=15",
+                   "points": w2.n, "nnz": nnz2, "T": w2.T, "stencil": "ring1", "input_copies": R,
+                   "nan_outputs": nan},
+        "roofline": rl,
+    })
+    log(f"2D forward: {ms * 1e3:.2f} us/step, {pts / 1e9:.2f} G points/s, {rl['achieved']} GB/s alg")
+    del fns
+
+    # ---- variants ----------------------------------------------------------
+    if not args.no_variants:
+        steps_v = max(10, args.steps // 2)
+        if want("fwd3d"):
+            log("generating 160^3 ABC workload")
+            w3 = configs.abc_3d(dev)
+            ms3 = [F.Mesh(w3.coords, w3.cells, "f32") for _ in range(R)]
+            nnz3 = ms3[0].info()["nnz"]
+            fl3 = [w3.flow.to(dev).clone().contiguous() for _ in range(R)]
+            ou3 = [torch.empty(w3.n, dtype=torch.float32, device=dev) for _ in range(R)]
+            fns = [lambda k=k: ms3[k].forward(fl3[k], w3.T, out=ou3[k]) for k in range(R)]
+            ms3[0].fp64_hits(reset=True)
+            t = time_steps(fns, steps_v, args.warmup, torch)
+            hits = ms3[0].fp64_hits()
+            calls0 = (args.warmup + steps_v + R - 1) // R
+            B3 = alg_bytes_fwd(w3.n, nnz3, 3)
+            variants["fwd_3d_160"] = {
+                "workload": "3D plain FTLE forward, 160^3 Kuhn tetrahedral grid, ABC flow, RK4 dt=0.02, T=10",
+                "points": w3.n, "nnz": nnz3, "ms_per_step": round(t, 5), "points_per_s": round(w3.n / (t * 1e-3), 1),
+                "roofline": dict(roofline(B3, t), alg_bytes_per_launch=B3,
+                                 format_bytes_per_launch=format_bytes_fwd(ms3[0], 3)),
+                "fp64_eigen_recomputes_per_call": round(hits / max(1, calls0), 1)}
+            log(f"3D forward: {t * 1e3:.2f} us/step")
+            del fns, ms3, fl3, ou3
+        if want("fwdbwd"):
+            log("generating 96^3 ABC workload (differentiated)")
+            wd = configs.diff_3d(dev)
+            msd = [F.Mesh(wd.coords, wd.cells, "f32") for _ in range(R)]
+            nnzd = msd[0].info()["nnz"]
+            fld = [wd.flow.to(dev).clone().contiguous() for _ in range(R)]
+            gw = torch.as_tensor(wd.extra["weights"], dtype=torch.float32, device=dev)
+            outd = [torch.empty(wd.n, dtype=torch.float32, device=dev) for _ in range(R)]
+            taped = [torch.empty(wd.n * 7, dtype=torch.float32, device=dev) for _ in range(R)]
+            gradd = [torch.empty(wd.n, 3, dtype=torch.float32, device=dev) for _ in range(R)]
+
+            def step(k):
+                msd[k].forward_tape(fld[k], wd.T, out=outd[k], tape=taped[k])
+                msd[k].backward_tape(taped[k], gw, grad_flow=gradd[k])
+            fns = [lambda k=k: step(k) for k in range(R)]
+            t = time_steps(fns, steps_v, args.warmup, torch)
+            Bd = alg_bytes_fwd(wd.n, nnzd, 3) + alg_bytes_bwd(wd.n, nnzd, 3)
+            variants["fwd_bwd_3d_96"] = {
+                "workload": "3D FTLE forward + adjoint (dL/dflow, L = sum w_i FTLE_i), 96^3 Kuhn grid, ABC flow, T=10",
+                "points": wd.n, "nnz": nnzd, "ms_per_step": round(t, 5), "points_per_s": round(wd.n / (t * 1e-3), 1),
+                "roofline": dict(roofline(Bd, t), alg_bytes_per_launch=Bd)}
+            log(f"fwd+bwd: {t * 1e3:.2f} us/step")
+            del fns, msd, fld, outd, taped, gradd
+        if want("batched"):
+            log("generating the 48-mesh batched workload")
+            wb = configs.batched_2d(dev)
+            Rb = 2
+            sets = []
+            for _ in range(Rb):
+                mb = [F.Mesh(w.coords, w.cells, "f32") for w in wb]
+                fb = [w.flow.to(dev).clone().contiguous() for w in wb]
+                ob = [torch.empty(w.n, dtype=torch.float32, device=dev) for w in wb]
+                sets.append((mb, fb, ob))
+            Ts = [w.T for w in wb]
+            fns = [lambda s=s: F.batched(s[0], s[1], Ts, outs=s[2]) for s in sets]
+            t = time_steps(fns, steps_v, args.warmup, torch)
+            npts = sum(w.n for w in wb)
+            nnzb = sum(m.info()["nnz"] for m in sets[0][0])
+            Bb = sum(alg_bytes_fwd(m.n, m.info()["nnz"], 2) for m in sets[0][0])
+            variants["batched_2d_48"] = {
+                "workload": "48 jittered triangulated double-gyre meshes, sides log-uniform in [64,1024], "
+                            "own t0 and T each, one persistent launch from a HIP graph",
+                "points": npts, "nnz": nnzb, "ms_per_step": round(t, 5), "points_per_s": round(npts / (t * 1e-3), 1),
+                "roofline": dict(roofline(Bb, t), alg_bytes_per_launch=Bb),
+                "autotuned": F.batched_config(sets[0][0])}
+            log(f"batched: {t * 1e3:.2f} us/step")
+            del fns, sets
+    if variants:
+        result["variants"] = variants
+
+    if not args.no_cpu_baseline:
+        try:
+            threads = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            threads = min(16, os.cpu_count() or 1)
+        log(f"timing the FP64 oracle on {threads} host threads")
+        result["cpu_baseline"] = cpu_baseline(w2, threads)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * ftle.h -- C ABI of the MI355X (gfx950) Finite-Time Lyapunov Exponent library.
+ *
+ * The library computes, for every point of a 2D triangle mesh or a 3D
+ * tetrahedral mesh, the finite-time Lyapunov exponent of a precomputed flow
+ * map (the per-point FTLE kernels of UVaFTLE studied in de Castro et al.,
+ * "Finite-Time Lyapunov Exponent Calculation on FPGA using High-Level
+ * Synthesis Tools", Section 2):
+ *
+ *   J_i   = flow-map gradient at point i, least squares over i's mesh
+ *           neighbours S(i):  J_i = B_i M_i^{-1},
+ *           M_i = sum_j (x_j - x_i)(x_j - x_i)^T,
+ *           B_i = sum_j (phi_j - phi_i)(x_j - x_i)^T;
+ *   C_i   = J_i^T J_i  (Cauchy-Green tensor, 2x2 or 3x3);
+ *   FTLE_i = ln( sqrt( lambda_max(C_i) ) ) / |T|.
+ *
+ * Problem statement as in Section 2.2 of the paper: point coordinates, mesh
+ * connectivity, the advected flow map and the integration time go in; one
+ * FTLE value per point comes out.  The neighbour list is computed once on the
+ * host (Section 2.2: neighbours precomputed on the CPU into a list of integer
+ * indices) when the mesh is created, and the GPU kernels only stream it.
+ *
+ * Conventions for every entry point:
+ *  - All functions return an ftle_status; none throws or aborts.  On failure
+ *    ftle_last_error() returns a message for the calling thread.
+ *  - Argument validation happens on the host before any device work, so
+ *    invalid calls fail without touching the GPU.
+ *  - "device pointer" arguments are HIP device memory of the current device
+ *    (e.g. torch CUDA tensors' data_ptr()); "host pointer" arguments are
+ *    ordinary CPU memory.  Point arrays are row-major n x dim in the CALLER's
+ *    point order ("user order").
+ *  - Device work is enqueued on the given stream (a hipStream_t, NULL means
+ *    the null stream) and returns without waiting.  A fault inside a kernel
+ *    surfaces as FTLE_ERR_DEVICE from a later call.
+ *  - A point whose stencil is rank deficient (fewer than dim neighbours, or
+ *    neighbours that do not span the space; this includes points that belong
+ *    to no cell) gets NaN.  lambda_max = 0 gives -inf.  NaN or inf in the flow
+ *    map propagate to NaN outputs.
+ */
+#ifndef FTLE_H
+#define FTLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ftle_mesh_s* ftle_mesh_t;  /* opaque; immutable after creation */
+typedef void* ftle_stream_t;              /* hipStream_t; NULL = null stream  */
+
+typedef enum { FTLE_F32 = 0, FTLE_F64 = 1 } ftle_dtype;
+
+typedef enum {
+    FTLE_OK = 0,
+    FTLE_ERR_INVALID_ARG = 1,   /* null pointer, bad dim/size, T = 0 or not finite, ... */
+    FTLE_ERR_BAD_MESH = 2,      /* cell index outside [0, n) or repeated inside a cell   */
+    FTLE_ERR_DTYPE = 3,         /* dtype differs from the mesh's dtype                    */
+    FTLE_ERR_UNSUPPORTED = 4,   /* n > 2^31-1, degree too large for one tile, no device   */
+    FTLE_ERR_OOM = 5,           /* host or device allocation failed                       */
+    FTLE_ERR_DEVICE = 6         /* a HIP runtime call failed                               */
+} ftle_status;
+
+/* Flags of ftle_create_mesh (OR them together). */
+enum {
+    /* Stencil S(i): every vertex sharing a cell with i (default). */
+    FTLE_STENCIL_RING1 = 0,
+    /* Stencil S(i): the paper's fixed-width list (Section 2.2, exactly 4 slots
+     * in 2D and 6 in 3D, -1 for an absent neighbour): for each signed axis
+     * direction the RING1 neighbour with the largest cosine to that
+     * direction among those on its side; absent slots are skipped. */
+    FTLE_STENCIL_AXIS = 1,
+    /* Keep the caller's point order instead of the Morton (Z-order) order. */
+    FTLE_NO_REORDER = 1 << 4,
+    /* Build the host-side structures only (no device upload).  Such a mesh
+     * serves ftle_mesh_info / ftle_mesh_get_csr / ftle_mesh_tile_stats;
+     * compute calls on it return FTLE_ERR_UNSUPPORTED. */
+    FTLE_HOST_ONLY = 1 << 5
+};
+/* Points per tile (one workgroup's share): FTLE_TILE(k) asks for 2^k points,
+ * 5 <= k <= 11; 0 selects the default (1024 in 2D, 512 in 3D). */
+#define FTLE_TILE(k) ((unsigned)(k) << 8)
+
+/*
+ * Build a mesh: validate, build the neighbour stencil from the cells on the
+ * host, order the points along a Morton curve, cut the order into tiles and
+ * upload everything to the current device.
+ *   dim      2 (triangles) or 3 (tetrahedra)
+ *   n_points number of points, 1 <= n_points <= 2^31-1
+ *   coords   host pointer, n_points x dim, float (FTLE_F32) or double (FTLE_F64);
+ *            copied, must be finite
+ *   dtype    storage and arithmetic precision of every later call on the mesh
+ *   n_cells  number of cells (>= 0)
+ *   cells    host pointer, n_cells x (dim+1) int32 point indices; copied
+ *   flags    FTLE_STENCIL_*, FTLE_NO_REORDER, FTLE_HOST_ONLY, FTLE_TILE(k)
+ *   out      receives the handle; the caller owns it until ftle_destroy_mesh
+ * Errors: INVALID_ARG (null pointer, dim, n_points < 1, non-finite coordinate,
+ * unknown flag), BAD_MESH (cell index out of range or repeated within a cell),
+ * UNSUPPORTED (n_points > 2^31-1, a point whose stencil does not fit one
+ * tile), OOM, DEVICE.
+ */
+ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                             int64_t n_cells, const int32_t* cells, unsigned flags,
+                             ftle_mesh_t* out);
+
+/* Release a mesh and its device memory (waits for the device).  NULL is a no-op. */
+void ftle_destroy_mesh(ftle_mesh_t mesh);
+
+/* Dimensions of a mesh: dim, number of points, number of stencil entries, dtype.
+ * Any output pointer may be NULL. */
+ftle_status ftle_mesh_info(ftle_mesh_t mesh, int* dim, int64_t* n_points, int64_t* nnz,
+                           int* dtype);
+
+/*
+ * Host copies of the stencil in Morton order (debug/test accessor).
+ *   row_ptr  host, n_points+1 int32: row r (Morton position r) spans
+ *            col[row_ptr[r] .. row_ptr[r+1])
+ *   col      host, nnz int32: Morton positions of the neighbours, ascending
+ *   perm     host, n_points int32: perm[r] = caller's index of Morton position r
+ * Any output pointer may be NULL.
+ */
+ftle_status ftle_mesh_get_csr(ftle_mesh_t mesh, int32_t* row_ptr, int32_t* col, int32_t* perm);
+
+/*
+ * Tile statistics (host): number of tiles, the largest tile, the total halo
+ * entries, and the bytes of the device-resident index records.  Any output
+ * pointer may be NULL.
+ */
+ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* max_tile_points,
+                                 int64_t* halo_entries, int64_t* record_bytes);
+
+/*
+ * Host copies of the tile records the kernels read (debug/test accessor).
+ *   adjoint   0: tiles of the stencil S; 1: tiles of its transpose S^T used by
+ *             the adjoint (the same tiles when S is symmetric, as RING1 is)
+ *   n_tiles, record_bytes: sizes (either may be NULL)
+ *   meta      host, n_tiles x 16 bytes: per tile uint32 {record offset in
+ *             16-byte units, own points P, halo points H, stencil entries nnz}
+ *   records   host, record_bytes bytes; per tile: uint32 caller indices of the
+ *             P own points (Morton order) then the H halo points, padded to a
+ *             multiple of 4; then uint16 row ends (P of them, relative to the
+ *             tile's first entry) and nnz uint16 tile-local stencil indices,
+ *             padded to a multiple of 8
+ * meta and records may be NULL (sizes only).
+ */
+ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,
+                                void* meta, void* records);
+
+/*
+ * Forward FTLE (the per-point kernel of Section 2).
+ *   flow     device pointer, n_points x dim of dtype, the flow map phi(x_i) in user order
+ *   dtype    must equal the mesh's dtype
+ *   T        integration time; T != 0 and finite; the sign is ignored (|T|)
+ *   out      device pointer, n_points of dtype; overwritten with FTLE in user order
+ * flow and out must not overlap.
+ */
+ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
+                         void* out, ftle_stream_t stream);
+
+/*
+ * Bytes of the adjoint tape written by ftle_forward_tape (2*dim+1 values of
+ * dtype per point).
+ */
+ftle_status ftle_tape_bytes(ftle_mesh_t mesh, int64_t* bytes);
+
+/*
+ * Forward FTLE that also records, per point, what the adjoint needs
+ * (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j (x_j - x_i), with v
+ * the unit top eigenvector of C).  Same arguments as ftle_forward plus
+ *   tape     device pointer of ftle_tape_bytes() bytes, caller-owned, overwritten
+ */
+ftle_status ftle_forward_tape(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
+                              void* out, void* tape, ftle_stream_t stream);
+
+/*
+ * Adjoint from a tape: dL/dphi for L = sum_i g_i FTLE_i, with the tape of an
+ * ftle_forward_tape call on the same mesh and flow map.
+ *   grad_ftle  device pointer, n_points of dtype (g, user order)
+ *   grad_flow  device pointer, n_points x dim of dtype; overwritten (not accumulated)
+ * Points whose FTLE is not finite contribute nothing.
+ */
+ftle_status ftle_backward_tape(ftle_mesh_t mesh, const void* tape, ftle_dtype dtype,
+                               const void* grad_ftle, void* grad_flow, ftle_stream_t stream);
+
+/*
+ * Adjoint without a tape: recomputes the forward quantities from the flow
+ * map into a workspace owned by the mesh, then gathers dL/dphi.
+ *   flow, dtype, T as in ftle_forward; grad_ftle, grad_flow as in ftle_backward_tape.
+ * Calls on one mesh share the workspace: they are ordered on the device
+ * (a later call on another stream waits for the previous one).
+ */
+ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
+                          const void* grad_ftle, void* grad_flow, ftle_stream_t stream);
+
+/*
+ * Batched forward FTLE over independent meshes (same dim and dtype), in one
+ * persistent launch with a work queue of (mesh, tile) items, replayed from a
+ * cached HIP graph.  The first call for a given list of meshes builds the
+ * work list, times candidate launch shapes (block size, tiles per queue pop,
+ * resident workgroups per CU) and keeps the fastest; later calls only update
+ * the graph's arguments.  Each output equals ftle_forward's bit for bit.
+ *   n         1 <= n <= 64 meshes
+ *   meshes    host array of n handles (all dim and dtype equal)
+ *   flows     host array of n device pointers (flow maps, user order)
+ *   T         host array of n integration times (each nonzero and finite)
+ *   outs      host array of n device pointers (FTLE outputs)
+ */
+ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* flows,
+                         const double* T, void* const* outs, ftle_dtype dtype,
+                         ftle_stream_t stream);
+
+/*
+ * The launch shape the batched autotuner chose for this list of meshes
+ * (after at least one ftle_batched call with it): threads per workgroup,
+ * tiles taken per queue pop, workgroups in the persistent grid.
+ */
+ftle_status ftle_batched_config(int n, const ftle_mesh_t* meshes, int* block, int* tiles_per_pop,
+                                int* grid);
+
+/*
+ * Number of points whose 3D float32 eigenvalue was recomputed in float64
+ * because the top two eigenvalues of C were nearly equal, accumulated over
+ * forward calls on this mesh since the last reset.  Synchronises the device.
+ */
+ftle_status ftle_mesh_fp64_hits(ftle_mesh_t mesh, int64_t* hits, int reset);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* ftle_last_error(void);
+
+/* Library version string. */
+const char* ftle_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTLE_H */

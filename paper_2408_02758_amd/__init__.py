@@ -1,0 +1,7 @@
+"""MI355X-native Finite-Time Lyapunov Exponent (FTLE) library.
+
+The compute path is libftle.so: hand-written HIP kernels for gfx950 behind the
+C ABI in include/ftle.h.  This package only marshals arguments to it.
+"""
+from .api import FTLEError, FTLEFunction, Mesh, batched, batched_config, ftle  # noqa: F401
+from ._lib import LIB_PATH, load  # noqa: F401

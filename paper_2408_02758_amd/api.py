@@ -1,0 +1,239 @@
+"""Python face of the FTLE library: argument marshalling over the C ABI only.
+
+Every computation runs in the HIP kernels of libftle.so; torch provides device
+memory and the current stream.  There is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FTLEError, check
+
+_DT = {"f32": (_lib.F32, np.float32, torch.float32), "f64": (_lib.F64, np.float64, torch.float64)}
+
+
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Mesh:
+    """A 2D triangle or 3D tetrahedral mesh prepared for FTLE on the GPU.
+
+    coords: (N, dim) array; cells: (ncells, dim+1) int32 point indices.
+    dtype: "f32" or "f64" (storage and arithmetic of every call).
+    stencil: "ring1" (all vertices sharing a cell) or "axis" (the 4/6-slot list).
+    """
+
+    def __init__(self, coords, cells, dtype: str = "f32", stencil: str = "ring1", reorder: bool = True,
+                 tile_log2: int = 0, host_only: bool = False):
+        if dtype not in _DT:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        L = _lib.load()
+        code, npdt, tdt = _DT[dtype]
+        coords = np.ascontiguousarray(np.asarray(coords), dtype=npdt)
+        cells = np.ascontiguousarray(np.asarray(cells), dtype=np.int32)
+        if coords.ndim != 2 or coords.shape[1] not in (2, 3):
+            raise ValueError("coords must have shape (N, 2) or (N, 3)")
+        dim = coords.shape[1]
+        if cells.size and (cells.ndim != 2 or cells.shape[1] != dim + 1):
+            raise ValueError(f"cells must have shape (ncells, {dim + 1})")
+        flags = {"ring1": _lib.STENCIL_RING1, "axis": _lib.STENCIL_AXIS}[stencil]
+        if not reorder:
+            flags |= _lib.NO_REORDER
+        if host_only:
+            flags |= _lib.HOST_ONLY
+        flags |= _lib.tile_flag(tile_log2)
+        h = ctypes.c_void_p()
+        ncells = cells.shape[0] if cells.size else 0
+        check(L.ftle_create_mesh(dim, coords.shape[0], coords.ctypes.data, code, ncells,
+                                 cells.ctypes.data if ncells else None, flags, ctypes.byref(h)))
+        self._h = h
+        self.dim = dim
+        self.n = coords.shape[0]
+        self.dtype = dtype
+        self.torch_dtype = tdt
+        self._code = code
+        self.host_only = host_only
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().ftle_destroy_mesh(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- host-side accessors ------------------------------------------------
+    def info(self):
+        d, n, nnz, dt = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        check(_lib.load().ftle_mesh_info(self._h, ctypes.byref(d), ctypes.byref(n), ctypes.byref(nnz),
+                                         ctypes.byref(dt)))
+        return {"dim": d.value, "n": n.value, "nnz": nnz.value, "dtype": "f64" if dt.value else "f32"}
+
+    def csr(self):
+        """(row_ptr, col, perm) in Morton order (col holds Morton positions)."""
+        nnz = self.info()["nnz"]
+        row_ptr = np.empty(self.n + 1, np.int32)
+        col = np.empty(max(nnz, 1), np.int32)
+        perm = np.empty(self.n, np.int32)
+        check(_lib.load().ftle_mesh_get_csr(self._h, row_ptr.ctypes.data, col.ctypes.data, perm.ctypes.data))
+        return row_ptr, col[:nnz], perm
+
+    def tile_stats(self):
+        vals = [ctypes.c_int64() for _ in range(4)]
+        check(_lib.load().ftle_mesh_tile_stats(self._h, *[ctypes.byref(v) for v in vals]))
+        return dict(zip(["n_tiles", "max_tile_points", "halo_entries", "record_bytes"], [v.value for v in vals]))
+
+    def tiles(self, adjoint: bool = False):
+        """Decoded tile records: list of (idx uint32[P+H], rowend uint16[P], lcol uint16[nnz], P, H)."""
+        L = _lib.load()
+        nt, rb = ctypes.c_int64(), ctypes.c_int64()
+        check(L.ftle_mesh_get_tiles(self._h, int(adjoint), ctypes.byref(nt), ctypes.byref(rb), None, None))
+        meta = np.empty((nt.value, 4), np.uint32)
+        rec = np.empty(max(rb.value // 4, 1), np.uint32)
+        check(L.ftle_mesh_get_tiles(self._h, int(adjoint), None, None, meta.ctypes.data, rec.ctypes.data))
+        out = []
+        for off, P, H, nnz in meta:
+            base = int(off) * 4
+            iw = (int(P) + int(H) + 3) & ~3
+            idx = rec[base:base + int(P) + int(H)]
+            seg = rec[base + iw:].view(np.uint16)
+            out.append((idx, seg[:P], seg[P:P + nnz], int(P), int(H)))
+        return out
+
+    def tape_bytes(self) -> int:
+        b = ctypes.c_int64()
+        check(_lib.load().ftle_tape_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    # -- device calls -------------------------------------------------------
+    def _check_flow(self, t: torch.Tensor, name="flow", shape=None):
+        shape = (self.n, self.dim) if shape is None else shape
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != self.torch_dtype:
+            raise TypeError(f"{name} must have dtype {self.torch_dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def forward(self, flow: torch.Tensor, T: float, out: torch.Tensor | None = None, stream=None):
+        self._check_flow(flow)
+        if out is None:
+            out = torch.empty(self.n, dtype=self.torch_dtype, device=flow.device)
+        self._check_flow(out, "out", (self.n,))
+        check(_lib.load().ftle_forward(self._h, ctypes.c_void_p(flow.data_ptr()), self._code, float(T),
+                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def forward_tape(self, flow: torch.Tensor, T: float, out=None, tape=None, stream=None):
+        self._check_flow(flow)
+        if out is None:
+            out = torch.empty(self.n, dtype=self.torch_dtype, device=flow.device)
+        if tape is None:
+            tape = torch.empty(self.n * (2 * self.dim + 1), dtype=self.torch_dtype, device=flow.device)
+        self._check_flow(out, "out", (self.n,))
+        self._check_flow(tape, "tape", (self.n * (2 * self.dim + 1),))
+        check(_lib.load().ftle_forward_tape(self._h, ctypes.c_void_p(flow.data_ptr()), self._code, float(T),
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(tape.data_ptr()),
+                                            _stream_handle(stream)))
+        return out, tape
+
+    def backward_tape(self, tape: torch.Tensor, grad_ftle: torch.Tensor, grad_flow=None, stream=None):
+        self._check_flow(tape, "tape", (self.n * (2 * self.dim + 1),))
+        self._check_flow(grad_ftle, "grad_ftle", (self.n,))
+        if grad_flow is None:
+            grad_flow = torch.empty(self.n, self.dim, dtype=self.torch_dtype, device=tape.device)
+        self._check_flow(grad_flow, "grad_flow")
+        check(_lib.load().ftle_backward_tape(self._h, ctypes.c_void_p(tape.data_ptr()), self._code,
+                                             ctypes.c_void_p(grad_ftle.data_ptr()),
+                                             ctypes.c_void_p(grad_flow.data_ptr()), _stream_handle(stream)))
+        return grad_flow
+
+    def backward(self, flow: torch.Tensor, T: float, grad_ftle: torch.Tensor, grad_flow=None, stream=None):
+        self._check_flow(flow)
+        self._check_flow(grad_ftle, "grad_ftle", (self.n,))
+        if grad_flow is None:
+            grad_flow = torch.empty(self.n, self.dim, dtype=self.torch_dtype, device=flow.device)
+        self._check_flow(grad_flow, "grad_flow")
+        check(_lib.load().ftle_backward(self._h, ctypes.c_void_p(flow.data_ptr()), self._code, float(T),
+                                        ctypes.c_void_p(grad_ftle.data_ptr()),
+                                        ctypes.c_void_p(grad_flow.data_ptr()), _stream_handle(stream)))
+        return grad_flow
+
+    def fp64_hits(self, reset: bool = False) -> int:
+        h = ctypes.c_int64()
+        check(_lib.load().ftle_mesh_fp64_hits(self._h, ctypes.byref(h), int(reset)))
+        return h.value
+
+
+def _handles(meshes: Sequence[Mesh]):
+    arr = (ctypes.c_void_p * len(meshes))(*[m.handle.value for m in meshes])
+    return arr
+
+
+def batched(meshes: Sequence[Mesh], flows: Sequence[torch.Tensor], Ts: Sequence[float], outs=None, stream=None):
+    """One persistent launch (replayed from a cached HIP graph) over many meshes."""
+    n = len(meshes)
+    if not (len(flows) == n == len(Ts)):
+        raise ValueError("meshes, flows and Ts must have the same length")
+    if n == 0:
+        return []
+    for m, f in zip(meshes, flows):
+        m._check_flow(f)
+    if outs is None:
+        outs = [torch.empty(m.n, dtype=m.torch_dtype, device=f.device) for m, f in zip(meshes, flows)]
+    for m, o in zip(meshes, outs):
+        m._check_flow(o, "out", (m.n,))
+    fl = (ctypes.c_void_p * n)(*[f.data_ptr() for f in flows])
+    ou = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    ts = (ctypes.c_double * n)(*[float(t) for t in Ts])
+    check(_lib.load().ftle_batched(n, _handles(meshes), fl, ts, ou, meshes[0]._code, _stream_handle(stream)))
+    return outs
+
+
+def batched_config(meshes: Sequence[Mesh]):
+    b, k, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(_lib.load().ftle_batched_config(len(meshes), _handles(meshes), ctypes.byref(b), ctypes.byref(k),
+                                          ctypes.byref(g)))
+    return {"block": b.value, "tiles_per_pop": k.value, "grid": g.value}
+
+
+class FTLEFunction(torch.autograd.Function):
+    """FTLE with a hand-written adjoint: forward records a tape, backward gathers dL/dflow."""
+
+    @staticmethod
+    def forward(ctx, flow, mesh: Mesh, T: float):
+        out, tape = mesh.forward_tape(flow.contiguous(), T)
+        ctx.mesh = mesh
+        ctx.tape = tape
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        grad = ctx.mesh.backward_tape(ctx.tape, grad_out.contiguous())
+        ctx.tape = None
+        return grad, None, None
+
+
+def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
+    """Differentiable FTLE of a flow map on a mesh."""
+    return FTLEFunction.apply(flow, mesh, T)
+
+
+__all__ = ["Mesh", "batched", "batched_config", "FTLEFunction", "ftle", "FTLEError"]

@@ -1,0 +1,1145 @@
+// Host side of the FTLE library: the C ABI declared in include/ftle.h.
+//
+// Mesh creation does, on the CPU, what Section 2.2 of de Castro et al.
+// assigns to the host processor: it determines every point's neighbours once
+// and stores them as a list of integer indices that the accelerator then
+// reads in a fixed order.  On top of that it orders the points along a
+// Morton curve and cuts the order into LDS-sized tiles (see
+// ftle_internal.h for the tile record layout), so the GPU reads every index
+// sequentially and every coordinate and flow-map value about once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ftle.h"
+#include "ftle_internal.h"
+
+using namespace ftle;
+
+// ===========================================================================
+// Errors
+// ===========================================================================
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+    ftle_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(ftle_status st, const std::string& msg) { throw Failure{st, msg}; }
+
+void check_hip(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) {
+        const ftle_status st = (e == hipErrorOutOfMemory) ? FTLE_ERR_OOM : FTLE_ERR_DEVICE;
+        fail(st, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+template <typename F>
+ftle_status guarded(F&& body)
+{
+    try {
+        body();
+        g_last_error.clear();
+        return FTLE_OK;
+    } catch (const Failure& f) {
+        g_last_error = f.msg;
+        return f.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return FTLE_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = std::string("internal error: ") + e.what();
+        return FTLE_ERR_DEVICE;
+    } catch (...) {
+        g_last_error = "internal error";
+        return FTLE_ERR_DEVICE;
+    }
+}
+
+// ===========================================================================
+// Small host utilities
+// ===========================================================================
+int host_threads()
+{
+    unsigned hc = std::thread::hardware_concurrency();
+    if (const char* e = std::getenv("FTLE_HOST_THREADS")) hc = (unsigned)std::max(1, std::atoi(e));
+    return (int)std::max(1u, std::min(hc, 32u));
+}
+
+// Run body(begin, end) over [0, n) split into contiguous chunks, one per thread.
+template <typename F>
+void parallel_for(int64_t n, F&& body, int64_t min_chunk = 16384)
+{
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), (n + min_chunk - 1) / min_chunk));
+    if (nt <= 1) {
+        body((int64_t)0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(nt);
+    for (int t = 0; t < nt; ++t) {
+        const int64_t b = n * t / nt, e = n * (t + 1) / nt;
+        th.emplace_back([&, b, e, t] {
+            try {
+                body(b, e, t);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
+    }
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+// Spread the low 32 bits of v to the even bit positions of a 64-bit word.
+uint64_t spread2(uint64_t v)
+{
+    v &= 0xffffffffULL;
+    v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
+    v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
+    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+    v = (v | (v << 2)) & 0x3333333333333333ULL;
+    v = (v | (v << 1)) & 0x5555555555555555ULL;
+    return v;
+}
+
+// Spread the low 21 bits of v to every third bit position.
+uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffULL;
+    v = (v | (v << 32)) & 0x001f00000000ffffULL;
+    v = (v | (v << 16)) & 0x001f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+// Stable LSD radix sort of (key, value) pairs by key, 16 bits per pass.
+void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<int32_t>& val)
+{
+    const size_t n = key.size();
+    std::vector<uint64_t> k2(n);
+    std::vector<int32_t> v2(n);
+    std::vector<size_t> cnt(65536 + 1);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int sh = 16 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < n; ++i) ++cnt[((key[i] >> sh) & 0xffff) + 1];
+        bool trivial = false;
+        for (size_t d = 1; d <= 65536; ++d)
+            if (cnt[d] == n) trivial = true;
+        if (trivial) continue;
+        for (size_t d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+        for (size_t i = 0; i < n; ++i) {
+            const size_t p = cnt[(key[i] >> sh) & 0xffff]++;
+            k2[p] = key[i];
+            v2[p] = val[i];
+        }
+        key.swap(k2);
+        val.swap(v2);
+    }
+}
+
+// ===========================================================================
+// CSR helpers (rows and columns are Morton positions)
+// ===========================================================================
+struct Csr {
+    std::vector<int32_t> row_ptr;  // n+1 (int32: nnz < 2^31 is checked)
+    std::vector<int32_t> col;
+};
+
+Csr transpose(const Csr& a, int64_t n)
+{
+    Csr t;
+    t.row_ptr.assign(n + 1, 0);
+    for (int32_t c : a.col) ++t.row_ptr[c + 1];
+    for (int64_t i = 0; i < n; ++i) t.row_ptr[i + 1] += t.row_ptr[i];
+    t.col.resize(a.col.size());
+    std::vector<int32_t> fill(t.row_ptr.begin(), t.row_ptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+        for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) t.col[fill[a.col[p]]++] = (int32_t)r;
+    return t;  // rows ascending by construction
+}
+
+bool csr_equal(const Csr& a, const Csr& b) { return a.row_ptr == b.row_ptr && a.col == b.col; }
+
+}  // namespace
+
+// ===========================================================================
+// Mesh object
+// ===========================================================================
+struct TileSet {
+    std::vector<TileMeta> meta;
+    std::vector<uint32_t> rec;     // record words (16-byte aligned blocks)
+    int max_staged = 0;
+    int max_seg = 0;
+    int max_P = 0;
+    int64_t halo_total = 0;
+    void* d_meta = nullptr;
+    void* d_rec = nullptr;
+
+    DevTiles dev() const
+    {
+        DevTiles d;
+        d.meta = static_cast<const TileMeta*>(d_meta);
+        d.rec = static_cast<const uint4*>(d_rec);
+        d.n_tiles = (int)meta.size();
+        d.max_staged = max_staged;
+        d.max_seg = max_seg;
+        return d;
+    }
+};
+
+struct ftle_mesh_s {
+    int dim = 0;
+    int64_t n = 0;
+    ftle_dtype dtype = FTLE_F32;
+    unsigned flags = 0;
+    int tile_points = 0;
+    bool symmetric = true;
+    bool host_only = false;
+    std::vector<int32_t> perm;     // Morton position -> user index
+    Csr csr;                       // forward stencil, Morton positions
+    TileSet fwd, bwd;              // bwd empty when symmetric (fwd serves both)
+    std::vector<unsigned char> x_user;   // coordinates, user order, dtype
+    int device = -1;
+    void* d_x = nullptr;
+    unsigned long long* d_hits = nullptr;
+    void* d_work = nullptr;        // adjoint workspace (tape) of ftle_backward
+    hipEvent_t work_done = nullptr;
+    hipStream_t work_stream = nullptr;
+    std::mutex mu;
+
+    bool f64() const { return dtype == FTLE_F64; }
+    size_t elem() const { return f64() ? 8 : 4; }
+    const TileSet& adj_tiles() const { return symmetric ? fwd : bwd; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Neighbour stencils (Section 2.2: computed once, on the host)
+// ---------------------------------------------------------------------------
+
+// RING1: every point sharing a cell with r, excluding r, ascending.
+// cells are already renumbered to Morton positions.
+Csr build_ring1(int dim, int64_t n, int64_t ncells, const std::vector<int32_t>& cells)
+{
+    const int k = dim + 1;
+    // point -> incident cells
+    std::vector<int64_t> inc_ptr(n + 1, 0);
+    for (int64_t c = 0; c < ncells * k; ++c) ++inc_ptr[cells[c] + 1];
+    for (int64_t i = 0; i < n; ++i) inc_ptr[i + 1] += inc_ptr[i];
+    std::vector<int32_t> inc(inc_ptr[n]);
+    {
+        std::vector<int64_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int64_t c = 0; c < ncells; ++c)
+            for (int a = 0; a < k; ++a) inc[fill[cells[c * k + a]]++] = (int32_t)c;
+    }
+    Csr out;
+    out.row_ptr.assign(n + 1, 0);
+    std::vector<int64_t> deg(n, 0);
+    auto row = [&](int64_t r, std::vector<int32_t>& buf) {
+        buf.clear();
+        for (int64_t p = inc_ptr[r]; p < inc_ptr[r + 1]; ++p) {
+            const int64_t c = inc[p];
+            for (int a = 0; a < k; ++a) {
+                const int32_t v = cells[c * k + a];
+                if (v != r) buf.push_back(v);
+            }
+        }
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    };
+    parallel_for(n, [&](int64_t b, int64_t e, int) {
+        std::vector<int32_t> buf;
+        for (int64_t r = b; r < e; ++r) {
+            row(r, buf);
+            deg[r] = (int64_t)buf.size();
+        }
+    });
+    int64_t total = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        total += deg[r];
+        if (total > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
+        out.row_ptr[r + 1] = (int32_t)total;
+    }
+    out.col.resize(total);
+    parallel_for(n, [&](int64_t b, int64_t e, int) {
+        std::vector<int32_t> buf;
+        for (int64_t r = b; r < e; ++r) {
+            row(r, buf);
+            std::copy(buf.begin(), buf.end(), out.col.begin() + out.row_ptr[r]);
+        }
+    });
+    return out;
+}
+
+// AXIS: the paper's fixed-width list (4 slots in 2D, 6 in 3D).  Slot (d, s)
+// takes, among the RING1 neighbours on side s of axis d, the one with the
+// largest cosine to that direction; ties go to the smaller caller index.
+// Absent slots are dropped from the row (the -1 entries of the paper's list).
+template <typename T>
+Csr build_axis(int dim, int64_t n, const Csr& ring, const T* xm /* Morton order */,
+               const std::vector<int32_t>& perm)
+{
+    Csr out;
+    out.row_ptr.assign(n + 1, 0);
+    std::vector<int32_t> slots((size_t)n * 2 * dim, -1);
+    parallel_for(n, [&](int64_t b, int64_t e, int) {
+        for (int64_t r = b; r < e; ++r) {
+            for (int d = 0; d < dim; ++d)
+                for (int sg = 0; sg < 2; ++sg) {
+                    const double sigma = sg ? 1.0 : -1.0;
+                    double best = 0.0;
+                    int32_t arg = -1;
+                    for (int32_t p = ring.row_ptr[r]; p < ring.row_ptr[r + 1]; ++p) {
+                        const int32_t c = ring.col[p];
+                        double nrm2 = 0.0;
+                        for (int q = 0; q < dim; ++q) {
+                            const double t = (double)xm[(size_t)c * dim + q] - (double)xm[(size_t)r * dim + q];
+                            nrm2 += t * t;
+                        }
+                        const double along = sigma * ((double)xm[(size_t)c * dim + d] - (double)xm[(size_t)r * dim + d]);
+                        if (!(along > 0.0)) continue;
+                        const double cs = along / std::sqrt(nrm2);
+                        if (arg < 0 || cs > best || (cs == best && perm[c] < perm[arg])) {
+                            best = cs;
+                            arg = c;
+                        }
+                    }
+                    slots[(size_t)r * 2 * dim + 2 * d + sg] = arg;
+                }
+        }
+    });
+    for (int64_t r = 0; r < n; ++r) {
+        int cnt = 0;
+        for (int s = 0; s < 2 * dim; ++s) cnt += slots[(size_t)r * 2 * dim + s] >= 0;
+        out.row_ptr[r + 1] = out.row_ptr[r] + cnt;
+    }
+    out.col.reserve(out.row_ptr[n]);
+    for (int64_t r = 0; r < n; ++r)
+        for (int s = 0; s < 2 * dim; ++s) {
+            const int32_t c = slots[(size_t)r * 2 * dim + s];
+            if (c >= 0) out.col.push_back(c);
+        }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Tiles
+// ---------------------------------------------------------------------------
+struct TileExtent {
+    int64_t begin, end;
+    uint32_t H, nnz;
+};
+
+// Halo of [b, e): neighbours outside the range, as Morton positions sorted by
+// caller index (so the staging gathers of a tile walk memory in order).
+void tile_halo(const Csr& a, const std::vector<int32_t>& perm, int64_t b, int64_t e,
+               std::vector<uint32_t>& stamp, uint32_t tag, std::vector<int32_t>& halo)
+{
+    halo.clear();
+    for (int64_t r = b; r < e; ++r)
+        for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
+            const int32_t c = a.col[p];
+            if (c >= b && c < e) continue;
+            if (stamp[c] == tag) continue;
+            stamp[c] = tag;
+            halo.push_back(c);
+        }
+    std::sort(halo.begin(), halo.end(), [&](int32_t u, int32_t v) { return perm[u] < perm[v]; });
+}
+
+bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nnz)
+{
+    if (P + H > kMaxLocal || nnz > kMaxTileNnz) return false;
+    const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nnz);
+    const size_t slot = std::max(fwd_slot_bytes(dim, f64), bwd_slot_bytes(dim, f64));
+    return tile_lds_bytes(slot, (int)(P + H), seg) <= kLdsBudget;
+}
+
+TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
+                    const std::vector<int32_t>& perm)
+{
+    // 1. extents: nominal chunks of tile_points, halved until they fit the caps
+    const int64_t nchunks = (n + tile_points - 1) / tile_points;
+    std::vector<std::vector<TileExtent>> per_chunk(nchunks);
+    parallel_for(nchunks, [&](int64_t cb, int64_t ce, int) {
+        std::vector<uint32_t> stamp(n, 0);
+        uint32_t tag = 0;
+        std::vector<int32_t> halo;
+        for (int64_t ch = cb; ch < ce; ++ch) {
+            std::vector<std::pair<int64_t, int64_t>> todo{{ch * tile_points, std::min<int64_t>(n, (ch + 1) * tile_points)}};
+            while (!todo.empty()) {
+                auto [b, e] = todo.back();
+                todo.pop_back();
+                if (++tag == 0) {
+                    std::fill(stamp.begin(), stamp.end(), 0);
+                    tag = 1;
+                }
+                tile_halo(a, perm, b, e, stamp, tag, halo);
+                const int64_t nnz = (int64_t)a.row_ptr[e] - a.row_ptr[b];
+                if (tile_fits(dim, f64, e - b, (int64_t)halo.size(), nnz)) {
+                    per_chunk[ch].push_back({b, e, (uint32_t)halo.size(), (uint32_t)nnz});
+                } else if (e - b == 1) {
+                    fail(FTLE_ERR_UNSUPPORTED, "point " + std::to_string(perm[b]) + " has " +
+                                                   std::to_string(nnz) + " neighbours, more than one tile holds");
+                } else {
+                    const int64_t m = b + (e - b) / 2;
+                    todo.push_back({m, e});   // processed after [b, m): keeps ascending order
+                    todo.push_back({b, m});
+                }
+            }
+        }
+    }, 1);
+    std::vector<TileExtent> ext;
+    for (auto& v : per_chunk) ext.insert(ext.end(), v.begin(), v.end());
+
+    // 2. record offsets
+    TileSet ts;
+    ts.meta.resize(ext.size());
+    uint64_t off = 0;  // in 16-byte units
+    for (size_t t = 0; t < ext.size(); ++t) {
+        const uint32_t P = (uint32_t)(ext[t].end - ext[t].begin);
+        const uint64_t words = idx_words(P, ext[t].H) + seg_halfs(P, ext[t].nnz) / 2;
+        if (off > UINT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "tile records exceed 64 GiB");
+        ts.meta[t] = TileMeta{(uint32_t)off, P, ext[t].H, ext[t].nnz};
+        off += words / 4;
+        ts.max_staged = std::max(ts.max_staged, (int)(P + ext[t].H));
+        ts.max_seg = std::max(ts.max_seg, (int)seg_halfs(P, ext[t].nnz));
+        ts.max_P = std::max(ts.max_P, (int)P);
+        ts.halo_total += ext[t].H;
+    }
+    ts.rec.assign(off * 4, 0u);
+
+    // 3. fill records
+    parallel_for((int64_t)ext.size(), [&](int64_t tb, int64_t te, int) {
+        std::vector<uint32_t> stamp(n, 0);
+        std::vector<int32_t> halo;
+        std::vector<int32_t> local(0);
+        uint32_t tag = 0;
+        for (int64_t t = tb; t < te; ++t) {
+            const TileMeta m = ts.meta[t];
+            const int64_t b = ext[t].begin, e = ext[t].end;
+            if (++tag == 0) {
+                std::fill(stamp.begin(), stamp.end(), 0);
+                tag = 1;
+            }
+            tile_halo(a, perm, b, e, stamp, tag, halo);
+            uint32_t* idx = ts.rec.data() + (size_t)m.rec_off * 4;
+            uint16_t* seg = reinterpret_cast<uint16_t*>(idx + idx_words(m.P, m.H));
+            for (int64_t r = b; r < e; ++r) idx[r - b] = (uint32_t)perm[r];
+            // halo slot of each halo point: reuse stamp as "slot + 1" storage is
+            // not possible (tag), so search in a small map
+            std::vector<std::pair<int32_t, int32_t>> hs(halo.size());
+            for (size_t h = 0; h < halo.size(); ++h) {
+                idx[m.P + h] = (uint32_t)perm[halo[h]];
+                hs[h] = {halo[h], (int32_t)(m.P + h)};
+            }
+            std::sort(hs.begin(), hs.end());
+            uint32_t pos = 0;
+            for (int64_t r = b; r < e; ++r) {
+                for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
+                    const int32_t c = a.col[p];
+                    int32_t loc;
+                    if (c >= b && c < e) {
+                        loc = (int32_t)(c - b);
+                    } else {
+                        auto it = std::lower_bound(hs.begin(), hs.end(), std::make_pair(c, INT32_MIN));
+                        loc = it->second;
+                    }
+                    seg[m.P + pos++] = (uint16_t)loc;
+                }
+                seg[r - b] = (uint16_t)pos;
+            }
+        }
+    }, 1);
+    return ts;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory
+// ---------------------------------------------------------------------------
+void* dev_upload(const void* src, size_t bytes)
+{
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    check_hip(hipMalloc(&p, bytes), "hipMalloc");
+    if (src) {
+        const hipError_t e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            check_hip(e, "hipMemcpy");
+        }
+    }
+    return p;
+}
+
+void free_tiles(TileSet& t)
+{
+    if (t.d_meta) (void)hipFree(t.d_meta);
+    if (t.d_rec) (void)hipFree(t.d_rec);
+    t.d_meta = t.d_rec = nullptr;
+}
+
+void upload_tiles(TileSet& t)
+{
+    t.d_meta = dev_upload(t.meta.data(), t.meta.size() * sizeof(TileMeta));
+    t.d_rec = dev_upload(t.rec.data(), t.rec.size() * sizeof(uint32_t));
+}
+
+void release_device(ftle_mesh_s* m)
+{
+    if (m->device < 0) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    free_tiles(m->fwd);
+    free_tiles(m->bwd);
+    if (m->d_x) (void)hipFree(m->d_x);
+    if (m->d_hits) (void)hipFree(m->d_hits);
+    if (m->d_work) (void)hipFree(m->d_work);
+    if (m->work_done) (void)hipEventDestroy(m->work_done);
+    m->d_x = nullptr;
+    m->d_hits = nullptr;
+    m->d_work = nullptr;
+    m->work_done = nullptr;
+    (void)hipSetDevice(cur);
+}
+
+// ---------------------------------------------------------------------------
+// Tunables (environment, read once)
+// ---------------------------------------------------------------------------
+double env_double(const char* name, double dflt)
+{
+    const char* v = std::getenv(name);
+    return v ? std::atof(v) : dflt;
+}
+
+// r < -1 + tau selects the float64 eigenvalue recompute (3D, float32 meshes).
+double eig_tau() { static const double t = env_double("FTLE_EIG_TAU", 2e-3); return t; }
+int fwd_block() { static const int b = (int)env_double("FTLE_FWD_BLOCK", 256); return b; }
+int bwd_block() { static const int b = (int)env_double("FTLE_BWD_BLOCK", 256); return b; }
+
+void check_mesh(ftle_mesh_t m)
+{
+    if (!m) fail(FTLE_ERR_INVALID_ARG, "mesh is NULL");
+}
+
+// Called after every argument check, right before device work.
+void need_device(ftle_mesh_t m)
+{
+    if (m->host_only) fail(FTLE_ERR_UNSUPPORTED, "mesh was created with FTLE_HOST_ONLY");
+}
+
+void check_T(double T)
+{
+    if (!(T != 0.0) || !std::isfinite(T)) fail(FTLE_ERR_INVALID_ARG, "T must be finite and nonzero");
+}
+
+void check_dtype(ftle_mesh_t m, ftle_dtype d)
+{
+    if (d != FTLE_F32 && d != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+    if (d != m->dtype) fail(FTLE_ERR_DTYPE, "dtype differs from the mesh's dtype");
+}
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        check_hip(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != dev) check_hip(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ftle_last_error(void) { return g_last_error.c_str(); }
+
+const char* ftle_version(void) { return "ftle-mi355x 0.1 (gfx950)"; }
+
+ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                             int64_t n_cells, const int32_t* cells, unsigned flags, ftle_mesh_t* out)
+{
+    return guarded([&] {
+        if (!out) fail(FTLE_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points must be >= 1");
+        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+        if (!coords) fail(FTLE_ERR_INVALID_ARG, "coords is NULL");
+        if (n_cells < 0) fail(FTLE_ERR_INVALID_ARG, "n_cells < 0");
+        if (n_cells > 0 && !cells) fail(FTLE_ERR_INVALID_ARG, "cells is NULL");
+        const unsigned known = FTLE_STENCIL_AXIS | FTLE_NO_REORDER | FTLE_HOST_ONLY | FTLE_TILE(0xff);
+        if (flags & ~known) fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
+        const int tile_log2 = (int)((flags >> 8) & 0xff);
+        if (tile_log2 != 0 && (tile_log2 < 5 || tile_log2 > 11))
+            fail(FTLE_ERR_INVALID_ARG, "FTLE_TILE(k) needs 5 <= k <= 11");
+        const int64_t n = n_points;
+        const int k = dim + 1;
+        if (n_cells > INT64_MAX / k) fail(FTLE_ERR_INVALID_ARG, "n_cells too large");
+
+        // validate coordinates
+        const bool f64 = dtype == FTLE_F64;
+        std::vector<double> xd((size_t)n * dim);
+        for (int64_t i = 0; i < n * dim; ++i) {
+            const double v = f64 ? static_cast<const double*>(coords)[i] : (double)static_cast<const float*>(coords)[i];
+            if (!std::isfinite(v)) fail(FTLE_ERR_INVALID_ARG, "coordinate " + std::to_string(i / dim) + " is not finite");
+            xd[i] = v;
+        }
+        // validate cells
+        std::atomic<int64_t> bad_cell{-1};
+        std::atomic<int> bad_kind{0};
+        parallel_for(n_cells, [&](int64_t b, int64_t e, int) {
+            for (int64_t c = b; c < e && bad_cell.load(std::memory_order_relaxed) < 0; ++c) {
+                for (int a = 0; a < k; ++a) {
+                    const int32_t v = cells[c * k + a];
+                    if (v < 0 || v >= n) {
+                        bad_kind = 1;
+                        bad_cell = c;
+                        return;
+                    }
+                    for (int q = 0; q < a; ++q)
+                        if (cells[c * k + q] == v) {
+                            bad_kind = 2;
+                            bad_cell = c;
+                            return;
+                        }
+                }
+            }
+        });
+        if (bad_cell >= 0)
+            fail(FTLE_ERR_BAD_MESH, std::string(bad_kind == 1 ? "cell index out of range" : "repeated vertex") +
+                                        " in cell " + std::to_string(bad_cell.load()));
+
+        std::unique_ptr<ftle_mesh_s> m(new ftle_mesh_s);
+        m->dim = dim;
+        m->n = n;
+        m->dtype = dtype;
+        m->flags = flags;
+        m->host_only = (flags & FTLE_HOST_ONLY) != 0;
+        m->tile_points = tile_log2 ? (1 << tile_log2) : (dim == 2 ? 1024 : 512);
+
+        // Morton order: quantise to the bounding box, interleave, stable sort
+        m->perm.resize(n);
+        for (int64_t i = 0; i < n; ++i) m->perm[i] = (int32_t)i;
+        if (!(flags & FTLE_NO_REORDER) && n > 1) {
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int64_t i = 0; i < n; ++i)
+                for (int d = 0; d < dim; ++d) {
+                    lo[d] = std::min(lo[d], xd[i * dim + d]);
+                    hi[d] = std::max(hi[d], xd[i * dim + d]);
+                }
+            // Quantise each axis in units of the mean point spacing, with
+            // `sub` fractional bits.  The unit is the span over n^(1/dim) - 1/2
+            // points and the offset 0.2 unit, so that floor() sends point i of
+            // an m-point lattice to i (i (1 + 1/(2m-2)) + 0.2 < i + 1) and also
+            // keeps cell-centred points jittered by up to +-0.3 spacing inside
+            // their own cell.  On such grids the integer parts are the grid
+            // indices, runs of 2^(k*dim) consecutive codes are aligned blocks
+            // and tiles have minimal halos; the fractional bits keep irregular
+            // meshes finely ordered.
+            const int bits = (dim == 2) ? 31 : 21;
+            const double per_axis = std::max(2.0, std::pow((double)n, 1.0 / dim));
+            double unit[3] = {1, 1, 1};
+            double range = 1.0;
+            for (int d = 0; d < dim; ++d) {
+                const double span = hi[d] - lo[d];
+                unit[d] = span > 0 ? span / (per_axis - 0.5) : 1.0;
+                range = std::max(range, span / unit[d] + 1.0);
+            }
+            int sub = 8;
+            while (sub > 0 && std::ldexp(range, sub) >= std::ldexp(1.0, bits)) --sub;
+            const double qmax = std::ldexp(1.0, bits) - 1.0;
+            std::vector<uint64_t> key(n);
+            parallel_for(n, [&](int64_t b, int64_t e, int) {
+                for (int64_t i = b; i < e; ++i) {
+                    uint64_t code = 0;
+                    for (int d = 0; d < dim; ++d) {
+                        const double t = std::floor(((xd[i * dim + d] - lo[d]) / unit[d] + 0.2) * std::ldexp(1.0, sub));
+                        const uint64_t q = (uint64_t)std::min(qmax, std::max(0.0, t));
+                        code |= (dim == 2 ? spread2(q) : spread3(q)) << d;
+                    }
+                    key[i] = code;
+                }
+            });
+            radix_sort_pairs(key, m->perm);
+        }
+        std::vector<int32_t> inv(n);
+        for (int64_t r = 0; r < n; ++r) inv[m->perm[r]] = (int32_t)r;
+
+        // cells in Morton positions, then the stencil
+        std::vector<int32_t> mc((size_t)n_cells * k);
+        parallel_for(n_cells * k, [&](int64_t b, int64_t e, int) {
+            for (int64_t i = b; i < e; ++i) mc[i] = inv[cells[i]];
+        });
+        Csr ring = build_ring1(dim, n, n_cells, mc);
+        mc.clear();
+        mc.shrink_to_fit();
+        if (flags & FTLE_STENCIL_AXIS) {
+            std::vector<double> xm((size_t)n * dim);
+            for (int64_t r = 0; r < n; ++r)
+                for (int d = 0; d < dim; ++d) xm[r * dim + d] = xd[(size_t)m->perm[r] * dim + d];
+            m->csr = build_axis<double>(dim, n, ring, xm.data(), m->perm);
+        } else {
+            m->csr = std::move(ring);
+        }
+        Csr tr = transpose(m->csr, n);
+        m->symmetric = csr_equal(tr, m->csr);
+        m->fwd = build_tiles(dim, f64, n, m->tile_points, m->csr, m->perm);
+        if (!m->symmetric) m->bwd = build_tiles(dim, f64, n, m->tile_points, tr, m->perm);
+
+        // coordinates in user order, stored in the mesh dtype
+        m->x_user.resize((size_t)n * dim * m->elem());
+        std::memcpy(m->x_user.data(), coords, m->x_user.size());
+
+        if (!m->host_only) {
+            int dev = 0;
+            check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+            m->device = dev;
+            try {
+                upload_tiles(m->fwd);
+                if (!m->symmetric) upload_tiles(m->bwd);
+                m->d_x = dev_upload(m->x_user.data(), m->x_user.size());
+                m->d_hits = static_cast<unsigned long long*>(dev_upload(nullptr, sizeof(unsigned long long)));
+                check_hip(hipMemset(m->d_hits, 0, sizeof(unsigned long long)), "hipMemset");
+                check_hip(hipEventCreateWithFlags(&m->work_done, hipEventDisableTiming), "hipEventCreate");
+            } catch (...) {
+                release_device(m.get());
+                throw;
+            }
+        }
+        *out = m.release();
+    });
+}
+
+
+ftle_status ftle_mesh_info(ftle_mesh_t mesh, int* dim, int64_t* n_points, int64_t* nnz, int* dtype)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        if (dim) *dim = mesh->dim;
+        if (n_points) *n_points = mesh->n;
+        if (nnz) *nnz = (int64_t)mesh->csr.col.size();
+        if (dtype) *dtype = (int)mesh->dtype;
+    });
+}
+
+ftle_status ftle_mesh_get_csr(ftle_mesh_t mesh, int32_t* row_ptr, int32_t* col, int32_t* perm)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        if (row_ptr) std::memcpy(row_ptr, mesh->csr.row_ptr.data(), mesh->csr.row_ptr.size() * 4);
+        if (col) std::memcpy(col, mesh->csr.col.data(), mesh->csr.col.size() * 4);
+        if (perm) std::memcpy(perm, mesh->perm.data(), mesh->perm.size() * 4);
+    });
+}
+
+ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* max_tile_points,
+                                 int64_t* halo_entries, int64_t* record_bytes)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        if (n_tiles) *n_tiles = (int64_t)mesh->fwd.meta.size();
+        if (max_tile_points) *max_tile_points = mesh->fwd.max_P;
+        if (halo_entries) *halo_entries = mesh->fwd.halo_total;
+        if (record_bytes) *record_bytes = (int64_t)(mesh->fwd.rec.size() * 4 + mesh->fwd.meta.size() * 16);
+    });
+}
+
+ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,
+                                void* meta, void* records)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        const TileSet& ts = adjoint ? mesh->adj_tiles() : mesh->fwd;
+        if (n_tiles) *n_tiles = (int64_t)ts.meta.size();
+        if (record_bytes) *record_bytes = (int64_t)ts.rec.size() * 4;
+        if (meta) std::memcpy(meta, ts.meta.data(), ts.meta.size() * sizeof(TileMeta));
+        if (records) std::memcpy(records, ts.rec.data(), ts.rec.size() * 4);
+    });
+}
+
+ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T, void* out,
+                         ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        check_dtype(mesh, dtype);
+        check_T(T);
+        if (!flow || !out) fail(FTLE_ERR_INVALID_ARG, "flow or out is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
+                                 out, nullptr, mesh->n, eig_tau(), mesh->d_hits, fwd_block(),
+                                 static_cast<hipStream_t>(stream)),
+                  "forward launch");
+    });
+}
+
+ftle_status ftle_tape_bytes(ftle_mesh_t mesh, int64_t* bytes)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        if (!bytes) fail(FTLE_ERR_INVALID_ARG, "bytes is NULL");
+        *bytes = mesh->n * (2 * mesh->dim + 1) * (int64_t)mesh->elem();
+    });
+}
+
+ftle_status ftle_forward_tape(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T, void* out,
+                              void* tape, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        check_dtype(mesh, dtype);
+        check_T(T);
+        if (!flow || !out || !tape) fail(FTLE_ERR_INVALID_ARG, "flow, out or tape is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
+                                 out, tape, mesh->n, eig_tau(), mesh->d_hits, fwd_block(),
+                                 static_cast<hipStream_t>(stream)),
+                  "forward+tape launch");
+    });
+}
+
+ftle_status ftle_backward_tape(ftle_mesh_t mesh, const void* tape, ftle_dtype dtype, const void* grad_ftle,
+                               void* grad_flow, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        check_dtype(mesh, dtype);
+        if (!tape || !grad_ftle || !grad_flow) fail(FTLE_ERR_INVALID_ARG, "tape, grad_ftle or grad_flow is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, tape,
+                                         mesh->n, grad_ftle, grad_flow, bwd_block(),
+                                         static_cast<hipStream_t>(stream)),
+                  "adjoint launch");
+    });
+}
+
+ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T, const void* grad_ftle,
+                          void* grad_flow, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        check_dtype(mesh, dtype);
+        check_T(T);
+        if (!flow || !grad_ftle || !grad_flow) fail(FTLE_ERR_INVALID_ARG, "flow, grad_ftle or grad_flow is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        std::lock_guard<std::mutex> lk(mesh->mu);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (!mesh->d_work) {
+            const size_t bytes = (size_t)mesh->n * (2 * mesh->dim + 1) * mesh->elem();
+            check_hip(hipMalloc(&mesh->d_work, bytes), "hipMalloc (adjoint workspace)");
+        } else if (mesh->work_stream != s) {
+            // the previous call on another stream may still use the workspace
+            check_hip(hipStreamWaitEvent(s, mesh->work_done, 0), "hipStreamWaitEvent");
+        }
+        check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
+                                 nullptr, mesh->d_work, mesh->n, eig_tau(), mesh->d_hits, fwd_block(), s),
+                  "adjoint tape launch");
+        check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, mesh->d_work,
+                                         mesh->n, grad_ftle, grad_flow, bwd_block(), s),
+                  "adjoint launch");
+        check_hip(hipEventRecord(mesh->work_done, s), "hipEventRecord");
+        mesh->work_stream = s;
+    });
+}
+
+ftle_status ftle_mesh_fp64_hits(ftle_mesh_t mesh, int64_t* hits, int reset)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        if (!hits) fail(FTLE_ERR_INVALID_ARG, "hits is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        unsigned long long h = 0;
+        check_hip(hipMemcpy(&h, mesh->d_hits, sizeof(h), hipMemcpyDeviceToHost), "hipMemcpy");
+        *hits = (int64_t)h;
+        if (reset) check_hip(hipMemset(mesh->d_hits, 0, sizeof(h)), "hipMemset");
+    });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched launches: work list, autotuner, graph cache
+// ===========================================================================
+namespace {
+
+struct BatchPlan {
+    int dim = 0;
+    bool f64 = false;
+    int device = -1;
+    std::vector<ftle_mesh_t> meshes;
+    void* d_meshes = nullptr;     // BatchMesh[n]
+    void* d_items = nullptr;      // uint32 items
+    unsigned* d_queue = nullptr;  // 2 counters
+    int n_items = 0;
+    size_t lds = 0;
+    // chosen launch shape
+    int block = 256, tiles_per_pop = 1, grid = 0;
+    bool tuned = false;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node = nullptr;
+    std::vector<unsigned char> arg_storage;
+    void* args[7] = {};
+};
+
+std::mutex g_batch_mu;
+std::map<std::vector<ftle_mesh_t>, std::unique_ptr<BatchPlan>> g_plans;
+
+BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
+{
+    std::vector<ftle_mesh_t> key(meshes, meshes + n);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second.get();
+    std::unique_ptr<BatchPlan> p(new BatchPlan);
+    p->meshes = key;
+    p->dim = meshes[0]->dim;
+    p->f64 = meshes[0]->f64();
+    p->device = meshes[0]->device;
+    std::vector<BatchMesh> bm(n);
+    DevTiles maxt{};
+    struct Item {
+        uint32_t item;
+        uint32_t cost;
+    };
+    std::vector<Item> items;
+    uint32_t max_cost = 1;
+    for (int k = 0; k < n; ++k) {
+        const ftle_mesh_t m = meshes[k];
+        bm[k].tiles = m->fwd.dev();
+        bm[k].x = m->d_x;
+        bm[k].fp64_hits = m->d_hits;
+        maxt.max_staged = std::max(maxt.max_staged, m->fwd.max_staged);
+        maxt.max_seg = std::max(maxt.max_seg, m->fwd.max_seg);
+        if (m->fwd.meta.size() >= (1u << kItemTileBits)) fail(FTLE_ERR_UNSUPPORTED, "mesh has too many tiles for a batch");
+        for (size_t t = 0; t < m->fwd.meta.size(); ++t) {
+            const TileMeta& tm = m->fwd.meta[t];
+            const uint32_t cost = tm.nnz + tm.P + tm.H;
+            items.push_back({((uint32_t)k << kItemTileBits) | (uint32_t)t, cost});
+            max_cost = std::max(max_cost, cost);
+        }
+    }
+    // costliest first (in eighths of the largest tile), natural order within a bucket
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+        return (a.cost * 8ull / (max_cost + 1)) > (b.cost * 8ull / (max_cost + 1));
+    });
+    std::vector<uint32_t> it32(items.size());
+    for (size_t i = 0; i < items.size(); ++i) it32[i] = items[i].item;
+    p->n_items = (int)it32.size();
+    p->lds = fwd_lds_bytes(p->dim, p->f64, maxt);
+    p->d_meshes = dev_upload(bm.data(), bm.size() * sizeof(BatchMesh));
+    p->d_items = dev_upload(it32.data(), it32.size() * sizeof(uint32_t));
+    p->d_queue = static_cast<unsigned*>(dev_upload(nullptr, 2 * sizeof(unsigned)));
+    check_hip(hipMemset(p->d_queue, 0, 2 * sizeof(unsigned)), "hipMemset");
+    check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    BatchPlan* raw = p.get();
+    g_plans[key] = std::move(p);
+    return raw;
+}
+
+int resident_grid(BatchPlan* p, int block, int per_cu_cap)
+{
+    int per_cu = 0;
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel_symbol(p->dim, p->f64, block),
+                                                           block, p->lds),
+              "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    int cus = 0;
+    check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device), "hipDeviceGetAttribute");
+    per_cu = std::max(1, std::min(per_cu, per_cu_cap));
+    return std::max(1, std::min(p->n_items, per_cu * cus));
+}
+
+void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    float best = INFINITY;
+    const int blocks[] = {128, 256, 512};
+    const int pops[] = {1, 2, 4, 8};
+    const int caps[] = {2, 4, 8};
+    for (int b : blocks)
+        for (int k : pops)
+            for (int cap : caps) {
+                const int grid = resident_grid(p, b, cap);
+                if (k > 1 && (int64_t)grid * k > p->n_items) continue;
+                float tot = 0.f;
+                for (int rep = 0; rep < 4; ++rep) {
+                    check_hip(hipEventRecord(e0, s), "hipEventRecord");
+                    check_hip(launch_batched(p->dim, p->f64, static_cast<const BatchMesh*>(p->d_meshes),
+                                             static_cast<const uint32_t*>(p->d_items), p->n_items, k, p->d_queue,
+                                             call, p->lds, eig_tau(), b, grid, s),
+                              "batched launch");
+                    check_hip(hipEventRecord(e1, s), "hipEventRecord");
+                    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0.f;
+                    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    if (rep > 0) tot += ms;   // first launch warms up
+                }
+                if (tot < best) {
+                    best = tot;
+                    p->block = b;
+                    p->tiles_per_pop = k;
+                    p->grid = grid;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->tuned = true;
+}
+
+void build_graph(BatchPlan* p, const BatchCall& call)
+{
+    p->arg_storage.resize(batched_kernel_arg_storage());
+    batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
+                        p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(), p->args);
+    check_hip(hipGraphCreate(&p->graph, 0), "hipGraphCreate");
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block));
+    kp.gridDim = dim3(p->grid);
+    kp.blockDim = dim3(p->block);
+    kp.sharedMemBytes = (unsigned)p->lds;
+    kp.kernelParams = p->args;
+    kp.extra = nullptr;
+    check_hip(hipGraphAddKernelNode(&p->node, p->graph, nullptr, 0, &kp), "hipGraphAddKernelNode");
+    check_hip(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+void free_plan(BatchPlan* p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_meshes) (void)hipFree(p->d_meshes);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_queue) (void)hipFree(p->d_queue);
+}
+
+// Drop every cached batch plan that references mesh (its device pointers die with it).
+void purge_plans(ftle_mesh_t mesh)
+{
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (std::find(it->first.begin(), it->first.end(), mesh) != it->first.end()) {
+            free_plan(it->second.get());
+            it = g_plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void ftle_destroy_mesh(ftle_mesh_t mesh)
+{
+    if (!mesh) return;
+    if (!mesh->host_only) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(mesh->device);
+        (void)hipDeviceSynchronize();
+        purge_plans(mesh);
+        (void)hipSetDevice(cur);
+    }
+    release_device(mesh);
+    delete mesh;
+}
+
+ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* flows, const double* T,
+                         void* const* outs, ftle_dtype dtype, ftle_stream_t stream)
+{
+    return guarded([&] {
+        if (n < 1 || n > kMaxBatch) fail(FTLE_ERR_INVALID_ARG, "n must be in [1, 64]");
+        if (!meshes || !flows || !T || !outs) fail(FTLE_ERR_INVALID_ARG, "NULL array argument");
+        for (int k = 0; k < n; ++k) {
+            check_mesh(meshes[k]);
+            check_dtype(meshes[k], dtype);
+            check_T(T[k]);
+            if (!flows[k] || !outs[k]) fail(FTLE_ERR_INVALID_ARG, "NULL flow or out pointer");
+            if (meshes[k]->dim != meshes[0]->dim) fail(FTLE_ERR_INVALID_ARG, "meshes of mixed dimension");
+            if (meshes[k]->device != meshes[0]->device) fail(FTLE_ERR_INVALID_ARG, "meshes on different devices");
+        }
+        for (int k = 0; k < n; ++k) need_device(meshes[k]);
+        DeviceScope ds(meshes[0]->device);
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        BatchPlan* p = get_plan(n, meshes);
+        BatchCall call{};
+        for (int k = 0; k < n; ++k) {
+            call.flow[k] = flows[k];
+            call.out[k] = outs[k];
+            call.inv2T[k] = 0.5 / std::fabs(T[k]);
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (!p->tuned) autotune(p, call, s);
+        if (!p->exec) build_graph(p, call);
+        batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
+                            p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(), p->args);
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block));
+        kp.gridDim = dim3(p->grid);
+        kp.blockDim = dim3(p->block);
+        kp.sharedMemBytes = (unsigned)p->lds;
+        kp.kernelParams = p->args;
+        kp.extra = nullptr;
+        check_hip(hipGraphExecKernelNodeSetParams(p->exec, p->node, &kp), "hipGraphExecKernelNodeSetParams");
+        check_hip(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
+    });
+}
+
+ftle_status ftle_batched_config(int n, const ftle_mesh_t* meshes, int* block, int* tiles_per_pop, int* grid)
+{
+    return guarded([&] {
+        if (n < 1 || !meshes) fail(FTLE_ERR_INVALID_ARG, "bad mesh list");
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        auto it = g_plans.find(std::vector<ftle_mesh_t>(meshes, meshes + n));
+        if (it == g_plans.end() || !it->second->tuned) fail(FTLE_ERR_INVALID_ARG, "no batched call with these meshes yet");
+        if (block) *block = it->second->block;
+        if (tiles_per_pop) *tiles_per_pop = it->second->tiles_per_pop;
+        if (grid) *grid = it->second->grid;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal declarations shared by the host side (ftle_host.cpp) and the HIP
+// kernels (ftle_kernels.hip) of the FTLE library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ftle {
+
+// ---------------------------------------------------------------------------
+// Tile records (device layout).
+//
+// The mesh's points are cut, in Morton order, into tiles of at most
+// tile_points points; one workgroup processes one tile.  A tile's record is
+// a contiguous, 16-byte aligned block:
+//
+//   uint32 idx[P + H]         caller (user) index of every staged point: the
+//                             tile's own P points in Morton order, then its H
+//                             halo points (neighbours owned by other tiles),
+//                             padded to a multiple of 4 entries
+//   uint16 seg[P + nnz]       seg[0..P): end of each own point's row, relative
+//                             to the tile's first stencil entry;
+//                             seg[P..P+nnz): stencil entries as local indices
+//                             into idx (own points first, then halo),
+//                             padded to a multiple of 8 entries
+//
+// A 16-bit local index is enough because P + H <= kMaxStaged and
+// nnz <= kMaxTileNnz, both enforced when the mesh is built.
+// ---------------------------------------------------------------------------
+struct TileMeta {
+    uint32_t rec_off;  // record offset in 16-byte units
+    uint32_t P;        // own points
+    uint32_t H;        // halo points
+    uint32_t nnz;      // stencil entries of the tile's own points
+};
+static_assert(sizeof(TileMeta) == 16, "TileMeta is one 16-byte load");
+
+constexpr int kMaxLocal = 65535;       // P + H: 16-bit local indices
+constexpr int kMaxTileNnz = 65535;     // stencil entries per tile: 16-bit row ends
+constexpr size_t kLdsBudget = 65536;   // LDS bytes one tile may stage (forward or adjoint)
+
+__host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+__host__ __device__ inline uint32_t idx_words(uint32_t P, uint32_t H) { return (P + H + 3u) & ~3u; }
+__host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nnz) { return (P + nnz + 7u) & ~7u; }
+
+// LDS bytes per staged point.  Forward: coordinates and flow map (2*dim
+// values).  Adjoint: coordinates, w = g p and h (3*dim values).
+__host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(2 * dim); }
+__host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(3 * dim); }
+__host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, int seg)
+{
+    return (size_t)round_up(staged, 4) * slot_bytes + (size_t)seg * 2;
+}
+
+// One tile set: the tiles of one stencil (the forward stencil, or its
+// transpose for the adjoint when the stencil is not symmetric).
+struct DevTiles {
+    const TileMeta* meta;
+    const uint4* rec;
+    int n_tiles;
+    int max_staged;   // max over tiles of P + H
+    int max_seg;      // max over tiles of seg_halfs(P, nnz)
+};
+
+// Per-mesh parameters of a batched launch that do not change between calls.
+struct BatchMesh {
+    DevTiles tiles;
+    const void* x;
+    unsigned long long* fp64_hits;
+};
+
+// Per-call parameters of a batched launch (kernel argument by value).
+constexpr int kMaxBatch = 64;
+struct BatchCall {
+    const void* flow[kMaxBatch];
+    void* out[kMaxBatch];
+    double inv2T[kMaxBatch];
+};
+
+// Work item of the batched queue: mesh in the top 8 bits, tile in the low 24.
+constexpr int kItemTileBits = 24;
+
+// Launch helpers implemented in ftle_kernels.hip.  All return hipSuccess or
+// the launch error.  lds_bytes() gives the dynamic LDS a launch needs.
+size_t fwd_lds_bytes(int dim, bool f64, const DevTiles& t);
+size_t bwd_lds_bytes(int dim, bool f64, const DevTiles& t);
+
+hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* x, const void* flow,
+                          double inv2T, void* out, void* tape, int64_t n, double eig_tau,
+                          unsigned long long* hits, int block, hipStream_t stream);
+
+hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
+                                  const void* tape, int64_t n, const void* g, void* grad,
+                                  int block, hipStream_t stream);
+
+hipError_t launch_batched(int dim, bool f64, const BatchMesh* meshes, const uint32_t* items,
+                          int n_items, int tiles_per_pop, unsigned* queue, const BatchCall& call,
+                          size_t lds, double eig_tau, int block, int grid, hipStream_t stream);
+
+// The kernel a batched launch runs (for occupancy queries and graph updates).
+const void* batched_kernel_symbol(int dim, bool f64, int block);
+void batched_kernel_args(const BatchMesh* meshes, const uint32_t* items, int n_items,
+                         int tiles_per_pop, unsigned* queue, const BatchCall& call,
+                         double eig_tau, void* storage, void** args);
+size_t batched_kernel_arg_storage();
+
+}  // namespace ftle

@@ -1,0 +1,636 @@
+// HIP kernels of the FTLE library (gfx950 / CDNA4, wave64).
+//
+// Per mesh point i (the per-point FTLE kernel of UVaFTLE, Section 2 of de
+// Castro et al.; Table 1 sizes its core):
+//   M = sum_j dx dx^T,  B = sum_j dphi dx^T   (j over the stencil S(i),
+//   dx = x_j - x_i, dphi = phi_j - phi_i), J = B M^{-1},
+//   C = J^T J, lambda = lambda_max(C), FTLE = ln(lambda) / (2 |T|).
+//
+// Design for the MI355X memory system:
+//  - The paper finds the gather of neighbour data to be the bottleneck
+//    (Section 2.2: irregular accesses with little reuse).  Here points are in
+//    Morton order and cut into tiles; a workgroup stages its tile's points
+//    and their one-ring halo (coordinates and flow map) into LDS with
+//    coalesced loads, so each value comes from HBM about once, and the
+//    stencil walk reads LDS only.
+//  - The neighbour list (Section 2.2: precomputed on the host, read in a
+//    fixed order) is stored per tile with 16-bit tile-local indices: half the
+//    bytes of a 32-bit list, streamed once with 16-byte loads.
+//  - One lane per point; everything else (Jacobian, tensor, eigenvalue,
+//    logarithm) stays in registers.  No MFMA: per point the work is a few
+//    dozen multiply-adds over a gathered stencil, not a dense contraction.
+//  - Consecutive workgroup ids land on different XCDs; tiles are remapped so
+//    that each XCD walks a contiguous stretch of the Morton order and halo
+//    reuse happens in its own L2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "ftle_internal.h"
+
+namespace ftle {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Small vector helpers
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> using vec2_t = typename Vec2<T>::type;
+template <typename T> using vec4_t = typename Vec4<T>::type;
+
+template <typename T> struct Packed3 { T a, b, c; };
+
+// Precision-explicit math (no silent promotion of float code to double).
+__device__ inline float dlog(float v) { return logf(v); }
+__device__ inline double dlog(double v) { return log(v); }
+__device__ inline float dsqrt(float v) { return sqrtf(v); }
+__device__ inline double dsqrt(double v) { return sqrt(v); }
+__device__ inline float dacos(float v) { return acosf(v); }
+__device__ inline double dacos(double v) { return acos(v); }
+__device__ inline float dcos(float v) { return cosf(v); }
+__device__ inline double dcos(double v) { return cos(v); }
+__device__ inline float dfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double dfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float dmin(float a, float b) { return fminf(a, b); }
+__device__ inline double dmin(double a, double b) { return fmin(a, b); }
+__device__ inline float dmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double dmax(double a, double b) { return fmax(a, b); }
+
+template <typename T> __device__ inline T quiet_nan();
+template <> __device__ inline float quiet_nan<float>() { return __builtin_nanf(""); }
+template <> __device__ inline double quiet_nan<double>() { return __builtin_nan(""); }
+
+// Rank threshold of the least-squares solve: the stencil is rank deficient
+// when det M <= tau (tr M / D)^D.  float32 cannot resolve an exactly singular
+// M below a few ulps of (tr M / D)^D, hence the looser float threshold.
+template <typename T> __device__ inline T rank_tau();
+template <> __device__ inline float rank_tau<float>() { return 1e-5f; }
+template <> __device__ inline double rank_tau<double>() { return 1e-12; }
+
+// Workgroup id -> tile.  The hardware deals consecutive ids round-robin to
+// the 8 XCDs; this gives XCD x the contiguous tile range
+// [x*q + min(x, r), ...) with q = n / 8, r = n % 8 (a bijection on [0, n)).
+__device__ inline int xcd_tile(int bid, int n)
+{
+    constexpr int kXcd = 8;
+    const int x = bid % kXcd, s = bid / kXcd;
+    const int q = n / kXcd, r = n % kXcd;
+    return x * q + min(x, r) + s;
+}
+
+// ---------------------------------------------------------------------------
+// Staging layouts in LDS.  Slot l of a tile holds point idx[l].
+//   forward, 2D: A = (x0, x1, phi0, phi1)
+//   forward, 3D: A = (x0, x1, x2, phi0), B = (phi1, phi2)
+//   adjoint, 2D: A = (x0, x1, w0, w1), B = (h0, h1)
+//   adjoint, 3D: A = (x0, x1, x2, h0), B = (h1, h2, w0, w1), C = w2
+// Every array spans round4(P+H) slots, so each starts 16-byte aligned; the
+// tile's 16-bit segment (row ends + local stencil) follows.
+// ---------------------------------------------------------------------------
+template <int D, typename T> struct FwdLds {
+    static constexpr size_t slot_bytes = 2 * D * sizeof(T);
+};
+template <int D, typename T> struct BwdLds {
+    static constexpr size_t slot_bytes = 3 * D * sizeof(T);
+};
+
+__device__ inline void stage_segment(const uint4* __restrict__ src, uint4* dst, int n16)
+{
+    for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 symmetric largest eigenvalue, closed form (trigonometric solution of
+// the characteristic cubic, O. K. Smith, CACM 4(4):168, 1961):
+//   q = tr C / 3, p = sqrt(|C - qI|_F^2 / 6), r = det((C - qI)/p) / 2,
+//   lambda_max = q + 2 p cos(acos(r) / 3).
+// Returns r through r_out so the caller can detect r -> -1 (top pair nearly
+// equal), where acos amplifies rounding in r.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T lam_max3(T c00, T c01, T c02, T c11, T c12, T c22, T& r_out)
+{
+    const T q = (c00 + c11 + c22) * T(1.0 / 3.0);
+    const T b00 = c00 - q, b11 = c11 - q, b22 = c22 - q;
+    const T p2 = (b00 * b00 + b11 * b11 + b22 * b22 + T(2) * (c01 * c01 + c02 * c02 + c12 * c12)) *
+                 T(1.0 / 6.0);
+    if (!(p2 > T(0))) {
+        r_out = T(1);
+        return q;
+    }
+    const T p = dsqrt(p2);
+    const T ip = T(1) / p;
+    const T n00 = b00 * ip, n11 = b11 * ip, n22 = b22 * ip;
+    const T n01 = c01 * ip, n02 = c02 * ip, n12 = c12 * ip;
+    T r = T(0.5) * (n00 * (n11 * n22 - n12 * n12) - n01 * (n01 * n22 - n12 * n02) +
+                    n02 * (n01 * n12 - n11 * n02));
+    r = dmin(dmax(r, T(-1)), T(1));
+    r_out = r;
+    return q + T(2) * p * dcos(dacos(r) * T(1.0 / 3.0));
+}
+
+// ---------------------------------------------------------------------------
+// One tile of the forward pass.  OUT: write FTLE.  TAPE: write the adjoint
+// tape (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j dx).
+// ---------------------------------------------------------------------------
+template <int D, typename T, bool OUT, bool TAPE>
+__device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const T* __restrict__ x,
+                         const T* __restrict__ flow, const T inv2T, T* __restrict__ out,
+                         T* __restrict__ tape, const int64_t n, const float eig_tau,
+                         unsigned long long* hits, unsigned char* lds)
+{
+    using V2 = vec2_t<T>;
+    using V4 = vec4_t<T>;
+    const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
+    const int S = P + H;
+    const int S4 = (S + 3) & ~3;
+    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
+    const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
+
+    V4* sa = reinterpret_cast<V4*>(lds);
+    V2* sb = reinterpret_cast<V2*>(lds + (size_t)S4 * sizeof(V4));   // 3D only
+    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)S4 * FwdLds<D, T>::slot_bytes);
+
+    stage_segment(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
+    for (int l = threadIdx.x; l < S; l += blockDim.x) {
+        const uint32_t u = idx[l];
+        if constexpr (D == 2) {
+            const V2 xv = reinterpret_cast<const V2*>(x)[u];
+            const V2 fv = reinterpret_cast<const V2*>(flow)[u];
+            sa[l] = V4{xv.x, xv.y, fv.x, fv.y};
+        } else {
+            const Packed3<T> xv = reinterpret_cast<const Packed3<T>*>(x)[u];
+            const Packed3<T> fv = reinterpret_cast<const Packed3<T>*>(flow)[u];
+            sa[l] = V4{xv.a, xv.b, xv.c, fv.a};
+            sb[l] = V2{fv.b, fv.c};
+        }
+    }
+    __syncthreads();
+
+    const uint16_t* __restrict__ lcol = seg + P;
+    for (int l = threadIdx.x; l < P; l += blockDim.x) {
+        const int s = l ? seg[l - 1] : 0;
+        const int e = seg[l];
+        const uint32_t u = idx[l];
+        T f;
+        if constexpr (D == 2) {
+            const V4 c0 = sa[l];
+            T m00 = 0, m01 = 0, m11 = 0, b00 = 0, b01 = 0, b10 = 0, b11 = 0, s0 = 0, s1 = 0;
+            for (int k = s; k < e; ++k) {
+                const V4 q = sa[lcol[k]];
+                const T dx0 = q.x - c0.x, dx1 = q.y - c0.y;
+                const T df0 = q.z - c0.z, df1 = q.w - c0.w;
+                m00 = dfma(dx0, dx0, m00);
+                m01 = dfma(dx0, dx1, m01);
+                m11 = dfma(dx1, dx1, m11);
+                b00 = dfma(df0, dx0, b00);
+                b01 = dfma(df0, dx1, b01);
+                b10 = dfma(df1, dx0, b10);
+                b11 = dfma(df1, dx1, b11);
+                if constexpr (TAPE) {
+                    s0 += dx0;
+                    s1 += dx1;
+                }
+            }
+            const T det = m00 * m11 - m01 * m01;
+            const T trh = (m00 + m11) * T(0.5);
+            const bool ok = (e - s >= 2) && (det > rank_tau<T>() * trh * trh);
+            const T id = T(1) / det;
+            const T j00 = (b00 * m11 - b01 * m01) * id, j01 = (b01 * m00 - b00 * m01) * id;
+            const T j10 = (b10 * m11 - b11 * m01) * id, j11 = (b11 * m00 - b10 * m01) * id;
+            const T c00 = j00 * j00 + j10 * j10, c01 = j00 * j01 + j10 * j11, c11 = j01 * j01 + j11 * j11;
+            const T mm = (c00 + c11) * T(0.5), dd = (c00 - c11) * T(0.5);
+            const T hh = dsqrt(dd * dd + c01 * c01);
+            const T lam = mm + hh;
+            f = ok ? dlog(lam) * inv2T : quiet_nan<T>();
+            if constexpr (TAPE) {
+                T v0 = (dd >= T(0)) ? dd + hh : c01;
+                T v1 = (dd >= T(0)) ? c01 : hh - dd;
+                const T nv = dsqrt(v0 * v0 + v1 * v1);
+                if (nv > T(0)) {
+                    v0 /= nv;
+                    v1 /= nv;
+                } else {
+                    v0 = T(1);
+                    v1 = T(0);
+                }
+                const bool use = ok && (lam > T(0)) && isfinite(f);
+                const T sc = use ? T(2) * inv2T / lam : T(0);
+                const T p0 = (j00 * v0 + j01 * v1) * sc, p1 = (j10 * v0 + j11 * v1) * sc;
+                const T h0 = use ? (m11 * v0 - m01 * v1) * id : T(0);
+                const T h1 = use ? (m00 * v1 - m01 * v0) * id : T(0);
+                reinterpret_cast<V4*>(tape)[u] = V4{p0, p1, h0, h1};
+                tape[(size_t)n * 4 + u] = h0 * s0 + h1 * s1;
+            }
+        } else {
+            const V4 c0 = sa[l];
+            const V2 c1 = sb[l];
+            T m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+            T b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b12 = 0, b20 = 0, b21 = 0, b22 = 0;
+            T s0 = 0, s1 = 0, s2 = 0;
+            for (int k = s; k < e; ++k) {
+                const int c = lcol[k];
+                const V4 qa = sa[c];
+                const V2 qb = sb[c];
+                const T dx0 = qa.x - c0.x, dx1 = qa.y - c0.y, dx2 = qa.z - c0.z;
+                const T df0 = qa.w - c0.w, df1 = qb.x - c1.x, df2 = qb.y - c1.y;
+                m00 = dfma(dx0, dx0, m00);
+                m01 = dfma(dx0, dx1, m01);
+                m02 = dfma(dx0, dx2, m02);
+                m11 = dfma(dx1, dx1, m11);
+                m12 = dfma(dx1, dx2, m12);
+                m22 = dfma(dx2, dx2, m22);
+                b00 = dfma(df0, dx0, b00);
+                b01 = dfma(df0, dx1, b01);
+                b02 = dfma(df0, dx2, b02);
+                b10 = dfma(df1, dx0, b10);
+                b11 = dfma(df1, dx1, b11);
+                b12 = dfma(df1, dx2, b12);
+                b20 = dfma(df2, dx0, b20);
+                b21 = dfma(df2, dx1, b21);
+                b22 = dfma(df2, dx2, b22);
+                if constexpr (TAPE) {
+                    s0 += dx0;
+                    s1 += dx1;
+                    s2 += dx2;
+                }
+            }
+            // adjugate of M (symmetric)
+            const T a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
+            const T a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
+            const T det = m00 * a00 + m01 * a01 + m02 * a02;
+            const T tr3 = (m00 + m11 + m22) * T(1.0 / 3.0);
+            const bool ok = (e - s >= 3) && (det > rank_tau<T>() * tr3 * tr3 * tr3);
+            const T id = T(1) / det;
+            const T j00 = (b00 * a00 + b01 * a01 + b02 * a02) * id;
+            const T j01 = (b00 * a01 + b01 * a11 + b02 * a12) * id;
+            const T j02 = (b00 * a02 + b01 * a12 + b02 * a22) * id;
+            const T j10 = (b10 * a00 + b11 * a01 + b12 * a02) * id;
+            const T j11 = (b10 * a01 + b11 * a11 + b12 * a12) * id;
+            const T j12 = (b10 * a02 + b11 * a12 + b12 * a22) * id;
+            const T j20 = (b20 * a00 + b21 * a01 + b22 * a02) * id;
+            const T j21 = (b20 * a01 + b21 * a11 + b22 * a12) * id;
+            const T j22 = (b20 * a02 + b21 * a12 + b22 * a22) * id;
+            const T c00 = j00 * j00 + j10 * j10 + j20 * j20;
+            const T c01 = j00 * j01 + j10 * j11 + j20 * j21;
+            const T c02 = j00 * j02 + j10 * j12 + j20 * j22;
+            const T c11 = j01 * j01 + j11 * j11 + j21 * j21;
+            const T c12 = j01 * j02 + j11 * j12 + j21 * j22;
+            const T c22 = j02 * j02 + j12 * j12 + j22 * j22;
+            T r;
+            T lam = lam_max3<T>(c00, c01, c02, c11, c12, c22, r);
+            if constexpr (sizeof(T) == 4) {
+                // Top pair nearly equal: acos' slope amplifies float rounding in
+                // r; redo the tensor and the eigenvalue in double from J.
+                const bool redo = ok && (r < -1.0f + eig_tau);
+                if (redo) {
+                    const double e00 = j00, e01 = j01, e02 = j02, e10 = j10, e11 = j11, e12 = j12;
+                    const double e20 = j20, e21 = j21, e22 = j22;
+                    double rd;
+                    const double lamd = lam_max3<double>(
+                        e00 * e00 + e10 * e10 + e20 * e20, e00 * e01 + e10 * e11 + e20 * e21,
+                        e00 * e02 + e10 * e12 + e20 * e22, e01 * e01 + e11 * e11 + e21 * e21,
+                        e01 * e02 + e11 * e12 + e21 * e22, e02 * e02 + e12 * e12 + e22 * e22, rd);
+                    lam = (float)lamd;
+                }
+                if (hits) {
+                    const unsigned long long ball = __ballot(redo);
+                    if (ball && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)ball) - 1))
+                        atomicAdd(hits, (unsigned long long)__popcll(ball));
+                }
+            }
+            f = ok ? dlog(lam) * inv2T : quiet_nan<T>();
+            if constexpr (TAPE) {
+                // unit top eigenvector: the largest cross product of two rows of C - lambda I
+                const T r00 = c00 - lam, r11 = c11 - lam, r22 = c22 - lam;
+                const T xa0 = c01 * c12 - c02 * r11, xa1 = c02 * c01 - r00 * c12, xa2 = r00 * r11 - c01 * c01;
+                const T xb0 = c01 * r22 - c02 * c12, xb1 = c02 * c02 - r00 * r22, xb2 = r00 * c12 - c01 * c02;
+                const T xc0 = r11 * r22 - c12 * c12, xc1 = c12 * c02 - c01 * r22, xc2 = c01 * c12 - r11 * c02;
+                const T na = xa0 * xa0 + xa1 * xa1 + xa2 * xa2;
+                const T nb = xb0 * xb0 + xb1 * xb1 + xb2 * xb2;
+                const T nc = xc0 * xc0 + xc1 * xc1 + xc2 * xc2;
+                T v0 = xa0, v1 = xa1, v2 = xa2, nv = na;
+                if (nb > nv) { v0 = xb0; v1 = xb1; v2 = xb2; nv = nb; }
+                if (nc > nv) { v0 = xc0; v1 = xc1; v2 = xc2; nv = nc; }
+                if (nv > T(0)) {
+                    const T iv = T(1) / dsqrt(nv);
+                    v0 *= iv; v1 *= iv; v2 *= iv;
+                } else {
+                    v0 = T(1); v1 = T(0); v2 = T(0);
+                }
+                const bool use = ok && (lam > T(0)) && isfinite(f);
+                const T sc = use ? T(2) * inv2T / lam : T(0);
+                const T hs = use ? id : T(0);
+                T* t = tape + (size_t)u * 6;
+                t[0] = (j00 * v0 + j01 * v1 + j02 * v2) * sc;
+                t[1] = (j10 * v0 + j11 * v1 + j12 * v2) * sc;
+                t[2] = (j20 * v0 + j21 * v1 + j22 * v2) * sc;
+                const T h0 = (a00 * v0 + a01 * v1 + a02 * v2) * hs;
+                const T h1 = (a01 * v0 + a11 * v1 + a12 * v2) * hs;
+                const T h2 = (a02 * v0 + a12 * v1 + a22 * v2) * hs;
+                t[3] = h0;
+                t[4] = h1;
+                t[5] = h2;
+                tape[(size_t)n * 6 + u] = h0 * s0 + h1 * s1 + h2 * s2;
+            }
+        }
+        if constexpr (OUT) out[u] = f;
+    }
+}
+
+template <int D, typename T, bool OUT, bool TAPE>
+__global__ void __launch_bounds__(512) fwd_kernel(const TileMeta* __restrict__ meta,
+                                                  const uint4* __restrict__ rec, int n_tiles,
+                                                  const T* __restrict__ x, const T* __restrict__ flow,
+                                                  T inv2T, T* __restrict__ out, T* __restrict__ tape,
+                                                  int64_t n, float eig_tau, unsigned long long* hits)
+{
+    extern __shared__ uint4 lds_raw[];
+    const int t = xcd_tile(blockIdx.x, n_tiles);
+    fwd_tile<D, T, OUT, TAPE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits,
+                              reinterpret_cast<unsigned char*>(lds_raw));
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gather.  With w_k = g_k p_k (p, h, sigma from the tape):
+//   dL/dphi_j = sum_{i : j in S(i)} w_i (h_i . (x_j - x_i))  -  g_j sigma_j p_j
+// The tile set here is the one of the transposed stencil S^T (equal to S for
+// the symmetric one-ring stencil).  Points with non-finite g add nothing.
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ meta,
+                                                  const uint4* __restrict__ rec, int n_tiles,
+                                                  const T* __restrict__ x, const T* __restrict__ tape,
+                                                  int64_t n, const T* __restrict__ g,
+                                                  T* __restrict__ grad)
+{
+    using V2 = vec2_t<T>;
+    using V4 = vec4_t<T>;
+    extern __shared__ uint4 lds_raw[];
+    unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
+    const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
+    const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
+    const int S = P + H;
+    const int S4 = (S + 3) & ~3;
+    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
+    const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
+
+    V4* sa = reinterpret_cast<V4*>(lds);
+    unsigned char* after_a = lds + (size_t)S4 * sizeof(V4);
+    V2* sb2 = reinterpret_cast<V2*>(after_a);          // 2D: (h0, h1)
+    V4* sb4 = reinterpret_cast<V4*>(after_a);          // 3D: (h1, h2, w0, w1)
+    T* sc = reinterpret_cast<T*>(after_a + (size_t)S4 * sizeof(V4));  // 3D: w2
+    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)S4 * BwdLds<D, T>::slot_bytes);
+
+    stage_segment(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
+    for (int l = threadIdx.x; l < S; l += blockDim.x) {
+        const uint32_t u = idx[l];
+        T gu = g[u];
+        if (!isfinite(gu)) gu = T(0);
+        if constexpr (D == 2) {
+            const V2 xv = reinterpret_cast<const V2*>(x)[u];
+            const V4 tv = reinterpret_cast<const V4*>(tape)[u];
+            sa[l] = V4{xv.x, xv.y, gu * tv.x, gu * tv.y};
+            sb2[l] = V2{tv.z, tv.w};
+        } else {
+            const Packed3<T> xv = reinterpret_cast<const Packed3<T>*>(x)[u];
+            const T* tp = tape + (size_t)u * 6;
+            sa[l] = V4{xv.a, xv.b, xv.c, tp[3]};
+            sb4[l] = V4{tp[4], tp[5], gu * tp[0], gu * tp[1]};
+            sc[l] = gu * tp[2];
+        }
+    }
+    __syncthreads();
+
+    const uint16_t* __restrict__ lcol = seg + P;
+    for (int l = threadIdx.x; l < P; l += blockDim.x) {
+        const int s = l ? seg[l - 1] : 0;
+        const int e = seg[l];
+        const uint32_t u = idx[l];
+        const T sig = tape[(size_t)n * (2 * D) + u];
+        if constexpr (D == 2) {
+            const V4 cj = sa[l];
+            T a0 = 0, a1 = 0;
+            for (int k = s; k < e; ++k) {
+                const int c = lcol[k];
+                const V4 q = sa[c];
+                const V2 hq = sb2[c];
+                const T d0 = cj.x - q.x, d1 = cj.y - q.y;
+                const T t = hq.x * d0 + hq.y * d1;
+                a0 = dfma(q.z, t, a0);
+                a1 = dfma(q.w, t, a1);
+            }
+            reinterpret_cast<V2*>(grad)[u] = V2{a0 - sig * cj.z, a1 - sig * cj.w};
+        } else {
+            const V4 cj = sa[l];
+            const V4 cb = sb4[l];
+            const T cw2 = sc[l];
+            T a0 = 0, a1 = 0, a2 = 0;
+            for (int k = s; k < e; ++k) {
+                const int c = lcol[k];
+                const V4 q = sa[c];
+                const V4 qb = sb4[c];
+                const T qw2 = sc[c];
+                const T d0 = cj.x - q.x, d1 = cj.y - q.y, d2 = cj.z - q.z;
+                const T t = q.w * d0 + qb.x * d1 + qb.y * d2;
+                a0 = dfma(qb.z, t, a0);
+                a1 = dfma(qb.w, t, a1);
+                a2 = dfma(qw2, t, a2);
+            }
+            T* gp = grad + (size_t)u * 3;
+            gp[0] = a0 - sig * cb.z;
+            gp[1] = a1 - sig * cb.w;
+            gp[2] = a2 - sig * cw2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched forward: one persistent grid drains a queue of (mesh, tile) work
+// items.  A workgroup takes tiles_per_pop consecutive items per atomic pop
+// and runs the same tile body as fwd_kernel, so results are bit-identical.
+// queue[0] is the next item, queue[1] counts finished workgroups; the last
+// workgroup to finish zeroes both for the next launch.
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__global__ void __launch_bounds__(512) batched_kernel(const BatchMesh* __restrict__ meshes,
+                                                      const uint32_t* __restrict__ items, int n_items,
+                                                      int tiles_per_pop, unsigned* queue,
+                                                      BatchCall call, float eig_tau)
+{
+    extern __shared__ uint4 lds_raw[];
+    __shared__ int sh_base;
+    unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
+    for (;;) {
+        if (threadIdx.x == 0) sh_base = (int)atomicAdd(&queue[0], (unsigned)tiles_per_pop);
+        __syncthreads();
+        const int base = sh_base;
+        __syncthreads();
+        if (base >= n_items) break;
+        const int lim = min(base + tiles_per_pop, n_items);
+        for (int it = base; it < lim; ++it) {
+            const uint32_t item = __builtin_amdgcn_readfirstlane(items[it]);
+            const int mk = (int)(item >> kItemTileBits);
+            const int t = (int)(item & ((1u << kItemTileBits) - 1));
+            const BatchMesh bm = meshes[mk];
+            fwd_tile<D, T, true, false>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
+                                        static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
+                                        static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau,
+                                        bm.fp64_hits, lds);
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&queue[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+            __threadfence();
+        }
+    }
+}
+
+template <int D, typename T>
+size_t fwd_lds(const DevTiles& t)
+{
+    return tile_lds_bytes(FwdLds<D, T>::slot_bytes, t.max_staged, t.max_seg);
+}
+template <int D, typename T>
+size_t bwd_lds(const DevTiles& t)
+{
+    return tile_lds_bytes(BwdLds<D, T>::slot_bytes, t.max_staged, t.max_seg);
+}
+
+template <int D, typename T>
+hipError_t fwd_launch(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
+                      void* tape, int64_t n, double eig_tau, unsigned long long* hits, int block,
+                      hipStream_t stream)
+{
+    const size_t lds = fwd_lds<D, T>(tiles);
+    const dim3 grid(tiles.n_tiles), blk(block);
+    const T* xp = static_cast<const T*>(x);
+    const T* fp = static_cast<const T*>(flow);
+    T* op = static_cast<T*>(out);
+    T* tp = static_cast<T*>(tape);
+    if (out && tape)
+        hipLaunchKernelGGL((fwd_kernel<D, T, true, true>), grid, blk, lds, stream, tiles.meta, tiles.rec,
+                           tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
+    else if (tape)
+        hipLaunchKernelGGL((fwd_kernel<D, T, false, true>), grid, blk, lds, stream, tiles.meta, tiles.rec,
+                           tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
+    else
+        hipLaunchKernelGGL((fwd_kernel<D, T, true, false>), grid, blk, lds, stream, tiles.meta, tiles.rec,
+                           tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+hipError_t bwd_launch(const DevTiles& tiles, const void* x, const void* tape, int64_t n, const void* g,
+                      void* grad, int block, hipStream_t stream)
+{
+    const size_t lds = bwd_lds<D, T>(tiles);
+    hipLaunchKernelGGL((bwd_kernel<D, T>), dim3(tiles.n_tiles), dim3(block), lds, stream, tiles.meta,
+                       tiles.rec, tiles.n_tiles, static_cast<const T*>(x), static_cast<const T*>(tape), n,
+                       static_cast<const T*>(g), static_cast<T*>(grad));
+    return hipGetLastError();
+}
+
+struct BatchArgs {
+    const BatchMesh* meshes;
+    const uint32_t* items;
+    int n_items;
+    int tiles_per_pop;
+    unsigned* queue;
+    BatchCall call;
+    float eig_tau;
+};
+
+}  // namespace
+
+size_t fwd_lds_bytes(int dim, bool f64, const DevTiles& t)
+{
+    if (dim == 2) return f64 ? fwd_lds<2, double>(t) : fwd_lds<2, float>(t);
+    return f64 ? fwd_lds<3, double>(t) : fwd_lds<3, float>(t);
+}
+
+size_t bwd_lds_bytes(int dim, bool f64, const DevTiles& t)
+{
+    if (dim == 2) return f64 ? bwd_lds<2, double>(t) : bwd_lds<2, float>(t);
+    return f64 ? bwd_lds<3, double>(t) : bwd_lds<3, float>(t);
+}
+
+hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* x, const void* flow,
+                          double inv2T, void* out, void* tape, int64_t n, double eig_tau,
+                          unsigned long long* hits, int block, hipStream_t stream)
+{
+    if (tiles.n_tiles == 0) return hipSuccess;
+    if (dim == 2)
+        return f64 ? fwd_launch<2, double>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream)
+                   : fwd_launch<2, float>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
+    return f64 ? fwd_launch<3, double>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream)
+               : fwd_launch<3, float>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
+}
+
+hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
+                                  const void* tape, int64_t n, const void* g, void* grad, int block,
+                                  hipStream_t stream)
+{
+    if (tiles.n_tiles == 0) return hipSuccess;
+    if (dim == 2)
+        return f64 ? bwd_launch<2, double>(tiles, x, tape, n, g, grad, block, stream)
+                   : bwd_launch<2, float>(tiles, x, tape, n, g, grad, block, stream);
+    return f64 ? bwd_launch<3, double>(tiles, x, tape, n, g, grad, block, stream)
+               : bwd_launch<3, float>(tiles, x, tape, n, g, grad, block, stream);
+}
+
+const void* batched_kernel_symbol(int dim, bool f64, int /*block*/)
+{
+    if (dim == 2)
+        return f64 ? reinterpret_cast<const void*>(&batched_kernel<2, double>)
+                   : reinterpret_cast<const void*>(&batched_kernel<2, float>);
+    return f64 ? reinterpret_cast<const void*>(&batched_kernel<3, double>)
+               : reinterpret_cast<const void*>(&batched_kernel<3, float>);
+}
+
+size_t batched_kernel_arg_storage() { return sizeof(BatchArgs); }
+
+void batched_kernel_args(const BatchMesh* meshes, const uint32_t* items, int n_items, int tiles_per_pop,
+                         unsigned* queue, const BatchCall& call, double eig_tau, void* storage,
+                         void** args)
+{
+    BatchArgs* a = static_cast<BatchArgs*>(storage);
+    a->meshes = meshes;
+    a->items = items;
+    a->n_items = n_items;
+    a->tiles_per_pop = tiles_per_pop;
+    a->queue = queue;
+    a->call = call;
+    a->eig_tau = (float)eig_tau;
+    args[0] = &a->meshes;
+    args[1] = &a->items;
+    args[2] = &a->n_items;
+    args[3] = &a->tiles_per_pop;
+    args[4] = &a->queue;
+    args[5] = &a->call;
+    args[6] = &a->eig_tau;
+}
+
+hipError_t launch_batched(int dim, bool f64, const BatchMesh* meshes, const uint32_t* items, int n_items,
+                          int tiles_per_pop, unsigned* queue, const BatchCall& call, size_t lds,
+                          double eig_tau, int block, int grid, hipStream_t stream)
+{
+    BatchArgs storage;
+    void* args[7];
+    batched_kernel_args(meshes, items, n_items, tiles_per_pop, queue, call, eig_tau, &storage, args);
+    return hipLaunchKernel(batched_kernel_symbol(dim, f64, block), dim3(grid), dim3(block), args, lds,
+                           stream);
+}
+
+}  // namespace ftle

@@ -1,0 +1,243 @@
+"""Host-side logic and the C ABI, on the CPU (no GPU call is made here).
+
+* every function declared in include/ftle.h is exported by libftle.so and
+  bound by the Python layer;
+* the host neighbour builder (Morton order, RING1/AXIS stencils, tile records)
+  agrees with the oracle's independently built stencils;
+* argument validation returns the documented status codes before any device
+  work.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2408_02758_amd as F
+from paper_2408_02758_amd import _lib
+from workloads import meshes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.load()
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "ftle.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ftle_[a-z0-9_]+)\s*\(", text)) - {"ftle_TILE"})
+
+
+def test_exports_match_header(L):
+    names = _header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in ftle.h but not exported"
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_version(L):
+    assert b"gfx950" in L.ftle_version()
+
+
+# ---------------------------------------------------------------------------
+# builder vs oracle
+# ---------------------------------------------------------------------------
+
+def _lib_stencil_user_order(m):
+    """The library's stencil, mapped back to caller indices: dict i -> sorted list."""
+    row_ptr, col, perm = m.csr()
+    out = {}
+    for r in range(m.n):
+        out[int(perm[r])] = sorted(int(perm[c]) for c in col[row_ptr[r]:row_ptr[r + 1]])
+    return out
+
+
+def _oracle_rows(st):
+    return {i: sorted(int(c) for c in st.col[st.row_ptr[i]:st.row_ptr[i + 1]] if c >= 0)
+            for i in range(st.n)}
+
+
+def _cases():
+    x2, c2 = meshes.jittered_tri_grid(37, 23, seed=3)
+    x3, c3 = meshes.kuhn_tet_grid(9)
+    xr, cr, _ = meshes.relabel(x2, c2, seed=5)
+    return [("tri2d", 2, x2, c2), ("kuhn3d", 3, x3, c3), ("tri2d_relabel", 2, xr, cr)]
+
+
+@pytest.mark.parametrize("name,dim,x,cells", _cases(), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("stencil", ["ring1", "axis"])
+def test_stencil_matches_oracle(name, dim, x, cells, stencil):
+    m = F.Mesh(x, cells, "f64", stencil=stencil, host_only=True)
+    ring = oracle.ring1(dim, x.shape[0], cells)
+    st = ring if stencil == "ring1" else oracle.axis(dim, x, ring)
+    got = _lib_stencil_user_order(m)
+    want = _oracle_rows(st)
+    assert got == want
+    assert m.info()["nnz"] == sum(len(v) for v in want.values())
+
+
+def test_morton_perm_is_permutation_and_no_reorder_is_identity():
+    x, c = meshes.jittered_tri_grid(50, 40, seed=1)
+    m = F.Mesh(x, c, "f32", host_only=True)
+    perm = m.csr()[2]
+    assert np.array_equal(np.sort(perm), np.arange(x.shape[0]))
+    assert not np.array_equal(perm, np.arange(x.shape[0]))
+    m2 = F.Mesh(x, c, "f32", reorder=False, host_only=True)
+    assert np.array_equal(m2.csr()[2], np.arange(x.shape[0]))
+
+
+@pytest.mark.parametrize("name,dim,x,cells", _cases(), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("stencil", ["ring1", "axis"])
+@pytest.mark.parametrize("tile_log2", [0, 5, 7])
+def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2):
+    """Decode the records the kernel reads: every own point appears exactly once,
+    and its local stencil (own + halo slots) maps back to the oracle's stencil;
+    the adjoint tiles hold the transposed stencil."""
+    m = F.Mesh(x, cells, "f32", stencil=stencil, tile_log2=tile_log2, host_only=True)
+    ring = oracle.ring1(dim, x.shape[0], cells)
+    st = ring if stencil == "ring1" else oracle.axis(dim, x, ring)
+    want = _oracle_rows(st)
+    wantT = {i: [] for i in range(st.n)}
+    for i, nb in want.items():
+        for j in nb:
+            wantT[j].append(i)
+    for adjoint, ref in ((False, want), (True, {k: sorted(v) for k, v in wantT.items()})):
+        seen = np.zeros(m.n, np.int64)
+        for idx, rowend, lcol, P, H in m.tiles(adjoint):
+            assert P >= 1 and P <= (1 << (tile_log2 or (10 if dim == 2 else 9)))
+            assert len(set(idx.tolist())) == P + H, "staged points must be distinct"
+            assert np.all(np.diff(rowend.astype(np.int64)) >= 0)
+            assert int(rowend[-1]) == len(lcol)
+            assert np.all(lcol < P + H)
+            start = 0
+            for l in range(P):
+                u = int(idx[l])
+                seen[u] += 1
+                row = sorted(int(idx[c]) for c in lcol[start:int(rowend[l])])
+                assert row == ref[u], (u, row, ref[u])
+                start = int(rowend[l])
+            # halo points are exactly the neighbours not owned by the tile
+            own = set(idx[:P].tolist())
+            used = {int(idx[c]) for c in lcol}
+            assert set(idx[P:].tolist()) == used - own
+        assert np.all(seen == 1)
+
+
+def test_ring1_symmetric_shares_adjoint_tiles():
+    x, c = meshes.jittered_tri_grid(20, 20, seed=2)
+    m = F.Mesh(x, c, "f32", host_only=True)
+    a = m.tiles(False)
+    b = m.tiles(True)
+    assert len(a) == len(b)
+    for (i1, r1, l1, _, _), (i2, r2, l2, _, _) in zip(a, b):
+        assert np.array_equal(i1, i2) and np.array_equal(r1, r2) and np.array_equal(l1, l2)
+
+
+def test_degenerate_meshes_build():
+    # one point, no cells; points referenced by no cell; a ragged last tile
+    F.Mesh(np.zeros((1, 2)), np.zeros((0, 3), np.int32), "f32", host_only=True)
+    x = np.random.default_rng(0).uniform(size=(1000, 3))
+    cells = np.array([[0, 1, 2, 3], [1, 2, 3, 4]], np.int32)
+    m = F.Mesh(x, cells, "f64", host_only=True, tile_log2=5)
+    assert m.tile_stats()["n_tiles"] == (1000 + 31) // 32
+    assert m.info()["nnz"] == 4 * 3 + 2 * 3 + 2 * 1 - 2   # {0..4}: deg 3,4,4,4,3
+
+
+def test_huge_degree_is_unsupported():
+    # a star whose centre has 70000 neighbours cannot be staged by one tile
+    k = 70000
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    x = np.vstack([[0.0, 0.0], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    cells = np.stack([np.zeros(k, np.int32), np.arange(1, k + 1), np.roll(np.arange(1, k + 1), -1)], 1)
+    with pytest.raises(F.FTLEError) as e:
+        F.Mesh(x, cells.astype(np.int32), "f32", host_only=True)
+    assert e.value.status == 4 and "neighbours" in e.value.message
+
+
+# ---------------------------------------------------------------------------
+# validation status codes (no device work happens before these checks)
+# ---------------------------------------------------------------------------
+
+def _create(L, dim=2, n=4, coords=None, dtype=0, ncells=1, cells=None, flags=_lib.HOST_ONLY):
+    if coords is None:
+        coords = np.zeros((max(n, 1), dim), np.float32 if dtype == 0 else np.float64)
+    if cells is None:
+        cells = np.array([list(range(dim + 1))], np.int32)
+    h = ctypes.c_void_p()
+    st = L.ftle_create_mesh(dim, n, coords.ctypes.data if coords is not False else None, dtype, ncells,
+                            cells.ctypes.data if cells is not False else None, flags, ctypes.byref(h))
+    return st, h
+
+
+def test_create_validation(L):
+    INVALID, BAD, UNSUP = 1, 2, 4
+    assert _create(L, dim=4)[0] == INVALID
+    assert _create(L, n=0)[0] == INVALID
+    assert _create(L, n=2 ** 31)[0] == UNSUP
+    assert _create(L, coords=False)[0] == INVALID
+    assert _create(L, cells=False)[0] == INVALID
+    assert _create(L, ncells=-1)[0] == INVALID
+    assert _create(L, dtype=7)[0] == INVALID
+    assert _create(L, flags=1 << 30)[0] == INVALID
+    assert _create(L, flags=_lib.HOST_ONLY | _lib.tile_flag(3))[0] == INVALID
+    assert _create(L, flags=_lib.HOST_ONLY | _lib.tile_flag(12))[0] == INVALID
+    assert _create(L, cells=np.array([[0, 1, 4]], np.int32))[0] == BAD
+    assert _create(L, cells=np.array([[0, -1, 2]], np.int32))[0] == BAD
+    assert _create(L, cells=np.array([[0, 1, 1]], np.int32))[0] == BAD
+    assert L.ftle_last_error()  # message for the last failure
+    c = np.zeros((4, 2), np.float32)
+    c[2, 1] = np.nan
+    assert _create(L, coords=c)[0] == INVALID
+    h = ctypes.c_void_p()
+    assert L.ftle_create_mesh(2, 4, c.ctypes.data, 0, 0, None, 0, None) == INVALID
+    st, h = _create(L)
+    assert st == 0 and h.value
+    assert L.ftle_last_error() == b""
+    L.ftle_destroy_mesh(h)
+    L.ftle_destroy_mesh(None)
+
+
+def test_call_validation(L):
+    INVALID, DTYPE, UNSUP = 1, 3, 4
+    st, h = _create(L)
+    assert st == 0
+    p = ctypes.c_void_p(16)   # never dereferenced: validation fails first
+    null = ctypes.c_void_p()
+    assert L.ftle_forward(null, p, 0, 1.0, p, None) == INVALID
+    assert L.ftle_forward(h, p, 1, 1.0, p, None) == DTYPE
+    assert L.ftle_forward(h, p, 5, 1.0, p, None) == INVALID
+    for T in (0.0, float("nan"), float("inf"), -float("inf")):
+        assert L.ftle_forward(h, p, 0, T, p, None) == INVALID
+    assert L.ftle_forward(h, null, 0, 1.0, p, None) == INVALID
+    assert L.ftle_forward(h, p, 0, 1.0, null, None) == INVALID
+    assert L.ftle_forward(h, p, 0, -2.0, p, None) == UNSUP     # valid call, host-only mesh
+    assert b"HOST_ONLY" in L.ftle_last_error()
+    assert L.ftle_forward_tape(h, p, 0, 1.0, p, null, None) == INVALID
+    assert L.ftle_backward(h, p, 0, 0.0, p, p, None) == INVALID
+    assert L.ftle_backward(h, p, 0, 1.0, null, p, None) == INVALID
+    assert L.ftle_backward_tape(h, null, 0, p, p, None) == INVALID
+    assert L.ftle_backward_tape(h, p, 1, p, p, None) == DTYPE
+    b = ctypes.c_int64()
+    assert L.ftle_tape_bytes(h, ctypes.byref(b)) == 0 and b.value == 4 * 5 * 4
+    assert L.ftle_mesh_fp64_hits(h, None, 0) == INVALID
+    # batched
+    hs = (ctypes.c_void_p * 2)(h.value, h.value)
+    ptrs = (ctypes.c_void_p * 2)(16, 16)
+    Ts = (ctypes.c_double * 2)(1.0, 0.0)
+    assert L.ftle_batched(0, hs, ptrs, Ts, ptrs, 0, None) == INVALID
+    assert L.ftle_batched(65, hs, ptrs, Ts, ptrs, 0, None) == INVALID
+    assert L.ftle_batched(2, hs, ptrs, Ts, ptrs, 0, None) == INVALID   # T[1] = 0
+    Ts[1] = 2.0
+    assert L.ftle_batched(2, hs, ptrs, Ts, ptrs, 1, None) == DTYPE
+    st3, h3 = _create(L, dim=3)
+    hs3 = (ctypes.c_void_p * 2)(h.value, h3.value)
+    assert L.ftle_batched(2, hs3, ptrs, Ts, ptrs, 0, None) == INVALID   # mixed dim
+    assert L.ftle_batched(2, hs, ptrs, Ts, ptrs, 0, None) == UNSUP      # host-only meshes
+    L.ftle_destroy_mesh(h)
+    L.ftle_destroy_mesh(h3)
