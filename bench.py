@@ -48,6 +48,41 @@ def format_bytes_fwd(mesh, dim, s=4):
     return st["record_bytes"] + 2 * dim * s * mesh.n + s * mesh.n
 
 
+def cached(name, make, cache_dir, dev):
+    """Generate a workload, or load it from cache_dir (written by an earlier run).
+
+    Profiling runs use the cache so that the profiler sees the FTLE kernels and
+    not the generator's RK4 kernels.
+    """
+    import numpy as np
+    import torch
+
+    from workloads import configs
+    if not cache_dir:
+        return make()
+    path = os.path.join(cache_dir, name + ".npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        ws = []
+        for k in range(int(z["count"])):
+            extra = {"weights": z[f"w{k}"]} if f"w{k}" in z else {}
+            ws.append(configs.Workload(str(z[f"name{k}"]), int(z[f"dim{k}"]), z[f"x{k}"], z[f"c{k}"],
+                                       torch.as_tensor(z[f"f{k}"], device=dev), float(z[f"T{k}"]),
+                                       str(z[f"dt{k}"]), extra))
+        return ws if bool(z["is_list"]) else ws[0]
+    w = make()
+    ws = w if isinstance(w, list) else [w]
+    arrays = {"count": len(ws), "is_list": isinstance(w, list)}
+    for k, x in enumerate(ws):
+        arrays.update({f"name{k}": x.name, f"dim{k}": x.dim, f"x{k}": x.coords, f"c{k}": x.cells,
+                       f"f{k}": x.flow_numpy(), f"T{k}": x.T, f"dt{k}": x.dtype})
+        if "weights" in x.extra:
+            arrays[f"w{k}"] = x.extra["weights"]
+    os.makedirs(cache_dir, exist_ok=True)
+    np.savez(path, **arrays)
+    return w
+
+
 def time_steps(fns, steps, warmup, torch):
     """Run warmup untimed steps, then exactly `steps` timed ones; ms per step."""
     for i in range(warmup):
@@ -100,7 +135,10 @@ def main():
     ap.add_argument("--copies", type=int, default=3, help="input copies rotated between steps")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of: fwd2d,fwd3d,fwdbwd,batched")
+    ap.add_argument("--only", default="", help="comma list of: fwd3d,fwdbwd,batched (the 2D headline always runs)")
+    ap.add_argument("--cache", default="", help="directory to keep generated workloads in (npz)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain elementwise copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the FTLE hot path is "
@@ -121,9 +159,16 @@ def main():
     result = {}
     variants = {}
 
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)       # reads and writes exactly copy_probe_mib MiB each
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- headline: 2D forward at 2048^2 ------------------------------------
     log("generating 2048^2 double-gyre workload (RK4 on the GPU)")
-    w2 = configs.scale_2d(dev)
+    w2 = cached("scale_2d", lambda: configs.scale_2d(dev), args.cache, dev)
     log("building meshes")
     meshes2 = [F.Mesh(w2.coords, w2.cells, "f32") for _ in range(R)]
     nnz2 = meshes2[0].info()["nnz"]
@@ -158,7 +203,7 @@ def main():
         steps_v = max(10, args.steps // 2)
         if want("fwd3d"):
             log("generating 160^3 ABC workload")
-            w3 = configs.abc_3d(dev)
+            w3 = cached("abc_3d", lambda: configs.abc_3d(dev), args.cache, dev)
             ms3 = [F.Mesh(w3.coords, w3.cells, "f32") for _ in range(R)]
             nnz3 = ms3[0].info()["nnz"]
             fl3 = [w3.flow.to(dev).clone().contiguous() for _ in range(R)]
@@ -179,7 +224,7 @@ def main():
             del fns, ms3, fl3, ou3
         if want("fwdbwd"):
             log("generating 96^3 ABC workload (differentiated)")
-            wd = configs.diff_3d(dev)
+            wd = cached("diff_3d", lambda: configs.diff_3d(dev), args.cache, dev)
             msd = [F.Mesh(wd.coords, wd.cells, "f32") for _ in range(R)]
             nnzd = msd[0].info()["nnz"]
             fld = [wd.flow.to(dev).clone().contiguous() for _ in range(R)]
@@ -202,7 +247,7 @@ def main():
             del fns, msd, fld, outd, taped, gradd
         if want("batched"):
             log("generating the 48-mesh batched workload")
-            wb = configs.batched_2d(dev)
+            wb = cached("batched_2d", lambda: configs.batched_2d(dev), args.cache, dev)
             Rb = 2
             sets = []
             for _ in range(Rb):

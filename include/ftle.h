@@ -138,13 +138,24 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
  *             16-byte units, own points P, halo points H, stencil entries nnz}
  *   records   host, record_bytes bytes; per tile: uint32 caller indices of the
  *             P own points (Morton order) then the H halo points, padded to a
- *             multiple of 4; then uint16 row ends (P of them, relative to the
- *             tile's first entry) and nnz uint16 tile-local stencil indices,
- *             padded to a multiple of 8
+ *             multiple of 4; then nnz uint16 stencil entries, each the local
+ *             index (position in that index list) times the forward LDS slot
+ *             stride (16 bytes in 2D, 32 in 3D; doubled for FTLE_F64), with
+ *             every row padded to even length by the point's own entry; then
+ *             P uint16 row ends (cumulative entry counts); padded to a
+ *             multiple of 8 uint16
  * meta and records may be NULL (sizes only).
  */
 ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,
                                 void* meta, void* records);
+
+/*
+ * Threads per workgroup of this mesh's forward (and forward+tape) kernel and
+ * of its adjoint gather kernel: each a multiple of 64 in [64, 512] (0 keeps
+ * the current value; the default is 256).  A workgroup always processes one
+ * whole tile.
+ */
+ftle_status ftle_mesh_set_blocks(ftle_mesh_t mesh, int fwd_block, int adjoint_block);
 
 /*
  * Forward FTLE (the per-point kernel of Section 2).

@@ -98,8 +98,15 @@ class Mesh:
         check(_lib.load().ftle_mesh_tile_stats(self._h, *[ctypes.byref(v) for v in vals]))
         return dict(zip(["n_tiles", "max_tile_points", "halo_entries", "record_bytes"], [v.value for v in vals]))
 
+    def slot_stride(self) -> int:
+        """Forward LDS slot stride in bytes (the unit of the tile records' stencil entries)."""
+        return (4 if self.dim == 2 else 8) * (8 if self.dtype == "f64" else 4)
+
     def tiles(self, adjoint: bool = False):
-        """Decoded tile records: list of (idx uint32[P+H], rowend uint16[P], lcol uint16[nnz], P, H)."""
+        """Raw tile records: list of (idx uint32[P+H], rowend uint16[P], entries uint16[nnz], P, H).
+
+        entries are LDS byte offsets (local index * slot_stride()), rows padded
+        to even length with the point's own entry."""
         L = _lib.load()
         nt, rb = ctypes.c_int64(), ctypes.c_int64()
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), ctypes.byref(nt), ctypes.byref(rb), None, None))
@@ -108,12 +115,16 @@ class Mesh:
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), None, None, meta.ctypes.data, rec.ctypes.data))
         out = []
         for off, P, H, nnz in meta:
+            P, H, nnz = int(P), int(H), int(nnz)
             base = int(off) * 4
-            iw = (int(P) + int(H) + 3) & ~3
-            idx = rec[base:base + int(P) + int(H)]
+            iw = (P + H + 3) & ~3
+            idx = rec[base:base + P + H]
             seg = rec[base + iw:].view(np.uint16)
-            out.append((idx, seg[:P], seg[P:P + nnz], int(P), int(H)))
+            out.append((idx, seg[nnz:nnz + P], seg[:nnz], P, H))
         return out
+
+    def set_blocks(self, fwd: int = 0, adjoint: int = 0):
+        check(_lib.load().ftle_mesh_set_blocks(self._h, int(fwd), int(adjoint)))
 
     def tape_bytes(self) -> int:
         b = ctypes.c_int64()

@@ -215,6 +215,8 @@ struct ftle_mesh_s {
     ftle_dtype dtype = FTLE_F32;
     unsigned flags = 0;
     int tile_points = 0;
+    int fwd_block = 256;
+    int bwd_block = 256;
     bool symmetric = true;
     bool host_only = false;
     std::vector<int32_t> perm;     // Morton position -> user index
@@ -370,10 +372,18 @@ void tile_halo(const Csr& a, const std::vector<int32_t>& perm, int64_t b, int64_
     std::sort(halo.begin(), halo.end(), [&](int32_t u, int32_t v) { return perm[u] < perm[v]; });
 }
 
-bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nnz)
+// Stencil entries of rows [b, e) once each row is padded to even length.
+int64_t padded_nnz(const Csr& a, int64_t b, int64_t e)
 {
-    if (P + H > kMaxLocal || nnz > kMaxTileNnz) return false;
-    const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nnz);
+    int64_t t = 0;
+    for (int64_t r = b; r < e; ++r) t += (a.row_ptr[r + 1] - a.row_ptr[r] + 1) & ~1;
+    return t;
+}
+
+bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nnz_padded)
+{
+    if ((P + H) * (int64_t)fwd_slot_bytes(dim, f64) > 65536 || nnz_padded > kMaxTileNnz) return false;
+    const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nnz_padded);
     const size_t slot = std::max(fwd_slot_bytes(dim, f64), bwd_slot_bytes(dim, f64));
     return tile_lds_bytes(slot, (int)(P + H), seg) <= kLdsBudget;
 }
@@ -382,6 +392,7 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                     const std::vector<int32_t>& perm)
 {
     // 1. extents: nominal chunks of tile_points, halved until they fit the caps
+    //    (16-bit LDS offsets, 16-bit row ends, the LDS budget)
     const int64_t nchunks = (n + tile_points - 1) / tile_points;
     std::vector<std::vector<TileExtent>> per_chunk(nchunks);
     parallel_for(nchunks, [&](int64_t cb, int64_t ce, int) {
@@ -398,12 +409,13 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                     tag = 1;
                 }
                 tile_halo(a, perm, b, e, stamp, tag, halo);
-                const int64_t nnz = (int64_t)a.row_ptr[e] - a.row_ptr[b];
+                const int64_t nnz = padded_nnz(a, b, e);
                 if (tile_fits(dim, f64, e - b, (int64_t)halo.size(), nnz)) {
                     per_chunk[ch].push_back({b, e, (uint32_t)halo.size(), (uint32_t)nnz});
                 } else if (e - b == 1) {
                     fail(FTLE_ERR_UNSUPPORTED, "point " + std::to_string(perm[b]) + " has " +
-                                                   std::to_string(nnz) + " neighbours, more than one tile holds");
+                                                   std::to_string(a.row_ptr[b + 1] - a.row_ptr[b]) +
+                                                   " neighbours, more than one tile holds");
                 } else {
                     const int64_t m = b + (e - b) / 2;
                     todo.push_back({m, e});   // processed after [b, m): keeps ascending order
@@ -448,6 +460,8 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
             tile_halo(a, perm, b, e, stamp, tag, halo);
             uint32_t* idx = ts.rec.data() + (size_t)m.rec_off * 4;
             uint16_t* seg = reinterpret_cast<uint16_t*>(idx + idx_words(m.P, m.H));
+            uint16_t* rowend = seg + m.nnz;
+            const uint32_t stride = (uint32_t)fwd_slot_bytes(dim, f64);
             for (int64_t r = b; r < e; ++r) idx[r - b] = (uint32_t)perm[r];
             // halo slot of each halo point: reuse stamp as "slot + 1" storage is
             // not possible (tag), so search in a small map
@@ -468,9 +482,10 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                         auto it = std::lower_bound(hs.begin(), hs.end(), std::make_pair(c, INT32_MIN));
                         loc = it->second;
                     }
-                    seg[m.P + pos++] = (uint16_t)loc;
+                    seg[pos++] = (uint16_t)((uint32_t)loc * stride);
                 }
-                seg[r - b] = (uint16_t)pos;
+                if (pos & 1u) seg[pos++] = (uint16_t)((uint32_t)(r - b) * stride);   // pad with self
+                rowend[r - b] = (uint16_t)pos;
             }
         }
     }, 1);
@@ -539,8 +554,6 @@ double env_double(const char* name, double dflt)
 
 // r < -1 + tau selects the float64 eigenvalue recompute (3D, float32 meshes).
 double eig_tau() { static const double t = env_double("FTLE_EIG_TAU", 2e-3); return t; }
-int fwd_block() { static const int b = (int)env_double("FTLE_FWD_BLOCK", 256); return b; }
-int bwd_block() { static const int b = (int)env_double("FTLE_BWD_BLOCK", 256); return b; }
 
 void check_mesh(ftle_mesh_t m)
 {
@@ -650,7 +663,7 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
         m->dtype = dtype;
         m->flags = flags;
         m->host_only = (flags & FTLE_HOST_ONLY) != 0;
-        m->tile_points = tile_log2 ? (1 << tile_log2) : (dim == 2 ? 1024 : 512);
+        m->tile_points = tile_log2 ? (1 << tile_log2) : 512;
 
         // Morton order: quantise to the bounding box, interleave, stable sort
         m->perm.resize(n);
@@ -779,6 +792,18 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
     });
 }
 
+ftle_status ftle_mesh_set_blocks(ftle_mesh_t mesh, int fwd_block, int adjoint_block)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        for (int b : {fwd_block, adjoint_block})
+            if (b != 0 && (b < 64 || b > 512 || b % 64 != 0))
+                fail(FTLE_ERR_INVALID_ARG, "block sizes must be multiples of 64 in [64, 512]");
+        if (fwd_block) mesh->fwd_block = fwd_block;
+        if (adjoint_block) mesh->bwd_block = adjoint_block;
+    });
+}
+
 ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,
                                 void* meta, void* records)
 {
@@ -803,7 +828,7 @@ ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, d
         need_device(mesh);
         DeviceScope ds(mesh->device);
         check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
-                                 out, nullptr, mesh->n, eig_tau(), mesh->d_hits, fwd_block(),
+                                 out, nullptr, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block,
                                  static_cast<hipStream_t>(stream)),
                   "forward launch");
     });
@@ -829,7 +854,7 @@ ftle_status ftle_forward_tape(ftle_mesh_t mesh, const void* flow, ftle_dtype dty
         need_device(mesh);
         DeviceScope ds(mesh->device);
         check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
-                                 out, tape, mesh->n, eig_tau(), mesh->d_hits, fwd_block(),
+                                 out, tape, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block,
                                  static_cast<hipStream_t>(stream)),
                   "forward+tape launch");
     });
@@ -845,7 +870,7 @@ ftle_status ftle_backward_tape(ftle_mesh_t mesh, const void* tape, ftle_dtype dt
         need_device(mesh);
         DeviceScope ds(mesh->device);
         check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, tape,
-                                         mesh->n, grad_ftle, grad_flow, bwd_block(),
+                                         mesh->n, grad_ftle, grad_flow, mesh->bwd_block,
                                          static_cast<hipStream_t>(stream)),
                   "adjoint launch");
     });
@@ -871,10 +896,10 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
             check_hip(hipStreamWaitEvent(s, mesh->work_done, 0), "hipStreamWaitEvent");
         }
         check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
-                                 nullptr, mesh->d_work, mesh->n, eig_tau(), mesh->d_hits, fwd_block(), s),
+                                 nullptr, mesh->d_work, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block, s),
                   "adjoint tape launch");
         check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, mesh->d_work,
-                                         mesh->n, grad_ftle, grad_flow, bwd_block(), s),
+                                         mesh->n, grad_ftle, grad_flow, mesh->bwd_block, s),
                   "adjoint launch");
         check_hip(hipEventRecord(mesh->work_done, s), "hipEventRecord");
         mesh->work_stream = s;

@@ -20,24 +20,25 @@ namespace ftle {
 //                             tile's own P points in Morton order, then its H
 //                             halo points (neighbours owned by other tiles),
 //                             padded to a multiple of 4 entries
-//   uint16 seg[P + nnz]       seg[0..P): end of each own point's row, relative
-//                             to the tile's first stencil entry;
-//                             seg[P..P+nnz): stencil entries as local indices
-//                             into idx (own points first, then halo),
-//                             padded to a multiple of 8 entries
+//   uint16 seg[nnz + P]       seg[0..nnz): the stencil rows of the own points,
+//                             each entry the LDS byte offset of the
+//                             neighbour's staged slot (local index times the
+//                             forward slot stride); every row is padded to
+//                             even length with the point's own offset;
+//                             seg[nnz..nnz+P): end of each row (cumulative,
+//                             in entries); padded to a multiple of 8 entries
 //
-// A 16-bit local index is enough because P + H <= kMaxStaged and
-// nnz <= kMaxTileNnz, both enforced when the mesh is built.
+// 16-bit offsets and row ends are enough because (P + H) * stride <= 65536
+// and nnz <= kMaxTileNnz, both enforced when the mesh is built.
 // ---------------------------------------------------------------------------
 struct TileMeta {
     uint32_t rec_off;  // record offset in 16-byte units
     uint32_t P;        // own points
     uint32_t H;        // halo points
-    uint32_t nnz;      // stencil entries of the tile's own points
+    uint32_t nnz;      // stencil entries of the own points, including row padding
 };
 static_assert(sizeof(TileMeta) == 16, "TileMeta is one 16-byte load");
 
-constexpr int kMaxLocal = 65535;       // P + H: 16-bit local indices
 constexpr int kMaxTileNnz = 65535;     // stencil entries per tile: 16-bit row ends
 constexpr size_t kLdsBudget = 65536;   // LDS bytes one tile may stage (forward or adjoint)
 
@@ -45,10 +46,12 @@ __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m *
 __host__ __device__ inline uint32_t idx_words(uint32_t P, uint32_t H) { return (P + H + 3u) & ~3u; }
 __host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nnz) { return (P + nnz + 7u) & ~7u; }
 
-// LDS bytes per staged point.  Forward: coordinates and flow map (2*dim
-// values).  Adjoint: coordinates, w = g p and h (3*dim values).
-__host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(2 * dim); }
-__host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(3 * dim); }
+// LDS bytes per staged point (the slot stride).  Forward: coordinates and
+// flow map, 4 values in 2D, 8 (6 used) in 3D.  Adjoint: coordinates,
+// w = g p and h, 8 (6 used) in 2D, 12 (9 used) in 3D.  Strides are multiples
+// of 16 bytes where 16-byte LDS reads need it.
+__host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(dim == 2 ? 4 : 8); }
+__host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(dim == 2 ? 8 : 12); }
 __host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, int seg)
 {
     return (size_t)round_up(staged, 4) * slot_bytes + (size_t)seg * 2;

@@ -11,14 +11,17 @@
 //    (Section 2.2: irregular accesses with little reuse).  Here points are in
 //    Morton order and cut into tiles; a workgroup stages its tile's points
 //    and their one-ring halo (coordinates and flow map) into LDS with
-//    coalesced loads, so each value comes from HBM about once, and the
+//    batched gathers, so each value comes from HBM about once, and the
 //    stencil walk reads LDS only.
 //  - The neighbour list (Section 2.2: precomputed on the host, read in a
-//    fixed order) is stored per tile with 16-bit tile-local indices: half the
-//    bytes of a 32-bit list, streamed once with 16-byte loads.
-//  - One lane per point; everything else (Jacobian, tensor, eigenvalue,
-//    logarithm) stays in registers.  No MFMA: per point the work is a few
-//    dozen multiply-adds over a gathered stencil, not a dense contraction.
+//    fixed order) is stored per tile as 16-bit LDS byte offsets of the
+//    neighbours' staged slots: half the bytes of a 32-bit list, streamed once
+//    with 16-byte loads, and no address arithmetic in the walk.  Rows are
+//    padded to even length with the point itself (which adds exact zeros), so
+//    the walk reads two neighbours per 32-bit LDS load.
+//  - One lane per point; Jacobian, tensor, eigenvalue and logarithm stay in
+//    registers.  No MFMA: per point the work is a few dozen multiply-adds
+//    over a gathered stencil, not a dense contraction.
 //  - Consecutive workgroup ids land on different XCDs; tiles are remapped so
 //    that each XCD walks a contiguous stretch of the Morton order and halo
 //    reuse happens in its own L2.
@@ -33,7 +36,7 @@ namespace ftle {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Small vector helpers
+// Small helpers
 // ---------------------------------------------------------------------------
 template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
@@ -47,13 +50,14 @@ template <typename T> using vec4_t = typename Vec4<T>::type;
 template <typename T> struct Packed3 { T a, b, c; };
 
 // Precision-explicit math (no silent promotion of float code to double).
-__device__ inline float dlog(float v) { return logf(v); }
-__device__ inline double dlog(double v) { return log(v); }
-__device__ inline float dsqrt(float v) { return sqrtf(v); }
+// The float versions use the hardware reciprocal, square root and base-2
+// logarithm (about 1 ulp): the Jacobian and eigenvalue they feed already
+// carry O(10) ulp of accumulated rounding.
+__device__ inline float drcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline double drcp(double v) { return 1.0 / v; }
+__device__ inline float dsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ inline double dsqrt(double v) { return sqrt(v); }
-__device__ inline float dacos(float v) { return acosf(v); }
 __device__ inline double dacos(double v) { return acos(v); }
-__device__ inline float dcos(float v) { return cosf(v); }
 __device__ inline double dcos(double v) { return cos(v); }
 __device__ inline float dfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double dfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -62,13 +66,24 @@ __device__ inline double dmin(double a, double b) { return fmin(a, b); }
 __device__ inline float dmax(float a, float b) { return fmaxf(a, b); }
 __device__ inline double dmax(double a, double b) { return fmax(a, b); }
 
+// ln(v) * scale.  Float: v_log_f32 (log2) on v pre-scaled out of the
+// subnormal range, times scale * ln 2.
+__device__ inline float log_scaled(float v, float scale)
+{
+    const bool tiny = v < 1.17549435e-38f;
+    const float l2 = __builtin_amdgcn_logf(tiny ? v * 4294967296.0f : v) - (tiny ? 32.0f : 0.0f);
+    return l2 * (scale * 0.693147180559945309f);
+}
+__device__ inline double log_scaled(double v, double scale) { return log(v) * scale; }
+
 template <typename T> __device__ inline T quiet_nan();
 template <> __device__ inline float quiet_nan<float>() { return __builtin_nanf(""); }
 template <> __device__ inline double quiet_nan<double>() { return __builtin_nan(""); }
 
 // Rank threshold of the least-squares solve: the stencil is rank deficient
-// when det M <= tau (tr M / D)^D.  float32 cannot resolve an exactly singular
-// M below a few ulps of (tr M / D)^D, hence the looser float threshold.
+// when det M <= tau (tr M / D)^D (this also covers fewer than D neighbours,
+// whose M is singular).  float32 cannot resolve an exactly singular M below a
+// few ulps of (tr M / D)^D, hence the looser float threshold.
 template <typename T> __device__ inline T rank_tau();
 template <> __device__ inline float rank_tau<float>() { return 1e-5f; }
 template <> __device__ inline double rank_tau<double>() { return 1e-12; }
@@ -85,105 +100,213 @@ __device__ inline int xcd_tile(int bid, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Staging layouts in LDS.  Slot l of a tile holds point idx[l].
-//   forward, 2D: A = (x0, x1, phi0, phi1)
-//   forward, 3D: A = (x0, x1, x2, phi0), B = (phi1, phi2)
-//   adjoint, 2D: A = (x0, x1, w0, w1), B = (h0, h1)
-//   adjoint, 3D: A = (x0, x1, x2, h0), B = (h1, h2, w0, w1), C = w2
-// Every array spans round4(P+H) slots, so each starts 16-byte aligned; the
-// tile's 16-bit segment (row ends + local stencil) follows.
+// Staged slots in LDS (slot l holds point idx[l]; strides as in
+// fwd_slot_bytes / bwd_slot_bytes):
+//   forward 2D (4 values):  (x0, x1, phi0, phi1)
+//   forward 3D (8 values):  (x0, x1, x2, phi0) (phi1, phi2, -, -)
+//   adjoint 2D (8 values):  (x0, x1, w0, w1) (h0, h1, -, -)
+//   adjoint 3D (12 values): (x0, x1, x2, h0) (h1, h2, w0, w1) (w2, -, -, -)
+// The stencil stores forward byte offsets o = l * fwd stride; the adjoint
+// offset is 2 o (2D) or 3 o / 2 (3D).  The tile's 16-bit segment follows the
+// slots: the padded stencil (offsets, nnz entries), then the P row ends.
 // ---------------------------------------------------------------------------
-template <int D, typename T> struct FwdLds {
-    static constexpr size_t slot_bytes = 2 * D * sizeof(T);
-};
-template <int D, typename T> struct BwdLds {
-    static constexpr size_t slot_bytes = 3 * D * sizeof(T);
+template <int D, typename T> struct Layout {
+    static constexpr uint32_t fwd = (D == 2 ? 4 : 8) * sizeof(T);
+    static constexpr uint32_t bwd = (D == 2 ? 8 : 12) * sizeof(T);
+    __device__ static uint32_t bwd_off(uint32_t o) { return D == 2 ? 2 * o : o + (o >> 1); }
 };
 
+// Copy a tile's 16-bit segment into LDS: up to four independent 16-byte loads
+// per thread are in flight before the stores.  Slices past the end are
+// skipped by a workgroup-uniform branch; idle lanes of the last live slice
+// reload the round's first chunk and do not store.
 __device__ inline void stage_segment(const uint4* __restrict__ src, uint4* dst, int n16)
 {
-    for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+    const int B = blockDim.x;
+    for (int r0 = 0; r0 < n16; r0 += 4 * B) {
+        const int live = min(4, (n16 - r0 + B - 1) / B);
+        const int i0 = r0 + (int)threadIdx.x, i1 = i0 + B, i2 = i1 + B, i3 = i2 + B;
+        uint4 v0 = src[i0 < n16 ? i0 : r0], v1{}, v2{}, v3{};
+        if (live > 1) v1 = src[i1 < n16 ? i1 : r0];
+        if (live > 2) v2 = src[i2 < n16 ? i2 : r0];
+        if (live > 3) v3 = src[i3 < n16 ? i3 : r0];
+        if (i0 < n16) dst[i0] = v0;
+        if (live > 1 && i1 < n16) dst[i1] = v1;
+        if (live > 2 && i2 < n16) dst[i2] = v2;
+        if (live > 3 && i3 < n16) dst[i3] = v3;
+    }
+}
+
+// Points staged per thread per round: all index loads, then all value
+// gathers, then the LDS stores (memory-level parallelism for the dependent
+// idx -> value loads), in workgroup-uniform slices as above.
+constexpr int kStage = 8;
+
+// Walk of one row of the padded stencil, four neighbours per step (two 32-bit
+// LDS loads of offset pairs, then the four slot loads, then the arithmetic),
+// with a final pair.  visit(o...) gets the neighbours' byte offsets.
+template <typename F>
+__device__ inline void walk_row(const uint32_t* __restrict__ pairs, int s, int e, F&& visit)
+{
+    int k = s;
+    for (; k + 4 <= e; k += 4) {
+        const uint32_t w0 = pairs[k >> 1], w1 = pairs[(k >> 1) + 1];
+        visit(w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16);
+    }
+    if (k < e) {
+        const uint32_t w0 = pairs[k >> 1];
+        visit(w0 & 0xffffu, w0 >> 16);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 symmetric largest eigenvalue, closed form (trigonometric solution of
-// the characteristic cubic, O. K. Smith, CACM 4(4):168, 1961):
-//   q = tr C / 3, p = sqrt(|C - qI|_F^2 / 6), r = det((C - qI)/p) / 2,
-//   lambda_max = q + 2 p cos(acos(r) / 3).
-// Returns r through r_out so the caller can detect r -> -1 (top pair nearly
-// equal), where acos amplifies rounding in r.
+// Largest eigenvalue of a symmetric 3x3 tensor, closed form: with
+// q = tr C / 3, p = sqrt(|C - qI|_F^2 / 6), r = det((C - qI)/p) / 2 in [-1, 1],
+// lambda_max = q + 2 p c, where c = cos(acos(r)/3) is the largest root of
+// 4c^3 - 3c = r (trigonometric solution of the characteristic cubic; O. K.
+// Smith, CACM 4(4):168, 1961).  r is returned so that the caller can detect
+// r -> -1 (top pair nearly equal), where c'(r) is unbounded.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline T lam_max3(T c00, T c01, T c02, T c11, T c12, T c22, T& r_out)
+__device__ inline void cubic_qpr(T c00, T c01, T c02, T c11, T c12, T c22, T& q, T& p, T& r)
 {
-    const T q = (c00 + c11 + c22) * T(1.0 / 3.0);
+    q = (c00 + c11 + c22) * T(1.0 / 3.0);
     const T b00 = c00 - q, b11 = c11 - q, b22 = c22 - q;
     const T p2 = (b00 * b00 + b11 * b11 + b22 * b22 + T(2) * (c01 * c01 + c02 * c02 + c12 * c12)) *
                  T(1.0 / 6.0);
     if (!(p2 > T(0))) {
-        r_out = T(1);
-        return q;
+        p = T(0);
+        r = T(1);
+        return;
     }
-    const T p = dsqrt(p2);
-    const T ip = T(1) / p;
+    p = dsqrt(p2);
+    const T ip = drcp(p);
     const T n00 = b00 * ip, n11 = b11 * ip, n22 = b22 * ip;
     const T n01 = c01 * ip, n02 = c02 * ip, n12 = c12 * ip;
-    T r = T(0.5) * (n00 * (n11 * n22 - n12 * n12) - n01 * (n01 * n22 - n12 * n02) +
-                    n02 * (n01 * n12 - n11 * n02));
+    r = T(0.5) * (n00 * (n11 * n22 - n12 * n12) - n01 * (n01 * n22 - n12 * n02) +
+                  n02 * (n01 * n12 - n11 * n02));
     r = dmin(dmax(r, T(-1)), T(1));
-    r_out = r;
-    return q + T(2) * p * dcos(dacos(r) * T(1.0 / 3.0));
+}
+
+__device__ inline double lam_max3_trig(double c00, double c01, double c02, double c11, double c12, double c22,
+                                       double& r)
+{
+    double q, p;
+    cubic_qpr<double>(c00, c01, c02, c11, c12, c22, q, p, r);
+    return q + 2.0 * p * dcos(dacos(r) * (1.0 / 3.0));
+}
+
+// float: c = cos(acos(r)/3) = P7(s), s = sqrt((1 + r)/2), with P7 a degree-7
+// least-squares fit of cos((2/3) acos(s)) on [0, 1] (csrc/gen_eig_poly.py;
+// error 1.2e-7 in float32 Horner form).
+__device__ inline float lam_max3_poly(float c00, float c01, float c02, float c11, float c12, float c22, float& r)
+{
+    float q, p;
+    cubic_qpr<float>(c00, c01, c02, c11, c12, c22, q, p, r);
+    const float s = dsqrt(dmax(0.5f * (1.0f + r), 0.0f));
+    float c = 1.138295594e-03f;
+    c = dfma(c, s, -6.106058646e-03f);
+    c = dfma(c, s, 1.603621716e-02f);
+    c = dfma(c, s, -3.019834156e-02f);
+    c = dfma(c, s, 5.281414940e-02f);
+    c = dfma(c, s, -1.110301883e-01f);
+    c = dfma(c, s, 5.773459112e-01f);
+    c = dfma(c, s, 5.000000579e-01f);
+    return dfma(2.0f * p, c, q);
+}
+
+// The float64 recompute of lambda_max from a float32 Jacobian: C = J^T J and
+// the trigonometric formula in double.  Out of line: it runs for a handful of
+// points per launch and would otherwise raise the register budget of every
+// lane.
+__device__ __noinline__ float lam_max3_f64_from_J(float j00, float j01, float j02, float j10, float j11,
+                                                  float j12, float j20, float j21, float j22)
+{
+    const double e00 = j00, e01 = j01, e02 = j02, e10 = j10, e11 = j11, e12 = j12;
+    const double e20 = j20, e21 = j21, e22 = j22;
+    double rd;
+    const double lamd = lam_max3_trig(e00 * e00 + e10 * e10 + e20 * e20, e00 * e01 + e10 * e11 + e20 * e21,
+                                      e00 * e02 + e10 * e12 + e20 * e22, e01 * e01 + e11 * e11 + e21 * e21,
+                                      e01 * e02 + e11 * e12 + e21 * e22, e02 * e02 + e12 * e12 + e22 * e22, rd);
+    return (float)lamd;
 }
 
 // ---------------------------------------------------------------------------
 // One tile of the forward pass.  OUT: write FTLE.  TAPE: write the adjoint
-// tape (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j dx).
+// tape (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j dx, with v
+// the unit top eigenvector of C).
 // ---------------------------------------------------------------------------
 template <int D, typename T, bool OUT, bool TAPE>
-__device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const T* __restrict__ x,
-                         const T* __restrict__ flow, const T inv2T, T* __restrict__ out,
-                         T* __restrict__ tape, const int64_t n, const float eig_tau,
-                         unsigned long long* hits, unsigned char* lds)
+__device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
+                                         const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
+                                         T* __restrict__ out, T* __restrict__ tape, const int64_t n,
+                                         const float eig_tau, unsigned long long* hits, unsigned char* lds)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
+    using L = Layout<D, T>;
     const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
     const int S = P + H;
-    const int S4 = (S + 3) & ~3;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-
-    V4* sa = reinterpret_cast<V4*>(lds);
-    V2* sb = reinterpret_cast<V2*>(lds + (size_t)S4 * sizeof(V4));   // 3D only
-    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)S4 * FwdLds<D, T>::slot_bytes);
+    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)round_up(S, 4) * L::fwd);
+    const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
+    const uint16_t* rowend = seg + nnz;
 
     stage_segment(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    for (int l = threadIdx.x; l < S; l += blockDim.x) {
-        const uint32_t u = idx[l];
+    const int B = blockDim.x;
+    for (int r0 = 0; r0 < S; r0 += kStage * B) {
+        const int live = min(kStage, (S - r0 + B - 1) / B);   // workgroup-uniform
+        const int base = r0 + (int)threadIdx.x;
+        uint32_t u[kStage] = {};
+#pragma unroll
+        for (int k = 0; k < kStage; ++k)
+            if (k < live) u[k] = idx[base + k * B < S ? base + k * B : r0];
         if constexpr (D == 2) {
-            const V2 xv = reinterpret_cast<const V2*>(x)[u];
-            const V2 fv = reinterpret_cast<const V2*>(flow)[u];
-            sa[l] = V4{xv.x, xv.y, fv.x, fv.y};
+            V2 xv[kStage] = {}, fv[kStage] = {};
+#pragma unroll
+            for (int k = 0; k < kStage; ++k)
+                if (k < live) {
+                    xv[k] = reinterpret_cast<const V2*>(x)[u[k]];
+                    fv[k] = reinterpret_cast<const V2*>(flow)[u[k]];
+                }
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) {
+                const int l = base + k * B;
+                if (k < live && l < S)
+                    *reinterpret_cast<V4*>(lds + (size_t)l * L::fwd) = V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y};
+            }
         } else {
-            const Packed3<T> xv = reinterpret_cast<const Packed3<T>*>(x)[u];
-            const Packed3<T> fv = reinterpret_cast<const Packed3<T>*>(flow)[u];
-            sa[l] = V4{xv.a, xv.b, xv.c, fv.a};
-            sb[l] = V2{fv.b, fv.c};
+            Packed3<T> xv[kStage] = {}, fv[kStage] = {};
+#pragma unroll
+            for (int k = 0; k < kStage; ++k)
+                if (k < live) {
+                    xv[k] = reinterpret_cast<const Packed3<T>*>(x)[u[k]];
+                    fv[k] = reinterpret_cast<const Packed3<T>*>(flow)[u[k]];
+                }
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) {
+                const int l = base + k * B;
+                if (k < live && l < S) {
+                    unsigned char* slot = lds + (size_t)l * L::fwd;
+                    *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a};
+                    *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{fv[k].b, fv[k].c};
+                }
+            }
         }
     }
     __syncthreads();
 
-    const uint16_t* __restrict__ lcol = seg + P;
-    for (int l = threadIdx.x; l < P; l += blockDim.x) {
-        const int s = l ? seg[l - 1] : 0;
-        const int e = seg[l];
+    for (int l = threadIdx.x; l < P; l += B) {
+        const int s = l ? rowend[l - 1] : 0;
+        const int e = rowend[l];
         const uint32_t u = idx[l];
+        const unsigned char* self = lds + (size_t)l * L::fwd;
         T f;
         if constexpr (D == 2) {
-            const V4 c0 = sa[l];
+            const V4 c0 = *reinterpret_cast<const V4*>(self);
             T m00 = 0, m01 = 0, m11 = 0, b00 = 0, b01 = 0, b10 = 0, b11 = 0, s0 = 0, s1 = 0;
-            for (int k = s; k < e; ++k) {
-                const V4 q = sa[lcol[k]];
+            auto acc = [&](const V4 q) {
                 const T dx0 = q.x - c0.x, dx1 = q.y - c0.y;
                 const T df0 = q.z - c0.z, df1 = q.w - c0.w;
                 m00 = dfma(dx0, dx0, m00);
@@ -197,31 +320,37 @@ __device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const 
                     s0 += dx0;
                     s1 += dx1;
                 }
-            }
+            };
+            auto at = [&](uint32_t o) { return *reinterpret_cast<const V4*>(lds + o); };
+            walk_row(pairs, s, e, [&](auto... o) {
+                const V4 q[] = {at(o)...};
+                for (const V4& v : q) acc(v);
+            });
             const T det = m00 * m11 - m01 * m01;
             const T trh = (m00 + m11) * T(0.5);
-            const bool ok = (e - s >= 2) && (det > rank_tau<T>() * trh * trh);
-            const T id = T(1) / det;
+            const bool ok = det > rank_tau<T>() * trh * trh;
+            const T id = drcp(det);
             const T j00 = (b00 * m11 - b01 * m01) * id, j01 = (b01 * m00 - b00 * m01) * id;
             const T j10 = (b10 * m11 - b11 * m01) * id, j11 = (b11 * m00 - b10 * m01) * id;
             const T c00 = j00 * j00 + j10 * j10, c01 = j00 * j01 + j10 * j11, c11 = j01 * j01 + j11 * j11;
             const T mm = (c00 + c11) * T(0.5), dd = (c00 - c11) * T(0.5);
             const T hh = dsqrt(dd * dd + c01 * c01);
             const T lam = mm + hh;
-            f = ok ? dlog(lam) * inv2T : quiet_nan<T>();
+            f = ok ? log_scaled(lam, inv2T) : quiet_nan<T>();
             if constexpr (TAPE) {
                 T v0 = (dd >= T(0)) ? dd + hh : c01;
                 T v1 = (dd >= T(0)) ? c01 : hh - dd;
-                const T nv = dsqrt(v0 * v0 + v1 * v1);
-                if (nv > T(0)) {
-                    v0 /= nv;
-                    v1 /= nv;
+                const T nv2 = v0 * v0 + v1 * v1;
+                if (nv2 > T(0)) {
+                    const T iv = drcp(dsqrt(nv2));
+                    v0 *= iv;
+                    v1 *= iv;
                 } else {
                     v0 = T(1);
                     v1 = T(0);
                 }
                 const bool use = ok && (lam > T(0)) && isfinite(f);
-                const T sc = use ? T(2) * inv2T / lam : T(0);
+                const T sc = use ? T(2) * inv2T * drcp(lam) : T(0);
                 const T p0 = (j00 * v0 + j01 * v1) * sc, p1 = (j10 * v0 + j11 * v1) * sc;
                 const T h0 = use ? (m11 * v0 - m01 * v1) * id : T(0);
                 const T h1 = use ? (m00 * v1 - m01 * v0) * id : T(0);
@@ -229,17 +358,18 @@ __device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const 
                 tape[(size_t)n * 4 + u] = h0 * s0 + h1 * s1;
             }
         } else {
-            const V4 c0 = sa[l];
-            const V2 c1 = sb[l];
+            const V4 c0 = *reinterpret_cast<const V4*>(self);
+            const V2 c1 = *reinterpret_cast<const V2*>(self + 4 * sizeof(T));
             T m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
             T b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b12 = 0, b20 = 0, b21 = 0, b22 = 0;
             T s0 = 0, s1 = 0, s2 = 0;
-            for (int k = s; k < e; ++k) {
-                const int c = lcol[k];
-                const V4 qa = sa[c];
-                const V2 qb = sb[c];
-                const T dx0 = qa.x - c0.x, dx1 = qa.y - c0.y, dx2 = qa.z - c0.z;
-                const T df0 = qa.w - c0.w, df1 = qb.x - c1.x, df2 = qb.y - c1.y;
+            struct Q {
+                V4 a;
+                V2 b;
+            };
+            auto acc = [&](const Q q) {
+                const T dx0 = q.a.x - c0.x, dx1 = q.a.y - c0.y, dx2 = q.a.z - c0.z;
+                const T df0 = q.a.w - c0.w, df1 = q.b.x - c1.x, df2 = q.b.y - c1.y;
                 m00 = dfma(dx0, dx0, m00);
                 m01 = dfma(dx0, dx1, m01);
                 m02 = dfma(dx0, dx2, m02);
@@ -260,14 +390,21 @@ __device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const 
                     s1 += dx1;
                     s2 += dx2;
                 }
-            }
+            };
+            auto at = [&](uint32_t o) {
+                return Q{*reinterpret_cast<const V4*>(lds + o), *reinterpret_cast<const V2*>(lds + o + 4 * sizeof(T))};
+            };
+            walk_row(pairs, s, e, [&](auto... o) {
+                const Q q[] = {at(o)...};
+                for (const Q& v : q) acc(v);
+            });
             // adjugate of M (symmetric)
             const T a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
             const T a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
             const T det = m00 * a00 + m01 * a01 + m02 * a02;
             const T tr3 = (m00 + m11 + m22) * T(1.0 / 3.0);
-            const bool ok = (e - s >= 3) && (det > rank_tau<T>() * tr3 * tr3 * tr3);
-            const T id = T(1) / det;
+            const bool ok = det > rank_tau<T>() * tr3 * tr3 * tr3;
+            const T id = drcp(det);
             const T j00 = (b00 * a00 + b01 * a01 + b02 * a02) * id;
             const T j01 = (b00 * a01 + b01 * a11 + b02 * a12) * id;
             const T j02 = (b00 * a02 + b01 * a12 + b02 * a22) * id;
@@ -283,29 +420,22 @@ __device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const 
             const T c11 = j01 * j01 + j11 * j11 + j21 * j21;
             const T c12 = j01 * j02 + j11 * j12 + j21 * j22;
             const T c22 = j02 * j02 + j12 * j12 + j22 * j22;
-            T r;
-            T lam = lam_max3<T>(c00, c01, c02, c11, c12, c22, r);
+            T r, lam;
             if constexpr (sizeof(T) == 4) {
-                // Top pair nearly equal: acos' slope amplifies float rounding in
-                // r; redo the tensor and the eigenvalue in double from J.
+                lam = lam_max3_poly(c00, c01, c02, c11, c12, c22, r);
+                // Top pair nearly equal: c'(r) amplifies float rounding in r;
+                // redo the tensor and the eigenvalue in double from J.
                 const bool redo = ok && (r < -1.0f + eig_tau);
-                if (redo) {
-                    const double e00 = j00, e01 = j01, e02 = j02, e10 = j10, e11 = j11, e12 = j12;
-                    const double e20 = j20, e21 = j21, e22 = j22;
-                    double rd;
-                    const double lamd = lam_max3<double>(
-                        e00 * e00 + e10 * e10 + e20 * e20, e00 * e01 + e10 * e11 + e20 * e21,
-                        e00 * e02 + e10 * e12 + e20 * e22, e01 * e01 + e11 * e11 + e21 * e21,
-                        e01 * e02 + e11 * e12 + e21 * e22, e02 * e02 + e12 * e12 + e22 * e22, rd);
-                    lam = (float)lamd;
-                }
+                if (redo) lam = lam_max3_f64_from_J(j00, j01, j02, j10, j11, j12, j20, j21, j22);
                 if (hits) {
                     const unsigned long long ball = __ballot(redo);
                     if (ball && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)ball) - 1))
                         atomicAdd(hits, (unsigned long long)__popcll(ball));
                 }
+            } else {
+                lam = lam_max3_trig(c00, c01, c02, c11, c12, c22, r);
             }
-            f = ok ? dlog(lam) * inv2T : quiet_nan<T>();
+            f = ok ? log_scaled(lam, inv2T) : quiet_nan<T>();
             if constexpr (TAPE) {
                 // unit top eigenvector: the largest cross product of two rows of C - lambda I
                 const T r00 = c00 - lam, r11 = c11 - lam, r22 = c22 - lam;
@@ -319,13 +449,13 @@ __device__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec, const 
                 if (nb > nv) { v0 = xb0; v1 = xb1; v2 = xb2; nv = nb; }
                 if (nc > nv) { v0 = xc0; v1 = xc1; v2 = xc2; nv = nc; }
                 if (nv > T(0)) {
-                    const T iv = T(1) / dsqrt(nv);
+                    const T iv = drcp(dsqrt(nv));
                     v0 *= iv; v1 *= iv; v2 *= iv;
                 } else {
                     v0 = T(1); v1 = T(0); v2 = T(0);
                 }
                 const bool use = ok && (lam > T(0)) && isfinite(f);
-                const T sc = use ? T(2) * inv2T / lam : T(0);
+                const T sc = use ? T(2) * inv2T * drcp(lam) : T(0);
                 const T hs = use ? id : T(0);
                 T* t = tape + (size_t)u * 6;
                 t[0] = (j00 * v0 + j01 * v1 + j02 * v2) * sc;
@@ -372,77 +502,125 @@ __global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ m
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
+    using L = Layout<D, T>;
     extern __shared__ uint4 lds_raw[];
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
     const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
     const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
     const int S = P + H;
-    const int S4 = (S + 3) & ~3;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-
-    V4* sa = reinterpret_cast<V4*>(lds);
-    unsigned char* after_a = lds + (size_t)S4 * sizeof(V4);
-    V2* sb2 = reinterpret_cast<V2*>(after_a);          // 2D: (h0, h1)
-    V4* sb4 = reinterpret_cast<V4*>(after_a);          // 3D: (h1, h2, w0, w1)
-    T* sc = reinterpret_cast<T*>(after_a + (size_t)S4 * sizeof(V4));  // 3D: w2
-    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)S4 * BwdLds<D, T>::slot_bytes);
+    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)round_up(S, 4) * L::bwd);
+    const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
+    const uint16_t* rowend = seg + nnz;
 
     stage_segment(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    for (int l = threadIdx.x; l < S; l += blockDim.x) {
-        const uint32_t u = idx[l];
-        T gu = g[u];
-        if (!isfinite(gu)) gu = T(0);
+    constexpr int kB = kStage / 2;
+    const int B = blockDim.x;
+    for (int r0 = 0; r0 < S; r0 += kB * B) {
+        const int live = min(kB, (S - r0 + B - 1) / B);   // workgroup-uniform
+        const int base = r0 + (int)threadIdx.x;
+        uint32_t u[kB] = {};
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+            if (k < live) u[k] = idx[base + k * B < S ? base + k * B : r0];
+        T gu[kB] = {};
         if constexpr (D == 2) {
-            const V2 xv = reinterpret_cast<const V2*>(x)[u];
-            const V4 tv = reinterpret_cast<const V4*>(tape)[u];
-            sa[l] = V4{xv.x, xv.y, gu * tv.x, gu * tv.y};
-            sb2[l] = V2{tv.z, tv.w};
+            V2 xv[kB] = {};
+            V4 tv[kB] = {};
+#pragma unroll
+            for (int k = 0; k < kB; ++k)
+                if (k < live) {
+                    gu[k] = g[u[k]];
+                    xv[k] = reinterpret_cast<const V2*>(x)[u[k]];
+                    tv[k] = reinterpret_cast<const V4*>(tape)[u[k]];
+                }
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                const int l = base + k * B;
+                if (k < live && l < S) {
+                    const T gg = isfinite(gu[k]) ? gu[k] : T(0);
+                    unsigned char* slot = lds + (size_t)l * L::bwd;
+                    *reinterpret_cast<V4*>(slot) = V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y};
+                    *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{tv[k].z, tv[k].w};
+                }
+            }
         } else {
-            const Packed3<T> xv = reinterpret_cast<const Packed3<T>*>(x)[u];
-            const T* tp = tape + (size_t)u * 6;
-            sa[l] = V4{xv.a, xv.b, xv.c, tp[3]};
-            sb4[l] = V4{tp[4], tp[5], gu * tp[0], gu * tp[1]};
-            sc[l] = gu * tp[2];
+            Packed3<T> xv[kB] = {}, pv[kB] = {}, hv[kB] = {};
+#pragma unroll
+            for (int k = 0; k < kB; ++k)
+                if (k < live) {
+                    gu[k] = g[u[k]];
+                    xv[k] = reinterpret_cast<const Packed3<T>*>(x)[u[k]];
+                    pv[k] = reinterpret_cast<const Packed3<T>*>(tape)[2 * (size_t)u[k]];
+                    hv[k] = reinterpret_cast<const Packed3<T>*>(tape)[2 * (size_t)u[k] + 1];
+                }
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                const int l = base + k * B;
+                if (k < live && l < S) {
+                    const T gg = isfinite(gu[k]) ? gu[k] : T(0);
+                    unsigned char* slot = lds + (size_t)l * L::bwd;
+                    *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a};
+                    *reinterpret_cast<V4*>(slot + 4 * sizeof(T)) = V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b};
+                    *reinterpret_cast<T*>(slot + 8 * sizeof(T)) = gg * pv[k].c;
+                }
+            }
         }
     }
     __syncthreads();
 
-    const uint16_t* __restrict__ lcol = seg + P;
-    for (int l = threadIdx.x; l < P; l += blockDim.x) {
-        const int s = l ? seg[l - 1] : 0;
-        const int e = seg[l];
+    for (int l = threadIdx.x; l < P; l += B) {
+        const int s = l ? rowend[l - 1] : 0;
+        const int e = rowend[l];
         const uint32_t u = idx[l];
         const T sig = tape[(size_t)n * (2 * D) + u];
+        const unsigned char* self = lds + (size_t)l * L::bwd;
         if constexpr (D == 2) {
-            const V4 cj = sa[l];
+            const V4 cj = *reinterpret_cast<const V4*>(self);
             T a0 = 0, a1 = 0;
-            for (int k = s; k < e; ++k) {
-                const int c = lcol[k];
-                const V4 q = sa[c];
-                const V2 hq = sb2[c];
-                const T d0 = cj.x - q.x, d1 = cj.y - q.y;
-                const T t = hq.x * d0 + hq.y * d1;
-                a0 = dfma(q.z, t, a0);
-                a1 = dfma(q.w, t, a1);
-            }
+            struct Q {
+                V4 a;
+                V2 h;
+            };
+            auto at = [&](uint32_t o) {
+                const unsigned char* q = lds + L::bwd_off(o);
+                return Q{*reinterpret_cast<const V4*>(q), *reinterpret_cast<const V2*>(q + 4 * sizeof(T))};
+            };
+            walk_row(pairs, s, e, [&](auto... o) {
+                const Q q[] = {at(o)...};
+                for (const Q& v : q) {
+                    const T d0 = cj.x - v.a.x, d1 = cj.y - v.a.y;
+                    const T t = v.h.x * d0 + v.h.y * d1;
+                    a0 = dfma(v.a.z, t, a0);
+                    a1 = dfma(v.a.w, t, a1);
+                }
+            });
             reinterpret_cast<V2*>(grad)[u] = V2{a0 - sig * cj.z, a1 - sig * cj.w};
         } else {
-            const V4 cj = sa[l];
-            const V4 cb = sb4[l];
-            const T cw2 = sc[l];
+            const V4 cj = *reinterpret_cast<const V4*>(self);
+            const V4 cb = *reinterpret_cast<const V4*>(self + 4 * sizeof(T));
+            const T cw2 = *reinterpret_cast<const T*>(self + 8 * sizeof(T));
             T a0 = 0, a1 = 0, a2 = 0;
-            for (int k = s; k < e; ++k) {
-                const int c = lcol[k];
-                const V4 q = sa[c];
-                const V4 qb = sb4[c];
-                const T qw2 = sc[c];
-                const T d0 = cj.x - q.x, d1 = cj.y - q.y, d2 = cj.z - q.z;
-                const T t = q.w * d0 + qb.x * d1 + qb.y * d2;
-                a0 = dfma(qb.z, t, a0);
-                a1 = dfma(qb.w, t, a1);
-                a2 = dfma(qw2, t, a2);
-            }
+            struct Q {
+                V4 a, b;
+                T c;
+            };
+            auto at = [&](uint32_t o) {
+                const unsigned char* q = lds + L::bwd_off(o);
+                return Q{*reinterpret_cast<const V4*>(q), *reinterpret_cast<const V4*>(q + 4 * sizeof(T)),
+                         *reinterpret_cast<const T*>(q + 8 * sizeof(T))};
+            };
+            walk_row(pairs, s, e, [&](auto... o) {
+                const Q q[] = {at(o)...};
+                for (const Q& v : q) {
+                    const T d0 = cj.x - v.a.x, d1 = cj.y - v.a.y, d2 = cj.z - v.a.z;
+                    const T t = v.a.w * d0 + v.b.x * d1 + v.b.y * d2;
+                    a0 = dfma(v.b.z, t, a0);
+                    a1 = dfma(v.b.w, t, a1);
+                    a2 = dfma(v.c, t, a2);
+                }
+            });
             T* gp = grad + (size_t)u * 3;
             gp[0] = a0 - sig * cb.z;
             gp[1] = a1 - sig * cb.w;
@@ -500,12 +678,12 @@ __global__ void __launch_bounds__(512) batched_kernel(const BatchMesh* __restric
 template <int D, typename T>
 size_t fwd_lds(const DevTiles& t)
 {
-    return tile_lds_bytes(FwdLds<D, T>::slot_bytes, t.max_staged, t.max_seg);
+    return tile_lds_bytes(Layout<D, T>::fwd, t.max_staged, t.max_seg);
 }
 template <int D, typename T>
 size_t bwd_lds(const DevTiles& t)
 {
-    return tile_lds_bytes(BwdLds<D, T>::slot_bytes, t.max_staged, t.max_seg);
+    return tile_lds_bytes(Layout<D, T>::bwd, t.max_staged, t.max_seg);
 }
 
 template <int D, typename T>

@@ -100,6 +100,7 @@ def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2)
     and its local stencil (own + halo slots) maps back to the oracle's stencil;
     the adjoint tiles hold the transposed stencil."""
     m = F.Mesh(x, cells, "f32", stencil=stencil, tile_log2=tile_log2, host_only=True)
+    stride = m.slot_stride()
     ring = oracle.ring1(dim, x.shape[0], cells)
     st = ring if stencil == "ring1" else oracle.axis(dim, x, ring)
     want = _oracle_rows(st)
@@ -110,21 +111,31 @@ def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2)
     for adjoint, ref in ((False, want), (True, {k: sorted(v) for k, v in wantT.items()})):
         seen = np.zeros(m.n, np.int64)
         for idx, rowend, lcol, P, H in m.tiles(adjoint):
-            assert P >= 1 and P <= (1 << (tile_log2 or (10 if dim == 2 else 9)))
+            assert P >= 1 and P <= (1 << (tile_log2 or 9))
             assert len(set(idx.tolist())) == P + H, "staged points must be distinct"
+            assert (P + H) * stride <= 65536
             assert np.all(np.diff(rowend.astype(np.int64)) >= 0)
             assert int(rowend[-1]) == len(lcol)
-            assert np.all(lcol < P + H)
+            assert np.all(lcol % stride == 0)
+            loc = lcol.astype(np.int64) // stride
+            assert np.all(loc < P + H)
             start = 0
             for l in range(P):
                 u = int(idx[l])
                 seen[u] += 1
-                row = sorted(int(idx[c]) for c in lcol[start:int(rowend[l])])
-                assert row == ref[u], (u, row, ref[u])
-                start = int(rowend[l])
+                end = int(rowend[l])
+                assert (end - start) % 2 == 0, "rows are padded to even length"
+                row = [int(c) for c in loc[start:end]]
+                if row.count(l):   # the only allowed self entry is the final pad of an odd row
+                    assert row.count(l) == 1 and row[-1] == l and len(ref[u]) % 2 == 1
+                    row = row[:-1]
+                else:
+                    assert len(ref[u]) % 2 == 0
+                assert sorted(int(idx[c]) for c in row) == ref[u], (u, row, ref[u])
+                start = end
             # halo points are exactly the neighbours not owned by the tile
             own = set(idx[:P].tolist())
-            used = {int(idx[c]) for c in lcol}
+            used = {int(idx[c]) for c in loc}
             assert set(idx[P:].tolist()) == used - own
         assert np.all(seen == 1)
 
@@ -241,3 +252,14 @@ def test_call_validation(L):
     assert L.ftle_batched(2, hs, ptrs, Ts, ptrs, 0, None) == UNSUP      # host-only meshes
     L.ftle_destroy_mesh(h)
     L.ftle_destroy_mesh(h3)
+
+
+def test_set_blocks_validation(L):
+    st, h = _create(L)
+    assert L.ftle_mesh_set_blocks(h, 128, 512) == 0
+    assert L.ftle_mesh_set_blocks(h, 0, 0) == 0
+    for bad in (32, 96, 576, -64):
+        assert L.ftle_mesh_set_blocks(h, bad, 0) == 1
+        assert L.ftle_mesh_set_blocks(h, 0, bad) == 1
+    assert L.ftle_mesh_set_blocks(None, 64, 64) == 1
+    L.ftle_destroy_mesh(h)
