@@ -151,9 +151,10 @@ ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles,
 
 /*
  * Threads per workgroup of this mesh's forward (and forward+tape) kernel and
- * of its adjoint gather kernel: each a multiple of 64 in [64, 512] (0 keeps
- * the current value; the default is 256).  A workgroup always processes one
- * whole tile.
+ * of its adjoint gather kernel: each 128, 256 or 512 (0 keeps the current
+ * value; the default is 256 in 2D and 512 in 3D).  A workgroup always
+ * processes one whole tile.
+ * Errors: INVALID_ARG for a NULL mesh or another block size.
  */
 ftle_status ftle_mesh_set_blocks(ftle_mesh_t mesh, int fwd_block, int adjoint_block);
 

@@ -664,6 +664,10 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
         m->flags = flags;
         m->host_only = (flags & FTLE_HOST_ONLY) != 0;
         m->tile_points = tile_log2 ? (1 << tile_log2) : 512;
+        // launch shapes measured best on MI355X for 512-point tiles: two points
+        // per lane in 2D, one in 3D (whose per-lane registers cap occupancy)
+        m->fwd_block = (dim == 2) ? 256 : 512;
+        m->bwd_block = (dim == 2) ? 256 : 512;
 
         // Morton order: quantise to the bounding box, interleave, stable sort
         m->perm.resize(n);
@@ -797,8 +801,7 @@ ftle_status ftle_mesh_set_blocks(ftle_mesh_t mesh, int fwd_block, int adjoint_bl
     return guarded([&] {
         check_mesh(mesh);
         for (int b : {fwd_block, adjoint_block})
-            if (b != 0 && (b < 64 || b > 512 || b % 64 != 0))
-                fail(FTLE_ERR_INVALID_ARG, "block sizes must be multiples of 64 in [64, 512]");
+            if (b != 0 && !supported_block(b)) fail(FTLE_ERR_INVALID_ARG, "block sizes must be 128, 256 or 512");
         if (fwd_block) mesh->fwd_block = fwd_block;
         if (adjoint_block) mesh->bwd_block = adjoint_block;
     });
@@ -931,6 +934,7 @@ namespace {
 struct BatchPlan {
     int dim = 0;
     bool f64 = false;
+    bool wide = false;   // 64-bit element offsets (some mesh is that large)
     int device = -1;
     std::vector<ftle_mesh_t> meshes;
     void* d_meshes = nullptr;     // BatchMesh[n]
@@ -975,6 +979,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
         bm[k].tiles = m->fwd.dev();
         bm[k].x = m->d_x;
         bm[k].fp64_hits = m->d_hits;
+        p->wide = p->wide || batched_needs_wide(p->dim, p->f64, m->n);
         maxt.max_staged = std::max(maxt.max_staged, m->fwd.max_staged);
         maxt.max_seg = std::max(maxt.max_seg, m->fwd.max_seg);
         if (m->fwd.meta.size() >= (1u << kItemTileBits)) fail(FTLE_ERR_UNSUPPORTED, "mesh has too many tiles for a batch");
@@ -1006,7 +1011,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
 int resident_grid(BatchPlan* p, int block, int per_cu_cap)
 {
     int per_cu = 0;
-    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel_symbol(p->dim, p->f64, block),
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel_symbol(p->dim, p->f64, block, p->wide),
                                                            block, p->lds),
               "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     int cus = 0;
@@ -1032,7 +1037,7 @@ void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
                 float tot = 0.f;
                 for (int rep = 0; rep < 4; ++rep) {
                     check_hip(hipEventRecord(e0, s), "hipEventRecord");
-                    check_hip(launch_batched(p->dim, p->f64, static_cast<const BatchMesh*>(p->d_meshes),
+                    check_hip(launch_batched(p->dim, p->f64, p->wide, static_cast<const BatchMesh*>(p->d_meshes),
                                              static_cast<const uint32_t*>(p->d_items), p->n_items, k, p->d_queue,
                                              call, p->lds, eig_tau(), b, grid, s),
                               "batched launch");
@@ -1061,7 +1066,7 @@ void build_graph(BatchPlan* p, const BatchCall& call)
                         p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(), p->args);
     check_hip(hipGraphCreate(&p->graph, 0), "hipGraphCreate");
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block));
+    kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
     kp.gridDim = dim3(p->grid);
     kp.blockDim = dim3(p->block);
     kp.sharedMemBytes = (unsigned)p->lds;
@@ -1143,7 +1148,7 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
         batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
                             p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(), p->args);
         hipKernelNodeParams kp{};
-        kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block));
+        kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
         kp.gridDim = dim3(p->grid);
         kp.blockDim = dim3(p->block);
         kp.sharedMemBytes = (unsigned)p->lds;

@@ -98,12 +98,18 @@ hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, cons
                                   const void* tape, int64_t n, const void* g, void* grad,
                                   int block, hipStream_t stream);
 
-hipError_t launch_batched(int dim, bool f64, const BatchMesh* meshes, const uint32_t* items,
+// Block sizes (threads per workgroup) the kernels are compiled for.
+inline bool supported_block(int b) { return b == 128 || b == 256 || b == 512; }
+
+hipError_t launch_batched(int dim, bool f64, bool wide, const BatchMesh* meshes, const uint32_t* items,
                           int n_items, int tiles_per_pop, unsigned* queue, const BatchCall& call,
                           size_t lds, double eig_tau, int block, int grid, hipStream_t stream);
 
-// The kernel a batched launch runs (for occupancy queries and graph updates).
-const void* batched_kernel_symbol(int dim, bool f64, int block);
+// The kernel a batched launch runs (for occupancy queries and graph nodes);
+// nullptr for an unsupported block size.  wide: 64-bit element offsets, needed
+// when some mesh of the batch has batched_needs_wide(dim, f64, n).
+const void* batched_kernel_symbol(int dim, bool f64, int block, bool wide);
+bool batched_needs_wide(int dim, bool f64, int64_t max_points);
 void batched_kernel_args(const BatchMesh* meshes, const uint32_t* items, int n_items,
                          int tiles_per_pop, unsigned* queue, const BatchCall& call,
                          double eig_tau, void* storage, void** args);

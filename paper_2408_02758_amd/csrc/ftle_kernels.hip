@@ -119,22 +119,44 @@ template <int D, typename T> struct Layout {
 // Copy a tile's 16-bit segment into LDS: up to four independent 16-byte loads
 // per thread are in flight before the stores.  Slices past the end are
 // skipped by a workgroup-uniform branch; idle lanes of the last live slice
-// reload the round's first chunk and do not store.
+// reload the segment's last chunk and do not store.
+template <int B>
 __device__ inline void stage_segment(const uint4* __restrict__ src, uint4* dst, int n16)
 {
-    const int B = blockDim.x;
+    // (named registers, not an array: a conditionally filled array is put in
+    // scratch memory by the compiler)
     for (int r0 = 0; r0 < n16; r0 += 4 * B) {
         const int live = min(4, (n16 - r0 + B - 1) / B);
         const int i0 = r0 + (int)threadIdx.x, i1 = i0 + B, i2 = i1 + B, i3 = i2 + B;
-        uint4 v0 = src[i0 < n16 ? i0 : r0], v1{}, v2{}, v3{};
-        if (live > 1) v1 = src[i1 < n16 ? i1 : r0];
-        if (live > 2) v2 = src[i2 < n16 ? i2 : r0];
-        if (live > 3) v3 = src[i3 < n16 ? i3 : r0];
+        const uint4 v0 = src[min(i0, n16 - 1)];
+        uint4 v1{}, v2{}, v3{};
+        if (live > 1) v1 = src[min(i1, n16 - 1)];
+        if (live > 2) v2 = src[min(i2, n16 - 1)];
+        if (live > 3) v3 = src[min(i3, n16 - 1)];
         if (i0 < n16) dst[i0] = v0;
         if (live > 1 && i1 < n16) dst[i1] = v1;
         if (live > 2 && i2 < n16) dst[i2] = v2;
         if (live > 3 && i3 < n16) dst[i3] = v3;
     }
+}
+
+// Element `i` of an array of records of `bytes` bytes, addressed with a 32-bit
+// byte offset from a uniform base (one shift per access) unless WIDE.
+template <bool WIDE, typename V, typename P>
+__device__ inline V rec_at(const P* base, uint32_t i, uint32_t bytes)
+{
+    if constexpr (WIDE)
+        return *reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(base) + (uint64_t)i * bytes);
+    else
+        return *reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(base) + i * bytes);
+}
+template <bool WIDE, typename V, typename P>
+__device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
+{
+    if constexpr (WIDE)
+        *reinterpret_cast<V*>(reinterpret_cast<unsigned char*>(base) + (uint64_t)i * bytes) = v;
+    else
+        *reinterpret_cast<V*>(reinterpret_cast<unsigned char*>(base) + i * bytes) = v;
 }
 
 // Points staged per thread per round: all index loads, then all value
@@ -236,7 +258,7 @@ __device__ __noinline__ float lam_max3_f64_from_J(float j00, float j01, float j0
 // tape (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j dx, with v
 // the unit top eigenvector of C).
 // ---------------------------------------------------------------------------
-template <int D, typename T, bool OUT, bool TAPE>
+template <int D, typename T, bool OUT, bool TAPE, int B, bool WIDE>
 __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
                                          const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
                                          T* __restrict__ out, T* __restrict__ tape, const int64_t n,
@@ -253,42 +275,41 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
     const uint16_t* rowend = seg + nnz;
 
-    stage_segment(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    const int B = blockDim.x;
+    stage_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
     for (int r0 = 0; r0 < S; r0 += kStage * B) {
         const int live = min(kStage, (S - r0 + B - 1) / B);   // workgroup-uniform
         const int base = r0 + (int)threadIdx.x;
-        uint32_t u[kStage] = {};
+        uint32_t u[kStage];
 #pragma unroll
         for (int k = 0; k < kStage; ++k)
-            if (k < live) u[k] = idx[base + k * B < S ? base + k * B : r0];
+            if (k < live) u[k] = idx[min(base + k * B, S - 1)];
         if constexpr (D == 2) {
-            V2 xv[kStage] = {}, fv[kStage] = {};
+            V2 xv[kStage], fv[kStage];
 #pragma unroll
             for (int k = 0; k < kStage; ++k)
                 if (k < live) {
-                    xv[k] = reinterpret_cast<const V2*>(x)[u[k]];
-                    fv[k] = reinterpret_cast<const V2*>(flow)[u[k]];
+                    xv[k] = rec_at<WIDE, V2>(x, u[k], sizeof(V2));
+                    fv[k] = rec_at<WIDE, V2>(flow, u[k], sizeof(V2));
                 }
 #pragma unroll
             for (int k = 0; k < kStage; ++k) {
                 const int l = base + k * B;
                 if (k < live && l < S)
-                    *reinterpret_cast<V4*>(lds + (size_t)l * L::fwd) = V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y};
+                    *reinterpret_cast<V4*>(lds + (uint32_t)l * L::fwd) = V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y};
             }
         } else {
-            Packed3<T> xv[kStage] = {}, fv[kStage] = {};
+            Packed3<T> xv[kStage], fv[kStage];
 #pragma unroll
             for (int k = 0; k < kStage; ++k)
                 if (k < live) {
-                    xv[k] = reinterpret_cast<const Packed3<T>*>(x)[u[k]];
-                    fv[k] = reinterpret_cast<const Packed3<T>*>(flow)[u[k]];
+                    xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
+                    fv[k] = rec_at<WIDE, Packed3<T>>(flow, u[k], sizeof(Packed3<T>));
                 }
 #pragma unroll
             for (int k = 0; k < kStage; ++k) {
                 const int l = base + k * B;
                 if (k < live && l < S) {
-                    unsigned char* slot = lds + (size_t)l * L::fwd;
+                    unsigned char* slot = lds + (uint32_t)l * L::fwd;
                     *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a};
                     *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{fv[k].b, fv[k].c};
                 }
@@ -354,8 +375,8 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                 const T p0 = (j00 * v0 + j01 * v1) * sc, p1 = (j10 * v0 + j11 * v1) * sc;
                 const T h0 = use ? (m11 * v0 - m01 * v1) * id : T(0);
                 const T h1 = use ? (m00 * v1 - m01 * v0) * id : T(0);
-                reinterpret_cast<V4*>(tape)[u] = V4{p0, p1, h0, h1};
-                tape[(size_t)n * 4 + u] = h0 * s0 + h1 * s1;
+                rec_put<WIDE>(tape, u, sizeof(V4), V4{p0, p1, h0, h1});
+                rec_put<WIDE>(tape + (size_t)n * 4, u, sizeof(T), h0 * s0 + h1 * s1);
             }
         } else {
             const V4 c0 = *reinterpret_cast<const V4*>(self);
@@ -457,25 +478,22 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                 const bool use = ok && (lam > T(0)) && isfinite(f);
                 const T sc = use ? T(2) * inv2T * drcp(lam) : T(0);
                 const T hs = use ? id : T(0);
-                T* t = tape + (size_t)u * 6;
-                t[0] = (j00 * v0 + j01 * v1 + j02 * v2) * sc;
-                t[1] = (j10 * v0 + j11 * v1 + j12 * v2) * sc;
-                t[2] = (j20 * v0 + j21 * v1 + j22 * v2) * sc;
                 const T h0 = (a00 * v0 + a01 * v1 + a02 * v2) * hs;
                 const T h1 = (a01 * v0 + a11 * v1 + a12 * v2) * hs;
                 const T h2 = (a02 * v0 + a12 * v1 + a22 * v2) * hs;
-                t[3] = h0;
-                t[4] = h1;
-                t[5] = h2;
-                tape[(size_t)n * 6 + u] = h0 * s0 + h1 * s1 + h2 * s2;
+                rec_put<WIDE>(tape, 2 * u, sizeof(Packed3<T>),
+                              Packed3<T>{(j00 * v0 + j01 * v1 + j02 * v2) * sc, (j10 * v0 + j11 * v1 + j12 * v2) * sc,
+                                         (j20 * v0 + j21 * v1 + j22 * v2) * sc});
+                rec_put<WIDE>(tape, 2 * u + 1, sizeof(Packed3<T>), Packed3<T>{h0, h1, h2});
+                rec_put<WIDE>(tape + (size_t)n * 6, u, sizeof(T), h0 * s0 + h1 * s1 + h2 * s2);
             }
         }
-        if constexpr (OUT) out[u] = f;
+        if constexpr (OUT) rec_put<WIDE>(out, u, sizeof(T), f);
     }
 }
 
-template <int D, typename T, bool OUT, bool TAPE>
-__global__ void __launch_bounds__(512) fwd_kernel(const TileMeta* __restrict__ meta,
+template <int D, typename T, bool OUT, bool TAPE, int B, bool WIDE>
+__global__ void __launch_bounds__(B) fwd_kernel(const TileMeta* __restrict__ meta,
                                                   const uint4* __restrict__ rec, int n_tiles,
                                                   const T* __restrict__ x, const T* __restrict__ flow,
                                                   T inv2T, T* __restrict__ out, T* __restrict__ tape,
@@ -483,8 +501,8 @@ __global__ void __launch_bounds__(512) fwd_kernel(const TileMeta* __restrict__ m
 {
     extern __shared__ uint4 lds_raw[];
     const int t = xcd_tile(blockIdx.x, n_tiles);
-    fwd_tile<D, T, OUT, TAPE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits,
-                              reinterpret_cast<unsigned char*>(lds_raw));
+    fwd_tile<D, T, OUT, TAPE, B, WIDE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits,
+                                       reinterpret_cast<unsigned char*>(lds_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -493,8 +511,8 @@ __global__ void __launch_bounds__(512) fwd_kernel(const TileMeta* __restrict__ m
 // The tile set here is the one of the transposed stencil S^T (equal to S for
 // the symmetric one-ring stencil).  Points with non-finite g add nothing.
 // ---------------------------------------------------------------------------
-template <int D, typename T>
-__global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ meta,
+template <int D, typename T, int B, bool WIDE>
+__global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ meta,
                                                   const uint4* __restrict__ rec, int n_tiles,
                                                   const T* __restrict__ x, const T* __restrict__ tape,
                                                   int64_t n, const T* __restrict__ g,
@@ -514,53 +532,52 @@ __global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ m
     const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
     const uint16_t* rowend = seg + nnz;
 
-    stage_segment(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
+    stage_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
     constexpr int kB = kStage / 2;
-    const int B = blockDim.x;
     for (int r0 = 0; r0 < S; r0 += kB * B) {
         const int live = min(kB, (S - r0 + B - 1) / B);   // workgroup-uniform
         const int base = r0 + (int)threadIdx.x;
-        uint32_t u[kB] = {};
+        uint32_t u[kB];
 #pragma unroll
         for (int k = 0; k < kB; ++k)
-            if (k < live) u[k] = idx[base + k * B < S ? base + k * B : r0];
-        T gu[kB] = {};
+            if (k < live) u[k] = idx[min(base + k * B, S - 1)];
+        T gu[kB];
         if constexpr (D == 2) {
-            V2 xv[kB] = {};
-            V4 tv[kB] = {};
+            V2 xv[kB];
+            V4 tv[kB];
 #pragma unroll
             for (int k = 0; k < kB; ++k)
                 if (k < live) {
-                    gu[k] = g[u[k]];
-                    xv[k] = reinterpret_cast<const V2*>(x)[u[k]];
-                    tv[k] = reinterpret_cast<const V4*>(tape)[u[k]];
+                    gu[k] = rec_at<WIDE, T>(g, u[k], sizeof(T));
+                    xv[k] = rec_at<WIDE, V2>(x, u[k], sizeof(V2));
+                    tv[k] = rec_at<WIDE, V4>(tape, u[k], sizeof(V4));
                 }
 #pragma unroll
             for (int k = 0; k < kB; ++k) {
                 const int l = base + k * B;
                 if (k < live && l < S) {
                     const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-                    unsigned char* slot = lds + (size_t)l * L::bwd;
+                    unsigned char* slot = lds + (uint32_t)l * L::bwd;
                     *reinterpret_cast<V4*>(slot) = V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y};
                     *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{tv[k].z, tv[k].w};
                 }
             }
         } else {
-            Packed3<T> xv[kB] = {}, pv[kB] = {}, hv[kB] = {};
+            Packed3<T> xv[kB], pv[kB], hv[kB];
 #pragma unroll
             for (int k = 0; k < kB; ++k)
                 if (k < live) {
-                    gu[k] = g[u[k]];
-                    xv[k] = reinterpret_cast<const Packed3<T>*>(x)[u[k]];
-                    pv[k] = reinterpret_cast<const Packed3<T>*>(tape)[2 * (size_t)u[k]];
-                    hv[k] = reinterpret_cast<const Packed3<T>*>(tape)[2 * (size_t)u[k] + 1];
+                    gu[k] = rec_at<WIDE, T>(g, u[k], sizeof(T));
+                    xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
+                    pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
+                    hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
                 }
 #pragma unroll
             for (int k = 0; k < kB; ++k) {
                 const int l = base + k * B;
                 if (k < live && l < S) {
                     const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-                    unsigned char* slot = lds + (size_t)l * L::bwd;
+                    unsigned char* slot = lds + (uint32_t)l * L::bwd;
                     *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a};
                     *reinterpret_cast<V4*>(slot + 4 * sizeof(T)) = V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b};
                     *reinterpret_cast<T*>(slot + 8 * sizeof(T)) = gg * pv[k].c;
@@ -574,7 +591,7 @@ __global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ m
         const int s = l ? rowend[l - 1] : 0;
         const int e = rowend[l];
         const uint32_t u = idx[l];
-        const T sig = tape[(size_t)n * (2 * D) + u];
+        const T sig = rec_at<WIDE, T>(tape + (size_t)n * (2 * D), u, sizeof(T));
         const unsigned char* self = lds + (size_t)l * L::bwd;
         if constexpr (D == 2) {
             const V4 cj = *reinterpret_cast<const V4*>(self);
@@ -596,7 +613,7 @@ __global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ m
                     a1 = dfma(v.a.w, t, a1);
                 }
             });
-            reinterpret_cast<V2*>(grad)[u] = V2{a0 - sig * cj.z, a1 - sig * cj.w};
+            rec_put<WIDE>(grad, u, sizeof(V2), V2{a0 - sig * cj.z, a1 - sig * cj.w});
         } else {
             const V4 cj = *reinterpret_cast<const V4*>(self);
             const V4 cb = *reinterpret_cast<const V4*>(self + 4 * sizeof(T));
@@ -621,10 +638,7 @@ __global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ m
                     a2 = dfma(v.c, t, a2);
                 }
             });
-            T* gp = grad + (size_t)u * 3;
-            gp[0] = a0 - sig * cb.z;
-            gp[1] = a1 - sig * cb.w;
-            gp[2] = a2 - sig * cw2;
+            rec_put<WIDE>(grad, u, sizeof(Packed3<T>), Packed3<T>{a0 - sig * cb.z, a1 - sig * cb.w, a2 - sig * cw2});
         }
     }
 }
@@ -636,8 +650,8 @@ __global__ void __launch_bounds__(512) bwd_kernel(const TileMeta* __restrict__ m
 // queue[0] is the next item, queue[1] counts finished workgroups; the last
 // workgroup to finish zeroes both for the next launch.
 // ---------------------------------------------------------------------------
-template <int D, typename T>
-__global__ void __launch_bounds__(512) batched_kernel(const BatchMesh* __restrict__ meshes,
+template <int D, typename T, int B, bool WIDE>
+__global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict__ meshes,
                                                       const uint32_t* __restrict__ items, int n_items,
                                                       int tiles_per_pop, unsigned* queue,
                                                       BatchCall call, float eig_tau)
@@ -657,7 +671,7 @@ __global__ void __launch_bounds__(512) batched_kernel(const BatchMesh* __restric
             const int mk = (int)(item >> kItemTileBits);
             const int t = (int)(item & ((1u << kItemTileBits) - 1));
             const BatchMesh bm = meshes[mk];
-            fwd_tile<D, T, true, false>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
+            fwd_tile<D, T, true, false, B, WIDE>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
                                         static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
                                         static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau,
                                         bm.fp64_hits, lds);
@@ -686,38 +700,87 @@ size_t bwd_lds(const DevTiles& t)
     return tile_lds_bytes(Layout<D, T>::bwd, t.max_staged, t.max_seg);
 }
 
-template <int D, typename T>
-hipError_t fwd_launch(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
-                      void* tape, int64_t n, double eig_tau, unsigned long long* hits, int block,
-                      hipStream_t stream)
+template <int D, typename T, int B, bool WIDE>
+hipError_t fwd_launch_b(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
+                        void* tape, int64_t n, double eig_tau, unsigned long long* hits, hipStream_t stream)
 {
     const size_t lds = fwd_lds<D, T>(tiles);
-    const dim3 grid(tiles.n_tiles), blk(block);
+    const dim3 grid(tiles.n_tiles), blk(B);
     const T* xp = static_cast<const T*>(x);
     const T* fp = static_cast<const T*>(flow);
     T* op = static_cast<T*>(out);
     T* tp = static_cast<T*>(tape);
     if (out && tape)
-        hipLaunchKernelGGL((fwd_kernel<D, T, true, true>), grid, blk, lds, stream, tiles.meta, tiles.rec,
+        hipLaunchKernelGGL((fwd_kernel<D, T, true, true, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,
                            tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
     else if (tape)
-        hipLaunchKernelGGL((fwd_kernel<D, T, false, true>), grid, blk, lds, stream, tiles.meta, tiles.rec,
+        hipLaunchKernelGGL((fwd_kernel<D, T, false, true, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,
                            tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
     else
-        hipLaunchKernelGGL((fwd_kernel<D, T, true, false>), grid, blk, lds, stream, tiles.meta, tiles.rec,
+        hipLaunchKernelGGL((fwd_kernel<D, T, true, false, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,
                            tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
     return hipGetLastError();
+}
+
+template <int D, typename T, int B, bool WIDE>
+hipError_t bwd_launch_b(const DevTiles& tiles, const void* x, const void* tape, int64_t n, const void* g,
+                        void* grad, hipStream_t stream)
+{
+    const size_t lds = bwd_lds<D, T>(tiles);
+    hipLaunchKernelGGL((bwd_kernel<D, T, B, WIDE>), dim3(tiles.n_tiles), dim3(B), lds, stream, tiles.meta,
+                       tiles.rec, tiles.n_tiles, static_cast<const T*>(x), static_cast<const T*>(tape), n,
+                       static_cast<const T*>(g), static_cast<T*>(grad));
+    return hipGetLastError();
+}
+
+// 32-bit byte offsets reach every array of an n-point mesh when the largest
+// per-point record (the 3D tape's 2*dim values) times n stays below 4 GiB.
+template <typename T>
+bool needs_wide(int dim, int64_t n)
+{
+    return (uint64_t)n * (uint64_t)(2 * dim) * sizeof(T) >= (1ull << 32);
+}
+
+template <int D, typename T, bool WIDE>
+hipError_t fwd_launch_w(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
+                        void* tape, int64_t n, double eig_tau, unsigned long long* hits, int block,
+                        hipStream_t stream)
+{
+    switch (block) {
+    case 128: return fwd_launch_b<D, T, 128, WIDE>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, stream);
+    case 256: return fwd_launch_b<D, T, 256, WIDE>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, stream);
+    case 512: return fwd_launch_b<D, T, 512, WIDE>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D, typename T>
+hipError_t fwd_launch(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
+                      void* tape, int64_t n, double eig_tau, unsigned long long* hits, int block,
+                      hipStream_t stream)
+{
+    if (needs_wide<T>(D, n))
+        return fwd_launch_w<D, T, true>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
+    return fwd_launch_w<D, T, false>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
 }
 
 template <int D, typename T>
 hipError_t bwd_launch(const DevTiles& tiles, const void* x, const void* tape, int64_t n, const void* g,
                       void* grad, int block, hipStream_t stream)
 {
-    const size_t lds = bwd_lds<D, T>(tiles);
-    hipLaunchKernelGGL((bwd_kernel<D, T>), dim3(tiles.n_tiles), dim3(block), lds, stream, tiles.meta,
-                       tiles.rec, tiles.n_tiles, static_cast<const T*>(x), static_cast<const T*>(tape), n,
-                       static_cast<const T*>(g), static_cast<T*>(grad));
-    return hipGetLastError();
+    const bool wide = needs_wide<T>(D, n);
+    switch (block) {
+    case 128:
+        return wide ? bwd_launch_b<D, T, 128, true>(tiles, x, tape, n, g, grad, stream)
+                    : bwd_launch_b<D, T, 128, false>(tiles, x, tape, n, g, grad, stream);
+    case 256:
+        return wide ? bwd_launch_b<D, T, 256, true>(tiles, x, tape, n, g, grad, stream)
+                    : bwd_launch_b<D, T, 256, false>(tiles, x, tape, n, g, grad, stream);
+    case 512:
+        return wide ? bwd_launch_b<D, T, 512, true>(tiles, x, tape, n, g, grad, stream)
+                    : bwd_launch_b<D, T, 512, false>(tiles, x, tape, n, g, grad, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 struct BatchArgs {
@@ -768,13 +831,30 @@ hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, cons
                : bwd_launch<3, float>(tiles, x, tape, n, g, grad, block, stream);
 }
 
-const void* batched_kernel_symbol(int dim, bool f64, int /*block*/)
+template <int D, typename T, bool WIDE>
+const void* batched_symbol_b(int block)
 {
-    if (dim == 2)
-        return f64 ? reinterpret_cast<const void*>(&batched_kernel<2, double>)
-                   : reinterpret_cast<const void*>(&batched_kernel<2, float>);
-    return f64 ? reinterpret_cast<const void*>(&batched_kernel<3, double>)
-               : reinterpret_cast<const void*>(&batched_kernel<3, float>);
+    switch (block) {
+    case 128: return reinterpret_cast<const void*>(&batched_kernel<D, T, 128, WIDE>);
+    case 256: return reinterpret_cast<const void*>(&batched_kernel<D, T, 256, WIDE>);
+    case 512: return reinterpret_cast<const void*>(&batched_kernel<D, T, 512, WIDE>);
+    default: return nullptr;
+    }
+}
+
+const void* batched_kernel_symbol(int dim, bool f64, int block, bool wide)
+{
+    if (dim == 2) {
+        if (f64) return wide ? batched_symbol_b<2, double, true>(block) : batched_symbol_b<2, double, false>(block);
+        return wide ? batched_symbol_b<2, float, true>(block) : batched_symbol_b<2, float, false>(block);
+    }
+    if (f64) return wide ? batched_symbol_b<3, double, true>(block) : batched_symbol_b<3, double, false>(block);
+    return wide ? batched_symbol_b<3, float, true>(block) : batched_symbol_b<3, float, false>(block);
+}
+
+bool batched_needs_wide(int dim, bool f64, int64_t max_points)
+{
+    return f64 ? needs_wide<double>(dim, max_points) : needs_wide<float>(dim, max_points);
 }
 
 size_t batched_kernel_arg_storage() { return sizeof(BatchArgs); }
@@ -800,15 +880,16 @@ void batched_kernel_args(const BatchMesh* meshes, const uint32_t* items, int n_i
     args[6] = &a->eig_tau;
 }
 
-hipError_t launch_batched(int dim, bool f64, const BatchMesh* meshes, const uint32_t* items, int n_items,
-                          int tiles_per_pop, unsigned* queue, const BatchCall& call, size_t lds,
+hipError_t launch_batched(int dim, bool f64, bool wide, const BatchMesh* meshes, const uint32_t* items,
+                          int n_items, int tiles_per_pop, unsigned* queue, const BatchCall& call, size_t lds,
                           double eig_tau, int block, int grid, hipStream_t stream)
 {
+    const void* k = batched_kernel_symbol(dim, f64, block, wide);
+    if (!k) return hipErrorInvalidValue;
     BatchArgs storage;
     void* args[7];
     batched_kernel_args(meshes, items, n_items, tiles_per_pop, queue, call, eig_tau, &storage, args);
-    return hipLaunchKernel(batched_kernel_symbol(dim, f64, block), dim3(grid), dim3(block), args, lds,
-                           stream);
+    return hipLaunchKernel(k, dim3(grid), dim3(block), args, lds, stream);
 }
 
 }  // namespace ftle

@@ -258,7 +258,7 @@ def test_set_blocks_validation(L):
     st, h = _create(L)
     assert L.ftle_mesh_set_blocks(h, 128, 512) == 0
     assert L.ftle_mesh_set_blocks(h, 0, 0) == 0
-    for bad in (32, 96, 576, -64):
+    for bad in (32, 64, 96, 192, 576, -64):
         assert L.ftle_mesh_set_blocks(h, bad, 0) == 1
         assert L.ftle_mesh_set_blocks(h, 0, bad) == 1
     assert L.ftle_mesh_set_blocks(None, 64, 64) == 1
