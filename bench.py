@@ -35,6 +35,19 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def paper_bits_per_point(dim):
+    """Input per point of the paper's FPGA core (Section 2.1, Table 1): 12 (2D) or
+    18 (3D) double-precision values and 4 or 6 32-bit neighbour indices."""
+    values, indices = (12, 4) if dim == 2 else (18, 6)
+    return 64 * values, 32 * indices
+
+
+def paper_required_gbps(dim, mhz):
+    """Bandwidth the II=1 core needs at clock `mhz`: (fp, index) GB/s."""
+    fp, idx = paper_bits_per_point(dim)
+    return fp / 8 * mhz * 1e6 / 1e9, idx / 8 * mhz * 1e6 / 1e9
+
+
 def alg_bytes_fwd(n, nnz, dim, s=4):
     return 4 * (n + 1) + 4 * nnz + 2 * dim * s * n + s * n
 
@@ -97,6 +110,48 @@ def time_steps(fns, steps, warmup, torch):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "ftle_counters_fetch_write.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2408_02758_amd", "csrc", "ftle_kernels.hip")
+
+
+def kernel_source_sha256():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per dispatch by kernel name, from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy-probe factors), or {} when the
+    summary was taken from another version of the kernel source."""
+    if not os.path.exists(COUNTERS):
+        return {}
+    meta, per_kernel = {}, {}
+    with open(COUNTERS) as f:
+        for ln in f:
+            ln = ln.strip()
+            if not ln or ln.startswith("#"):
+                continue
+            if ln.startswith("kernel:"):
+                fields = dict(part.strip().split(": ", 1) for part in ln.split(" | "))
+                per_kernel[fields["kernel"]] = (float(fields["fetch_kib"]), float(fields["write_kib"]))
+            elif "=" in ln:
+                k, v = ln.split("=", 1)
+                meta[k.strip()] = v.strip()
+    if meta.get("kernel_source_sha256") != kernel_source_sha256():
+        return {}
+    ff, wf = float(meta["fetch_factor"]), float(meta["write_factor"])
+    return {k: round((fe * ff + wr * wf) * 1024) for k, (fe, wr) in per_kernel.items()}
+
+
+def traffic_for(traffic, *names):
+    """Sum of the per-dispatch traffic of the named kernels, or None if any is missing."""
+    try:
+        return sum(traffic[n] for n in names)
+    except KeyError:
+        return None
 
 
 def roofline(alg_bytes, ms):
@@ -179,7 +234,9 @@ def main():
     ms = time_steps(fns, args.steps, args.warmup, torch)
     B = alg_bytes_fwd(w2.n, nnz2, 2)
     pts = w2.n / (ms * 1e-3)
+    traffic = measured_traffic()
     rl = roofline(B, ms)
+    rl["traffic"] = traffic_for(traffic, f"fwd_kernel<2, float, true, false, {meshes2[0].blocks()[0]}, false>")
     rl["alg_bytes_per_launch"] = B
     rl["format_bytes_per_launch"] = format_bytes_fwd(meshes2[0], 2)
     rl["format_frac"] = round(rl["format_bytes_per_launch"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
@@ -218,7 +275,8 @@ def main():
                 "workload": "3D plain FTLE forward, 160^3 Kuhn tetrahedral grid, ABC flow, RK4 dt=0.02, T=10",
                 "points": w3.n, "nnz": nnz3, "ms_per_step": round(t, 5), "points_per_s": round(w3.n / (t * 1e-3), 1),
                 "roofline": dict(roofline(B3, t), alg_bytes_per_launch=B3,
-                                 format_bytes_per_launch=format_bytes_fwd(ms3[0], 3)),
+                                 format_bytes_per_launch=format_bytes_fwd(ms3[0], 3),
+                                 traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, false, {ms3[0].blocks()[0]}, false>")),
                 "fp64_eigen_recomputes_per_call": round(hits / max(1, calls0), 1)}
             log(f"3D forward: {t * 1e3:.2f} us/step")
             del fns, ms3, fl3, ou3
@@ -242,7 +300,9 @@ def main():
             variants["fwd_bwd_3d_96"] = {
                 "workload": "3D FTLE forward + adjoint (dL/dflow, L = sum w_i FTLE_i), 96^3 Kuhn grid, ABC flow, T=10",
                 "points": wd.n, "nnz": nnzd, "ms_per_step": round(t, 5), "points_per_s": round(wd.n / (t * 1e-3), 1),
-                "roofline": dict(roofline(Bd, t), alg_bytes_per_launch=Bd)}
+                "roofline": dict(roofline(Bd, t), alg_bytes_per_launch=Bd,
+                                 traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, true, {msd[0].blocks()[0]}, false>",
+                                                     f"bwd_kernel<3, float, {msd[0].blocks()[1]}, false>"))}
             log(f"fwd+bwd: {t * 1e3:.2f} us/step")
             del fns, msd, fld, outd, taped, gradd
         if want("batched"):
@@ -256,7 +316,7 @@ def main():
                 ob = [torch.empty(w.n, dtype=torch.float32, device=dev) for w in wb]
                 sets.append((mb, fb, ob))
             Ts = [w.T for w in wb]
-            fns = [lambda s=s: F.batched(s[0], s[1], Ts, outs=s[2]) for s in sets]
+            fns = [F.BatchedCall(s[0], s[1], Ts, outs=s[2]) for s in sets]
             t = time_steps(fns, steps_v, args.warmup, torch)
             npts = sum(w.n for w in wb)
             nnzb = sum(m.info()["nnz"] for m in sets[0][0])
@@ -265,8 +325,11 @@ def main():
                 "workload": "48 jittered triangulated double-gyre meshes, sides log-uniform in [64,1024], "
                             "own t0 and T each, one persistent launch from a HIP graph",
                 "points": npts, "nnz": nnzb, "ms_per_step": round(t, 5), "points_per_s": round(npts / (t * 1e-3), 1),
-                "roofline": dict(roofline(Bb, t), alg_bytes_per_launch=Bb),
                 "autotuned": F.batched_config(sets[0][0])}
+            cfg = variants["batched_2d_48"]["autotuned"]
+            variants["batched_2d_48"]["roofline"] = dict(
+                roofline(Bb, t), alg_bytes_per_launch=Bb,
+                traffic=traffic_for(traffic, f"batched_kernel<2, float, {cfg['block']}, false>"))
             log(f"batched: {t * 1e3:.2f} us/step")
             del fns, sets
     if variants:

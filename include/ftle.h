@@ -158,6 +158,10 @@ ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles,
  */
 ftle_status ftle_mesh_set_blocks(ftle_mesh_t mesh, int fwd_block, int adjoint_block);
 
+/* The current threads per workgroup of the forward and adjoint kernels of a
+ * mesh (either output pointer may be NULL). */
+ftle_status ftle_mesh_get_blocks(ftle_mesh_t mesh, int* fwd_block, int* adjoint_block);
+
 /*
  * Forward FTLE (the per-point kernel of Section 2).
  *   flow     device pointer, n_points x dim of dtype, the flow map phi(x_i) in user order
@@ -206,16 +210,22 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
 
 /*
  * Batched forward FTLE over independent meshes (same dim and dtype), in one
- * persistent launch with a work queue of (mesh, tile) items, replayed from a
- * cached HIP graph.  The first call for a given list of meshes builds the
- * work list, times candidate launch shapes (block size, tiles per queue pop,
- * resident workgroups per CU) and keeps the fastest; later calls only update
- * the graph's arguments.  Each output equals ftle_forward's bit for bit.
+ * launch over a work list of (mesh, tile) items, replayed from a cached HIP
+ * graph.  The first call for a given list of meshes builds the work list,
+ * times candidate launch shapes -- a persistent grid draining an atomic work
+ * queue (threads per workgroup, tiles per queue pop, resident workgroups per
+ * CU) or a flat grid of one workgroup per tile -- and keeps the fastest;
+ * later calls only update the graph node's arguments.  Each output equals
+ * ftle_forward's bit for bit (same tile body).  Calls with one list of meshes
+ * share its queue counters: they are ordered on one stream; concurrent calls
+ * with the same list on different streams race.
  *   n         1 <= n <= 64 meshes
  *   meshes    host array of n handles (all dim and dtype equal)
  *   flows     host array of n device pointers (flow maps, user order)
  *   T         host array of n integration times (each nonzero and finite)
  *   outs      host array of n device pointers (FTLE outputs)
+ * Errors: INVALID_ARG (n, NULL arrays or pointers, T, mixed dim or device),
+ * DTYPE, UNSUPPORTED (host-only mesh), DEVICE.
  */
 ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* flows,
                          const double* T, void* const* outs, ftle_dtype dtype,
@@ -224,7 +234,8 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
 /*
  * The launch shape the batched autotuner chose for this list of meshes
  * (after at least one ftle_batched call with it): threads per workgroup,
- * tiles taken per queue pop, workgroups in the persistent grid.
+ * tiles taken per queue pop (0 for the flat one-tile-per-workgroup grid),
+ * workgroups in the grid.
  */
 ftle_status ftle_batched_config(int n, const ftle_mesh_t* meshes, int* block, int* tiles_per_pop,
                                 int* grid);

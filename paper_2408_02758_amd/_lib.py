@@ -43,6 +43,7 @@ SIGNATURES = {
     "ftle_mesh_tile_stats": (_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)]),
     "ftle_mesh_get_tiles": (_int, [_vp, _int, _P(_i64), _P(_i64), _vp, _vp]),
     "ftle_mesh_set_blocks": (_int, [_vp, _int, _int]),
+    "ftle_mesh_get_blocks": (_int, [_vp, _P(_int), _P(_int)]),
     "ftle_forward": (_int, [_vp, _vp, _int, _dbl, _vp, _vp]),
     "ftle_tape_bytes": (_int, [_vp, _P(_i64)]),
     "ftle_forward_tape": (_int, [_vp, _vp, _int, _dbl, _vp, _vp, _vp]),

@@ -126,6 +126,12 @@ class Mesh:
     def set_blocks(self, fwd: int = 0, adjoint: int = 0):
         check(_lib.load().ftle_mesh_set_blocks(self._h, int(fwd), int(adjoint)))
 
+    def blocks(self):
+        """(forward, adjoint) threads per workgroup."""
+        f, a = ctypes.c_int(), ctypes.c_int()
+        check(_lib.load().ftle_mesh_get_blocks(self._h, ctypes.byref(f), ctypes.byref(a)))
+        return f.value, a.value
+
     def tape_bytes(self) -> int:
         b = ctypes.c_int64()
         check(_lib.load().ftle_tape_bytes(self._h, ctypes.byref(b)))
@@ -218,6 +224,36 @@ def batched(meshes: Sequence[Mesh], flows: Sequence[torch.Tensor], Ts: Sequence[
     return outs
 
 
+class BatchedCall:
+    """A batched forward call prepared once: validates and marshals the meshes,
+    flow maps, times and outputs a single time, then launches with one C call
+    per __call__ (for serving loops and benchmarks that reuse their buffers).
+    Holds references to the tensors it was built with."""
+
+    def __init__(self, meshes: Sequence[Mesh], flows: Sequence[torch.Tensor], Ts: Sequence[float], outs=None):
+        n = len(meshes)
+        if not (len(flows) == n == len(Ts)) or n == 0:
+            raise ValueError("meshes, flows and Ts must be non-empty and of the same length")
+        for m, f in zip(meshes, flows):
+            m._check_flow(f)
+        if outs is None:
+            outs = [torch.empty(m.n, dtype=m.torch_dtype, device=f.device) for m, f in zip(meshes, flows)]
+        for m, o in zip(meshes, outs):
+            m._check_flow(o, "out", (m.n,))
+        self.meshes, self.flows, self.outs = list(meshes), list(flows), list(outs)
+        self._n = n
+        self._h = _handles(meshes)
+        self._fl = (ctypes.c_void_p * n)(*[f.data_ptr() for f in flows])
+        self._ou = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        self._ts = (ctypes.c_double * n)(*[float(t) for t in Ts])
+        self._code = meshes[0]._code
+        self._fn = _lib.load().ftle_batched
+
+    def __call__(self, stream=None):
+        check(self._fn(self._n, self._h, self._fl, self._ts, self._ou, self._code, _stream_handle(stream)))
+        return self.outs
+
+
 def batched_config(meshes: Sequence[Mesh]):
     b, k, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     check(_lib.load().ftle_batched_config(len(meshes), _handles(meshes), ctypes.byref(b), ctypes.byref(k),
@@ -247,4 +283,4 @@ def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
     return FTLEFunction.apply(flow, mesh, T)
 
 
-__all__ = ["Mesh", "batched", "batched_config", "FTLEFunction", "ftle", "FTLEError"]
+__all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError"]

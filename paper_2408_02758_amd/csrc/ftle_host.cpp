@@ -807,6 +807,15 @@ ftle_status ftle_mesh_set_blocks(ftle_mesh_t mesh, int fwd_block, int adjoint_bl
     });
 }
 
+ftle_status ftle_mesh_get_blocks(ftle_mesh_t mesh, int* fwd_block, int* adjoint_block)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        if (fwd_block) *fwd_block = mesh->fwd_block;
+        if (adjoint_block) *adjoint_block = mesh->bwd_block;
+    });
+}
+
 ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,
                                 void* meta, void* records)
 {
@@ -951,6 +960,7 @@ struct BatchPlan {
     hipGraphNode_t node = nullptr;
     std::vector<unsigned char> arg_storage;
     void* args[7] = {};
+    BatchCall last{};          // arguments the graph node holds now
 };
 
 std::mutex g_batch_mu;
@@ -1025,14 +1035,16 @@ void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
     hipEvent_t e0, e1;
     check_hip(hipEventCreate(&e0), "hipEventCreate");
     check_hip(hipEventCreate(&e1), "hipEventCreate");
+    static const bool verbose = std::getenv("FTLE_AUTOTUNE_LOG") != nullptr;
     float best = INFINITY;
     const int blocks[] = {128, 256, 512};
-    const int pops[] = {1, 2, 4, 8};
+    const int pops[] = {0, 1, 2, 4, 8};   // 0: flat launch, one item per workgroup
     const int caps[] = {2, 4, 8};
     for (int b : blocks)
         for (int k : pops)
             for (int cap : caps) {
-                const int grid = resident_grid(p, b, cap);
+                if (k == 0 && cap != caps[0]) continue;   // the flat grid has no residency cap
+                const int grid = (k == 0) ? p->n_items : resident_grid(p, b, cap);
                 if (k > 1 && (int64_t)grid * k > p->n_items) continue;
                 float tot = 0.f;
                 for (int rep = 0; rep < 4; ++rep) {
@@ -1047,6 +1059,9 @@ void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
                     check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
                     if (rep > 0) tot += ms;   // first launch warms up
                 }
+                if (verbose)
+                    std::fprintf(stderr, "[ftle autotune] block %d tiles/pop %d grid %d: %.2f us\n", b, k, grid,
+                                 1e3f * tot / 3.0f);
                 if (tot < best) {
                     best = tot;
                     p->block = b;
@@ -1144,17 +1159,25 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         if (!p->tuned) autotune(p, call, s);
-        if (!p->exec) build_graph(p, call);
-        batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
-                            p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(), p->args);
-        hipKernelNodeParams kp{};
-        kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
-        kp.gridDim = dim3(p->grid);
-        kp.blockDim = dim3(p->block);
-        kp.sharedMemBytes = (unsigned)p->lds;
-        kp.kernelParams = p->args;
-        kp.extra = nullptr;
-        check_hip(hipGraphExecKernelNodeSetParams(p->exec, p->node, &kp), "hipGraphExecKernelNodeSetParams");
+        if (!p->exec) {
+            build_graph(p, call);
+            p->last = call;
+        }
+        if (std::memcmp(&p->last, &call, sizeof(BatchCall)) != 0) {
+            // new pointers or times: update the graph's kernel node in place
+            batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
+                                p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(),
+                                p->args);
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
+            kp.gridDim = dim3(p->grid);
+            kp.blockDim = dim3(p->block);
+            kp.sharedMemBytes = (unsigned)p->lds;
+            kp.kernelParams = p->args;
+            kp.extra = nullptr;
+            check_hip(hipGraphExecKernelNodeSetParams(p->exec, p->node, &kp), "hipGraphExecKernelNodeSetParams");
+            p->last = call;
+        }
         check_hip(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
     });
 }

@@ -644,11 +644,13 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
 }
 
 // ---------------------------------------------------------------------------
-// Batched forward: one persistent grid drains a queue of (mesh, tile) work
-// items.  A workgroup takes tiles_per_pop consecutive items per atomic pop
-// and runs the same tile body as fwd_kernel, so results are bit-identical.
-// queue[0] is the next item, queue[1] counts finished workgroups; the last
-// workgroup to finish zeroes both for the next launch.
+// Batched forward over (mesh, tile) work items, running the same tile body as
+// fwd_kernel (results are bit-identical).  Two launch forms:
+//  - persistent (tiles_per_pop > 0): a resident grid drains an atomic queue,
+//    each workgroup taking tiles_per_pop consecutive items per pop; queue[0]
+//    is the next item, queue[1] counts finished workgroups, and the last
+//    workgroup to finish zeroes both for the next launch;
+//  - flat (tiles_per_pop == 0): one workgroup per item (grid = n_items).
 // ---------------------------------------------------------------------------
 template <int D, typename T, int B, bool WIDE>
 __global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict__ meshes,
@@ -659,6 +661,17 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict_
     extern __shared__ uint4 lds_raw[];
     __shared__ int sh_base;
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
+    if (tiles_per_pop == 0) {
+        // flat launch: one work item per workgroup, dealt XCD-contiguously
+        const uint32_t item = __builtin_amdgcn_readfirstlane(items[xcd_tile(blockIdx.x, n_items)]);
+        const int mk = (int)(item >> kItemTileBits);
+        const int t = (int)(item & ((1u << kItemTileBits) - 1));
+        const BatchMesh bm = meshes[mk];
+        fwd_tile<D, T, true, false, B, WIDE>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
+                                             static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
+                                             static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau, bm.fp64_hits, lds);
+        return;
+    }
     for (;;) {
         if (threadIdx.x == 0) sh_base = (int)atomicAdd(&queue[0], (unsigned)tiles_per_pop);
         __syncthreads();

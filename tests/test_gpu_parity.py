@@ -338,6 +338,13 @@ def test_batched_matches_forward_bitwise_and_replays():
         torch.cuda.synchronize()
         for m, o, f, T in zip(ms, outs2, fl2, Ts2):
             assert torch.equal(o, m.forward(f, T))
+    # a prepared call gives the same results and can be replayed
+    call = F.BatchedCall(ms, fl2, Ts2)
+    for rep in range(2):
+        outs3 = call()
+        torch.cuda.synchronize()
+        for o2, o3 in zip(outs2, outs3):
+            assert torch.equal(o2, o3)
     # against the oracle for a few meshes
     for k in (0, 4, 9):
         ref, gap, _ = ref_ftle(ws[k])

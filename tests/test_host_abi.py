@@ -256,8 +256,11 @@ def test_call_validation(L):
 
 def test_set_blocks_validation(L):
     st, h = _create(L)
+    f, a = ctypes.c_int(), ctypes.c_int()
+    assert L.ftle_mesh_get_blocks(h, ctypes.byref(f), ctypes.byref(a)) == 0 and (f.value, a.value) == (256, 256)
     assert L.ftle_mesh_set_blocks(h, 128, 512) == 0
     assert L.ftle_mesh_set_blocks(h, 0, 0) == 0
+    assert L.ftle_mesh_get_blocks(h, ctypes.byref(f), None) == 0 and f.value == 128
     for bad in (32, 64, 96, 192, 576, -64):
         assert L.ftle_mesh_set_blocks(h, bad, 0) == 1
         assert L.ftle_mesh_set_blocks(h, 0, bad) == 1
