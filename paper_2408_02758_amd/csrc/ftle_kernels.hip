@@ -29,6 +29,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "ftle_internal.h"
 
@@ -116,27 +117,20 @@ template <int D, typename T> struct Layout {
     __device__ static uint32_t bwd_off(uint32_t o) { return D == 2 ? 2 * o : o + (o >> 1); }
 };
 
-// Copy a tile's 16-bit segment into LDS: up to four independent 16-byte loads
-// per thread are in flight before the stores.  Slices past the end are
-// skipped by a workgroup-uniform branch; idle lanes of the last live slice
-// reload the segment's last chunk and do not store.
+// Copy of a tile's 16-bit segment (n16 chunks of 16 bytes) into LDS as a
+// direct global -> LDS transfer (global_load_lds_dwordx4): each wave moves 64
+// consecutive 16-byte chunks to consecutive LDS chunks without passing
+// through registers, so the copy stays in flight while the caller issues
+// other loads.  The caller waits (vmcnt 0) and synchronises the workgroup
+// before reading dst.
 template <int B>
-__device__ inline void stage_segment(const uint4* __restrict__ src, uint4* dst, int n16)
+__device__ inline void dma_segment(const uint4* __restrict__ src, uint4* dst, int n16)
 {
-    // (named registers, not an array: a conditionally filled array is put in
-    // scratch memory by the compiler)
-    for (int r0 = 0; r0 < n16; r0 += 4 * B) {
-        const int live = min(4, (n16 - r0 + B - 1) / B);
-        const int i0 = r0 + (int)threadIdx.x, i1 = i0 + B, i2 = i1 + B, i3 = i2 + B;
-        const uint4 v0 = src[min(i0, n16 - 1)];
-        uint4 v1{}, v2{}, v3{};
-        if (live > 1) v1 = src[min(i1, n16 - 1)];
-        if (live > 2) v2 = src[min(i2, n16 - 1)];
-        if (live > 3) v3 = src[min(i3, n16 - 1)];
-        if (i0 < n16) dst[i0] = v0;
-        if (live > 1 && i1 < n16) dst[i1] = v1;
-        if (live > 2 && i2 < n16) dst[i2] = v2;
-        if (live > 3 && i3 < n16) dst[i3] = v3;
+    const int lane = (int)threadIdx.x & 63;
+    for (int c0 = (int)threadIdx.x - lane; c0 < n16; c0 += B) {   // wave-uniform chunk base
+        if (c0 + lane < n16)
+            __builtin_amdgcn_global_load_lds(src + c0 + lane, (__attribute__((address_space(3))) void*)(dst + c0),
+                                             16, 0, 0);
     }
 }
 
@@ -158,11 +152,6 @@ __device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
     else
         *reinterpret_cast<V*>(reinterpret_cast<unsigned char*>(base) + i * bytes) = v;
 }
-
-// Points staged per thread per round: all index loads, then all value
-// gathers, then the LDS stores (memory-level parallelism for the dependent
-// idx -> value loads), in workgroup-uniform slices as above.
-constexpr int kStage = 8;
 
 // Walk of one row of the padded stencil, four neighbours per step (two 32-bit
 // LDS loads of offset pairs, then the four slot loads, then the arithmetic),
@@ -254,6 +243,76 @@ __device__ __noinline__ float lam_max3_f64_from_J(float j00, float j01, float j0
 }
 
 // ---------------------------------------------------------------------------
+// Staging of the tile's points (own + halo) into their LDS slots.  One round
+// stages K slots per thread: K index loads, then the 2K gathers (coordinates
+// and flow map), then the K LDS stores.  K is a compile-time constant and the
+// loads and stores are unconditional, so the compiler counts outstanding
+// loads exactly and every gather waits only for its own index: one index
+// round trip and one gather round trip per round.  (With loads under
+// per-slot branches it must wait for all outstanding loads before each
+// gather.)  Lanes past the last slot S-1 load slot S-1's point and store the
+// same values to it again.
+// ---------------------------------------------------------------------------
+template <int D, typename T, int B, bool WIDE, int K>
+__device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
+                                 const T* __restrict__ flow, int S, int r0, unsigned char* lds)
+{
+    using V2 = vec2_t<T>;
+    using V4 = vec4_t<T>;
+    using L = Layout<D, T>;
+    const int base = r0 + (int)threadIdx.x;
+    uint32_t u[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = idx[min(base + k * B, S - 1)];
+    if constexpr (D == 2) {
+        V2 xv[K], fv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            xv[k] = rec_at<WIDE, V2>(x, u[k], sizeof(V2));
+            fv[k] = rec_at<WIDE, V2>(flow, u[k], sizeof(V2));
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int l = min(base + k * B, S - 1);
+            *reinterpret_cast<V4*>(lds + (uint32_t)l * L::fwd) = V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y};
+        }
+    } else {
+        Packed3<T> xv[K], fv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
+            fv[k] = rec_at<WIDE, Packed3<T>>(flow, u[k], sizeof(Packed3<T>));
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int l = min(base + k * B, S - 1);
+            unsigned char* slot = lds + (uint32_t)l * L::fwd;
+            *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a};
+            *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{fv[k].b, fv[k].c};
+        }
+    }
+}
+
+template <int K> using IntK = std::integral_constant<int, K>;
+
+// Rounds over S staged slots: full rounds of kMaxK slots per thread, then one
+// round of the K (1..kMaxK) the rest needs.  K is workgroup-uniform, so the
+// switch is a scalar branch and each case is straight-line code.
+constexpr int kMaxK = 4;
+template <int B, typename F>
+__device__ inline void stage_points(int S, F&& round)
+{
+    int r0 = 0;
+    for (; S - r0 > kMaxK * B; r0 += kMaxK * B) round(IntK<kMaxK>{}, r0);
+    switch ((S - r0 + B - 1) / B) {
+    case 1: round(IntK<1>{}, r0); break;
+    case 2: round(IntK<2>{}, r0); break;
+    case 3: round(IntK<3>{}, r0); break;
+    default: round(IntK<4>{}, r0); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One tile of the forward pass.  OUT: write FTLE.  TAPE: write the adjoint
 // tape (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j dx, with v
 // the unit top eigenvector of C).
@@ -275,47 +334,11 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
     const uint16_t* rowend = seg + nnz;
 
-    stage_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    for (int r0 = 0; r0 < S; r0 += kStage * B) {
-        const int live = min(kStage, (S - r0 + B - 1) / B);   // workgroup-uniform
-        const int base = r0 + (int)threadIdx.x;
-        uint32_t u[kStage];
-#pragma unroll
-        for (int k = 0; k < kStage; ++k)
-            if (k < live) u[k] = idx[min(base + k * B, S - 1)];
-        if constexpr (D == 2) {
-            V2 xv[kStage], fv[kStage];
-#pragma unroll
-            for (int k = 0; k < kStage; ++k)
-                if (k < live) {
-                    xv[k] = rec_at<WIDE, V2>(x, u[k], sizeof(V2));
-                    fv[k] = rec_at<WIDE, V2>(flow, u[k], sizeof(V2));
-                }
-#pragma unroll
-            for (int k = 0; k < kStage; ++k) {
-                const int l = base + k * B;
-                if (k < live && l < S)
-                    *reinterpret_cast<V4*>(lds + (uint32_t)l * L::fwd) = V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y};
-            }
-        } else {
-            Packed3<T> xv[kStage], fv[kStage];
-#pragma unroll
-            for (int k = 0; k < kStage; ++k)
-                if (k < live) {
-                    xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
-                    fv[k] = rec_at<WIDE, Packed3<T>>(flow, u[k], sizeof(Packed3<T>));
-                }
-#pragma unroll
-            for (int k = 0; k < kStage; ++k) {
-                const int l = base + k * B;
-                if (k < live && l < S) {
-                    unsigned char* slot = lds + (uint32_t)l * L::fwd;
-                    *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a};
-                    *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{fv[k].b, fv[k].c};
-                }
-            }
-        }
-    }
+    // The stencil segment goes straight to LDS first; then the staged points
+    // in rounds of K slots per thread (fwd_stage).
+    dma_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
+    stage_points<B>(S, [&](auto kc, int r0) { fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds); });
+    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
 
     for (int l = threadIdx.x; l < P; l += B) {
@@ -511,6 +534,59 @@ __global__ void __launch_bounds__(B) fwd_kernel(const TileMeta* __restrict__ met
 // The tile set here is the one of the transposed stencil S^T (equal to S for
 // the symmetric one-ring stencil).  Points with non-finite g add nothing.
 // ---------------------------------------------------------------------------
+// Adjoint staging round (as fwd_stage): slot l holds x, h and w = g p of
+// point idx[l] (g non-finite -> 0).
+template <int D, typename T, int B, bool WIDE, int K>
+__device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
+                                 const T* __restrict__ tape, const T* __restrict__ g, int S, int r0,
+                                 unsigned char* lds)
+{
+    using V2 = vec2_t<T>;
+    using V4 = vec4_t<T>;
+    using L = Layout<D, T>;
+    const int base = r0 + (int)threadIdx.x;
+    uint32_t u[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = idx[min(base + k * B, S - 1)];
+    T gu[K];
+    if constexpr (D == 2) {
+        V2 xv[K];
+        V4 tv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            gu[k] = rec_at<WIDE, T>(g, u[k], sizeof(T));
+            xv[k] = rec_at<WIDE, V2>(x, u[k], sizeof(V2));
+            tv[k] = rec_at<WIDE, V4>(tape, u[k], sizeof(V4));
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int l = min(base + k * B, S - 1);
+            const T gg = isfinite(gu[k]) ? gu[k] : T(0);
+            unsigned char* slot = lds + (uint32_t)l * L::bwd;
+            *reinterpret_cast<V4*>(slot) = V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y};
+            *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{tv[k].z, tv[k].w};
+        }
+    } else {
+        Packed3<T> xv[K], pv[K], hv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            gu[k] = rec_at<WIDE, T>(g, u[k], sizeof(T));
+            xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
+            pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
+            hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int l = min(base + k * B, S - 1);
+            const T gg = isfinite(gu[k]) ? gu[k] : T(0);
+            unsigned char* slot = lds + (uint32_t)l * L::bwd;
+            *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a};
+            *reinterpret_cast<V4*>(slot + 4 * sizeof(T)) = V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b};
+            *reinterpret_cast<T*>(slot + 8 * sizeof(T)) = gg * pv[k].c;
+        }
+    }
+}
+
 template <int D, typename T, int B, bool WIDE>
 __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ meta,
                                                   const uint4* __restrict__ rec, int n_tiles,
@@ -532,59 +608,9 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
     const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
     const uint16_t* rowend = seg + nnz;
 
-    stage_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    constexpr int kB = kStage / 2;
-    for (int r0 = 0; r0 < S; r0 += kB * B) {
-        const int live = min(kB, (S - r0 + B - 1) / B);   // workgroup-uniform
-        const int base = r0 + (int)threadIdx.x;
-        uint32_t u[kB];
-#pragma unroll
-        for (int k = 0; k < kB; ++k)
-            if (k < live) u[k] = idx[min(base + k * B, S - 1)];
-        T gu[kB];
-        if constexpr (D == 2) {
-            V2 xv[kB];
-            V4 tv[kB];
-#pragma unroll
-            for (int k = 0; k < kB; ++k)
-                if (k < live) {
-                    gu[k] = rec_at<WIDE, T>(g, u[k], sizeof(T));
-                    xv[k] = rec_at<WIDE, V2>(x, u[k], sizeof(V2));
-                    tv[k] = rec_at<WIDE, V4>(tape, u[k], sizeof(V4));
-                }
-#pragma unroll
-            for (int k = 0; k < kB; ++k) {
-                const int l = base + k * B;
-                if (k < live && l < S) {
-                    const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-                    unsigned char* slot = lds + (uint32_t)l * L::bwd;
-                    *reinterpret_cast<V4*>(slot) = V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y};
-                    *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{tv[k].z, tv[k].w};
-                }
-            }
-        } else {
-            Packed3<T> xv[kB], pv[kB], hv[kB];
-#pragma unroll
-            for (int k = 0; k < kB; ++k)
-                if (k < live) {
-                    gu[k] = rec_at<WIDE, T>(g, u[k], sizeof(T));
-                    xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
-                    pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
-                    hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
-                }
-#pragma unroll
-            for (int k = 0; k < kB; ++k) {
-                const int l = base + k * B;
-                if (k < live && l < S) {
-                    const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-                    unsigned char* slot = lds + (uint32_t)l * L::bwd;
-                    *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a};
-                    *reinterpret_cast<V4*>(slot + 4 * sizeof(T)) = V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b};
-                    *reinterpret_cast<T*>(slot + 8 * sizeof(T)) = gg * pv[k].c;
-                }
-            }
-        }
-    }
+    dma_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
+    stage_points<B>(S, [&](auto kc, int r0) { bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0, lds); });
+    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
 
     for (int l = threadIdx.x; l < P; l += B) {
