@@ -139,11 +139,11 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
  *   records   host, record_bytes bytes; per tile: uint32 caller indices of the
  *             P own points (Morton order) then the H halo points, padded to a
  *             multiple of 4; then nnz uint16 stencil entries, each the local
- *             index (position in that index list) times the forward LDS slot
- *             stride (16 bytes in 2D, 32 in 3D; doubled for FTLE_F64), with
- *             every row padded to even length by the point's own entry; then
- *             P uint16 row ends (cumulative entry counts); padded to a
- *             multiple of 8 uint16
+ *             index (position in that index list) times 16 in 2D or 8 in 3D
+ *             (doubled for FTLE_F64: byte offsets into the kernels' staged
+ *             LDS arrays), with every row padded to even length by the
+ *             point's own entry; then P uint16 row ends (cumulative entry
+ *             counts); padded to a multiple of 8 uint16
  * meta and records may be NULL (sizes only).
  */
 ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,

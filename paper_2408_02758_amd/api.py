@@ -99,14 +99,15 @@ class Mesh:
         return dict(zip(["n_tiles", "max_tile_points", "halo_entries", "record_bytes"], [v.value for v in vals]))
 
     def slot_stride(self) -> int:
-        """Forward LDS slot stride in bytes (the unit of the tile records' stencil entries)."""
-        return (4 if self.dim == 2 else 8) * (8 if self.dtype == "f64" else 4)
+        """Unit of the tile records' stencil entries (entry = local index * unit):
+        4 values in 2D, 2 in 3D, times the value size."""
+        return (4 if self.dim == 2 else 2) * (8 if self.dtype == "f64" else 4)
 
     def tiles(self, adjoint: bool = False):
         """Raw tile records: list of (idx uint32[P+H], rowend uint16[P], entries uint16[nnz], P, H).
 
-        entries are LDS byte offsets (local index * slot_stride()), rows padded
-        to even length with the point's own entry."""
+        entries are local index * slot_stride() (LDS byte offsets of the first
+        staged array), rows padded to even length with the point's own entry."""
         L = _lib.load()
         nt, rb = ctypes.c_int64(), ctypes.c_int64()
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), ctypes.byref(nt), ctypes.byref(rb), None, None))

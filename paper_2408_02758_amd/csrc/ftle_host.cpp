@@ -382,7 +382,7 @@ int64_t padded_nnz(const Csr& a, int64_t b, int64_t e)
 
 bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nnz_padded)
 {
-    if ((P + H) * (int64_t)fwd_slot_bytes(dim, f64) > 65536 || nnz_padded > kMaxTileNnz) return false;
+    if ((P + H) * (int64_t)fwd_offset_unit(dim, f64) > 65536 || nnz_padded > kMaxTileNnz) return false;
     const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nnz_padded);
     const size_t slot = std::max(fwd_slot_bytes(dim, f64), bwd_slot_bytes(dim, f64));
     return tile_lds_bytes(slot, (int)(P + H), seg) <= kLdsBudget;
@@ -461,7 +461,7 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
             uint32_t* idx = ts.rec.data() + (size_t)m.rec_off * 4;
             uint16_t* seg = reinterpret_cast<uint16_t*>(idx + idx_words(m.P, m.H));
             uint16_t* rowend = seg + m.nnz;
-            const uint32_t stride = (uint32_t)fwd_slot_bytes(dim, f64);
+            const uint32_t stride = (uint32_t)fwd_offset_unit(dim, f64);
             for (int64_t r = b; r < e; ++r) idx[r - b] = (uint32_t)perm[r];
             // halo slot of each halo point: reuse stamp as "slot + 1" storage is
             // not possible (tag), so search in a small map
@@ -1007,7 +1007,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
     std::vector<uint32_t> it32(items.size());
     for (size_t i = 0; i < items.size(); ++i) it32[i] = items[i].item;
     p->n_items = (int)it32.size();
-    p->lds = fwd_lds_bytes(p->dim, p->f64, maxt);
+    p->lds = fwd_lds_bytes(p->dim, p->f64, maxt) + kBatchedLdsHead;
     p->d_meshes = dev_upload(bm.data(), bm.size() * sizeof(BatchMesh));
     p->d_items = dev_upload(it32.data(), it32.size() * sizeof(uint32_t));
     p->d_queue = static_cast<unsigned*>(dev_upload(nullptr, 2 * sizeof(unsigned)));

@@ -21,15 +21,15 @@ namespace ftle {
 //                             halo points (neighbours owned by other tiles),
 //                             padded to a multiple of 4 entries
 //   uint16 seg[nnz + P]       seg[0..nnz): the stencil rows of the own points,
-//                             each entry the LDS byte offset of the
-//                             neighbour's staged slot (local index times the
-//                             forward slot stride); every row is padded to
-//                             even length with the point's own offset;
+//                             each entry the neighbour's local index (its
+//                             position in idx) times fwd_offset_unit; every
+//                             row is padded to even length with the point's
+//                             own entry;
 //                             seg[nnz..nnz+P): end of each row (cumulative,
 //                             in entries); padded to a multiple of 8 entries
 //
-// 16-bit offsets and row ends are enough because (P + H) * stride <= 65536
-// and nnz <= kMaxTileNnz, both enforced when the mesh is built.
+// 16-bit entries and row ends are enough because (P + H) * fwd_offset_unit
+// <= 65536 and nnz <= kMaxTileNnz, both enforced when the mesh is built.
 // ---------------------------------------------------------------------------
 struct TileMeta {
     uint32_t rec_off;  // record offset in 16-byte units
@@ -46,12 +46,21 @@ __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m *
 __host__ __device__ inline uint32_t idx_words(uint32_t P, uint32_t H) { return (P + H + 3u) & ~3u; }
 __host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nnz) { return (P + nnz + 7u) & ~7u; }
 
-// LDS bytes per staged point (the slot stride).  Forward: coordinates and
-// flow map, 4 values in 2D, 8 (6 used) in 3D.  Adjoint: coordinates,
-// w = g p and h, 8 (6 used) in 2D, 12 (9 used) in 3D.  Strides are multiples
-// of 16 bytes where 16-byte LDS reads need it.
-__host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(dim == 2 ? 4 : 8); }
-__host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return (f64 ? 8 : 4) * (size_t)(dim == 2 ? 8 : 12); }
+// LDS bytes per staged point, in units of the value size e (4 or 8 bytes):
+//   forward  2D: 4e, one slot (x0, x1, phi0, phi1)
+//            3D: 6e, two arrays: (phi1, phi2) slots of 2e at the start of
+//                LDS, then (x0, x1, x2, phi0) slots of 4e
+//   adjoint  2D: 8e, one slot (x0, x1, w0, w1) (h0, h1, -, -)
+//            3D: 9e, two arrays: w2 slots of e, then (x0, x1, x2, h0)
+//                (h1, h2, w0, w1) slots of 8e
+// Each array holds round_up(P + H, 4) slots, so every array and the 16-bit
+// segment after them start 16-byte aligned.  The stencil entries are the
+// staged point's local index times fwd_offset_unit: 4e in 2D (the forward
+// slot), 2e in 3D (the first array's slot; the others are reached by a shift).
+__host__ __device__ inline size_t elem_bytes(bool f64) { return f64 ? 8 : 4; }
+__host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 4 : 6); }
+__host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 8 : 9); }
+__host__ __device__ inline size_t fwd_offset_unit(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 4 : 2); }
 __host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, int seg)
 {
     return (size_t)round_up(staged, 4) * slot_bytes + (size_t)seg * 2;
@@ -84,6 +93,9 @@ struct BatchCall {
 
 // Work item of the batched queue: mesh in the top 8 bits, tile in the low 24.
 constexpr int kItemTileBits = 24;
+// The batched kernel keeps its queue word in the first bytes of its dynamic
+// LDS and the tile's staged data after them.
+constexpr uint32_t kBatchedLdsHead = 16;
 
 // Launch helpers implemented in ftle_kernels.hip.  All return hipSuccess or
 // the launch error.  lds_bytes() gives the dynamic LDS a launch needs.

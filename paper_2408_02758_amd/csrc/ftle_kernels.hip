@@ -50,6 +50,42 @@ template <typename T> using vec4_t = typename Vec4<T>::type;
 
 template <typename T> struct Packed3 { T a, b, c; };
 
+// LDS by byte address.  No kernel here declares static LDS: all of it is the
+// dynamic allocation, which then starts at LDS address 0, so staged data have
+// plain 32-bit addresses whose constant parts fold into the instruction's
+// offset field.  Vectors move as native (ext_vector_type) vectors.
+template <typename T, int N> using native_vec = T __attribute__((ext_vector_type(N)));
+template <typename V> struct LdsIo {   // scalars
+    __device__ static V ld(uint32_t a) { return *(const __attribute__((address_space(3))) V*)(size_t)a; }
+    __device__ static void st(uint32_t a, const V v) { *(__attribute__((address_space(3))) V*)(size_t)a = v; }
+};
+template <typename T> struct LdsIo<HIP_vector_type<T, 2>> {
+    using N = native_vec<T, 2>;
+    __device__ static HIP_vector_type<T, 2> ld(uint32_t a)
+    {
+        const N v = *(const __attribute__((address_space(3))) N*)(size_t)a;
+        return HIP_vector_type<T, 2>{v[0], v[1]};
+    }
+    __device__ static void st(uint32_t a, const HIP_vector_type<T, 2> v)
+    {
+        *(__attribute__((address_space(3))) N*)(size_t)a = N{v.x, v.y};
+    }
+};
+template <typename T> struct LdsIo<HIP_vector_type<T, 4>> {
+    using N = native_vec<T, 4>;
+    __device__ static HIP_vector_type<T, 4> ld(uint32_t a)
+    {
+        const N v = *(const __attribute__((address_space(3))) N*)(size_t)a;
+        return HIP_vector_type<T, 4>{v[0], v[1], v[2], v[3]};
+    }
+    __device__ static void st(uint32_t a, const HIP_vector_type<T, 4> v)
+    {
+        *(__attribute__((address_space(3))) N*)(size_t)a = N{v.x, v.y, v.z, v.w};
+    }
+};
+template <typename V> __device__ inline V lds_ld(uint32_t a) { return LdsIo<V>::ld(a); }
+template <typename V> __device__ inline void lds_st(uint32_t a, const V v) { LdsIo<V>::st(a, v); }
+
 // Precision-explicit math (no silent promotion of float code to double).
 // The float versions use the hardware reciprocal, square root and base-2
 // logarithm (about 1 ulp): the Jacobian and eigenvalue they feed already
@@ -101,20 +137,22 @@ __device__ inline int xcd_tile(int bid, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Staged slots in LDS (slot l holds point idx[l]; strides as in
-// fwd_slot_bytes / bwd_slot_bytes):
-//   forward 2D (4 values):  (x0, x1, phi0, phi1)
-//   forward 3D (8 values):  (x0, x1, x2, phi0) (phi1, phi2, -, -)
-//   adjoint 2D (8 values):  (x0, x1, w0, w1) (h0, h1, -, -)
-//   adjoint 3D (12 values): (x0, x1, x2, h0) (h1, h2, w0, w1) (w2, -, -, -)
-// The stencil stores forward byte offsets o = l * fwd stride; the adjoint
-// offset is 2 o (2D) or 3 o / 2 (3D).  The tile's 16-bit segment follows the
-// slots: the padded stencil (offsets, nnz entries), then the P row ends.
+// Staged points in LDS.  Staged point l (point idx[l]) has the stencil entry
+// o = l * unit; with e = sizeof(T) and R = round_up(P + H, 4):
+//   forward 2D: (x0, x1, phi0, phi1) at o                     (unit 4e)
+//   forward 3D: (phi1, phi2) at o, (x0, x1, x2, phi0) at
+//               2 o + 2eR                                     (unit 2e)
+//   adjoint 2D: (x0, x1, w0, w1) (h0, h1, -, -) at 2 o
+//   adjoint 3D: w2 at o / 2, (x0, x1, x2, h0) (h1, h2, w0, w1) at 4 o + eR
+// so that 16-byte reads are 16-byte aligned, no LDS is padding in 3D, and
+// neighbouring points sit in neighbouring banks.  The tile's 16-bit segment
+// follows: the padded stencil (nnz entries), then the P row ends.
 // ---------------------------------------------------------------------------
 template <int D, typename T> struct Layout {
-    static constexpr uint32_t fwd = (D == 2 ? 4 : 8) * sizeof(T);
-    static constexpr uint32_t bwd = (D == 2 ? 8 : 12) * sizeof(T);
-    __device__ static uint32_t bwd_off(uint32_t o) { return D == 2 ? 2 * o : o + (o >> 1); }
+    static constexpr uint32_t e = sizeof(T);
+    static constexpr uint32_t unit = (D == 2 ? 4 : 2) * e;
+    static constexpr uint32_t fwd = (D == 2 ? 4 : 6) * e;   // LDS bytes per staged point
+    static constexpr uint32_t bwd = (D == 2 ? 8 : 9) * e;
 };
 
 // Copy of a tile's 16-bit segment (n16 chunks of 16 bytes) into LDS as a
@@ -124,13 +162,13 @@ template <int D, typename T> struct Layout {
 // other loads.  The caller waits (vmcnt 0) and synchronises the workgroup
 // before reading dst.
 template <int B>
-__device__ inline void dma_segment(const uint4* __restrict__ src, uint4* dst, int n16)
+__device__ inline void dma_segment(const uint4* __restrict__ src, uint32_t dst, int n16)
 {
     const int lane = (int)threadIdx.x & 63;
     for (int c0 = (int)threadIdx.x - lane; c0 < n16; c0 += B) {   // wave-uniform chunk base
         if (c0 + lane < n16)
-            __builtin_amdgcn_global_load_lds(src + c0 + lane, (__attribute__((address_space(3))) void*)(dst + c0),
-                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds(src + c0 + lane,
+                                             (__attribute__((address_space(3))) void*)(size_t)(dst + 16u * c0), 16, 0, 0);
     }
 }
 
@@ -157,15 +195,15 @@ __device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
 // LDS loads of offset pairs, then the four slot loads, then the arithmetic),
 // with a final pair.  visit(o...) gets the neighbours' byte offsets.
 template <typename F>
-__device__ inline void walk_row(const uint32_t* __restrict__ pairs, int s, int e, F&& visit)
+__device__ inline void walk_row(uint32_t pairs, int s, int e, F&& visit)
 {
     int k = s;
     for (; k + 4 <= e; k += 4) {
-        const uint32_t w0 = pairs[k >> 1], w1 = pairs[(k >> 1) + 1];
+        const uint32_t w0 = lds_ld<uint32_t>(pairs + 2u * k), w1 = lds_ld<uint32_t>(pairs + 2u * k + 4u);
         visit(w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16);
     }
     if (k < e) {
-        const uint32_t w0 = pairs[k >> 1];
+        const uint32_t w0 = lds_ld<uint32_t>(pairs + 2u * k);
         visit(w0 & 0xffffu, w0 >> 16);
     }
 }
@@ -255,7 +293,7 @@ __device__ __noinline__ float lam_max3_f64_from_J(float j00, float j01, float j0
 // ---------------------------------------------------------------------------
 template <int D, typename T, int B, bool WIDE, int K>
 __device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
-                                 const T* __restrict__ flow, int S, int r0, unsigned char* lds)
+                                 const T* __restrict__ flow, int S, int r0, uint32_t lds0)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
@@ -273,8 +311,8 @@ __device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __re
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int l = min(base + k * B, S - 1);
-            *reinterpret_cast<V4*>(lds + (uint32_t)l * L::fwd) = V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y};
+            const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
+            lds_st(lds0 + o, V4{xv[k].x, xv[k].y, fv[k].x, fv[k].y});
         }
     } else {
         Packed3<T> xv[K], fv[K];
@@ -283,12 +321,12 @@ __device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __re
             xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
             fv[k] = rec_at<WIDE, Packed3<T>>(flow, u[k], sizeof(Packed3<T>));
         }
+        const uint32_t abase = lds0 + (uint32_t)round_up(S, 4) * 2 * sizeof(T);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int l = min(base + k * B, S - 1);
-            unsigned char* slot = lds + (uint32_t)l * L::fwd;
-            *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a};
-            *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{fv[k].b, fv[k].c};
+            const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
+            lds_st(2 * o + abase, V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a});
+            lds_st(lds0 + o, V2{fv[k].b, fv[k].c});
         }
     }
 }
@@ -321,7 +359,7 @@ template <int D, typename T, bool OUT, bool TAPE, int B, bool WIDE>
 __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
                                          const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
                                          T* __restrict__ out, T* __restrict__ tape, const int64_t n,
-                                         const float eig_tau, unsigned long long* hits, unsigned char* lds)
+                                         const float eig_tau, unsigned long long* hits, const uint32_t lds0)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
@@ -330,25 +368,25 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     const int S = P + H;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)round_up(S, 4) * L::fwd);
-    const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
-    const uint16_t* rowend = seg + nnz;
+    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the segment
+    const uint32_t pairs = seg, rowend = seg + 2u * nnz;
 
     // The stencil segment goes straight to LDS first; then the staged points
     // in rounds of K slots per thread (fwd_stage).
-    dma_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    stage_points<B>(S, [&](auto kc, int r0) { fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds); });
+    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nnz) / 8));
+    stage_points<B>(S, [&](auto kc, int r0) { fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds0); });
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
 
+    const uint32_t abase = lds0 + (uint32_t)round_up(S, 4) * 2 * sizeof(T);   // 3D: (x0, x1, x2, phi0) array
     for (int l = threadIdx.x; l < P; l += B) {
-        const int s = l ? rowend[l - 1] : 0;
-        const int e = rowend[l];
+        const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
+        const int e = lds_ld<uint16_t>(rowend + 2u * l);
         const uint32_t u = idx[l];
-        const unsigned char* self = lds + (size_t)l * L::fwd;
+        const uint32_t oself = (uint32_t)l * L::unit;
         T f;
         if constexpr (D == 2) {
-            const V4 c0 = *reinterpret_cast<const V4*>(self);
+            const V4 c0 = lds_ld<V4>(lds0 + oself);
             T m00 = 0, m01 = 0, m11 = 0, b00 = 0, b01 = 0, b10 = 0, b11 = 0, s0 = 0, s1 = 0;
             auto acc = [&](const V4 q) {
                 const T dx0 = q.x - c0.x, dx1 = q.y - c0.y;
@@ -365,7 +403,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                     s1 += dx1;
                 }
             };
-            auto at = [&](uint32_t o) { return *reinterpret_cast<const V4*>(lds + o); };
+            auto at = [&](uint32_t o) { return lds_ld<V4>(lds0 + o); };
             walk_row(pairs, s, e, [&](auto... o) {
                 const V4 q[] = {at(o)...};
                 for (const V4& v : q) acc(v);
@@ -402,8 +440,8 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                 rec_put<WIDE>(tape + (size_t)n * 4, u, sizeof(T), h0 * s0 + h1 * s1);
             }
         } else {
-            const V4 c0 = *reinterpret_cast<const V4*>(self);
-            const V2 c1 = *reinterpret_cast<const V2*>(self + 4 * sizeof(T));
+            const V4 c0 = lds_ld<V4>(2 * oself + abase);
+            const V2 c1 = lds_ld<V2>(lds0 + oself);
             T m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
             T b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b12 = 0, b20 = 0, b21 = 0, b22 = 0;
             T s0 = 0, s1 = 0, s2 = 0;
@@ -435,9 +473,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                     s2 += dx2;
                 }
             };
-            auto at = [&](uint32_t o) {
-                return Q{*reinterpret_cast<const V4*>(lds + o), *reinterpret_cast<const V2*>(lds + o + 4 * sizeof(T))};
-            };
+            auto at = [&](uint32_t o) { return Q{lds_ld<V4>(2 * o + abase), lds_ld<V2>(lds0 + o)}; };
             walk_row(pairs, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
                 for (const Q& v : q) acc(v);
@@ -522,10 +558,8 @@ __global__ void __launch_bounds__(B) fwd_kernel(const TileMeta* __restrict__ met
                                                   T inv2T, T* __restrict__ out, T* __restrict__ tape,
                                                   int64_t n, float eig_tau, unsigned long long* hits)
 {
-    extern __shared__ uint4 lds_raw[];
     const int t = xcd_tile(blockIdx.x, n_tiles);
-    fwd_tile<D, T, OUT, TAPE, B, WIDE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits,
-                                       reinterpret_cast<unsigned char*>(lds_raw));
+    fwd_tile<D, T, OUT, TAPE, B, WIDE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits, 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,8 +572,7 @@ __global__ void __launch_bounds__(B) fwd_kernel(const TileMeta* __restrict__ met
 // point idx[l] (g non-finite -> 0).
 template <int D, typename T, int B, bool WIDE, int K>
 __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
-                                 const T* __restrict__ tape, const T* __restrict__ g, int S, int r0,
-                                 unsigned char* lds)
+                                 const T* __restrict__ tape, const T* __restrict__ g, int S, int r0)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
@@ -560,11 +593,10 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int l = min(base + k * B, S - 1);
+            const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
             const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-            unsigned char* slot = lds + (uint32_t)l * L::bwd;
-            *reinterpret_cast<V4*>(slot) = V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y};
-            *reinterpret_cast<V2*>(slot + 4 * sizeof(T)) = V2{tv[k].z, tv[k].w};
+            lds_st(2 * o, V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y});
+            lds_st(2 * o + 4 * sizeof(T), V2{tv[k].z, tv[k].w});
         }
     } else {
         Packed3<T> xv[K], pv[K], hv[K];
@@ -575,14 +607,14 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
             pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
             hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
         }
+        const uint32_t cbase = (uint32_t)round_up(S, 4) * sizeof(T);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int l = min(base + k * B, S - 1);
+            const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
             const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-            unsigned char* slot = lds + (uint32_t)l * L::bwd;
-            *reinterpret_cast<V4*>(slot) = V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a};
-            *reinterpret_cast<V4*>(slot + 4 * sizeof(T)) = V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b};
-            *reinterpret_cast<T*>(slot + 8 * sizeof(T)) = gg * pv[k].c;
+            lds_st(4 * o + cbase, V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a});
+            lds_st(4 * o + cbase + 4 * sizeof(T), V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b});
+            lds_st(o >> 1, gg * pv[k].c);
         }
     }
 }
@@ -597,39 +629,34 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    extern __shared__ uint4 lds_raw[];
-    unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
     const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
     const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
     const int S = P + H;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-    uint16_t* seg = reinterpret_cast<uint16_t*>(lds + (size_t)round_up(S, 4) * L::bwd);
-    const uint32_t* pairs = reinterpret_cast<const uint32_t*>(seg);
-    const uint16_t* rowend = seg + nnz;
+    const uint32_t seg = (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment (LDS starts at 0)
+    const uint32_t pairs = seg, rowend = seg + 2u * nnz;
 
-    dma_segment<B>(segsrc, reinterpret_cast<uint4*>(seg), (int)(seg_halfs(P, nnz) / 8));
-    stage_points<B>(S, [&](auto kc, int r0) { bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0, lds); });
+    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nnz) / 8));
+    stage_points<B>(S, [&](auto kc, int r0) { bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0); });
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
 
+    const uint32_t cbase = (uint32_t)round_up(S, 4) * sizeof(T);   // 3D: the 8-value slots
     for (int l = threadIdx.x; l < P; l += B) {
-        const int s = l ? rowend[l - 1] : 0;
-        const int e = rowend[l];
+        const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
+        const int e = lds_ld<uint16_t>(rowend + 2u * l);
         const uint32_t u = idx[l];
         const T sig = rec_at<WIDE, T>(tape + (size_t)n * (2 * D), u, sizeof(T));
-        const unsigned char* self = lds + (size_t)l * L::bwd;
+        const uint32_t oself = (uint32_t)l * L::unit;
         if constexpr (D == 2) {
-            const V4 cj = *reinterpret_cast<const V4*>(self);
+            const V4 cj = lds_ld<V4>(2 * oself);
             T a0 = 0, a1 = 0;
             struct Q {
                 V4 a;
                 V2 h;
             };
-            auto at = [&](uint32_t o) {
-                const unsigned char* q = lds + L::bwd_off(o);
-                return Q{*reinterpret_cast<const V4*>(q), *reinterpret_cast<const V2*>(q + 4 * sizeof(T))};
-            };
+            auto at = [&](uint32_t o) { return Q{lds_ld<V4>(2 * o), lds_ld<V2>(2 * o + 4 * sizeof(T))}; };
             walk_row(pairs, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
                 for (const Q& v : q) {
@@ -641,18 +668,16 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
             });
             rec_put<WIDE>(grad, u, sizeof(V2), V2{a0 - sig * cj.z, a1 - sig * cj.w});
         } else {
-            const V4 cj = *reinterpret_cast<const V4*>(self);
-            const V4 cb = *reinterpret_cast<const V4*>(self + 4 * sizeof(T));
-            const T cw2 = *reinterpret_cast<const T*>(self + 8 * sizeof(T));
+            const V4 cj = lds_ld<V4>(4 * oself + cbase);
+            const V4 cb = lds_ld<V4>(4 * oself + cbase + 4 * sizeof(T));
+            const T cw2 = lds_ld<T>(oself >> 1);
             T a0 = 0, a1 = 0, a2 = 0;
             struct Q {
                 V4 a, b;
                 T c;
             };
             auto at = [&](uint32_t o) {
-                const unsigned char* q = lds + L::bwd_off(o);
-                return Q{*reinterpret_cast<const V4*>(q), *reinterpret_cast<const V4*>(q + 4 * sizeof(T)),
-                         *reinterpret_cast<const T*>(q + 8 * sizeof(T))};
+                return Q{lds_ld<V4>(4 * o + cbase), lds_ld<V4>(4 * o + cbase + 4 * sizeof(T)), lds_ld<T>(o >> 1)};
             };
             walk_row(pairs, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
@@ -684,9 +709,6 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict_
                                                       int tiles_per_pop, unsigned* queue,
                                                       BatchCall call, float eig_tau)
 {
-    extern __shared__ uint4 lds_raw[];
-    __shared__ int sh_base;
-    unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
     if (tiles_per_pop == 0) {
         // flat launch: one work item per workgroup, dealt XCD-contiguously
         const uint32_t item = __builtin_amdgcn_readfirstlane(items[xcd_tile(blockIdx.x, n_items)]);
@@ -695,13 +717,14 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict_
         const BatchMesh bm = meshes[mk];
         fwd_tile<D, T, true, false, B, WIDE>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
                                              static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
-                                             static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau, bm.fp64_hits, lds);
+                                             static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau, bm.fp64_hits,
+                                             kBatchedLdsHead);
         return;
     }
     for (;;) {
-        if (threadIdx.x == 0) sh_base = (int)atomicAdd(&queue[0], (unsigned)tiles_per_pop);
+        if (threadIdx.x == 0) lds_st(0u, (int)atomicAdd(&queue[0], (unsigned)tiles_per_pop));
         __syncthreads();
-        const int base = sh_base;
+        const int base = lds_ld<int>(0u);
         __syncthreads();
         if (base >= n_items) break;
         const int lim = min(base + tiles_per_pop, n_items);
@@ -713,7 +736,7 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict_
             fwd_tile<D, T, true, false, B, WIDE>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
                                         static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
                                         static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau,
-                                        bm.fp64_hits, lds);
+                                        bm.fp64_hits, kBatchedLdsHead);
             __syncthreads();
         }
     }
