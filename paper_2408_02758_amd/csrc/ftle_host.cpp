@@ -946,8 +946,7 @@ struct BatchPlan {
     bool wide = false;   // 64-bit element offsets (some mesh is that large)
     int device = -1;
     std::vector<ftle_mesh_t> meshes;
-    void* d_meshes = nullptr;     // BatchMesh[n]
-    void* d_items = nullptr;      // uint32 items
+    void* d_items = nullptr;      // BatchItem[n_items], costliest tiles first
     unsigned* d_queue = nullptr;  // 2 counters
     int n_items = 0;
     size_t lds = 0;
@@ -959,7 +958,7 @@ struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node = nullptr;
     std::vector<unsigned char> arg_storage;
-    void* args[7] = {};
+    void* args[6] = {};
     BatchCall last{};          // arguments the graph node holds now
 };
 
@@ -976,40 +975,42 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
     p->dim = meshes[0]->dim;
     p->f64 = meshes[0]->f64();
     p->device = meshes[0]->device;
-    std::vector<BatchMesh> bm(n);
     DevTiles maxt{};
     struct Item {
-        uint32_t item;
+        BatchItem it;
         uint32_t cost;
     };
     std::vector<Item> items;
     uint32_t max_cost = 1;
     for (int k = 0; k < n; ++k) {
         const ftle_mesh_t m = meshes[k];
-        bm[k].tiles = m->fwd.dev();
-        bm[k].x = m->d_x;
-        bm[k].fp64_hits = m->d_hits;
         p->wide = p->wide || batched_needs_wide(p->dim, p->f64, m->n);
         maxt.max_staged = std::max(maxt.max_staged, m->fwd.max_staged);
         maxt.max_seg = std::max(maxt.max_seg, m->fwd.max_seg);
-        if (m->fwd.meta.size() >= (1u << kItemTileBits)) fail(FTLE_ERR_UNSUPPORTED, "mesh has too many tiles for a batch");
+        const DevTiles dt = m->fwd.dev();
         for (size_t t = 0; t < m->fwd.meta.size(); ++t) {
             const TileMeta& tm = m->fwd.meta[t];
-            const uint32_t cost = tm.nnz + tm.P + tm.H;
-            items.push_back({((uint32_t)k << kItemTileBits) | (uint32_t)t, cost});
-            max_cost = std::max(max_cost, cost);
+            Item e{};
+            e.it.meta = tm;
+            e.it.rec = dt.rec;
+            e.it.x = m->d_x;
+            e.it.fp64_hits = m->d_hits;
+            e.it.mesh = (uint32_t)k;
+            e.cost = tm.nnz + tm.P + tm.H;
+            items.push_back(e);
+            max_cost = std::max(max_cost, e.cost);
         }
     }
+    if (items.size() > (size_t)INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "too many tiles for one batch");
     // costliest first (in eighths of the largest tile), natural order within a bucket
     std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
         return (a.cost * 8ull / (max_cost + 1)) > (b.cost * 8ull / (max_cost + 1));
     });
-    std::vector<uint32_t> it32(items.size());
-    for (size_t i = 0; i < items.size(); ++i) it32[i] = items[i].item;
-    p->n_items = (int)it32.size();
+    std::vector<BatchItem> flat(items.size());
+    for (size_t i = 0; i < items.size(); ++i) flat[i] = items[i].it;
+    p->n_items = (int)flat.size();
     p->lds = fwd_lds_bytes(p->dim, p->f64, maxt) + kBatchedLdsHead;
-    p->d_meshes = dev_upload(bm.data(), bm.size() * sizeof(BatchMesh));
-    p->d_items = dev_upload(it32.data(), it32.size() * sizeof(uint32_t));
+    p->d_items = dev_upload(flat.data(), flat.size() * sizeof(BatchItem));
     p->d_queue = static_cast<unsigned*>(dev_upload(nullptr, 2 * sizeof(unsigned)));
     check_hip(hipMemset(p->d_queue, 0, 2 * sizeof(unsigned)), "hipMemset");
     check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -1049,9 +1050,8 @@ void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
                 float tot = 0.f;
                 for (int rep = 0; rep < 4; ++rep) {
                     check_hip(hipEventRecord(e0, s), "hipEventRecord");
-                    check_hip(launch_batched(p->dim, p->f64, p->wide, static_cast<const BatchMesh*>(p->d_meshes),
-                                             static_cast<const uint32_t*>(p->d_items), p->n_items, k, p->d_queue,
-                                             call, p->lds, eig_tau(), b, grid, s),
+                    check_hip(launch_batched(p->dim, p->f64, p->wide, static_cast<const BatchItem*>(p->d_items),
+                                             p->n_items, k, p->d_queue, call, p->lds, eig_tau(), b, grid, s),
                               "batched launch");
                     check_hip(hipEventRecord(e1, s), "hipEventRecord");
                     check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -1077,8 +1077,8 @@ void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
 void build_graph(BatchPlan* p, const BatchCall& call)
 {
     p->arg_storage.resize(batched_kernel_arg_storage());
-    batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
-                        p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(), p->args);
+    batched_kernel_args(static_cast<const BatchItem*>(p->d_items), p->n_items, p->tiles_per_pop, p->d_queue, call,
+                        eig_tau(), p->arg_storage.data(), p->args);
     check_hip(hipGraphCreate(&p->graph, 0), "hipGraphCreate");
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
@@ -1095,7 +1095,6 @@ void free_plan(BatchPlan* p)
 {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->d_meshes) (void)hipFree(p->d_meshes);
     if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_queue) (void)hipFree(p->d_queue);
 }
@@ -1165,9 +1164,8 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
         }
         if (std::memcmp(&p->last, &call, sizeof(BatchCall)) != 0) {
             // new pointers or times: update the graph's kernel node in place
-            batched_kernel_args(static_cast<const BatchMesh*>(p->d_meshes), static_cast<const uint32_t*>(p->d_items),
-                                p->n_items, p->tiles_per_pop, p->d_queue, call, eig_tau(), p->arg_storage.data(),
-                                p->args);
+            batched_kernel_args(static_cast<const BatchItem*>(p->d_items), p->n_items, p->tiles_per_pop, p->d_queue,
+                                call, eig_tau(), p->arg_storage.data(), p->args);
             hipKernelNodeParams kp{};
             kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
             kp.gridDim = dim3(p->grid);

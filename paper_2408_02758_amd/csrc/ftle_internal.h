@@ -76,12 +76,17 @@ struct DevTiles {
     int max_seg;      // max over tiles of seg_halfs(P, nnz)
 };
 
-// Per-mesh parameters of a batched launch that do not change between calls.
-struct BatchMesh {
-    DevTiles tiles;
-    const void* x;
-    unsigned long long* fp64_hits;
+// One work item of a batched launch: a tile of one mesh, with everything the
+// workgroup needs to start on it (one 48-byte scalar load).
+struct BatchItem {
+    TileMeta meta;                  // rec_off relative to rec
+    const uint4* rec;               // the mesh's tile records
+    const void* x;                  // the mesh's coordinates
+    unsigned long long* fp64_hits;  // the mesh's FP64-branch counter
+    uint32_t mesh;                  // index into the call's flow/out/time arrays
+    uint32_t pad;
 };
+static_assert(sizeof(BatchItem) == 48, "BatchItem is 48 bytes");
 
 // Per-call parameters of a batched launch (kernel argument by value).
 constexpr int kMaxBatch = 64;
@@ -91,8 +96,6 @@ struct BatchCall {
     double inv2T[kMaxBatch];
 };
 
-// Work item of the batched queue: mesh in the top 8 bits, tile in the low 24.
-constexpr int kItemTileBits = 24;
 // The batched kernel keeps its queue word in the first bytes of its dynamic
 // LDS and the tile's staged data after them.
 constexpr uint32_t kBatchedLdsHead = 16;
@@ -113,18 +116,17 @@ hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, cons
 // Block sizes (threads per workgroup) the kernels are compiled for.
 inline bool supported_block(int b) { return b == 128 || b == 256 || b == 512; }
 
-hipError_t launch_batched(int dim, bool f64, bool wide, const BatchMesh* meshes, const uint32_t* items,
-                          int n_items, int tiles_per_pop, unsigned* queue, const BatchCall& call,
-                          size_t lds, double eig_tau, int block, int grid, hipStream_t stream);
+hipError_t launch_batched(int dim, bool f64, bool wide, const BatchItem* items, int n_items, int tiles_per_pop,
+                          unsigned* queue, const BatchCall& call, size_t lds, double eig_tau, int block, int grid,
+                          hipStream_t stream);
 
 // The kernel a batched launch runs (for occupancy queries and graph nodes);
 // nullptr for an unsupported block size.  wide: 64-bit element offsets, needed
 // when some mesh of the batch has batched_needs_wide(dim, f64, n).
 const void* batched_kernel_symbol(int dim, bool f64, int block, bool wide);
 bool batched_needs_wide(int dim, bool f64, int64_t max_points);
-void batched_kernel_args(const BatchMesh* meshes, const uint32_t* items, int n_items,
-                         int tiles_per_pop, unsigned* queue, const BatchCall& call,
-                         double eig_tau, void* storage, void** args);
+void batched_kernel_args(const BatchItem* items, int n_items, int tiles_per_pop, unsigned* queue,
+                         const BatchCall& call, double eig_tau, void* storage, void** args);
 size_t batched_kernel_arg_storage();
 
 }  // namespace ftle

@@ -551,12 +551,13 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     }
 }
 
+// float: at most 64 VGPRs (8 waves per SIMD), so that the LDS, not the
+// registers, bounds the workgroups per CU; the tape variant needs the hint.
 template <int D, typename T, bool OUT, bool TAPE, int B, bool WIDE>
-__global__ void __launch_bounds__(B) fwd_kernel(const TileMeta* __restrict__ meta,
-                                                  const uint4* __restrict__ rec, int n_tiles,
-                                                  const T* __restrict__ x, const T* __restrict__ flow,
-                                                  T inv2T, T* __restrict__ out, T* __restrict__ tape,
-                                                  int64_t n, float eig_tau, unsigned long long* hits)
+__global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
+fwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int n_tiles, const T* __restrict__ x,
+           const T* __restrict__ flow, T inv2T, T* __restrict__ out, T* __restrict__ tape, int64_t n, float eig_tau,
+           unsigned long long* hits)
 {
     const int t = xcd_tile(blockIdx.x, n_tiles);
     fwd_tile<D, T, OUT, TAPE, B, WIDE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits, 0u);
@@ -704,20 +705,18 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
 //  - flat (tiles_per_pop == 0): one workgroup per item (grid = n_items).
 // ---------------------------------------------------------------------------
 template <int D, typename T, int B, bool WIDE>
-__global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict__ meshes,
-                                                      const uint32_t* __restrict__ items, int n_items,
+__global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict__ items, int n_items,
                                                       int tiles_per_pop, unsigned* queue,
                                                       BatchCall call, float eig_tau)
 {
+    // (the call's arrays are indexed here, in the kernel body, so that they
+    // are read from the kernel arguments and never copied)
     if (tiles_per_pop == 0) {
         // flat launch: one work item per workgroup, dealt XCD-contiguously
-        const uint32_t item = __builtin_amdgcn_readfirstlane(items[xcd_tile(blockIdx.x, n_items)]);
-        const int mk = (int)(item >> kItemTileBits);
-        const int t = (int)(item & ((1u << kItemTileBits) - 1));
-        const BatchMesh bm = meshes[mk];
-        fwd_tile<D, T, true, false, B, WIDE>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
-                                             static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
-                                             static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau, bm.fp64_hits,
+        const BatchItem it = items[xcd_tile(blockIdx.x, n_items)];
+        fwd_tile<D, T, true, false, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
+                                             static_cast<const T*>(call.flow[it.mesh]), (T)call.inv2T[it.mesh],
+                                             static_cast<T*>(call.out[it.mesh]), nullptr, 0, eig_tau, it.fp64_hits,
                                              kBatchedLdsHead);
         return;
     }
@@ -728,15 +727,12 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchMesh* __restrict_
         __syncthreads();
         if (base >= n_items) break;
         const int lim = min(base + tiles_per_pop, n_items);
-        for (int it = base; it < lim; ++it) {
-            const uint32_t item = __builtin_amdgcn_readfirstlane(items[it]);
-            const int mk = (int)(item >> kItemTileBits);
-            const int t = (int)(item & ((1u << kItemTileBits) - 1));
-            const BatchMesh bm = meshes[mk];
-            fwd_tile<D, T, true, false, B, WIDE>(bm.tiles.meta[t], bm.tiles.rec, static_cast<const T*>(bm.x),
-                                        static_cast<const T*>(call.flow[mk]), (T)call.inv2T[mk],
-                                        static_cast<T*>(call.out[mk]), nullptr, 0, eig_tau,
-                                        bm.fp64_hits, kBatchedLdsHead);
+        for (int i = base; i < lim; ++i) {
+            const BatchItem it = items[i];
+            fwd_tile<D, T, true, false, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
+                                                 static_cast<const T*>(call.flow[it.mesh]), (T)call.inv2T[it.mesh],
+                                                 static_cast<T*>(call.out[it.mesh]), nullptr, 0, eig_tau,
+                                                 it.fp64_hits, kBatchedLdsHead);
             __syncthreads();
         }
     }
@@ -846,8 +842,7 @@ hipError_t bwd_launch(const DevTiles& tiles, const void* x, const void* tape, in
 }
 
 struct BatchArgs {
-    const BatchMesh* meshes;
-    const uint32_t* items;
+    const BatchItem* items;
     int n_items;
     int tiles_per_pop;
     unsigned* queue;
@@ -921,36 +916,33 @@ bool batched_needs_wide(int dim, bool f64, int64_t max_points)
 
 size_t batched_kernel_arg_storage() { return sizeof(BatchArgs); }
 
-void batched_kernel_args(const BatchMesh* meshes, const uint32_t* items, int n_items, int tiles_per_pop,
-                         unsigned* queue, const BatchCall& call, double eig_tau, void* storage,
-                         void** args)
+void batched_kernel_args(const BatchItem* items, int n_items, int tiles_per_pop, unsigned* queue,
+                         const BatchCall& call, double eig_tau, void* storage, void** args)
 {
     BatchArgs* a = static_cast<BatchArgs*>(storage);
-    a->meshes = meshes;
     a->items = items;
     a->n_items = n_items;
     a->tiles_per_pop = tiles_per_pop;
     a->queue = queue;
     a->call = call;
     a->eig_tau = (float)eig_tau;
-    args[0] = &a->meshes;
-    args[1] = &a->items;
-    args[2] = &a->n_items;
-    args[3] = &a->tiles_per_pop;
-    args[4] = &a->queue;
-    args[5] = &a->call;
-    args[6] = &a->eig_tau;
+    args[0] = &a->items;
+    args[1] = &a->n_items;
+    args[2] = &a->tiles_per_pop;
+    args[3] = &a->queue;
+    args[4] = &a->call;
+    args[5] = &a->eig_tau;
 }
 
-hipError_t launch_batched(int dim, bool f64, bool wide, const BatchMesh* meshes, const uint32_t* items,
-                          int n_items, int tiles_per_pop, unsigned* queue, const BatchCall& call, size_t lds,
-                          double eig_tau, int block, int grid, hipStream_t stream)
+hipError_t launch_batched(int dim, bool f64, bool wide, const BatchItem* items, int n_items, int tiles_per_pop,
+                          unsigned* queue, const BatchCall& call, size_t lds, double eig_tau, int block, int grid,
+                          hipStream_t stream)
 {
     const void* k = batched_kernel_symbol(dim, f64, block, wide);
     if (!k) return hipErrorInvalidValue;
     BatchArgs storage;
-    void* args[7];
-    batched_kernel_args(meshes, items, n_items, tiles_per_pop, queue, call, eig_tau, &storage, args);
+    void* args[6];
+    batched_kernel_args(items, n_items, tiles_per_pop, queue, call, eig_tau, &storage, args);
     return hipLaunchKernel(k, dim3(grid), dim3(block), args, lds, stream);
 }
 
