@@ -78,7 +78,8 @@ enum {
     FTLE_HOST_ONLY = 1 << 5
 };
 /* Points per tile (one workgroup's share): FTLE_TILE(k) asks for 2^k points,
- * 5 <= k <= 11; 0 selects the default (1024 in 2D, 512 in 3D). */
+ * 5 <= k <= 11; 0 selects the default, 512.  A tile is halved until its own
+ * and halo points fit 1024 staged slots and 64 KiB of LDS. */
 #define FTLE_TILE(k) ((unsigned)(k) << 8)
 
 /*
@@ -135,15 +136,15 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
  *             the adjoint (the same tiles when S is symmetric, as RING1 is)
  *   n_tiles, record_bytes: sizes (either may be NULL)
  *   meta      host, n_tiles x 16 bytes: per tile uint32 {record offset in
- *             16-byte units, own points P, halo points H, stencil entries nnz}
+ *             16-byte units, own points P, halo points H, stencil words nw}
  *   records   host, record_bytes bytes; per tile: uint32 caller indices of the
  *             P own points (Morton order) then the H halo points, padded to a
- *             multiple of 4; then nnz uint16 stencil entries, each the local
- *             index (position in that index list) times 16 in 2D or 8 in 3D
- *             (doubled for FTLE_F64: byte offsets into the kernels' staged
- *             LDS arrays), with every row padded to even length by the
- *             point's own entry; then P uint16 row ends (cumulative entry
- *             counts); padded to a multiple of 8 uint16
+ *             multiple of 4; then nw uint32 stencil words, each holding three
+ *             10-bit local indices (positions in that index list) in bits
+ *             0-9, 10-19 and 20-29, with every row padded to a multiple of 3
+ *             entries by the point's own index; then P uint16 row ends
+ *             (cumulative word counts); padded to a multiple of 16 bytes.
+ *             P + H <= 1024: larger nominal tiles are split when built.
  * meta and records may be NULL (sizes only).
  */
 ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles, int64_t* record_bytes,

@@ -98,16 +98,12 @@ class Mesh:
         check(_lib.load().ftle_mesh_tile_stats(self._h, *[ctypes.byref(v) for v in vals]))
         return dict(zip(["n_tiles", "max_tile_points", "halo_entries", "record_bytes"], [v.value for v in vals]))
 
-    def slot_stride(self) -> int:
-        """Unit of the tile records' stencil entries (entry = local index * unit):
-        4 values in 2D, 2 in 3D, times the value size."""
-        return (4 if self.dim == 2 else 2) * (8 if self.dtype == "f64" else 4)
-
     def tiles(self, adjoint: bool = False):
-        """Raw tile records: list of (idx uint32[P+H], rowend uint16[P], entries uint16[nnz], P, H).
+        """Raw tile records: list of (idx uint32[P+H], rowend uint16[P], entries uint16[3 nw], P, H).
 
-        entries are local index * slot_stride() (LDS byte offsets of the first
-        staged array), rows padded to even length with the point's own entry."""
+        entries are the neighbours' local indices (positions in idx), three per
+        stencil word, each row padded to a multiple of 3 with the point's own
+        index; rowend counts words."""
         L = _lib.load()
         nt, rb = ctypes.c_int64(), ctypes.c_int64()
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), ctypes.byref(nt), ctypes.byref(rb), None, None))
@@ -115,13 +111,15 @@ class Mesh:
         rec = np.empty(max(rb.value // 4, 1), np.uint32)
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), None, None, meta.ctypes.data, rec.ctypes.data))
         out = []
-        for off, P, H, nnz in meta:
-            P, H, nnz = int(P), int(H), int(nnz)
+        for off, P, H, nw in meta:
+            P, H, nw = int(P), int(H), int(nw)
             base = int(off) * 4
             iw = (P + H + 3) & ~3
             idx = rec[base:base + P + H]
-            seg = rec[base + iw:].view(np.uint16)
-            out.append((idx, seg[nnz:nnz + P], seg[:nnz], P, H))
+            words = rec[base + iw:base + iw + nw]
+            ent = np.stack([words & 0x3FF, (words >> 10) & 0x3FF, words >> 20], 1).reshape(-1).astype(np.uint16)
+            rowend = rec[base + iw + nw:].view(np.uint16)[:P]
+            out.append((idx, rowend, ent, P, H))
         return out
 
     def set_blocks(self, fwd: int = 0, adjoint: int = 0):

@@ -352,7 +352,7 @@ Csr build_axis(int dim, int64_t n, const Csr& ring, const T* xm /* Morton order 
 // ---------------------------------------------------------------------------
 struct TileExtent {
     int64_t begin, end;
-    uint32_t H, nnz;
+    uint32_t H, nw;
 };
 
 // Halo of [b, e): neighbours outside the range, as Morton positions sorted by
@@ -372,18 +372,18 @@ void tile_halo(const Csr& a, const std::vector<int32_t>& perm, int64_t b, int64_
     std::sort(halo.begin(), halo.end(), [&](int32_t u, int32_t v) { return perm[u] < perm[v]; });
 }
 
-// Stencil entries of rows [b, e) once each row is padded to even length.
-int64_t padded_nnz(const Csr& a, int64_t b, int64_t e)
+// Stencil words of rows [b, e): each row padded to a multiple of 3 entries.
+int64_t padded_words(const Csr& a, int64_t b, int64_t e)
 {
     int64_t t = 0;
-    for (int64_t r = b; r < e; ++r) t += (a.row_ptr[r + 1] - a.row_ptr[r] + 1) & ~1;
+    for (int64_t r = b; r < e; ++r) t += (a.row_ptr[r + 1] - a.row_ptr[r] + 2) / 3;
     return t;
 }
 
-bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nnz_padded)
+bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nw)
 {
-    if ((P + H) * (int64_t)fwd_offset_unit(dim, f64) > 65536 || nnz_padded > kMaxTileNnz) return false;
-    const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nnz_padded);
+    if (P + H > kMaxStaged || nw > kMaxTileWords) return false;
+    const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nw);
     const size_t slot = std::max(fwd_slot_bytes(dim, f64), bwd_slot_bytes(dim, f64));
     return tile_lds_bytes(slot, (int)(P + H), seg) <= kLdsBudget;
 }
@@ -409,9 +409,9 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                     tag = 1;
                 }
                 tile_halo(a, perm, b, e, stamp, tag, halo);
-                const int64_t nnz = padded_nnz(a, b, e);
-                if (tile_fits(dim, f64, e - b, (int64_t)halo.size(), nnz)) {
-                    per_chunk[ch].push_back({b, e, (uint32_t)halo.size(), (uint32_t)nnz});
+                const int64_t nw = padded_words(a, b, e);
+                if (tile_fits(dim, f64, e - b, (int64_t)halo.size(), nw)) {
+                    per_chunk[ch].push_back({b, e, (uint32_t)halo.size(), (uint32_t)nw});
                 } else if (e - b == 1) {
                     fail(FTLE_ERR_UNSUPPORTED, "point " + std::to_string(perm[b]) + " has " +
                                                    std::to_string(a.row_ptr[b + 1] - a.row_ptr[b]) +
@@ -433,12 +433,12 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
     uint64_t off = 0;  // in 16-byte units
     for (size_t t = 0; t < ext.size(); ++t) {
         const uint32_t P = (uint32_t)(ext[t].end - ext[t].begin);
-        const uint64_t words = idx_words(P, ext[t].H) + seg_halfs(P, ext[t].nnz) / 2;
+        const uint64_t words = idx_words(P, ext[t].H) + seg_halfs(P, ext[t].nw) / 2;
         if (off > UINT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "tile records exceed 64 GiB");
-        ts.meta[t] = TileMeta{(uint32_t)off, P, ext[t].H, ext[t].nnz};
+        ts.meta[t] = TileMeta{(uint32_t)off, P, ext[t].H, ext[t].nw};
         off += words / 4;
         ts.max_staged = std::max(ts.max_staged, (int)(P + ext[t].H));
-        ts.max_seg = std::max(ts.max_seg, (int)seg_halfs(P, ext[t].nnz));
+        ts.max_seg = std::max(ts.max_seg, (int)seg_halfs(P, ext[t].nw));
         ts.max_P = std::max(ts.max_P, (int)P);
         ts.halo_total += ext[t].H;
     }
@@ -459,9 +459,8 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
             }
             tile_halo(a, perm, b, e, stamp, tag, halo);
             uint32_t* idx = ts.rec.data() + (size_t)m.rec_off * 4;
-            uint16_t* seg = reinterpret_cast<uint16_t*>(idx + idx_words(m.P, m.H));
-            uint16_t* rowend = seg + m.nnz;
-            const uint32_t stride = (uint32_t)fwd_offset_unit(dim, f64);
+            uint32_t* words = idx + idx_words(m.P, m.H);
+            uint16_t* rowend = reinterpret_cast<uint16_t*>(words + m.nw);
             for (int64_t r = b; r < e; ++r) idx[r - b] = (uint32_t)perm[r];
             // halo slot of each halo point: reuse stamp as "slot + 1" storage is
             // not possible (tag), so search in a small map
@@ -471,8 +470,10 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                 hs[h] = {halo[h], (int32_t)(m.P + h)};
             }
             std::sort(hs.begin(), hs.end());
-            uint32_t pos = 0;
+            uint32_t pos = 0;   // words written
             for (int64_t r = b; r < e; ++r) {
+                uint32_t word = 0;
+                int k = 0;   // entries in `word`
                 for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
                     const int32_t c = a.col[p];
                     int32_t loc;
@@ -482,9 +483,17 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                         auto it = std::lower_bound(hs.begin(), hs.end(), std::make_pair(c, INT32_MIN));
                         loc = it->second;
                     }
-                    seg[pos++] = (uint16_t)((uint32_t)loc * stride);
+                    word |= (uint32_t)loc << (10 * k);
+                    if (++k == 3) {
+                        words[pos++] = word;
+                        word = 0;
+                        k = 0;
+                    }
                 }
-                if (pos & 1u) seg[pos++] = (uint16_t)((uint32_t)(r - b) * stride);   // pad with self
+                if (k) {   // pad the row with the point itself
+                    for (; k < 3; ++k) word |= (uint32_t)(r - b) << (10 * k);
+                    words[pos++] = word;
+                }
                 rowend[r - b] = (uint16_t)pos;
             }
         }
@@ -996,7 +1005,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
             e.it.x = m->d_x;
             e.it.fp64_hits = m->d_hits;
             e.it.mesh = (uint32_t)k;
-            e.cost = tm.nnz + tm.P + tm.H;
+            e.cost = 3 * tm.nw + tm.P + tm.H;
             items.push_back(e);
             max_cost = std::max(max_cost, e.cost);
         }

@@ -20,31 +20,34 @@ namespace ftle {
 //                             tile's own P points in Morton order, then its H
 //                             halo points (neighbours owned by other tiles),
 //                             padded to a multiple of 4 entries
-//   uint16 seg[nnz + P]       seg[0..nnz): the stencil rows of the own points,
-//                             each entry the neighbour's local index (its
-//                             position in idx) times fwd_offset_unit; every
-//                             row is padded to even length with the point's
-//                             own entry;
-//                             seg[nnz..nnz+P): end of each row (cumulative,
-//                             in entries); padded to a multiple of 8 entries
+//   uint32 words[nw]          the stencil rows of the own points, three
+//                             10-bit local indices (positions in idx) per
+//                             word, in bits 0-9, 10-19 and 20-29; every row
+//                             is padded to a multiple of 3 entries with the
+//                             point's own index
+//   uint16 rowend[P]          end of each row (cumulative, in words)
+//                             (words and rowend: the "segment", padded to a
+//                             multiple of 16 bytes)
 //
-// 16-bit entries and row ends are enough because (P + H) * fwd_offset_unit
-// <= 65536 and nnz <= kMaxTileNnz, both enforced when the mesh is built.
+// 10-bit indices and 16-bit row ends are enough because P + H <= kMaxStaged
+// and nw <= kMaxTileWords, both enforced when the mesh is built.
 // ---------------------------------------------------------------------------
 struct TileMeta {
     uint32_t rec_off;  // record offset in 16-byte units
     uint32_t P;        // own points
     uint32_t H;        // halo points
-    uint32_t nnz;      // stencil entries of the own points, including row padding
+    uint32_t nw;       // stencil words of the own points (3 entries each, rows padded)
 };
 static_assert(sizeof(TileMeta) == 16, "TileMeta is one 16-byte load");
 
-constexpr int kMaxTileNnz = 65535;     // stencil entries per tile: 16-bit row ends
+constexpr int kMaxStaged = 1024;       // staged points per tile: 10-bit local indices
+constexpr int kMaxTileWords = 65535;   // stencil words per tile: 16-bit row ends
 constexpr size_t kLdsBudget = 65536;   // LDS bytes one tile may stage (forward or adjoint)
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 __host__ __device__ inline uint32_t idx_words(uint32_t P, uint32_t H) { return (P + H + 3u) & ~3u; }
-__host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nnz) { return (P + nnz + 7u) & ~7u; }
+// segment size in 16-bit units (a multiple of 8, i.e. of 16 bytes)
+__host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nw) { return (2u * nw + P + 7u) & ~7u; }
 
 // LDS bytes per staged point, in units of the value size e (4 or 8 bytes):
 //   forward  2D: 4e, one slot (x0, x1, phi0, phi1)
@@ -53,14 +56,11 @@ __host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nnz) { return
 //   adjoint  2D: 8e, one slot (x0, x1, w0, w1) (h0, h1, -, -)
 //            3D: 9e, two arrays: w2 slots of e, then (x0, x1, x2, h0)
 //                (h1, h2, w0, w1) slots of 8e
-// Each array holds round_up(P + H, 4) slots, so every array and the 16-bit
-// segment after them start 16-byte aligned.  The stencil entries are the
-// staged point's local index times fwd_offset_unit: 4e in 2D (the forward
-// slot), 2e in 3D (the first array's slot; the others are reached by a shift).
+// Each array holds round_up(P + H, 4) slots, so every array and the segment
+// after them start 16-byte aligned.
 __host__ __device__ inline size_t elem_bytes(bool f64) { return f64 ? 8 : 4; }
 __host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 4 : 6); }
 __host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 8 : 9); }
-__host__ __device__ inline size_t fwd_offset_unit(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 4 : 2); }
 __host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, int seg)
 {
     return (size_t)round_up(staged, 4) * slot_bytes + (size_t)seg * 2;
@@ -73,7 +73,7 @@ struct DevTiles {
     const uint4* rec;
     int n_tiles;
     int max_staged;   // max over tiles of P + H
-    int max_seg;      // max over tiles of seg_halfs(P, nnz)
+    int max_seg;      // max over tiles of seg_halfs(P, nw)
 };
 
 // One work item of a batched launch: a tile of one mesh, with everything the

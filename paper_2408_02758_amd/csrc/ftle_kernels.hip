@@ -14,11 +14,11 @@
 //    batched gathers, so each value comes from HBM about once, and the
 //    stencil walk reads LDS only.
 //  - The neighbour list (Section 2.2: precomputed on the host, read in a
-//    fixed order) is stored per tile as 16-bit LDS byte offsets of the
-//    neighbours' staged slots: half the bytes of a 32-bit list, streamed once
-//    with 16-byte loads, and no address arithmetic in the walk.  Rows are
-//    padded to even length with the point itself (which adds exact zeros), so
-//    the walk reads two neighbours per 32-bit LDS load.
+//    fixed order) is stored per tile as 10-bit indices of the neighbours'
+//    staged slots, three per 32-bit word: a third of the bytes of a 32-bit
+//    list, copied to LDS once.  Rows are padded to a multiple of three with
+//    the point itself (which adds exact zeros), so the walk reads three
+//    neighbours per 32-bit LDS load with no per-entry branch.
 //  - One lane per point; Jacobian, tensor, eigenvalue and logarithm stay in
 //    registers.  No MFMA: per point the work is a few dozen multiply-adds
 //    over a gathered stencil, not a dense contraction.
@@ -137,16 +137,17 @@ __device__ inline int xcd_tile(int bid, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Staged points in LDS.  Staged point l (point idx[l]) has the stencil entry
-// o = l * unit; with e = sizeof(T) and R = round_up(P + H, 4):
+// Staged points in LDS.  Staged point l (point idx[l]; l is the stencil
+// entry) has o = l * unit; with e = sizeof(T) and R = round_up(P + H, 4):
 //   forward 2D: (x0, x1, phi0, phi1) at o                     (unit 4e)
 //   forward 3D: (phi1, phi2) at o, (x0, x1, x2, phi0) at
 //               2 o + 2eR                                     (unit 2e)
 //   adjoint 2D: (x0, x1, w0, w1) (h0, h1, -, -) at 2 o
 //   adjoint 3D: w2 at o / 2, (x0, x1, x2, h0) (h1, h2, w0, w1) at 4 o + eR
 // so that 16-byte reads are 16-byte aligned, no LDS is padding in 3D, and
-// neighbouring points sit in neighbouring banks.  The tile's 16-bit segment
-// follows: the padded stencil (nnz entries), then the P row ends.
+// neighbouring points sit in neighbouring banks.  The tile's segment follows:
+// the padded stencil (nw words of three 10-bit entries), then the P 16-bit
+// row ends.
 // ---------------------------------------------------------------------------
 template <int D, typename T> struct Layout {
     static constexpr uint32_t e = sizeof(T);
@@ -191,20 +192,24 @@ __device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
         *reinterpret_cast<V*>(reinterpret_cast<unsigned char*>(base) + i * bytes) = v;
 }
 
-// Walk of one row of the padded stencil, four neighbours per step (two 32-bit
-// LDS loads of offset pairs, then the four slot loads, then the arithmetic),
-// with a final pair.  visit(o...) gets the neighbours' byte offsets.
-template <typename F>
-__device__ inline void walk_row(uint32_t pairs, int s, int e, F&& visit)
+// Walk of one row of the padded stencil, WPS words (3 WPS neighbours) per
+// step: the words' LDS loads, then the neighbours' slot loads, then the
+// arithmetic; a final single word.  visit(l...) gets the neighbours' local
+// indices.
+template <int WPS, typename F>
+__device__ inline void walk_row(uint32_t words, int s, int e, F&& visit)
 {
+    auto ix = [](uint32_t w, int k) { return k == 2 ? w >> 20 : (w >> (10 * k)) & 0x3ffu; };
     int k = s;
-    for (; k + 4 <= e; k += 4) {
-        const uint32_t w0 = lds_ld<uint32_t>(pairs + 2u * k), w1 = lds_ld<uint32_t>(pairs + 2u * k + 4u);
-        visit(w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16);
+    if constexpr (WPS == 2) {
+        for (; k + 2 <= e; k += 2) {
+            const uint32_t w0 = lds_ld<uint32_t>(words + 4u * k), w1 = lds_ld<uint32_t>(words + 4u * k + 4u);
+            visit(ix(w0, 0), ix(w0, 1), ix(w0, 2), ix(w1, 0), ix(w1, 1), ix(w1, 2));
+        }
     }
-    if (k < e) {
-        const uint32_t w0 = lds_ld<uint32_t>(pairs + 2u * k);
-        visit(w0 & 0xffffu, w0 >> 16);
+    for (; k < e; ++k) {
+        const uint32_t w0 = lds_ld<uint32_t>(words + 4u * k);
+        visit(ix(w0, 0), ix(w0, 1), ix(w0, 2));
     }
 }
 
@@ -364,16 +369,16 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
+    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
     const int S = P + H;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
     const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the segment
-    const uint32_t pairs = seg, rowend = seg + 2u * nnz;
+    const uint32_t words = seg, rowend = seg + 4u * nw;
 
     // The stencil segment goes straight to LDS first; then the staged points
     // in rounds of K slots per thread (fwd_stage).
-    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nnz) / 8));
+    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8));
     stage_points<B>(S, [&](auto kc, int r0) { fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds0); });
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
@@ -403,8 +408,8 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                     s1 += dx1;
                 }
             };
-            auto at = [&](uint32_t o) { return lds_ld<V4>(lds0 + o); };
-            walk_row(pairs, s, e, [&](auto... o) {
+            auto at = [&](uint32_t j) { return lds_ld<V4>(lds0 + j * L::unit); };
+            walk_row<2>(words, s, e, [&](auto... o) {
                 const V4 q[] = {at(o)...};
                 for (const V4& v : q) acc(v);
             });
@@ -473,8 +478,11 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                     s2 += dx2;
                 }
             };
-            auto at = [&](uint32_t o) { return Q{lds_ld<V4>(2 * o + abase), lds_ld<V2>(lds0 + o)}; };
-            walk_row(pairs, s, e, [&](auto... o) {
+            auto at = [&](uint32_t j) {
+                const uint32_t o = j * L::unit;
+                return Q{lds_ld<V4>(2 * o + abase), lds_ld<V2>(lds0 + o)};
+            };
+            walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
                 for (const Q& v : q) acc(v);
             });
@@ -631,14 +639,14 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
     const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
-    const int P = (int)m.P, H = (int)m.H, nnz = (int)m.nnz;
+    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
     const int S = P + H;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
     const uint32_t seg = (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment (LDS starts at 0)
-    const uint32_t pairs = seg, rowend = seg + 2u * nnz;
+    const uint32_t words = seg, rowend = seg + 4u * nw;
 
-    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nnz) / 8));
+    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8));
     stage_points<B>(S, [&](auto kc, int r0) { bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0); });
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
@@ -657,8 +665,11 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
                 V4 a;
                 V2 h;
             };
-            auto at = [&](uint32_t o) { return Q{lds_ld<V4>(2 * o), lds_ld<V2>(2 * o + 4 * sizeof(T))}; };
-            walk_row(pairs, s, e, [&](auto... o) {
+            auto at = [&](uint32_t j) {
+                const uint32_t o = j * L::unit;
+                return Q{lds_ld<V4>(2 * o), lds_ld<V2>(2 * o + 4 * sizeof(T))};
+            };
+            walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
                 for (const Q& v : q) {
                     const T d0 = cj.x - v.a.x, d1 = cj.y - v.a.y;
@@ -677,10 +688,11 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
                 V4 a, b;
                 T c;
             };
-            auto at = [&](uint32_t o) {
+            auto at = [&](uint32_t j) {
+                const uint32_t o = j * L::unit;
                 return Q{lds_ld<V4>(4 * o + cbase), lds_ld<V4>(4 * o + cbase + 4 * sizeof(T)), lds_ld<T>(o >> 1)};
             };
-            walk_row(pairs, s, e, [&](auto... o) {
+            walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
                 for (const Q& v : q) {
                     const T d0 = cj.x - v.a.x, d1 = cj.y - v.a.y, d2 = cj.z - v.a.z;

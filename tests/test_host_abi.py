@@ -100,7 +100,6 @@ def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2)
     and its local stencil (own + halo slots) maps back to the oracle's stencil;
     the adjoint tiles hold the transposed stencil."""
     m = F.Mesh(x, cells, "f32", stencil=stencil, tile_log2=tile_log2, host_only=True)
-    stride = m.slot_stride()
     ring = oracle.ring1(dim, x.shape[0], cells)
     st = ring if stencil == "ring1" else oracle.axis(dim, x, ring)
     want = _oracle_rows(st)
@@ -110,27 +109,25 @@ def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2)
             wantT[j].append(i)
     for adjoint, ref in ((False, want), (True, {k: sorted(v) for k, v in wantT.items()})):
         seen = np.zeros(m.n, np.int64)
-        for idx, rowend, lcol, P, H in m.tiles(adjoint):
+        for idx, rowend, ent, P, H in m.tiles(adjoint):
             assert P >= 1 and P <= (1 << (tile_log2 or 9))
             assert len(set(idx.tolist())) == P + H, "staged points must be distinct"
-            assert (P + H) * stride <= 65536
+            assert P + H <= 1024, "10-bit local indices"
             assert np.all(np.diff(rowend.astype(np.int64)) >= 0)
-            assert int(rowend[-1]) == len(lcol)
-            assert np.all(lcol % stride == 0)
-            loc = lcol.astype(np.int64) // stride
+            assert 3 * int(rowend[-1]) == len(ent)
+            loc = ent.astype(np.int64)
             assert np.all(loc < P + H)
             start = 0
             for l in range(P):
                 u = int(idx[l])
                 seen[u] += 1
-                end = int(rowend[l])
-                assert (end - start) % 2 == 0, "rows are padded to even length"
+                end = 3 * int(rowend[l])
                 row = [int(c) for c in loc[start:end]]
-                if row.count(l):   # the only allowed self entry is the final pad of an odd row
-                    assert row.count(l) == 1 and row[-1] == l and len(ref[u]) % 2 == 1
-                    row = row[:-1]
-                else:
-                    assert len(ref[u]) % 2 == 0
+                k = len(ref[u])
+                assert len(row) == (k + 2) // 3 * 3, "rows are padded to a multiple of 3"
+                # the padding is the point itself, after the stencil
+                assert row[k:] == [l] * (len(row) - k) and l not in row[:k]
+                row = row[:k]
                 assert sorted(int(idx[c]) for c in row) == ref[u], (u, row, ref[u])
                 start = end
             # halo points are exactly the neighbours not owned by the tile
