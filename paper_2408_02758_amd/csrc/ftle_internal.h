@@ -54,8 +54,8 @@ __host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nw) { return 
 //            3D: 6e, two arrays: (phi1, phi2) slots of 2e at the start of
 //                LDS, then (x0, x1, x2, phi0) slots of 4e
 //   adjoint  2D: 8e, one slot (x0, x1, w0, w1) (h0, h1, -, -)
-//            3D: 9e, two arrays: w2 slots of e, then (x0, x1, x2, h0)
-//                (h1, h2, w0, w1) slots of 8e
+//            3D: 9e, three arrays: w2 slots of e, then (x0, x1, x2, h0)
+//                slots of 4e, then (h1, h2, w0, w1) slots of 4e
 // Each array holds round_up(P + H, 4) slots, so every array and the segment
 // after them start 16-byte aligned.
 __host__ __device__ inline size_t elem_bytes(bool f64) { return f64 ? 8 : 4; }

@@ -143,7 +143,8 @@ __device__ inline int xcd_tile(int bid, int n)
 //   forward 3D: (phi1, phi2) at o, (x0, x1, x2, phi0) at
 //               2 o + 2eR                                     (unit 2e)
 //   adjoint 2D: (x0, x1, w0, w1) (h0, h1, -, -) at 2 o
-//   adjoint 3D: w2 at o / 2, (x0, x1, x2, h0) (h1, h2, w0, w1) at 4 o + eR
+//   adjoint 3D: w2 at o / 2, (x0, x1, x2, h0) at 2 o + eR,
+//               (h1, h2, w0, w1) at 2 o + 5eR
 // so that 16-byte reads are 16-byte aligned, no LDS is padding in 3D, and
 // neighbouring points sit in neighbouring banks.  The tile's segment follows:
 // the padded stencil (nw words of three 10-bit entries), then the P 16-bit
@@ -616,13 +617,13 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
             pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
             hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
         }
-        const uint32_t cbase = (uint32_t)round_up(S, 4) * sizeof(T);
+        const uint32_t c1 = (uint32_t)round_up(S, 4) * sizeof(T), c2 = 5 * c1;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
             const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-            lds_st(4 * o + cbase, V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a});
-            lds_st(4 * o + cbase + 4 * sizeof(T), V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b});
+            lds_st(2 * o + c1, V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a});
+            lds_st(2 * o + c2, V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b});
             lds_st(o >> 1, gg * pv[k].c);
         }
     }
@@ -651,7 +652,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
 
-    const uint32_t cbase = (uint32_t)round_up(S, 4) * sizeof(T);   // 3D: the 8-value slots
+    const uint32_t c1 = (uint32_t)round_up(S, 4) * sizeof(T), c2 = 5 * c1;   // 3D: the two 4-value arrays
     for (int l = threadIdx.x; l < P; l += B) {
         const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
         const int e = lds_ld<uint16_t>(rowend + 2u * l);
@@ -680,8 +681,8 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
             });
             rec_put<WIDE>(grad, u, sizeof(V2), V2{a0 - sig * cj.z, a1 - sig * cj.w});
         } else {
-            const V4 cj = lds_ld<V4>(4 * oself + cbase);
-            const V4 cb = lds_ld<V4>(4 * oself + cbase + 4 * sizeof(T));
+            const V4 cj = lds_ld<V4>(2 * oself + c1);
+            const V4 cb = lds_ld<V4>(2 * oself + c2);
             const T cw2 = lds_ld<T>(oself >> 1);
             T a0 = 0, a1 = 0, a2 = 0;
             struct Q {
@@ -690,7 +691,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
             };
             auto at = [&](uint32_t j) {
                 const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(4 * o + cbase), lds_ld<V4>(4 * o + cbase + 4 * sizeof(T)), lds_ld<T>(o >> 1)};
+                return Q{lds_ld<V4>(2 * o + c1), lds_ld<V4>(2 * o + c2), lds_ld<T>(o >> 1)};
             };
             walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
