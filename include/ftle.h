@@ -182,8 +182,10 @@ ftle_status ftle_tape_bytes(ftle_mesh_t mesh, int64_t* bytes);
 
 /*
  * Forward FTLE that also records, per point, what the adjoint needs
- * (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j (x_j - x_i), with v
- * the unit top eigenvector of C).  Same arguments as ftle_forward plus
+ * (p = J v / (|T| lambda), h = M^{-1} v, with v the unit top eigenvector of
+ * C, and for a non-symmetric stencil sigma = h . sum_j (x_j - x_i), which
+ * the adjoint otherwise forms itself).  The tape's layout is internal.  Same
+ * arguments as ftle_forward plus
  *   tape     device pointer of ftle_tape_bytes() bytes, caller-owned, overwritten
  */
 ftle_status ftle_forward_tape(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,

@@ -849,7 +849,7 @@ ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, d
         need_device(mesh);
         DeviceScope ds(mesh->device);
         check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
-                                 out, nullptr, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block,
+                                 out, nullptr, false, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block,
                                  static_cast<hipStream_t>(stream)),
                   "forward launch");
     });
@@ -875,7 +875,7 @@ ftle_status ftle_forward_tape(ftle_mesh_t mesh, const void* flow, ftle_dtype dty
         need_device(mesh);
         DeviceScope ds(mesh->device);
         check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
-                                 out, tape, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block,
+                                 out, tape, !mesh->symmetric, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block,
                                  static_cast<hipStream_t>(stream)),
                   "forward+tape launch");
     });
@@ -891,7 +891,7 @@ ftle_status ftle_backward_tape(ftle_mesh_t mesh, const void* tape, ftle_dtype dt
         need_device(mesh);
         DeviceScope ds(mesh->device);
         check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, tape,
-                                         mesh->n, grad_ftle, grad_flow, mesh->bwd_block,
+                                         !mesh->symmetric, mesh->n, grad_ftle, grad_flow, mesh->bwd_block,
                                          static_cast<hipStream_t>(stream)),
                   "adjoint launch");
     });
@@ -917,10 +917,11 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
             check_hip(hipStreamWaitEvent(s, mesh->work_done, 0), "hipStreamWaitEvent");
         }
         check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
-                                 nullptr, mesh->d_work, mesh->n, eig_tau(), mesh->d_hits, mesh->fwd_block, s),
+                                 nullptr, mesh->d_work, !mesh->symmetric, mesh->n, eig_tau(), mesh->d_hits,
+                                 mesh->fwd_block, s),
                   "adjoint tape launch");
         check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, mesh->d_work,
-                                         mesh->n, grad_ftle, grad_flow, mesh->bwd_block, s),
+                                         !mesh->symmetric, mesh->n, grad_ftle, grad_flow, mesh->bwd_block, s),
                   "adjoint launch");
         check_hip(hipEventRecord(mesh->work_done, s), "hipEventRecord");
         mesh->work_stream = s;

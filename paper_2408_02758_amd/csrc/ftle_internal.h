@@ -105,12 +105,14 @@ constexpr uint32_t kBatchedLdsHead = 16;
 size_t fwd_lds_bytes(int dim, bool f64, const DevTiles& t);
 size_t bwd_lds_bytes(int dim, bool f64, const DevTiles& t);
 
+// tape_sigma: the tape carries sigma (needed when the stencil is not
+// symmetric; with a symmetric stencil the adjoint forms it itself).
 hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* x, const void* flow,
-                          double inv2T, void* out, void* tape, int64_t n, double eig_tau,
+                          double inv2T, void* out, void* tape, bool tape_sigma, int64_t n, double eig_tau,
                           unsigned long long* hits, int block, hipStream_t stream);
 
 hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
-                                  const void* tape, int64_t n, const void* g, void* grad,
+                                  const void* tape, bool tape_sigma, int64_t n, const void* g, void* grad,
                                   int block, hipStream_t stream);
 
 // Block sizes (threads per workgroup) the kernels are compiled for.

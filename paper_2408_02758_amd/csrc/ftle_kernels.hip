@@ -358,10 +358,11 @@ __device__ inline void stage_points(int S, F&& round)
 
 // ---------------------------------------------------------------------------
 // One tile of the forward pass.  OUT: write FTLE.  TAPE: write the adjoint
-// tape (p = J v / (|T| lambda), h = M^{-1} v, sigma = h . sum_j dx, with v
-// the unit top eigenvector of C).
+// tape: p = J v / (|T| lambda) and h = M^{-1} v, with v the unit top
+// eigenvector of C (TAPE 1), and also sigma = h . sum_j dx (TAPE 2; with a
+// symmetric stencil the adjoint forms sigma itself).
 // ---------------------------------------------------------------------------
-template <int D, typename T, bool OUT, bool TAPE, int B, bool WIDE>
+template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
 __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
                                          const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
                                          T* __restrict__ out, T* __restrict__ tape, const int64_t n,
@@ -404,7 +405,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                 b01 = dfma(df0, dx1, b01);
                 b10 = dfma(df1, dx0, b10);
                 b11 = dfma(df1, dx1, b11);
-                if constexpr (TAPE) {
+                if constexpr (TAPE == 2) {
                     s0 += dx0;
                     s1 += dx1;
                 }
@@ -443,7 +444,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                 const T h0 = use ? (m11 * v0 - m01 * v1) * id : T(0);
                 const T h1 = use ? (m00 * v1 - m01 * v0) * id : T(0);
                 rec_put<WIDE>(tape, u, sizeof(V4), V4{p0, p1, h0, h1});
-                rec_put<WIDE>(tape + (size_t)n * 4, u, sizeof(T), h0 * s0 + h1 * s1);
+                if constexpr (TAPE == 2) rec_put<WIDE>(tape + (size_t)n * 4, u, sizeof(T), h0 * s0 + h1 * s1);
             }
         } else {
             const V4 c0 = lds_ld<V4>(2 * oself + abase);
@@ -473,7 +474,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                 b20 = dfma(df2, dx0, b20);
                 b21 = dfma(df2, dx1, b21);
                 b22 = dfma(df2, dx2, b22);
-                if constexpr (TAPE) {
+                if constexpr (TAPE == 2) {
                     s0 += dx0;
                     s1 += dx1;
                     s2 += dx2;
@@ -553,7 +554,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                               Packed3<T>{(j00 * v0 + j01 * v1 + j02 * v2) * sc, (j10 * v0 + j11 * v1 + j12 * v2) * sc,
                                          (j20 * v0 + j21 * v1 + j22 * v2) * sc});
                 rec_put<WIDE>(tape, 2 * u + 1, sizeof(Packed3<T>), Packed3<T>{h0, h1, h2});
-                rec_put<WIDE>(tape + (size_t)n * 6, u, sizeof(T), h0 * s0 + h1 * s1 + h2 * s2);
+                if constexpr (TAPE == 2) rec_put<WIDE>(tape + (size_t)n * 6, u, sizeof(T), h0 * s0 + h1 * s1 + h2 * s2);
             }
         }
         if constexpr (OUT) rec_put<WIDE>(out, u, sizeof(T), f);
@@ -562,7 +563,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
 
 // float: at most 64 VGPRs (8 waves per SIMD), so that the LDS, not the
 // registers, bounds the workgroups per CU; the tape variant needs the hint.
-template <int D, typename T, bool OUT, bool TAPE, int B, bool WIDE>
+template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
 __global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
 fwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int n_tiles, const T* __restrict__ x,
            const T* __restrict__ flow, T inv2T, T* __restrict__ out, T* __restrict__ tape, int64_t n, float eig_tau,
@@ -629,12 +630,13 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
     }
 }
 
-template <int D, typename T, int B, bool WIDE>
-__global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ meta,
-                                                  const uint4* __restrict__ rec, int n_tiles,
-                                                  const T* __restrict__ x, const T* __restrict__ tape,
-                                                  int64_t n, const T* __restrict__ g,
-                                                  T* __restrict__ grad)
+// SIG: sigma_j from the tape (non-symmetric stencil).  Otherwise S^T = S, the
+// walk visits exactly the stencil of j, and sigma_j = h_j . sum_i (x_i - x_j)
+// is formed from the same differences.
+template <int D, typename T, int B, bool WIDE, bool SIG>
+__global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec,
+                                                  int n_tiles, const T* __restrict__ x, const T* __restrict__ tape,
+                                                  int64_t n, const T* __restrict__ g, T* __restrict__ grad)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
@@ -657,11 +659,12 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
         const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
         const int e = lds_ld<uint16_t>(rowend + 2u * l);
         const uint32_t u = idx[l];
-        const T sig = rec_at<WIDE, T>(tape + (size_t)n * (2 * D), u, sizeof(T));
+        T sig = T(0);
+        if constexpr (SIG) sig = rec_at<WIDE, T>(tape + (size_t)n * (2 * D), u, sizeof(T));
         const uint32_t oself = (uint32_t)l * L::unit;
         if constexpr (D == 2) {
             const V4 cj = lds_ld<V4>(2 * oself);
-            T a0 = 0, a1 = 0;
+            T a0 = 0, a1 = 0, s0 = 0, s1 = 0;
             struct Q {
                 V4 a;
                 V2 h;
@@ -677,14 +680,22 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
                     const T t = v.h.x * d0 + v.h.y * d1;
                     a0 = dfma(v.a.z, t, a0);
                     a1 = dfma(v.a.w, t, a1);
+                    if constexpr (!SIG) {
+                        s0 += d0;
+                        s1 += d1;
+                    }
                 }
             });
+            if constexpr (!SIG) {
+                const V2 hj = lds_ld<V2>(2 * oself + 4 * sizeof(T));
+                sig = -(hj.x * s0 + hj.y * s1);
+            }
             rec_put<WIDE>(grad, u, sizeof(V2), V2{a0 - sig * cj.z, a1 - sig * cj.w});
         } else {
             const V4 cj = lds_ld<V4>(2 * oself + c1);
             const V4 cb = lds_ld<V4>(2 * oself + c2);
             const T cw2 = lds_ld<T>(oself >> 1);
-            T a0 = 0, a1 = 0, a2 = 0;
+            T a0 = 0, a1 = 0, a2 = 0, s0 = 0, s1 = 0, s2 = 0;
             struct Q {
                 V4 a, b;
                 T c;
@@ -701,8 +712,14 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
                     a0 = dfma(v.b.z, t, a0);
                     a1 = dfma(v.b.w, t, a1);
                     a2 = dfma(v.c, t, a2);
+                    if constexpr (!SIG) {
+                        s0 += d0;
+                        s1 += d1;
+                        s2 += d2;
+                    }
                 }
             });
+            if constexpr (!SIG) sig = -(cj.w * s0 + cb.x * s1 + cb.y * s2);
             rec_put<WIDE>(grad, u, sizeof(Packed3<T>), Packed3<T>{a0 - sig * cb.z, a1 - sig * cb.w, a2 - sig * cw2});
         }
     }
@@ -727,7 +744,7 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict_
     if (tiles_per_pop == 0) {
         // flat launch: one work item per workgroup, dealt XCD-contiguously
         const BatchItem it = items[xcd_tile(blockIdx.x, n_items)];
-        fwd_tile<D, T, true, false, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
+        fwd_tile<D, T, true, 0, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
                                              static_cast<const T*>(call.flow[it.mesh]), (T)call.inv2T[it.mesh],
                                              static_cast<T*>(call.out[it.mesh]), nullptr, 0, eig_tau, it.fp64_hits,
                                              kBatchedLdsHead);
@@ -742,7 +759,7 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict_
         const int lim = min(base + tiles_per_pop, n_items);
         for (int i = base; i < lim; ++i) {
             const BatchItem it = items[i];
-            fwd_tile<D, T, true, false, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
+            fwd_tile<D, T, true, 0, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
                                                  static_cast<const T*>(call.flow[it.mesh]), (T)call.inv2T[it.mesh],
                                                  static_cast<T*>(call.out[it.mesh]), nullptr, 0, eig_tau,
                                                  it.fp64_hits, kBatchedLdsHead);
@@ -773,7 +790,8 @@ size_t bwd_lds(const DevTiles& t)
 
 template <int D, typename T, int B, bool WIDE>
 hipError_t fwd_launch_b(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
-                        void* tape, int64_t n, double eig_tau, unsigned long long* hits, hipStream_t stream)
+                        void* tape, bool tape_sigma, int64_t n, double eig_tau, unsigned long long* hits,
+                        hipStream_t stream)
 {
     const size_t lds = fwd_lds<D, T>(tiles);
     const dim3 grid(tiles.n_tiles), blk(B);
@@ -781,26 +799,36 @@ hipError_t fwd_launch_b(const DevTiles& tiles, const void* x, const void* flow, 
     const T* fp = static_cast<const T*>(flow);
     T* op = static_cast<T*>(out);
     T* tp = static_cast<T*>(tape);
-    if (out && tape)
-        hipLaunchKernelGGL((fwd_kernel<D, T, true, true, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,
-                           tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
-    else if (tape)
-        hipLaunchKernelGGL((fwd_kernel<D, T, false, true, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,
-                           tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
+#define FTLE_FWD_LAUNCH(OUT, TAPE)                                                                              \
+    hipLaunchKernelGGL((fwd_kernel<D, T, OUT, TAPE, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,   \
+                       tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits)
+    if (!tape)
+        FTLE_FWD_LAUNCH(true, 0);
+    else if (out && tape_sigma)
+        FTLE_FWD_LAUNCH(true, 2);
+    else if (out)
+        FTLE_FWD_LAUNCH(true, 1);
+    else if (tape_sigma)
+        FTLE_FWD_LAUNCH(false, 2);
     else
-        hipLaunchKernelGGL((fwd_kernel<D, T, true, false, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,
-                           tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits);
+        FTLE_FWD_LAUNCH(false, 1);
+#undef FTLE_FWD_LAUNCH
     return hipGetLastError();
 }
 
 template <int D, typename T, int B, bool WIDE>
-hipError_t bwd_launch_b(const DevTiles& tiles, const void* x, const void* tape, int64_t n, const void* g,
-                        void* grad, hipStream_t stream)
+hipError_t bwd_launch_b(const DevTiles& tiles, const void* x, const void* tape, bool tape_sigma, int64_t n,
+                        const void* g, void* grad, hipStream_t stream)
 {
     const size_t lds = bwd_lds<D, T>(tiles);
-    hipLaunchKernelGGL((bwd_kernel<D, T, B, WIDE>), dim3(tiles.n_tiles), dim3(B), lds, stream, tiles.meta,
-                       tiles.rec, tiles.n_tiles, static_cast<const T*>(x), static_cast<const T*>(tape), n,
-                       static_cast<const T*>(g), static_cast<T*>(grad));
+    if (tape_sigma)
+        hipLaunchKernelGGL((bwd_kernel<D, T, B, WIDE, true>), dim3(tiles.n_tiles), dim3(B), lds, stream, tiles.meta,
+                           tiles.rec, tiles.n_tiles, static_cast<const T*>(x), static_cast<const T*>(tape), n,
+                           static_cast<const T*>(g), static_cast<T*>(grad));
+    else
+        hipLaunchKernelGGL((bwd_kernel<D, T, B, WIDE, false>), dim3(tiles.n_tiles), dim3(B), lds, stream, tiles.meta,
+                           tiles.rec, tiles.n_tiles, static_cast<const T*>(x), static_cast<const T*>(tape), n,
+                           static_cast<const T*>(g), static_cast<T*>(grad));
     return hipGetLastError();
 }
 
@@ -814,42 +842,42 @@ bool needs_wide(int dim, int64_t n)
 
 template <int D, typename T, bool WIDE>
 hipError_t fwd_launch_w(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
-                        void* tape, int64_t n, double eig_tau, unsigned long long* hits, int block,
+                        void* tape, bool ts, int64_t n, double eig_tau, unsigned long long* hits, int block,
                         hipStream_t stream)
 {
     switch (block) {
-    case 128: return fwd_launch_b<D, T, 128, WIDE>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, stream);
-    case 256: return fwd_launch_b<D, T, 256, WIDE>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, stream);
-    case 512: return fwd_launch_b<D, T, 512, WIDE>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, stream);
+    case 128: return fwd_launch_b<D, T, 128, WIDE>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, stream);
+    case 256: return fwd_launch_b<D, T, 256, WIDE>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, stream);
+    case 512: return fwd_launch_b<D, T, 512, WIDE>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int D, typename T>
 hipError_t fwd_launch(const DevTiles& tiles, const void* x, const void* flow, double inv2T, void* out,
-                      void* tape, int64_t n, double eig_tau, unsigned long long* hits, int block,
+                      void* tape, bool ts, int64_t n, double eig_tau, unsigned long long* hits, int block,
                       hipStream_t stream)
 {
     if (needs_wide<T>(D, n))
-        return fwd_launch_w<D, T, true>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
-    return fwd_launch_w<D, T, false>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
+        return fwd_launch_w<D, T, true>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream);
+    return fwd_launch_w<D, T, false>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream);
 }
 
 template <int D, typename T>
-hipError_t bwd_launch(const DevTiles& tiles, const void* x, const void* tape, int64_t n, const void* g,
+hipError_t bwd_launch(const DevTiles& tiles, const void* x, const void* tape, bool ts, int64_t n, const void* g,
                       void* grad, int block, hipStream_t stream)
 {
     const bool wide = needs_wide<T>(D, n);
     switch (block) {
     case 128:
-        return wide ? bwd_launch_b<D, T, 128, true>(tiles, x, tape, n, g, grad, stream)
-                    : bwd_launch_b<D, T, 128, false>(tiles, x, tape, n, g, grad, stream);
+        return wide ? bwd_launch_b<D, T, 128, true>(tiles, x, tape, ts, n, g, grad, stream)
+                    : bwd_launch_b<D, T, 128, false>(tiles, x, tape, ts, n, g, grad, stream);
     case 256:
-        return wide ? bwd_launch_b<D, T, 256, true>(tiles, x, tape, n, g, grad, stream)
-                    : bwd_launch_b<D, T, 256, false>(tiles, x, tape, n, g, grad, stream);
+        return wide ? bwd_launch_b<D, T, 256, true>(tiles, x, tape, ts, n, g, grad, stream)
+                    : bwd_launch_b<D, T, 256, false>(tiles, x, tape, ts, n, g, grad, stream);
     case 512:
-        return wide ? bwd_launch_b<D, T, 512, true>(tiles, x, tape, n, g, grad, stream)
-                    : bwd_launch_b<D, T, 512, false>(tiles, x, tape, n, g, grad, stream);
+        return wide ? bwd_launch_b<D, T, 512, true>(tiles, x, tape, ts, n, g, grad, stream)
+                    : bwd_launch_b<D, T, 512, false>(tiles, x, tape, ts, n, g, grad, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -878,27 +906,29 @@ size_t bwd_lds_bytes(int dim, bool f64, const DevTiles& t)
 }
 
 hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* x, const void* flow,
-                          double inv2T, void* out, void* tape, int64_t n, double eig_tau,
+                          double inv2T, void* out, void* tape, bool tape_sigma, int64_t n, double eig_tau,
                           unsigned long long* hits, int block, hipStream_t stream)
 {
     if (tiles.n_tiles == 0) return hipSuccess;
+    const bool ts = tape_sigma;
     if (dim == 2)
-        return f64 ? fwd_launch<2, double>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream)
-                   : fwd_launch<2, float>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
-    return f64 ? fwd_launch<3, double>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream)
-               : fwd_launch<3, float>(tiles, x, flow, inv2T, out, tape, n, eig_tau, hits, block, stream);
+        return f64 ? fwd_launch<2, double>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream)
+                   : fwd_launch<2, float>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream);
+    return f64 ? fwd_launch<3, double>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream)
+               : fwd_launch<3, float>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream);
 }
 
 hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
-                                  const void* tape, int64_t n, const void* g, void* grad, int block,
-                                  hipStream_t stream)
+                                  const void* tape, bool tape_sigma, int64_t n, const void* g, void* grad,
+                                  int block, hipStream_t stream)
 {
     if (tiles.n_tiles == 0) return hipSuccess;
+    const bool ts = tape_sigma;
     if (dim == 2)
-        return f64 ? bwd_launch<2, double>(tiles, x, tape, n, g, grad, block, stream)
-                   : bwd_launch<2, float>(tiles, x, tape, n, g, grad, block, stream);
-    return f64 ? bwd_launch<3, double>(tiles, x, tape, n, g, grad, block, stream)
-               : bwd_launch<3, float>(tiles, x, tape, n, g, grad, block, stream);
+        return f64 ? bwd_launch<2, double>(tiles, x, tape, ts, n, g, grad, block, stream)
+                   : bwd_launch<2, float>(tiles, x, tape, ts, n, g, grad, block, stream);
+    return f64 ? bwd_launch<3, double>(tiles, x, tape, ts, n, g, grad, block, stream)
+               : bwd_launch<3, float>(tiles, x, tape, ts, n, g, grad, block, stream);
 }
 
 template <int D, typename T, bool WIDE>
