@@ -236,7 +236,7 @@ def main():
     pts = w2.n / (ms * 1e-3)
     traffic = measured_traffic()
     rl = roofline(B, ms)
-    rl["traffic"] = traffic_for(traffic, f"fwd_kernel<2, float, true, false, {meshes2[0].blocks()[0]}, false>")
+    rl["traffic"] = traffic_for(traffic, f"fwd_kernel<2, float, true, 0, {meshes2[0].blocks()[0]}, false>")
     rl["alg_bytes_per_launch"] = B
     rl["format_bytes_per_launch"] = format_bytes_fwd(meshes2[0], 2)
     rl["format_frac"] = round(rl["format_bytes_per_launch"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
@@ -276,7 +276,7 @@ def main():
                 "points": w3.n, "nnz": nnz3, "ms_per_step": round(t, 5), "points_per_s": round(w3.n / (t * 1e-3), 1),
                 "roofline": dict(roofline(B3, t), alg_bytes_per_launch=B3,
                                  format_bytes_per_launch=format_bytes_fwd(ms3[0], 3),
-                                 traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, false, {ms3[0].blocks()[0]}, false>")),
+                                 traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, 0, {ms3[0].blocks()[0]}, false>")),
                 "fp64_eigen_recomputes_per_call": round(hits / max(1, calls0), 1)}
             log(f"3D forward: {t * 1e3:.2f} us/step")
             del fns, ms3, fl3, ou3
@@ -301,8 +301,8 @@ def main():
                 "workload": "3D FTLE forward + adjoint (dL/dflow, L = sum w_i FTLE_i), 96^3 Kuhn grid, ABC flow, T=10",
                 "points": wd.n, "nnz": nnzd, "ms_per_step": round(t, 5), "points_per_s": round(wd.n / (t * 1e-3), 1),
                 "roofline": dict(roofline(Bd, t), alg_bytes_per_launch=Bd,
-                                 traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, true, {msd[0].blocks()[0]}, false>",
-                                                     f"bwd_kernel<3, float, {msd[0].blocks()[1]}, false>"))}
+                                 traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, 1, {msd[0].blocks()[0]}, false>",
+                                                     f"bwd_kernel<3, float, {msd[0].blocks()[1]}, false, false>"))}
             log(f"fwd+bwd: {t * 1e3:.2f} us/step")
             del fns, msd, fld, outd, taped, gradd
         if want("batched"):
