@@ -250,6 +250,15 @@ ftle_status ftle_batched_config(int n, const ftle_mesh_t* meshes, int* block, in
  */
 ftle_status ftle_mesh_fp64_hits(ftle_mesh_t mesh, int64_t* hits, int reset);
 
+/*
+ * Testing aid: while on is nonzero, every launch uses the kernels' 64-bit
+ * element offsets, the code path otherwise taken only when some per-point
+ * array of a mesh reaches 4 GiB, so that path can be checked against the
+ * default one on small meshes.  Process-wide; a batched plan keeps the choice
+ * it was built with.  Always returns FTLE_OK.
+ */
+ftle_status ftle_force_wide_offsets(int on);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* ftle_last_error(void);
 

@@ -277,9 +277,15 @@ class FTLEFunction(torch.autograd.Function):
         return grad, None, None
 
 
+def force_wide_offsets(on: bool) -> None:
+    """Testing aid: make every later launch take the 64-bit offset path (see ftle_force_wide_offsets)."""
+    check(_lib.load().ftle_force_wide_offsets(int(bool(on))))
+
+
 def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
     """Differentiable FTLE of a flow map on a mesh."""
     return FTLEFunction.apply(flow, mesh, T)
 
 
-__all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError"]
+__all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError",
+           "force_wide_offsets"]

@@ -611,6 +611,12 @@ const char* ftle_last_error(void) { return g_last_error.c_str(); }
 
 const char* ftle_version(void) { return "ftle-mi355x 0.1 (gfx950)"; }
 
+ftle_status ftle_force_wide_offsets(int on)
+{
+    set_force_wide(on != 0);
+    return FTLE_OK;
+}
+
 ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
                              int64_t n_cells, const int32_t* cells, unsigned flags, ftle_mesh_t* out)
 {

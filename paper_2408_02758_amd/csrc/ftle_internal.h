@@ -127,6 +127,8 @@ hipError_t launch_batched(int dim, bool f64, bool wide, const BatchItem* items, 
 // when some mesh of the batch has batched_needs_wide(dim, f64, n).
 const void* batched_kernel_symbol(int dim, bool f64, int block, bool wide);
 bool batched_needs_wide(int dim, bool f64, int64_t max_points);
+// Testing aid: make every launch take the 64-bit offset path.
+void set_force_wide(bool on);
 void batched_kernel_args(const BatchItem* items, int n_items, int tiles_per_pop, unsigned* queue,
                          const BatchCall& call, double eig_tau, void* storage, void** args);
 size_t batched_kernel_arg_storage();

@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
+#include <atomic>
 
 #include "ftle_internal.h"
 
@@ -834,9 +835,12 @@ hipError_t bwd_launch_b(const DevTiles& tiles, const void* x, const void* tape, 
 
 // 32-bit byte offsets reach every array of an n-point mesh when the largest
 // per-point record (the 3D tape's 2*dim values) times n stays below 4 GiB.
+std::atomic<bool> g_force_wide{false};
+
 template <typename T>
 bool needs_wide(int dim, int64_t n)
 {
+    if (g_force_wide.load(std::memory_order_relaxed)) return true;
     return (uint64_t)n * (uint64_t)(2 * dim) * sizeof(T) >= (1ull << 32);
 }
 
@@ -951,6 +955,8 @@ const void* batched_kernel_symbol(int dim, bool f64, int block, bool wide)
     if (f64) return wide ? batched_symbol_b<3, double, true>(block) : batched_symbol_b<3, double, false>(block);
     return wide ? batched_symbol_b<3, float, true>(block) : batched_symbol_b<3, float, false>(block);
 }
+
+void set_force_wide(bool on) { g_force_wide.store(on, std::memory_order_relaxed); }
 
 bool batched_needs_wide(int dim, bool f64, int64_t max_points)
 {

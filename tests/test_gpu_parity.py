@@ -362,3 +362,47 @@ def test_batched_full_48():
         sel = _sample(ws[k].n, min(ws[k].n - 200, 5000), k)
         ref, gap, _ = ref_ftle(ws[k], sel=sel)
         check_f32(f"batched48 mesh {k}", outs[k].cpu().numpy().astype(np.float64)[sel], ref, gap, ws[k].T)
+
+
+@pytest.mark.gpu
+def test_wide_offsets_match_default():
+    """The 64-bit offset kernels (the path taken when a mesh's per-point arrays
+    reach 4 GiB) give bit-identical results to the default 32-bit ones, for the
+    forward, tape forward, adjoint (RING1 and AXIS) and batched launches, in
+    float32 and float64."""
+    cases = [configs.tri2d(37, 29, 11, 0.0, 15.0, "f32", DEV),
+             configs.abc3d(12, 10.0, "f32", DEV),
+             configs.abc3d(9, 10.0, "f64", DEV)]
+
+    def run(w, stencil):
+        m = F.Mesh(w.coords, w.cells, w.dtype, stencil=stencil, tile_log2=6)
+        fl = w.flow.to(DEV).contiguous()
+        f = m.forward(fl, w.T)
+        tape = torch.empty(m.tape_bytes() // fl.element_size(), dtype=fl.dtype, device=DEV)
+        ft, _ = m.forward_tape(fl, w.T, tape=tape)
+        g = torch.linspace(-1.0, 1.0, w.n, dtype=fl.dtype, device=DEV)
+        gr = m.backward_tape(tape, g)
+        torch.cuda.synchronize()
+        return [f, ft, gr]
+
+    try:
+        for w in cases:
+            for stencil in ("ring1", "axis"):
+                F.force_wide_offsets(False)
+                ref = run(w, stencil)
+                F.force_wide_offsets(True)
+                got = run(w, stencil)
+                for a, b in zip(ref, got):
+                    assert torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b, nan=7.0)), (w.name, stencil)
+        # batched: fresh meshes, so that the plan is built with the wide kernels
+        w2 = [configs.tri2d(n, n, s, 1.0, 10.0, "f32", DEV) for n, s in ((20, 1), (45, 2), (33, 3))]
+        fl = [w.flow.to(DEV).contiguous() for w in w2]
+        F.force_wide_offsets(False)
+        ref = F.batched([F.Mesh(w.coords, w.cells, "f32") for w in w2], fl, [w.T for w in w2])
+        F.force_wide_offsets(True)
+        got = F.batched([F.Mesh(w.coords, w.cells, "f32") for w in w2], fl, [w.T for w in w2])
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got):
+            assert torch.equal(torch.nan_to_num(a, nan=7.0), torch.nan_to_num(b, nan=7.0))
+    finally:
+        F.force_wide_offsets(False)
