@@ -138,8 +138,9 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
  *   meta      host, n_tiles x 16 bytes: per tile uint32 {record offset in
  *             16-byte units, own points P, halo points H, stencil words nw}
  *   records   host, record_bytes bytes; per tile: uint32 caller indices of the
- *             P own points (Morton order) then the H halo points, padded to a
- *             multiple of 4; then nw uint32 stencil words, each holding three
+ *             P own points (a range of the Morton order) then of the H halo
+ *             points, each part sorted, padded to a multiple of 4; then nw
+ *             uint32 stencil words, each holding three
  *             10-bit local indices (positions in that index list) in bits
  *             0-9, 10-19 and 20-29, with every row padded to a multiple of 3
  *             entries by the point's own index; then P uint16 row ends

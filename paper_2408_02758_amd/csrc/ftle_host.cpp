@@ -448,7 +448,7 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
     parallel_for((int64_t)ext.size(), [&](int64_t tb, int64_t te, int) {
         std::vector<uint32_t> stamp(n, 0);
         std::vector<int32_t> halo;
-        std::vector<int32_t> local(0);
+        std::vector<int32_t> order, slot;   // own points in caller order; Morton position -> slot
         uint32_t tag = 0;
         for (int64_t t = tb; t < te; ++t) {
             const TileMeta m = ts.meta[t];
@@ -461,7 +461,16 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
             uint32_t* idx = ts.rec.data() + (size_t)m.rec_off * 4;
             uint32_t* words = idx + idx_words(m.P, m.H);
             uint16_t* rowend = reinterpret_cast<uint16_t*>(words + m.nw);
-            for (int64_t r = b; r < e; ++r) idx[r - b] = (uint32_t)perm[r];
+            // Own points take slots in caller order (as the halo does): adjacent
+            // lanes then load and store adjacent caller-order entries.
+            order.resize((size_t)(e - b));
+            slot.resize((size_t)(e - b));
+            for (int64_t r = b; r < e; ++r) order[r - b] = (int32_t)r;
+            std::sort(order.begin(), order.end(), [&](int32_t u, int32_t v) { return perm[u] < perm[v]; });
+            for (size_t l = 0; l < order.size(); ++l) {
+                idx[l] = (uint32_t)perm[order[l]];
+                slot[order[l] - b] = (int32_t)l;
+            }
             // halo slot of each halo point: reuse stamp as "slot + 1" storage is
             // not possible (tag), so search in a small map
             std::vector<std::pair<int32_t, int32_t>> hs(halo.size());
@@ -471,14 +480,15 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
             }
             std::sort(hs.begin(), hs.end());
             uint32_t pos = 0;   // words written
-            for (int64_t r = b; r < e; ++r) {
+            for (uint32_t l = 0; l < m.P; ++l) {
+                const int64_t r = order[l];
                 uint32_t word = 0;
                 int k = 0;   // entries in `word`
                 for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
                     const int32_t c = a.col[p];
                     int32_t loc;
                     if (c >= b && c < e) {
-                        loc = (int32_t)(c - b);
+                        loc = slot[c - b];
                     } else {
                         auto it = std::lower_bound(hs.begin(), hs.end(), std::make_pair(c, INT32_MIN));
                         loc = it->second;
@@ -491,10 +501,10 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                     }
                 }
                 if (k) {   // pad the row with the point itself
-                    for (; k < 3; ++k) word |= (uint32_t)(r - b) << (10 * k);
+                    for (; k < 3; ++k) word |= l << (10 * k);
                     words[pos++] = word;
                 }
-                rowend[r - b] = (uint16_t)pos;
+                rowend[l] = (uint16_t)pos;
             }
         }
     }, 1);

@@ -17,9 +17,10 @@ namespace ftle {
 // a contiguous, 16-byte aligned block:
 //
 //   uint32 idx[P + H]         caller (user) index of every staged point: the
-//                             tile's own P points in Morton order, then its H
+//                             tile's own P points (a Morton range), then its H
 //                             halo points (neighbours owned by other tiles),
-//                             padded to a multiple of 4 entries
+//                             each part in increasing caller index, padded to
+//                             a multiple of 4 entries
 //   uint32 words[nw]          the stencil rows of the own points, three
 //                             10-bit local indices (positions in idx) per
 //                             word, in bits 0-9, 10-19 and 20-29; every row

@@ -112,6 +112,8 @@ def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2)
         for idx, rowend, ent, P, H in m.tiles(adjoint):
             assert P >= 1 and P <= (1 << (tile_log2 or 9))
             assert len(set(idx.tolist())) == P + H, "staged points must be distinct"
+            # own points, then halo points, each in increasing caller index
+            assert np.all(np.diff(idx[:P].astype(np.int64)) > 0) and np.all(np.diff(idx[P:].astype(np.int64)) > 0)
             assert P + H <= 1024, "10-bit local indices"
             assert np.all(np.diff(rowend.astype(np.int64)) >= 0)
             assert 3 * int(rowend[-1]) == len(ent)
