@@ -351,6 +351,23 @@ def test_batched_matches_forward_bitwise_and_replays():
         check_f32(f"batched mesh {k}", outs[k].cpu().numpy().astype(np.float64), ref, gap, ws[k].T)
 
 
+def test_batched_3d_and_f64_match_forward():
+    """Batched launches of 3D float32 meshes and of 2D float64 meshes give the
+    single-mesh forward's results bit for bit (same tile body, other launch)."""
+    groups = [
+        [configs.abc3d(n, T, "f32", DEV) for n, T in ((10, 10.0), (17, 6.0), (13, -8.0))],
+        [configs.tri2d(n, m, s, t0, T, "f64", DEV) for n, m, s, t0, T in ((30, 20, 1, 0.0, 15.0), (41, 41, 2, 3.0, 7.5))],
+    ]
+    for ws in groups:
+        ms = [F.Mesh(w.coords, w.cells, w.dtype) for w in ws]
+        fl = [w.flow.to(DEV).contiguous() for w in ws]
+        outs = F.batched(ms, fl, [w.T for w in ws])
+        torch.cuda.synchronize()
+        for m, o, f, w in zip(ms, outs, fl, ws):
+            single = m.forward(f, w.T)
+            assert torch.equal(torch.nan_to_num(o, nan=7.0), torch.nan_to_num(single, nan=7.0)), w.name
+
+
 def test_batched_full_48():
     ws = configs.batched_2d(DEV)
     ms = [F.Mesh(w.coords, w.cells, "f32") for w in ws]
