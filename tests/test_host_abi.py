@@ -265,3 +265,23 @@ def test_set_blocks_validation(L):
         assert L.ftle_mesh_set_blocks(h, 0, bad) == 1
     assert L.ftle_mesh_set_blocks(None, 64, 64) == 1
     L.ftle_destroy_mesh(h)
+
+
+def test_tiles_follow_caller_order_axis():
+    """A structured grid stored row by row gets tiles twice as long along the
+    row (16 x 8 x 4 in 3D), so a tile's own points form caller-order runs of
+    16; the same points in random caller order get the plain Morton cut, and
+    both meshes hold the same stencil."""
+    x, c = meshes.kuhn_tet_grid(32, length=1.0)   # 32^3: whole 16 x 8 x 4 blocks
+    m = F.Mesh(x, c, "f32", host_only=True)
+    runs = set()
+    for idx, _, _, P, H in m.tiles(False):
+        assert P == 512
+        own = idx[:P].astype(np.int64)
+        cuts = np.flatnonzero(np.diff(own) != 1)
+        runs |= set(np.diff(np.concatenate([[-1], cuts, [P - 1]])).tolist())
+    assert runs == {16}
+    x2, c2, p = meshes.relabel(x, c, seed=4)
+    m2 = F.Mesh(x2, c2, "f32", host_only=True)
+    assert m2.info()["nnz"] == m.info()["nnz"]
+    assert all(P + H <= 1024 for _, _, _, P, H in m2.tiles(False))
