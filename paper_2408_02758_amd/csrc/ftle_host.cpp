@@ -752,9 +752,10 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
             // Caller order that walks one axis (consecutive caller indices one
             // spacing apart along it and fixed along the others, as in a
             // structured grid stored row by row): the other axes' codes move up
-            // one bit, so a run of 2^(k*dim) codes is a block twice as long
-            // along that axis (16 x 8 x 4 instead of 8^3 in 3D) and a tile's
-            // points form longer caller-order runs.
+            // one bit, so a run of 512 codes is a block long along that axis
+            // (32 x 16 in 2D, 16 x 8 x 4 instead of 8^3 in 3D) and a tile's
+            // points form longer caller-order runs.  (Longer blocks, 64 x 8 in
+            // 2D, grow the halo more than they gain.)
             const int fast = caller_order_axis(dim, n, xd.data(), unit);
             const int shift_bits = fast >= 0 ? 1 : 0;
             int sub = 8;
@@ -767,7 +768,7 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
                     for (int d = 0; d < dim; ++d) {
                         const double t = std::floor(((xd[i * dim + d] - lo[d]) / unit[d] + 0.2) * std::ldexp(1.0, sub));
                         uint64_t q = (uint64_t)std::min(qmax, std::max(0.0, t));
-                        if (fast >= 0 && d != fast) q <<= 1;
+                        if (fast >= 0 && d != fast) q <<= shift_bits;
                         code |= (dim == 2 ? spread2(q) : spread3(q)) << d;
                     }
                     key[i] = code;
