@@ -392,7 +392,7 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
                     const std::vector<int32_t>& perm)
 {
     // 1. extents: nominal chunks of tile_points, halved until they fit the caps
-    //    (16-bit LDS offsets, 16-bit row ends, the LDS budget)
+    //    (10-bit local indices, 16-bit row ends, the LDS budget)
     const int64_t nchunks = (n + tile_points - 1) / tile_points;
     std::vector<std::vector<TileExtent>> per_chunk(nchunks);
     parallel_for(nchunks, [&](int64_t cb, int64_t ce, int) {

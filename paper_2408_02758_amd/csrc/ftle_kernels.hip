@@ -19,8 +19,9 @@
 //    list, copied to LDS once.  Rows are padded to a multiple of three with
 //    the point itself (which adds exact zeros), so the walk reads three
 //    neighbours per 32-bit LDS load with no per-entry branch.
-//  - One lane per point; Jacobian, tensor, eigenvalue and logarithm stay in
-//    registers.  No MFMA: per point the work is a few dozen multiply-adds
+//  - A lane computes one point at a time (a workgroup of B lanes walks its
+//    tile's P points in steps of B); Jacobian, tensor, eigenvalue and
+//    logarithm stay in registers.  No MFMA: per point the work is a few dozen multiply-adds
 //    over a gathered stencil, not a dense contraction.
 //  - Consecutive workgroup ids land on different XCDs; tiles are remapped so
 //    that each XCD walks a contiguous stretch of the Morton order and halo
@@ -158,12 +159,12 @@ template <int D, typename T> struct Layout {
     static constexpr uint32_t bwd = (D == 2 ? 8 : 9) * e;
 };
 
-// Copy of a tile's 16-bit segment (n16 chunks of 16 bytes) into LDS as a
-// direct global -> LDS transfer (global_load_lds_dwordx4): each wave moves 64
-// consecutive 16-byte chunks to consecutive LDS chunks without passing
-// through registers, so the copy stays in flight while the caller issues
-// other loads.  The caller waits (vmcnt 0) and synchronises the workgroup
-// before reading dst.
+// Copy of a tile's segment (stencil words and row ends, n16 chunks of 16
+// bytes) into LDS as a direct global -> LDS transfer
+// (global_load_lds_dwordx4): each wave moves 64 consecutive 16-byte chunks to
+// consecutive LDS chunks without passing through registers, so the copy stays
+// in flight while the caller issues other loads.  The caller waits (vmcnt 0)
+// and synchronises the workgroup before reading dst.
 template <int B>
 __device__ inline void dma_segment(const uint4* __restrict__ src, uint32_t dst, int n16)
 {
