@@ -182,6 +182,66 @@ def cpu_baseline(w, threads):
                       f"(stencil built beforehand), float64, OpenMP {threads} threads"}
 
 
+def error_vs_oracle(w, got, sel=None):
+    """Error of a float32 GPU FTLE field against the FP64 oracle on the same
+    (float32-rounded) inputs: max |error| over finite points, and the relative
+    error where the top eigenvalue is separated (gap >= 1e-3) and |ln lambda|
+    >= 0.05, the mask the parity tests use."""
+    import numpy as np
+
+    import oracle
+    st = oracle.ring1(w.dim, w.n, w.cells)
+    ref, gap, _ = oracle.ftle(w.dim, w.coords.astype(np.float64), w.flow_numpy().astype(np.float64), st, w.T,
+                              sel=sel, diagnostics=True)
+    g = np.asarray(got, dtype=np.float64)
+    if sel is not None:
+        g = g[sel]
+    fin = np.isfinite(ref)
+    mask = fin & (gap >= 1e-3) & (2 * abs(w.T) * np.abs(ref) >= 0.05)
+    rel = np.abs(g[mask] - ref[mask]) / np.abs(ref[mask])
+    return {"points": int(ref.size), "max_abs_err": float(np.abs(g[fin] - ref[fin]).max(initial=0)),
+            "masked_max_rel_err": float(rel.max(initial=0)), "masked_p99_rel_err": float(np.percentile(rel, 99)) if rel.size else 0.0,
+            "mask_fraction": round(float(mask.mean()), 4), "nan_masks_equal": bool(np.array_equal(np.isnan(g), np.isnan(ref)))}
+
+
+def grad_error_vs_oracle(w, g_in, grad):
+    """Max |error| of the GPU adjoint over the max |gradient| of the FP64 oracle,
+    leaving out points next to a nearly repeated top eigenvalue (gap < 1e-6),
+    whose eigenvector is ill-defined (as the parity tests do)."""
+    import numpy as np
+
+    import oracle
+    st = oracle.ring1(w.dim, w.n, w.cells)
+    x, phi = w.coords.astype(np.float64), w.flow_numpy().astype(np.float64)
+    ref = oracle.ftle_grad(w.dim, x, phi, st, w.T, np.asarray(g_in, dtype=np.float64))
+    _, gap, _ = oracle.ftle(w.dim, x, phi, st, w.T, diagnostics=True)
+    bad = np.zeros(w.n, bool)
+    for i in np.nonzero(~(gap >= 1e-6))[0]:
+        bad[i] = True
+        bad[st.col[st.row_ptr[i]:st.row_ptr[i + 1]]] = True
+    got = np.asarray(grad, dtype=np.float64).reshape(ref.shape)
+    return {"points": int(w.n), "excluded_near_repeated_eigenvalue": int(bad.sum()),
+            "max_err_over_max_grad": float(np.abs(got - ref)[~bad].max() / np.abs(ref).max())}
+
+
+def copy_probe_gbps(torch, dev, mib=1024, reps=10):
+    """Bandwidth of a plain elementwise kernel (torch.neg: mib MiB read + mib MiB written)."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return round(2 * (mib << 20) / t / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +301,7 @@ def main():
     rl["format_bytes_per_launch"] = format_bytes_fwd(meshes2[0], 2)
     rl["format_frac"] = round(rl["format_bytes_per_launch"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
     nan = int(torch.isnan(outs2[0]).sum().item())
+    keep = {"2d": outs2[0].cpu().numpy()}   # GPU fields checked against the oracle at the end
     result.update({
         "metric": "FTLE points/s (fwd, fwd+bwd, batched) + % HBM roofline at stated err vs FP64",
         "value": round(pts, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -253,6 +314,9 @@ def main():
         "roofline": rl,
     })
     log(f"2D forward: {ms * 1e3:.2f} us/step, {pts / 1e9:.2f} G points/s, {rl['achieved']} GB/s alg")
+    copy_gbps = copy_probe_gbps(torch, dev)
+    result["copy_probe"] = {"GBps": copy_gbps, "kernel": "torch.neg, 1 GiB read + 1 GiB written"}
+    rl["frac_of_copy_probe"] = round(rl["achieved"] / copy_gbps, 4)
     del fns
 
     # ---- variants ----------------------------------------------------------
@@ -279,6 +343,7 @@ def main():
                                  traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, 0, {ms3[0].blocks()[0]}, false>")),
                 "fp64_eigen_recomputes_per_call": round(hits / max(1, calls0), 1)}
             log(f"3D forward: {t * 1e3:.2f} us/step")
+            keep["3d"] = (w3, ou3[0].cpu().numpy())
             del fns, ms3, fl3, ou3
         if want("fwdbwd"):
             log("generating 96^3 ABC workload (differentiated)")
@@ -304,6 +369,7 @@ def main():
                                  traffic=traffic_for(traffic, f"fwd_kernel<3, float, true, 1, {msd[0].blocks()[0]}, false>",
                                                      f"bwd_kernel<3, float, {msd[0].blocks()[1]}, false, false>"))}
             log(f"fwd+bwd: {t * 1e3:.2f} us/step")
+            keep["fwdbwd"] = (wd, outd[0].cpu().numpy(), gw.cpu().numpy(), gradd[0].cpu().numpy())
             del fns, msd, fld, outd, taped, gradd
         if want("batched"):
             log("generating the 48-mesh batched workload")
@@ -331,7 +397,10 @@ def main():
                 roofline(Bb, t), alg_bytes_per_launch=Bb,
                 traffic=traffic_for(traffic, f"batched_kernel<2, float, {cfg['block']}, false>"))
             log(f"batched: {t * 1e3:.2f} us/step")
+            keep["batched"] = [(wb[k], sets[0][2][k].cpu().numpy()) for k in (0, 24, 47)]
             del fns, sets
+    for v in variants.values():
+        v["roofline"]["frac_of_copy_probe"] = round(v["roofline"]["achieved"] / copy_gbps, 4)
     if variants:
         result["variants"] = variants
 
@@ -342,6 +411,19 @@ def main():
             threads = min(16, os.cpu_count() or 1)
         log(f"timing the FP64 oracle on {threads} host threads")
         result["cpu_baseline"] = cpu_baseline(w2, threads)
+        # the float32 fields of this run against the FP64 oracle on the same inputs
+        log("checking the GPU fields against the FP64 oracle")
+        err = {"2d_2048": error_vs_oracle(w2, keep["2d"])}
+        rng = np.random.default_rng(0)
+        if "3d" in keep:
+            w3, got3 = keep["3d"]
+            err["3d_160_sample"] = error_vs_oracle(w3, got3, sel=np.sort(rng.choice(w3.n, 200000, replace=False)))
+        if "fwdbwd" in keep:
+            wd, outd0, g0, grad0 = keep["fwdbwd"]
+            err["fwd_bwd_96"] = {"ftle": error_vs_oracle(wd, outd0), "grad": grad_error_vs_oracle(wd, g0, grad0)}
+        if "batched" in keep:
+            err["batched_48"] = {w.name: error_vs_oracle(w, got) for w, got in keep["batched"]}
+        result["error_vs_fp64"] = err
 
     print(json.dumps(result), flush=True)
 
