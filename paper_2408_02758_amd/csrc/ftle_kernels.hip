@@ -166,10 +166,10 @@ template <int D, typename T> struct Layout {
 // in flight while the caller issues other loads.  The caller waits (vmcnt 0)
 // and synchronises the workgroup before reading dst.
 template <int B>
-__device__ inline void dma_segment(const uint4* __restrict__ src, uint32_t dst, int n16)
+__device__ inline void dma_segment(const uint4* __restrict__ src, uint32_t dst, int n16, int tid)
 {
-    const int lane = (int)threadIdx.x & 63;
-    for (int c0 = (int)threadIdx.x - lane; c0 < n16; c0 += B) {   // wave-uniform chunk base
+    const int lane = tid & 63;
+    for (int c0 = tid - lane; c0 < n16; c0 += B) {   // wave-uniform chunk base
         if (c0 + lane < n16)
             __builtin_amdgcn_global_load_lds(src + c0 + lane,
                                              (__attribute__((address_space(3))) void*)(size_t)(dst + 16u * c0), 16, 0, 0);
@@ -301,12 +301,12 @@ __device__ __noinline__ float lam_max3_f64_from_J(float j00, float j01, float j0
 // ---------------------------------------------------------------------------
 template <int D, typename T, int B, bool WIDE, int K>
 __device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
-                                 const T* __restrict__ flow, int S, int r0, uint32_t lds0)
+                                 const T* __restrict__ flow, int S, int r0, uint32_t lds0, int tid)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    const int base = r0 + (int)threadIdx.x;
+    const int base = r0 + tid;
     uint32_t u[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = idx[min(base + k * B, S - 1)];
@@ -364,11 +364,33 @@ __device__ inline void stage_points(int S, F&& round)
 // eigenvector of C (TAPE 1), and also sigma = h . sum_j dx (TAPE 2; with a
 // symmetric stencil the adjoint forms sigma itself).
 // ---------------------------------------------------------------------------
+// Staging of a forward tile by B threads (tid in [0, B)) into the LDS
+// region at lds0: the stencil segment straight to LDS, then the staged points
+// in rounds of K slots per thread (fwd_stage).  The caller waits (vmcnt 0)
+// and synchronises before the compute.
+template <int D, typename T, int B, bool WIDE>
+__device__ __forceinline__ void fwd_stage_tile(const TileMeta m, const uint4* __restrict__ rec,
+                                               const T* __restrict__ x, const T* __restrict__ flow,
+                                               const uint32_t lds0, const int tid)
+{
+    using L = Layout<D, T>;
+    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
+    const int S = P + H;
+    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
+    const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
+    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the segment
+    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8), tid);
+    stage_points<B>(S, [&](auto kc, int r0) {
+        fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds0, tid);
+    });
+}
+
+// The compute of a staged forward tile by B threads (tid in [0, B)).
 template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
-__device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
-                                         const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
-                                         T* __restrict__ out, T* __restrict__ tape, const int64_t n,
-                                         const float eig_tau, unsigned long long* hits, const uint32_t lds0)
+__device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const uint4* __restrict__ rec, const T inv2T,
+                                                 T* __restrict__ out, T* __restrict__ tape, const int64_t n,
+                                                 const float eig_tau, unsigned long long* hits,
+                                                 const uint32_t lds0, const int tid)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
@@ -376,19 +398,10 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
     const int S = P + H;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
-    const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
     const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the segment
     const uint32_t words = seg, rowend = seg + 4u * nw;
-
-    // The stencil segment goes straight to LDS first; then the staged points
-    // in rounds of K slots per thread (fwd_stage).
-    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8));
-    stage_points<B>(S, [&](auto kc, int r0) { fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds0); });
-    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
-    __syncthreads();
-
     const uint32_t abase = lds0 + (uint32_t)round_up(S, 4) * 2 * sizeof(T);   // 3D: (x0, x1, x2, phi0) array
-    for (int l = threadIdx.x; l < P; l += B) {
+    for (int l = tid; l < P; l += B) {
         const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
         const int e = lds_ld<uint16_t>(rowend + 2u * l);
         const uint32_t u = idx[l];
@@ -563,6 +576,19 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     }
 }
 
+// One tile of the forward pass by the whole workgroup of B threads.
+template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
+__device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
+                                         const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
+                                         T* __restrict__ out, T* __restrict__ tape, const int64_t n,
+                                         const float eig_tau, unsigned long long* hits, const uint32_t lds0)
+{
+    fwd_stage_tile<D, T, B, WIDE>(m, rec, x, flow, lds0, (int)threadIdx.x);
+    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
+    __syncthreads();
+    fwd_compute_tile<D, T, OUT, TAPE, B, WIDE>(m, rec, inv2T, out, tape, n, eig_tau, hits, lds0, (int)threadIdx.x);
+}
+
 // float: at most 64 VGPRs (8 waves per SIMD), so that the LDS, not the
 // registers, bounds the workgroups per CU; the tape variant needs the hint.
 template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
@@ -585,12 +611,13 @@ fwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int
 // point idx[l] (g non-finite -> 0).
 template <int D, typename T, int B, bool WIDE, int K>
 __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
-                                 const T* __restrict__ tape, const T* __restrict__ g, int S, int r0)
+                                 const T* __restrict__ tape, const T* __restrict__ g, int S, int r0,
+                                 uint32_t lds0, int tid)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    const int base = r0 + (int)threadIdx.x;
+    const int base = r0 + tid;
     uint32_t u[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = idx[min(base + k * B, S - 1)];
@@ -608,8 +635,8 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
         for (int k = 0; k < K; ++k) {
             const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
             const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-            lds_st(2 * o, V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y});
-            lds_st(2 * o + 4 * sizeof(T), V2{tv[k].z, tv[k].w});
+            lds_st(lds0 + 2 * o, V4{xv[k].x, xv[k].y, gg * tv[k].x, gg * tv[k].y});
+            lds_st(lds0 + 2 * o + 4 * sizeof(T), V2{tv[k].z, tv[k].w});
         }
     } else {
         Packed3<T> xv[K], pv[K], hv[K];
@@ -620,44 +647,57 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
             pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
             hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
         }
-        const uint32_t c1 = (uint32_t)round_up(S, 4) * sizeof(T), c2 = 5 * c1;
+        const uint32_t r4 = (uint32_t)round_up(S, 4) * sizeof(T), c1 = lds0 + r4, c2 = lds0 + 5 * r4;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
             const T gg = isfinite(gu[k]) ? gu[k] : T(0);
             lds_st(2 * o + c1, V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a});
             lds_st(2 * o + c2, V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b});
-            lds_st(o >> 1, gg * pv[k].c);
+            lds_st(lds0 + (o >> 1), gg * pv[k].c);
         }
     }
 }
 
-// SIG: sigma_j from the tape (non-symmetric stencil).  Otherwise S^T = S, the
-// walk visits exactly the stencil of j, and sigma_j = h_j . sum_i (x_i - x_j)
-// is formed from the same differences.
-template <int D, typename T, int B, bool WIDE, bool SIG>
-__global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec,
-                                                  int n_tiles, const T* __restrict__ x, const T* __restrict__ tape,
-                                                  int64_t n, const T* __restrict__ g, T* __restrict__ grad)
+// Staging of an adjoint tile by B threads (tid in [0, B)) into the LDS region
+// at lds0 (as fwd_stage_tile).
+template <int D, typename T, int B, bool WIDE>
+__device__ __forceinline__ void bwd_stage_tile(const TileMeta m, const uint4* __restrict__ rec,
+                                               const T* __restrict__ x, const T* __restrict__ tape,
+                                               const T* __restrict__ g, const uint32_t lds0, const int tid)
 {
-    using V2 = vec2_t<T>;
-    using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
     const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
     const int S = P + H;
     const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
     const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-    const uint32_t seg = (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment (LDS starts at 0)
+    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment
+    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8), tid);
+    stage_points<B>(S, [&](auto kc, int r0) {
+        bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0, lds0, tid);
+    });
+}
+
+// The gather of a staged adjoint tile by B threads (tid in [0, B)).
+// SIG: sigma_j from the tape (non-symmetric stencil).  Otherwise S^T = S, the
+// walk visits exactly the stencil of j, and sigma_j = h_j . sum_i (x_i - x_j)
+// is formed from the same differences.
+template <int D, typename T, int B, bool WIDE, bool SIG>
+__device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const uint4* __restrict__ rec,
+                                                 const T* __restrict__ tape, const int64_t n, T* __restrict__ grad,
+                                                 const uint32_t lds0, const int tid)
+{
+    using V2 = vec2_t<T>;
+    using V4 = vec4_t<T>;
+    using L = Layout<D, T>;
+    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
+    const int S = P + H;
+    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
+    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment
     const uint32_t words = seg, rowend = seg + 4u * nw;
-
-    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8));
-    stage_points<B>(S, [&](auto kc, int r0) { bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0); });
-    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
-    __syncthreads();
-
-    const uint32_t c1 = (uint32_t)round_up(S, 4) * sizeof(T), c2 = 5 * c1;   // 3D: the two 4-value arrays
-    for (int l = threadIdx.x; l < P; l += B) {
+    // 2D: the slot array at lds0; 3D: w2 at lds0 and the two 4-value arrays
+    const uint32_t r4 = (uint32_t)round_up(S, 4) * sizeof(T), c0 = lds0, c1 = lds0 + r4, c2 = lds0 + 5 * r4;
+    for (int l = tid; l < P; l += B) {
         const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
         const int e = lds_ld<uint16_t>(rowend + 2u * l);
         const uint32_t u = idx[l];
@@ -665,7 +705,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
         if constexpr (SIG) sig = rec_at<WIDE, T>(tape + (size_t)n * (2 * D), u, sizeof(T));
         const uint32_t oself = (uint32_t)l * L::unit;
         if constexpr (D == 2) {
-            const V4 cj = lds_ld<V4>(2 * oself);
+            const V4 cj = lds_ld<V4>(c0 + 2 * oself);
             T a0 = 0, a1 = 0, s0 = 0, s1 = 0;
             struct Q {
                 V4 a;
@@ -673,7 +713,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
             };
             auto at = [&](uint32_t j) {
                 const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(2 * o), lds_ld<V2>(2 * o + 4 * sizeof(T))};
+                return Q{lds_ld<V4>(c0 + 2 * o), lds_ld<V2>(c0 + 2 * o + 4 * sizeof(T))};
             };
             walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
@@ -689,14 +729,14 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
                 }
             });
             if constexpr (!SIG) {
-                const V2 hj = lds_ld<V2>(2 * oself + 4 * sizeof(T));
+                const V2 hj = lds_ld<V2>(c0 + 2 * oself + 4 * sizeof(T));
                 sig = -(hj.x * s0 + hj.y * s1);
             }
             rec_put<WIDE>(grad, u, sizeof(V2), V2{a0 - sig * cj.z, a1 - sig * cj.w});
         } else {
             const V4 cj = lds_ld<V4>(2 * oself + c1);
             const V4 cb = lds_ld<V4>(2 * oself + c2);
-            const T cw2 = lds_ld<T>(oself >> 1);
+            const T cw2 = lds_ld<T>(c0 + (oself >> 1));
             T a0 = 0, a1 = 0, a2 = 0, s0 = 0, s1 = 0, s2 = 0;
             struct Q {
                 V4 a, b;
@@ -704,7 +744,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
             };
             auto at = [&](uint32_t j) {
                 const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(2 * o + c1), lds_ld<V4>(2 * o + c2), lds_ld<T>(o >> 1)};
+                return Q{lds_ld<V4>(2 * o + c1), lds_ld<V4>(2 * o + c2), lds_ld<T>(c0 + (o >> 1))};
             };
             walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
@@ -725,6 +765,18 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
             rec_put<WIDE>(grad, u, sizeof(Packed3<T>), Packed3<T>{a0 - sig * cb.z, a1 - sig * cb.w, a2 - sig * cw2});
         }
     }
+}
+
+template <int D, typename T, int B, bool WIDE, bool SIG>
+__global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec,
+                                                  int n_tiles, const T* __restrict__ x, const T* __restrict__ tape,
+                                                  int64_t n, const T* __restrict__ g, T* __restrict__ grad)
+{
+    const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
+    bwd_stage_tile<D, T, B, WIDE>(m, rec, x, tape, g, 0u, (int)threadIdx.x);
+    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
+    __syncthreads();
+    bwd_compute_tile<D, T, B, WIDE, SIG>(m, rec, tape, n, grad, 0u, (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
