@@ -135,16 +135,28 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
  *   adjoint   0: tiles of the stencil S; 1: tiles of its transpose S^T used by
  *             the adjoint (the same tiles when S is symmetric, as RING1 is)
  *   n_tiles, record_bytes: sizes (either may be NULL)
- *   meta      host, n_tiles x 16 bytes: per tile uint32 {record offset in
- *             16-byte units, own points P, halo points H, stencil words nw}
- *   records   host, record_bytes bytes; per tile: uint32 caller indices of the
- *             P own points (a range of the Morton order) then of the H halo
- *             points, each part sorted, padded to a multiple of 4; then nw
- *             uint32 stencil words, each holding three
- *             10-bit local indices (positions in that index list) in bits
- *             0-9, 10-19 and 20-29, with every row padded to a multiple of 3
- *             entries by the point's own index; then P uint16 row ends
- *             (cumulative word counts); padded to a multiple of 16 bytes.
+ *   meta      host, n_tiles x 16 bytes: per tile a uint32 record offset in
+ *             16-byte units, then uint16 {P own points, H halo points, nw
+ *             stored stencil words, nr index runs, nx explicit rows, nwf
+ *             stencil words of all rows}
+ *   records   host, record_bytes bytes; per tile, 16-byte aligned, in this
+ *             order (S = P + H staged slots: the P own points, a range of the
+ *             Morton order, then the H halo points, each part ascending in
+ *             caller index; G = ceil(S/32), Q = ceil(P/32)):
+ *               uint32 words[nw]  stencil rows of the explicit rows, three
+ *                                 10-bit slots per word (bits 0-9, 10-19,
+ *                                 20-29), ascending, each row padded to a
+ *                                 multiple of 3 with the row's own slot
+ *               uint32 runs[nr]   per run of consecutive caller indices:
+ *                                 caller index of its first slot minus that
+ *                                 slot
+ *               uint32 smask[G]   bit l%32 of word l/32: slot l starts a run
+ *               uint32 xmask[Q]   bit l%32 of word l/32: row l is explicit
+ *               uint16 spre[G], xpre[Q]  set bits before each word
+ *               uint16 xlast[Q]   last explicit row before row 32 q
+ *               uint16 xend[nx]   cumulative word ends of the explicit rows
+ *             Row l is explicit unless it equals row l-1 with every slot
+ *             plus one; then it is its last explicit row a plus l - a.
  *             P + H <= 1024: larger nominal tiles are split when built.
  * meta and records may be NULL (sizes only).
  */

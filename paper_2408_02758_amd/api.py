@@ -98,28 +98,74 @@ class Mesh:
         check(_lib.load().ftle_mesh_tile_stats(self._h, *[ctypes.byref(v) for v in vals]))
         return dict(zip(["n_tiles", "max_tile_points", "halo_entries", "record_bytes"], [v.value for v in vals]))
 
-    def tiles(self, adjoint: bool = False):
-        """Raw tile records: list of (idx uint32[P+H], rowend uint16[P], entries uint16[3 nw], P, H).
-
-        entries are the neighbours' local indices (positions in idx), three per
-        stencil word, each row padded to a multiple of 3 with the point's own
-        index; rowend counts words."""
+    def tile_records(self, adjoint: bool = False):
+        """Raw tile records, one dict per tile: P, H and the record's arrays
+        (words, runs, smask, xmask, spre, xpre, xlast, xend)."""
         L = _lib.load()
         nt, rb = ctypes.c_int64(), ctypes.c_int64()
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), ctypes.byref(nt), ctypes.byref(rb), None, None))
         meta = np.empty((nt.value, 4), np.uint32)
         rec = np.empty(max(rb.value // 4, 1), np.uint32)
         check(L.ftle_mesh_get_tiles(self._h, int(adjoint), None, None, meta.ctypes.data, rec.ctypes.data))
+        h16 = meta.view(np.uint16).reshape(-1, 8)
         out = []
-        for off, P, H, nw in meta:
-            P, H, nw = int(P), int(H), int(nw)
-            base = int(off) * 4
-            iw = (P + H + 3) & ~3
-            idx = rec[base:base + P + H]
-            words = rec[base + iw:base + iw + nw]
-            ent = np.stack([words & 0x3FF, (words >> 10) & 0x3FF, words >> 20], 1).reshape(-1).astype(np.uint16)
-            rowend = rec[base + iw + nw:].view(np.uint16)[:P]
-            out.append((idx, rowend, ent, P, H))
+        for t in range(nt.value):
+            P, H, nw, nr, nx = (int(v) for v in h16[t, 2:7])
+            G, Q = (P + H + 31) // 32, (P + 31) // 32
+            b = int(meta[t, 0]) * 16   # byte offset
+            o_runs = 4 * nw
+            o_smask = o_runs + 4 * nr
+            o_xmask = o_smask + 4 * G
+            o_spre = o_xmask + 4 * Q
+            o_xpre = o_spre + 2 * G
+            o_xlast = o_xpre + 2 * Q
+            o_xend = o_xlast + 2 * Q
+            by = rec.view(np.uint8)
+
+            def arr(off, cnt, dt):
+                size = np.dtype(dt).itemsize
+                return by[b + off:b + off + cnt * size].view(dt).copy()
+
+            out.append(dict(P=P, H=H, nwf=int(h16[t, 7]), words=arr(0, nw, np.uint32),
+                            runs=arr(o_runs, nr, np.uint32), smask=arr(o_smask, G, np.uint32),
+                            xmask=arr(o_xmask, Q, np.uint32), spre=arr(o_spre, G, np.uint16),
+                            xpre=arr(o_xpre, Q, np.uint16), xlast=arr(o_xlast, Q, np.uint16),
+                            xend=arr(o_xend, nx, np.uint16)))
+        return out
+
+    def tiles(self, adjoint: bool = False):
+        """Tile records decoded: list of (idx uint32[P+H], rowend uint16[P],
+        entries uint16[3 nwf], P, H).
+
+        idx is the caller index of every staged slot; entries are the
+        neighbours' local indices (slots), three per stencil word, each row
+        padded to a multiple of 3 with the point's own slot; rowend counts
+        words.  Rows that the record stores as shifts of an earlier row are
+        expanded."""
+        out = []
+        for r in self.tile_records(adjoint):
+            P, H = r["P"], r["H"]
+            S = P + H
+            bits = lambda m, k: ((m[:, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(-1)[:k].astype(bool)
+            starts = bits(r["smask"], S)
+            run_of = np.cumsum(starts) - 1
+            idx = (r["runs"][run_of].astype(np.uint64) + np.arange(S, dtype=np.uint64)) % (1 << 32)
+            w = r["words"]
+            ent_x = np.stack([w & 0x3FF, (w >> 10) & 0x3FF, w >> 20], 1).reshape(-1).astype(np.int64)
+            xend = r["xend"].astype(np.int64)
+            expl = np.flatnonzero(bits(r["xmask"], P))
+            rows, ends, pos = [], [], 0
+            k = -1
+            for l in range(P):
+                if k + 1 < len(expl) and expl[k + 1] == l:
+                    k += 1
+                a = int(expl[k])
+                s0 = int(xend[k - 1]) if k else 0
+                rows.append(ent_x[3 * s0:3 * int(xend[k])] + (l - a))
+                pos += len(rows[-1]) // 3
+                ends.append(pos)
+            ent = np.concatenate(rows).astype(np.uint16) if rows else np.zeros(0, np.uint16)
+            out.append((idx.astype(np.uint32), np.array(ends, np.uint16), ent, P, H))
         return out
 
     def set_blocks(self, fwd: int = 0, adjoint: int = 0):

@@ -191,7 +191,7 @@ struct TileSet {
     std::vector<TileMeta> meta;
     std::vector<uint32_t> rec;     // record words (16-byte aligned blocks)
     int max_staged = 0;
-    int max_seg = 0;
+    int max_rec = 0;
     int max_P = 0;
     int64_t halo_total = 0;
     void* d_meta = nullptr;
@@ -204,7 +204,7 @@ struct TileSet {
         d.rec = static_cast<const uint4*>(d_rec);
         d.n_tiles = (int)meta.size();
         d.max_staged = max_staged;
-        d.max_seg = max_seg;
+        d.max_rec = max_rec;
         return d;
     }
 };
@@ -380,12 +380,117 @@ int64_t padded_words(const Csr& a, int64_t b, int64_t e)
     return t;
 }
 
+// nw: the padded stencil words of all P rows.  The record is checked at its
+// largest (every row explicit, one run per slot).
 bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nw)
 {
     if (P + H > kMaxStaged || nw > kMaxTileWords) return false;
-    const int seg = (int)seg_halfs((uint32_t)P, (uint32_t)nw);
+    const RecLayout r = rec_layout((uint32_t)P, (uint32_t)H, (uint32_t)nw, (uint32_t)(P + H), (uint32_t)P);
     const size_t slot = std::max(fwd_slot_bytes(dim, f64), bwd_slot_bytes(dim, f64));
-    return tile_lds_bytes(slot, (int)(P + H), seg) <= kLdsBudget;
+    return tile_lds_bytes(slot, (int)(P + H), r.bytes) <= kLdsBudget;
+}
+
+// The record of one tile (layout in ftle_internal.h): own points [b, e) of
+// the Morton order, halo `halo` (ascending in caller index).
+void tile_record(const Csr& a, const std::vector<int32_t>& perm, int64_t b, int64_t e,
+                 const std::vector<int32_t>& halo, TileMeta& m, std::vector<uint32_t>& out)
+{
+    const uint32_t P = (uint32_t)(e - b), H = (uint32_t)halo.size(), S = P + H;
+    // own points take slots in caller order, as the halo does: adjacent lanes
+    // then load and store adjacent caller-order entries
+    std::vector<int32_t> order((size_t)P), slot((size_t)P);
+    for (int64_t r = b; r < e; ++r) order[r - b] = (int32_t)r;
+    std::sort(order.begin(), order.end(), [&](int32_t u, int32_t v) { return perm[u] < perm[v]; });
+    std::vector<uint32_t> caller(S);
+    for (uint32_t l = 0; l < P; ++l) {
+        caller[l] = (uint32_t)perm[order[l]];
+        slot[order[l] - b] = (int32_t)l;
+    }
+    std::vector<std::pair<int32_t, int32_t>> hs(H);   // (Morton position, slot) of the halo
+    for (uint32_t h = 0; h < H; ++h) {
+        caller[P + h] = (uint32_t)perm[halo[h]];
+        hs[h] = {halo[h], (int32_t)(P + h)};
+    }
+    std::sort(hs.begin(), hs.end());
+
+    // runs of consecutive caller indices
+    std::vector<uint32_t> runs;
+    std::vector<uint8_t> starts(S, 0);
+    for (uint32_t l = 0; l < S; ++l)
+        if (l == 0 || caller[l] != caller[l - 1] + 1u) {
+            starts[l] = 1;
+            runs.push_back(caller[l] - l);
+        }
+
+    // rows: local indices ascending, padded with the row's own slot; a row
+    // equal to the previous one plus one is not stored
+    std::vector<uint32_t> words, prev, row;
+    std::vector<uint16_t> xend;
+    std::vector<uint8_t> expl(P, 0);
+    uint32_t nwf = 0;
+    for (uint32_t l = 0; l < P; ++l) {
+        const int64_t r = order[l];
+        row.clear();
+        for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
+            const int32_t c = a.col[p];
+            if (c >= b && c < e) {
+                row.push_back((uint32_t)slot[c - b]);
+            } else {
+                auto it = std::lower_bound(hs.begin(), hs.end(), std::make_pair(c, INT32_MIN));
+                row.push_back((uint32_t)it->second);
+            }
+        }
+        std::sort(row.begin(), row.end());
+        while (row.size() % 3) row.push_back(l);
+        nwf += (uint32_t)row.size() / 3;
+        bool shift = l > 0 && row.size() == prev.size();
+        for (size_t k = 0; shift && k < row.size(); ++k) shift = row[k] == prev[k] + 1u;
+        if (!shift) {
+            expl[l] = 1;
+            for (size_t k = 0; k < row.size(); k += 3) words.push_back(row[k] | row[k + 1] << 10 | row[k + 2] << 20);
+            xend.push_back((uint16_t)words.size());
+        }
+        prev.swap(row);
+    }
+
+    m.P = (uint16_t)P;
+    m.H = (uint16_t)H;
+    m.nw = (uint16_t)words.size();
+    m.nr = (uint16_t)runs.size();
+    m.nx = (uint16_t)xend.size();
+    m.nwf = (uint16_t)nwf;
+    const RecLayout L = rec_layout(m);
+    out.assign(L.bytes / 4, 0u);
+    unsigned char* base = reinterpret_cast<unsigned char*>(out.data());
+    std::memcpy(base, words.data(), words.size() * 4);
+    std::memcpy(base + L.runs, runs.data(), runs.size() * 4);
+    uint32_t* smask = reinterpret_cast<uint32_t*>(base + L.smask);
+    uint32_t* xmask = reinterpret_cast<uint32_t*>(base + L.xmask);
+    uint16_t* spre = reinterpret_cast<uint16_t*>(base + L.spre);
+    uint16_t* xpre = reinterpret_cast<uint16_t*>(base + L.xpre);
+    uint16_t* xlast = reinterpret_cast<uint16_t*>(base + L.xlast);
+    uint32_t cnt = 0;
+    for (uint32_t l = 0; l < S; ++l) {
+        if (l % 32 == 0) spre[l / 32] = (uint16_t)cnt;
+        if (starts[l]) {
+            smask[l / 32] |= 1u << (l % 32);
+            ++cnt;
+        }
+    }
+    cnt = 0;
+    uint32_t last = 0;
+    for (uint32_t l = 0; l < P; ++l) {
+        if (l % 32 == 0) {
+            xpre[l / 32] = (uint16_t)cnt;
+            xlast[l / 32] = (uint16_t)last;
+        }
+        if (expl[l]) {
+            xmask[l / 32] |= 1u << (l % 32);
+            ++cnt;
+            last = l;
+        }
+    }
+    std::memcpy(base + L.xend, xend.data(), xend.size() * 2);
 }
 
 TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
@@ -427,86 +532,38 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
     std::vector<TileExtent> ext;
     for (auto& v : per_chunk) ext.insert(ext.end(), v.begin(), v.end());
 
-    // 2. record offsets
+    // 2. records, then their offsets
     TileSet ts;
     ts.meta.resize(ext.size());
-    uint64_t off = 0;  // in 16-byte units
-    for (size_t t = 0; t < ext.size(); ++t) {
-        const uint32_t P = (uint32_t)(ext[t].end - ext[t].begin);
-        const uint64_t words = idx_words(P, ext[t].H) + seg_halfs(P, ext[t].nw) / 2;
-        if (off > UINT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "tile records exceed 64 GiB");
-        ts.meta[t] = TileMeta{(uint32_t)off, P, ext[t].H, ext[t].nw};
-        off += words / 4;
-        ts.max_staged = std::max(ts.max_staged, (int)(P + ext[t].H));
-        ts.max_seg = std::max(ts.max_seg, (int)seg_halfs(P, ext[t].nw));
-        ts.max_P = std::max(ts.max_P, (int)P);
-        ts.halo_total += ext[t].H;
-    }
-    ts.rec.assign(off * 4, 0u);
-
-    // 3. fill records
+    std::vector<std::vector<uint32_t>> recs(ext.size());
     parallel_for((int64_t)ext.size(), [&](int64_t tb, int64_t te, int) {
         std::vector<uint32_t> stamp(n, 0);
         std::vector<int32_t> halo;
-        std::vector<int32_t> order, slot;   // own points in caller order; Morton position -> slot
         uint32_t tag = 0;
         for (int64_t t = tb; t < te; ++t) {
-            const TileMeta m = ts.meta[t];
-            const int64_t b = ext[t].begin, e = ext[t].end;
             if (++tag == 0) {
                 std::fill(stamp.begin(), stamp.end(), 0);
                 tag = 1;
             }
-            tile_halo(a, perm, b, e, stamp, tag, halo);
-            uint32_t* idx = ts.rec.data() + (size_t)m.rec_off * 4;
-            uint32_t* words = idx + idx_words(m.P, m.H);
-            uint16_t* rowend = reinterpret_cast<uint16_t*>(words + m.nw);
-            // Own points take slots in caller order (as the halo does): adjacent
-            // lanes then load and store adjacent caller-order entries.
-            order.resize((size_t)(e - b));
-            slot.resize((size_t)(e - b));
-            for (int64_t r = b; r < e; ++r) order[r - b] = (int32_t)r;
-            std::sort(order.begin(), order.end(), [&](int32_t u, int32_t v) { return perm[u] < perm[v]; });
-            for (size_t l = 0; l < order.size(); ++l) {
-                idx[l] = (uint32_t)perm[order[l]];
-                slot[order[l] - b] = (int32_t)l;
-            }
-            // halo slot of each halo point: reuse stamp as "slot + 1" storage is
-            // not possible (tag), so search in a small map
-            std::vector<std::pair<int32_t, int32_t>> hs(halo.size());
-            for (size_t h = 0; h < halo.size(); ++h) {
-                idx[m.P + h] = (uint32_t)perm[halo[h]];
-                hs[h] = {halo[h], (int32_t)(m.P + h)};
-            }
-            std::sort(hs.begin(), hs.end());
-            uint32_t pos = 0;   // words written
-            for (uint32_t l = 0; l < m.P; ++l) {
-                const int64_t r = order[l];
-                uint32_t word = 0;
-                int k = 0;   // entries in `word`
-                for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
-                    const int32_t c = a.col[p];
-                    int32_t loc;
-                    if (c >= b && c < e) {
-                        loc = slot[c - b];
-                    } else {
-                        auto it = std::lower_bound(hs.begin(), hs.end(), std::make_pair(c, INT32_MIN));
-                        loc = it->second;
-                    }
-                    word |= (uint32_t)loc << (10 * k);
-                    if (++k == 3) {
-                        words[pos++] = word;
-                        word = 0;
-                        k = 0;
-                    }
-                }
-                if (k) {   // pad the row with the point itself
-                    for (; k < 3; ++k) word |= l << (10 * k);
-                    words[pos++] = word;
-                }
-                rowend[l] = (uint16_t)pos;
-            }
+            tile_halo(a, perm, ext[t].begin, ext[t].end, stamp, tag, halo);
+            tile_record(a, perm, ext[t].begin, ext[t].end, halo, ts.meta[t], recs[t]);
         }
+    }, 1);
+    uint64_t off = 0;  // in 16-byte units
+    for (size_t t = 0; t < ext.size(); ++t) {
+        if (off > UINT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "tile records exceed 64 GiB");
+        TileMeta& m = ts.meta[t];
+        m.rec_off = (uint32_t)off;
+        off += recs[t].size() / 4;
+        ts.max_staged = std::max(ts.max_staged, (int)(m.P + m.H));
+        ts.max_rec = std::max(ts.max_rec, (int)(recs[t].size() * 4));
+        ts.max_P = std::max(ts.max_P, (int)m.P);
+        ts.halo_total += m.H;
+    }
+    ts.rec.resize(off * 4);
+    parallel_for((int64_t)ext.size(), [&](int64_t tb, int64_t te, int) {
+        for (int64_t t = tb; t < te; ++t)
+            std::copy(recs[t].begin(), recs[t].end(), ts.rec.begin() + (size_t)ts.meta[t].rec_off * 4);
     }, 1);
     return ts;
 }
@@ -1049,7 +1106,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
         const ftle_mesh_t m = meshes[k];
         p->wide = p->wide || batched_needs_wide(p->dim, p->f64, m->n);
         maxt.max_staged = std::max(maxt.max_staged, m->fwd.max_staged);
-        maxt.max_seg = std::max(maxt.max_seg, m->fwd.max_seg);
+        maxt.max_rec = std::max(maxt.max_rec, m->fwd.max_rec);
         const DevTiles dt = m->fwd.dev();
         for (size_t t = 0; t < m->fwd.meta.size(); ++t) {
             const TileMeta& tm = m->fwd.meta[t];
@@ -1059,7 +1116,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
             e.it.x = m->d_x;
             e.it.fp64_hits = m->d_hits;
             e.it.mesh = (uint32_t)k;
-            e.cost = 3 * tm.nw + tm.P + tm.H;
+            e.cost = 3 * tm.nwf + tm.P + tm.H;
             items.push_back(e);
             max_cost = std::max(max_cost, e.cost);
         }

@@ -13,31 +13,48 @@ namespace ftle {
 // Tile records (device layout).
 //
 // The mesh's points are cut, in Morton order, into tiles of at most
-// tile_points points; one workgroup processes one tile.  A tile's record is
-// a contiguous, 16-byte aligned block:
+// tile_points points; one workgroup processes one tile.  The tile stages
+// S = P + H points: its own P points (a Morton range), then its H halo points
+// (neighbours owned by other tiles), each part in increasing caller (user)
+// index; slot l is the position of a staged point in that order, and the
+// stencil refers to staged points by slot ("local index").  A tile's record
+// is a contiguous, 16-byte aligned block, copied whole into LDS:
 //
-//   uint32 idx[P + H]         caller (user) index of every staged point: the
-//                             tile's own P points (a Morton range), then its H
-//                             halo points (neighbours owned by other tiles),
-//                             each part in increasing caller index, padded to
-//                             a multiple of 4 entries
-//   uint32 words[nw]          the stencil rows of the own points, three
-//                             10-bit local indices (positions in idx) per
-//                             word, in bits 0-9, 10-19 and 20-29; every row
-//                             is padded to a multiple of 3 entries with the
-//                             point's own index
-//   uint16 rowend[P]          end of each row (cumulative, in words)
-//                             (words and rowend: the "segment", padded to a
-//                             multiple of 16 bytes)
+//   uint32 words[nw]   stencil rows of the explicit rows (below): three
+//                      10-bit local indices per word, in bits 0-9, 10-19 and
+//                      20-29; a row's entries ascend and are padded to a
+//                      multiple of 3 with the row's own slot
+//   uint32 runs[nr]    run r (a maximal stretch of slots with consecutive
+//                      caller indices): caller index of its first slot minus
+//                      that slot, so that slot l of run r is point runs[r] + l
+//   uint32 smask[G]    bit i of smask[g]: slot 32 g + i starts a run
+//   uint32 xmask[Q]    bit i of xmask[q]: row 32 q + i is explicit
+//   uint16 spre[G]     runs that start before slot 32 g
+//   uint16 xpre[Q]     explicit rows before row 32 q
+//   uint16 xlast[Q]    the last explicit row before row 32 q
+//   uint16 xend[nx]    end of explicit row k in words (cumulative)
+//   (zero padding to a multiple of 16 bytes)
+//
+// with G = ceil(S / 32) and Q = ceil(P / 32).  Row l (the stencil of own slot
+// l) is explicit unless l > 0 and it equals row l - 1 with every entry plus
+// one; a row that is not explicit therefore equals its anchor, the last
+// explicit row a <= l, with every entry plus l - a.  On a mesh whose points
+// are numbered along grid lines most rows are such shifts, and the runs are
+// the grid lines crossing the tile; on any other mesh the record degrades to
+// one explicit row per point and one run per slot.
 //
 // 10-bit indices and 16-bit row ends are enough because P + H <= kMaxStaged
-// and nw <= kMaxTileWords, both enforced when the mesh is built.
+// and the explicit words stay <= kMaxTileWords, both enforced when the mesh
+// is built.
 // ---------------------------------------------------------------------------
 struct TileMeta {
     uint32_t rec_off;  // record offset in 16-byte units
-    uint32_t P;        // own points
-    uint32_t H;        // halo points
-    uint32_t nw;       // stencil words of the own points (3 entries each, rows padded)
+    uint16_t P;        // own points
+    uint16_t H;        // halo points
+    uint16_t nw;       // stencil words of the explicit rows
+    uint16_t nr;       // runs
+    uint16_t nx;       // explicit rows
+    uint16_t nwf;      // stencil words of all rows (the tile's work; host only)
 };
 static_assert(sizeof(TileMeta) == 16, "TileMeta is one 16-byte load");
 
@@ -46,9 +63,29 @@ constexpr int kMaxTileWords = 65535;   // stencil words per tile: 16-bit row end
 constexpr size_t kLdsBudget = 65536;   // LDS bytes one tile may stage (forward or adjoint)
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
-__host__ __device__ inline uint32_t idx_words(uint32_t P, uint32_t H) { return (P + H + 3u) & ~3u; }
-// segment size in 16-bit units (a multiple of 8, i.e. of 16 bytes)
-__host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nw) { return (2u * nw + P + 7u) & ~7u; }
+
+// Byte offsets of the record's arrays (words at 0) and its padded size.
+struct RecLayout {
+    uint32_t runs, smask, xmask, spre, xpre, xlast, xend, bytes;
+};
+__host__ __device__ inline RecLayout rec_layout(uint32_t P, uint32_t H, uint32_t nw, uint32_t nr, uint32_t nx)
+{
+    const uint32_t G = (P + H + 31u) / 32u, Q = (P + 31u) / 32u;
+    RecLayout r;
+    r.runs = 4u * nw;
+    r.smask = r.runs + 4u * nr;
+    r.xmask = r.smask + 4u * G;
+    r.spre = r.xmask + 4u * Q;
+    r.xpre = r.spre + 2u * G;
+    r.xlast = r.xpre + 2u * Q;
+    r.xend = r.xlast + 2u * Q;
+    r.bytes = (r.xend + 2u * nx + 15u) & ~15u;
+    return r;
+}
+__host__ __device__ inline RecLayout rec_layout(const TileMeta& m)
+{
+    return rec_layout(m.P, m.H, m.nw, m.nr, m.nx);
+}
 
 // LDS bytes per staged point, in units of the value size e (4 or 8 bytes):
 //   forward  2D: 4e, one slot (x0, x1, phi0, phi1)
@@ -57,14 +94,14 @@ __host__ __device__ inline uint32_t seg_halfs(uint32_t P, uint32_t nw) { return 
 //   adjoint  2D: 8e, one slot (x0, x1, w0, w1) (h0, h1, -, -)
 //            3D: 9e, three arrays: w2 slots of e, then (x0, x1, x2, h0)
 //                slots of 4e, then (h1, h2, w0, w1) slots of 4e
-// Each array holds round_up(P + H, 4) slots, so every array and the segment
-// after them start 16-byte aligned.
+// Each array holds round_up(P + H, 4) slots, so every array and the record
+// copy after them start 16-byte aligned.
 __host__ __device__ inline size_t elem_bytes(bool f64) { return f64 ? 8 : 4; }
 __host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 4 : 6); }
 __host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 8 : 9); }
-__host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, int seg)
+__host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, size_t rec_bytes)
 {
-    return (size_t)round_up(staged, 4) * slot_bytes + (size_t)seg * 2;
+    return (size_t)round_up(staged, 4) * slot_bytes + rec_bytes;
 }
 
 // One tile set: the tiles of one stencil (the forward stencil, or its
@@ -74,7 +111,7 @@ struct DevTiles {
     const uint4* rec;
     int n_tiles;
     int max_staged;   // max over tiles of P + H
-    int max_seg;      // max over tiles of seg_halfs(P, nw)
+    int max_rec;      // max over tiles of the record bytes
 };
 
 // One work item of a batched launch: a tile of one mesh, with everything the

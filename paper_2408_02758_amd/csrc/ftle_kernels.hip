@@ -139,8 +139,8 @@ __device__ inline int xcd_tile(int bid, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Staged points in LDS.  Staged point l (point idx[l]; l is the stencil
-// entry) has o = l * unit; with e = sizeof(T) and R = round_up(P + H, 4):
+// Staged points in LDS.  Staged slot l (l is the stencil's local index) has
+// o = l * unit; with e = sizeof(T) and R = round_up(P + H, 4):
 //   forward 2D: (x0, x1, phi0, phi1) at o                     (unit 4e)
 //   forward 3D: (phi1, phi2) at o, (x0, x1, x2, phi0) at
 //               2 o + 2eR                                     (unit 2e)
@@ -148,9 +148,8 @@ __device__ inline int xcd_tile(int bid, int n)
 //   adjoint 3D: w2 at o / 2, (x0, x1, x2, h0) at 2 o + eR,
 //               (h1, h2, w0, w1) at 2 o + 5eR
 // so that 16-byte reads are 16-byte aligned, no LDS is padding in 3D, and
-// neighbouring points sit in neighbouring banks.  The tile's segment follows:
-// the padded stencil (nw words of three 10-bit entries), then the P 16-bit
-// row ends.
+// neighbouring points sit in neighbouring banks.  A copy of the tile's record
+// follows.
 // ---------------------------------------------------------------------------
 template <int D, typename T> struct Layout {
     static constexpr uint32_t e = sizeof(T);
@@ -159,12 +158,12 @@ template <int D, typename T> struct Layout {
     static constexpr uint32_t bwd = (D == 2 ? 8 : 9) * e;
 };
 
-// Copy of a tile's segment (stencil words and row ends, n16 chunks of 16
-// bytes) into LDS as a direct global -> LDS transfer
+// Copy of a tile's record (n16 chunks of 16 bytes) into LDS as a direct
+// global -> LDS transfer
 // (global_load_lds_dwordx4): each wave moves 64 consecutive 16-byte chunks to
 // consecutive LDS chunks without passing through registers, so the copy stays
-// in flight while the caller issues other loads.  The caller waits (vmcnt 0)
-// and synchronises the workgroup before reading dst.
+// in flight while the wave issues other instructions.  The caller waits
+// (vmcnt 0) and synchronises the workgroup before reading dst.
 template <int B>
 __device__ inline void dma_segment(const uint4* __restrict__ src, uint32_t dst, int n16, int tid)
 {
@@ -214,6 +213,35 @@ __device__ inline void walk_row(uint32_t words, int s, int e, F&& visit)
         const uint32_t w0 = lds_ld<uint32_t>(words + 4u * k);
         visit(ix(w0, 0), ix(w0, 1), ix(w0, 2));
     }
+}
+
+// Decoding of a tile record held in LDS at address rec (layout R).
+// Caller index of staged slot l: its run is the last one starting at or
+// before l.
+__device__ inline uint32_t slot_point(uint32_t rec, const RecLayout& R, int l)
+{
+    const int g = l >> 5;
+    const uint32_t m = lds_ld<uint32_t>(rec + R.smask + 4u * g) & (0xffffffffu >> (31 - (l & 31)));
+    const int r = (int)lds_ld<uint16_t>(rec + R.spre + 2u * g) + __popc(m) - 1;
+    return lds_ld<uint32_t>(rec + R.runs + 4u * r) + (uint32_t)l;
+}
+
+// Row of own slot l: the words [s, e) of its anchor (the last explicit row
+// a <= l) and the shift l - a that every entry takes.
+struct RowRef {
+    int s, e, shift;
+};
+__device__ inline RowRef row_ref(uint32_t rec, const RecLayout& R, int l)
+{
+    const int q = l >> 5;
+    const uint32_t m = lds_ld<uint32_t>(rec + R.xmask + 4u * q) & (0xffffffffu >> (31 - (l & 31)));
+    const int pre = lds_ld<uint16_t>(rec + R.xpre + 2u * q);
+    const int last = lds_ld<uint16_t>(rec + R.xlast + 2u * q);
+    const int a = m ? (q << 5) + 31 - __clz((int)m) : last;
+    const int k = pre + __popc(m) - 1;   // explicit row number of a
+    const int s = k ? lds_ld<uint16_t>(rec + R.xend + 2u * (k - 1)) : 0;
+    const int e = lds_ld<uint16_t>(rec + R.xend + 2u * k);
+    return RowRef{s, e, l - a};
 }
 
 // ---------------------------------------------------------------------------
@@ -289,18 +317,17 @@ __device__ __noinline__ float lam_max3_f64_from_J(float j00, float j01, float j0
 }
 
 // ---------------------------------------------------------------------------
-// Staging of the tile's points (own + halo) into their LDS slots.  One round
-// stages K slots per thread: K index loads, then the 2K gathers (coordinates
-// and flow map), then the K LDS stores.  K is a compile-time constant and the
-// loads and stores are unconditional, so the compiler counts outstanding
-// loads exactly and every gather waits only for its own index: one index
-// round trip and one gather round trip per round.  (With loads under
-// per-slot branches it must wait for all outstanding loads before each
-// gather.)  Lanes past the last slot S-1 load slot S-1's point and store the
-// same values to it again.
+// Staging of the tile's points (own + halo) into their LDS slots, once the
+// record is in LDS.  One round stages K slots per thread: K caller indices
+// decoded from the record, then the 2K gathers (coordinates and flow map),
+// then the K LDS stores.  K is a compile-time constant and the loads and
+// stores are unconditional, so the compiler counts outstanding loads exactly:
+// one gather round trip per round.  (With loads under per-slot branches it
+// must wait for all outstanding loads before each gather.)  Lanes past the
+// last slot S-1 load slot S-1's point and store the same values to it again.
 // ---------------------------------------------------------------------------
 template <int D, typename T, int B, bool WIDE, int K>
-__device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
+__device__ inline void fwd_stage(uint32_t rec, const RecLayout& R, const T* __restrict__ x,
                                  const T* __restrict__ flow, int S, int r0, uint32_t lds0, int tid)
 {
     using V2 = vec2_t<T>;
@@ -309,7 +336,7 @@ __device__ inline void fwd_stage(const uint32_t* __restrict__ idx, const T* __re
     const int base = r0 + tid;
     uint32_t u[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = idx[min(base + k * B, S - 1)];
+    for (int k = 0; k < K; ++k) u[k] = slot_point(rec, R, min(base + k * B, S - 1));
     if constexpr (D == 2) {
         V2 xv[K], fv[K];
 #pragma unroll
@@ -364,8 +391,8 @@ __device__ inline void stage_points(int S, F&& round)
 // eigenvector of C (TAPE 1), and also sigma = h . sum_j dx (TAPE 2; with a
 // symmetric stencil the adjoint forms sigma itself).
 // ---------------------------------------------------------------------------
-// Staging of a forward tile by B threads (tid in [0, B)) into the LDS
-// region at lds0: the stencil segment straight to LDS, then the staged points
+// Staging of a forward tile by the workgroup's B threads (tid in [0, B)) into
+// the LDS region at lds0: the record straight to LDS, then the staged points
 // in rounds of K slots per thread (fwd_stage).  The caller waits (vmcnt 0)
 // and synchronises before the compute.
 template <int D, typename T, int B, bool WIDE>
@@ -374,37 +401,38 @@ __device__ __forceinline__ void fwd_stage_tile(const TileMeta m, const uint4* __
                                                const uint32_t lds0, const int tid)
 {
     using L = Layout<D, T>;
-    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
-    const int S = P + H;
-    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
-    const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the segment
-    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8), tid);
+    const int S = (int)m.P + (int)m.H;
+    const RecLayout R = rec_layout(m);
+    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the record
+    dma_segment<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
+    __syncthreads();
     stage_points<B>(S, [&](auto kc, int r0) {
-        fwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, flow, S, r0, lds0, tid);
+        fwd_stage<D, T, B, WIDE, decltype(kc)::value>(recl, R, x, flow, S, r0, lds0, tid);
     });
 }
 
 // The compute of a staged forward tile by B threads (tid in [0, B)).
 template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
-__device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const uint4* __restrict__ rec, const T inv2T,
-                                                 T* __restrict__ out, T* __restrict__ tape, const int64_t n,
-                                                 const float eig_tau, unsigned long long* hits,
-                                                 const uint32_t lds0, const int tid)
+__device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T, T* __restrict__ out,
+                                                 T* __restrict__ tape, const int64_t n, const float eig_tau,
+                                                 unsigned long long* hits, const uint32_t lds0, const int tid)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
-    const int S = P + H;
-    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
-    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the segment
-    const uint32_t words = seg, rowend = seg + 4u * nw;
+    const int P = (int)m.P;
+    const int S = P + (int)m.H;
+    const RecLayout R = rec_layout(m);
+    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the record
+    const uint32_t words = recl;
     const uint32_t abase = lds0 + (uint32_t)round_up(S, 4) * 2 * sizeof(T);   // 3D: (x0, x1, x2, phi0) array
+    uint32_t redone = 0;   // points of this lane that took the float64 recompute
     for (int l = tid; l < P; l += B) {
-        const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
-        const int e = lds_ld<uint16_t>(rowend + 2u * l);
-        const uint32_t u = idx[l];
+        const RowRef row = row_ref(recl, R, l);
+        const int s = row.s, e = row.e;
+        const uint32_t sh = (uint32_t)row.shift * L::unit;   // the row's entries are its anchor's plus shift
+        uint32_t u;   // caller index of slot l, decoded after the walk (one register less in it)
         const uint32_t oself = (uint32_t)l * L::unit;
         T f;
         if constexpr (D == 2) {
@@ -425,11 +453,13 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const uint4* 
                     s1 += dx1;
                 }
             };
-            auto at = [&](uint32_t j) { return lds_ld<V4>(lds0 + j * L::unit); };
+            const uint32_t b0 = lds0 + sh;
+            auto at = [&](uint32_t j) { return lds_ld<V4>(b0 + j * L::unit); };
             walk_row<2>(words, s, e, [&](auto... o) {
                 const V4 q[] = {at(o)...};
                 for (const V4& v : q) acc(v);
             });
+            u = slot_point(recl, R, l);
             const T det = m00 * m11 - m01 * m01;
             const T trh = (m00 + m11) * T(0.5);
             const bool ok = det > rank_tau<T>() * trh * trh;
@@ -495,14 +525,18 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const uint4* 
                     s2 += dx2;
                 }
             };
+            // one per-lane base: slot j of the (phi1, phi2) array at t = b0 + j unit,
+            // of the (x0, x1, x2, phi0) array at 2 t + (abase - 2 lds0)
+            const uint32_t b0 = lds0 + sh, kx = abase - 2 * lds0;
             auto at = [&](uint32_t j) {
-                const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(2 * o + abase), lds_ld<V2>(lds0 + o)};
+                const uint32_t t = b0 + j * L::unit;
+                return Q{lds_ld<V4>(2 * t + kx), lds_ld<V2>(t)};
             };
             walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
                 for (const Q& v : q) acc(v);
             });
+            u = slot_point(recl, R, l);
             // adjugate of M (symmetric)
             const T a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
             const T a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
@@ -531,11 +565,9 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const uint4* 
                 // Top pair nearly equal: c'(r) amplifies float rounding in r;
                 // redo the tensor and the eigenvalue in double from J.
                 const bool redo = ok && (r < -1.0f + eig_tau);
-                if (redo) lam = lam_max3_f64_from_J(j00, j01, j02, j10, j11, j12, j20, j21, j22);
-                if (hits) {
-                    const unsigned long long ball = __ballot(redo);
-                    if (ball && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)ball) - 1))
-                        atomicAdd(hits, (unsigned long long)__popcll(ball));
+                if (redo) {
+                    lam = lam_max3_f64_from_J(j00, j01, j02, j10, j11, j12, j20, j21, j22);
+                    ++redone;
                 }
             } else {
                 lam = lam_max3_trig(c00, c01, c02, c11, c12, c22, r);
@@ -574,6 +606,7 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const uint4* 
         }
         if constexpr (OUT) rec_put<WIDE>(out, u, sizeof(T), f);
     }
+    if (hits && redone) atomicAdd(hits, (unsigned long long)redone);   // rare: nearly equal top pairs
 }
 
 // One tile of the forward pass by the whole workgroup of B threads.
@@ -586,7 +619,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
     fwd_stage_tile<D, T, B, WIDE>(m, rec, x, flow, lds0, (int)threadIdx.x);
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
-    fwd_compute_tile<D, T, OUT, TAPE, B, WIDE>(m, rec, inv2T, out, tape, n, eig_tau, hits, lds0, (int)threadIdx.x);
+    fwd_compute_tile<D, T, OUT, TAPE, B, WIDE>(m, inv2T, out, tape, n, eig_tau, hits, lds0, (int)threadIdx.x);
 }
 
 // float: at most 64 VGPRs (8 waves per SIMD), so that the LDS, not the
@@ -607,10 +640,10 @@ fwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int
 // The tile set here is the one of the transposed stencil S^T (equal to S for
 // the symmetric one-ring stencil).  Points with non-finite g add nothing.
 // ---------------------------------------------------------------------------
-// Adjoint staging round (as fwd_stage): slot l holds x, h and w = g p of
-// point idx[l] (g non-finite -> 0).
+// Adjoint staging round (as fwd_stage): slot l holds x, h and w = g p of its
+// point (g non-finite -> 0).
 template <int D, typename T, int B, bool WIDE, int K>
-__device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __restrict__ x,
+__device__ inline void bwd_stage(uint32_t rec, const RecLayout& R, const T* __restrict__ x,
                                  const T* __restrict__ tape, const T* __restrict__ g, int S, int r0,
                                  uint32_t lds0, int tid)
 {
@@ -620,7 +653,7 @@ __device__ inline void bwd_stage(const uint32_t* __restrict__ idx, const T* __re
     const int base = r0 + tid;
     uint32_t u[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = idx[min(base + k * B, S - 1)];
+    for (int k = 0; k < K; ++k) u[k] = slot_point(rec, R, min(base + k * B, S - 1));
     T gu[K];
     if constexpr (D == 2) {
         V2 xv[K];
@@ -667,14 +700,14 @@ __device__ __forceinline__ void bwd_stage_tile(const TileMeta m, const uint4* __
                                                const T* __restrict__ g, const uint32_t lds0, const int tid)
 {
     using L = Layout<D, T>;
-    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
-    const int S = P + H;
-    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
-    const uint4* segsrc = rec + m.rec_off + idx_words(P, H) / 4;
-    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment
-    dma_segment<B>(segsrc, seg, (int)(seg_halfs(P, nw) / 8), tid);
+    const int S = (int)m.P + (int)m.H;
+    const RecLayout R = rec_layout(m);
+    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the record
+    dma_segment<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
+    __syncthreads();
     stage_points<B>(S, [&](auto kc, int r0) {
-        bwd_stage<D, T, B, WIDE, decltype(kc)::value>(idx, x, tape, g, S, r0, lds0, tid);
+        bwd_stage<D, T, B, WIDE, decltype(kc)::value>(recl, R, x, tape, g, S, r0, lds0, tid);
     });
 }
 
@@ -683,24 +716,24 @@ __device__ __forceinline__ void bwd_stage_tile(const TileMeta m, const uint4* __
 // walk visits exactly the stencil of j, and sigma_j = h_j . sum_i (x_i - x_j)
 // is formed from the same differences.
 template <int D, typename T, int B, bool WIDE, bool SIG>
-__device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const uint4* __restrict__ rec,
-                                                 const T* __restrict__ tape, const int64_t n, T* __restrict__ grad,
-                                                 const uint32_t lds0, const int tid)
+__device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const T* __restrict__ tape, const int64_t n,
+                                                 T* __restrict__ grad, const uint32_t lds0, const int tid)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
     using L = Layout<D, T>;
-    const int P = (int)m.P, H = (int)m.H, nw = (int)m.nw;
-    const int S = P + H;
-    const uint32_t* __restrict__ idx = reinterpret_cast<const uint32_t*>(rec + m.rec_off);
-    const uint32_t seg = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the segment
-    const uint32_t words = seg, rowend = seg + 4u * nw;
+    const int P = (int)m.P;
+    const int S = P + (int)m.H;
+    const RecLayout R = rec_layout(m);
+    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the record
+    const uint32_t words = recl;
     // 2D: the slot array at lds0; 3D: w2 at lds0 and the two 4-value arrays
     const uint32_t r4 = (uint32_t)round_up(S, 4) * sizeof(T), c0 = lds0, c1 = lds0 + r4, c2 = lds0 + 5 * r4;
     for (int l = tid; l < P; l += B) {
-        const int s = l ? lds_ld<uint16_t>(rowend + 2u * (l - 1)) : 0;
-        const int e = lds_ld<uint16_t>(rowend + 2u * l);
-        const uint32_t u = idx[l];
+        const RowRef row = row_ref(recl, R, l);
+        const int s = row.s, e = row.e;
+        const uint32_t sh = (uint32_t)row.shift * L::unit;   // the row's entries are its anchor's plus shift
+        const uint32_t u = slot_point(recl, R, l);
         T sig = T(0);
         if constexpr (SIG) sig = rec_at<WIDE, T>(tape + (size_t)n * (2 * D), u, sizeof(T));
         const uint32_t oself = (uint32_t)l * L::unit;
@@ -711,9 +744,10 @@ __device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const uint4* 
                 V4 a;
                 V2 h;
             };
+            const uint32_t b0 = c0 + 2 * sh;
             auto at = [&](uint32_t j) {
                 const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(c0 + 2 * o), lds_ld<V2>(c0 + 2 * o + 4 * sizeof(T))};
+                return Q{lds_ld<V4>(b0 + 2 * o), lds_ld<V2>(b0 + 2 * o + 4 * sizeof(T))};
             };
             walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
@@ -742,9 +776,10 @@ __device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const uint4* 
                 V4 a, b;
                 T c;
             };
+            const uint32_t b0 = c0 + (sh >> 1), b1 = c1 + 2 * sh, b2 = c2 + 2 * sh;
             auto at = [&](uint32_t j) {
                 const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(2 * o + c1), lds_ld<V4>(2 * o + c2), lds_ld<T>(c0 + (o >> 1))};
+                return Q{lds_ld<V4>(2 * o + b1), lds_ld<V4>(2 * o + b2), lds_ld<T>(b0 + (o >> 1))};
             };
             walk_row<1>(words, s, e, [&](auto... o) {
                 const Q q[] = {at(o)...};
@@ -776,7 +811,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
     bwd_stage_tile<D, T, B, WIDE>(m, rec, x, tape, g, 0u, (int)threadIdx.x);
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
-    bwd_compute_tile<D, T, B, WIDE, SIG>(m, rec, tape, n, grad, 0u, (int)threadIdx.x);
+    bwd_compute_tile<D, T, B, WIDE, SIG>(m, tape, n, grad, 0u, (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,12 +869,12 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict_
 template <int D, typename T>
 size_t fwd_lds(const DevTiles& t)
 {
-    return tile_lds_bytes(Layout<D, T>::fwd, t.max_staged, t.max_seg);
+    return tile_lds_bytes(Layout<D, T>::fwd, t.max_staged, (size_t)t.max_rec);
 }
 template <int D, typename T>
 size_t bwd_lds(const DevTiles& t)
 {
-    return tile_lds_bytes(Layout<D, T>::bwd, t.max_staged, t.max_seg);
+    return tile_lds_bytes(Layout<D, T>::bwd, t.max_staged, (size_t)t.max_rec);
 }
 
 template <int D, typename T, int B, bool WIDE>

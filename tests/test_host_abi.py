@@ -139,6 +139,59 @@ def test_tile_records_reproduce_stencil(name, dim, x, cells, stencil, tile_log2)
         assert np.all(seen == 1)
 
 
+def _popc(a):
+    return int(sum(bin(int(v)).count("1") for v in a))
+
+
+@pytest.mark.parametrize("name,dim,x,cells", _cases(), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("stencil", ["ring1", "axis"])
+def test_record_index_arrays_are_consistent(name, dim, x, cells, stencil):
+    """The prefix arrays the kernels use for O(1) decoding agree with the
+    bit masks: spre / xpre count the set bits before each 32-slot group,
+    xlast is the last explicit row before it; slot 0 starts a run, row 0 is
+    explicit; explicit rows ascend before their padding."""
+    m = F.Mesh(x, cells, "f32", stencil=stencil, tile_log2=5, host_only=True)
+    for adjoint in (False, True):
+        for r in m.tile_records(adjoint):
+            P, S = r["P"], r["P"] + r["H"]
+            assert r["smask"][0] & 1 and r["xmask"][0] & 1
+            assert _popc(r["smask"]) == len(r["runs"]) and _popc(r["xmask"]) == len(r["xend"])
+            # no mask bit beyond the last slot / row
+            assert _popc(r["smask"]) == sum(int(r["smask"][l // 32]) >> (l % 32) & 1 for l in range(S))
+            assert _popc(r["xmask"]) == sum(int(r["xmask"][l // 32]) >> (l % 32) & 1 for l in range(P))
+            expl = [l for l in range(P) if int(r["xmask"][l // 32]) >> (l % 32) & 1]
+            for g in range(len(r["smask"])):
+                assert r["spre"][g] == _popc(r["smask"][:g])
+            for q in range(len(r["xmask"])):
+                assert r["xpre"][q] == _popc(r["xmask"][:q])
+                if q:
+                    assert r["xlast"][q] == max(l for l in expl if l < 32 * q)
+            xe = r["xend"].astype(np.int64)
+            assert np.all(np.diff(np.concatenate([[0], xe])) > 0) and int(xe[-1]) == len(r["words"])
+            w = r["words"]
+            ent = np.stack([w & 0x3FF, (w >> 10) & 0x3FF, w >> 20], 1).reshape(-1)
+            for k, l in enumerate(expl):
+                row = ent[3 * (int(xe[k - 1]) if k else 0):3 * int(xe[k])].astype(np.int64)
+                body = row[row != l]   # the padding is the row's own slot, never a neighbour
+                assert np.all(np.diff(body) >= 0) and np.all(row[len(body):] == l)
+
+
+def test_grid_numbered_records_compress():
+    """Points numbered along grid lines: most rows are shifts of the previous
+    row and the runs are the grid lines, so the record stays far below the
+    4 bytes per stencil entry of a plain index list; the same points in random
+    order give one explicit row per point and still decode (see above)."""
+    x, c = meshes.kuhn_tet_grid(32, length=1.0)
+    m = F.Mesh(x, c, "f32", host_only=True)
+    recs = m.tile_records(False)
+    rows = sum(r["P"] for r in recs)
+    assert sum(len(r["xend"]) for r in recs) < 0.25 * rows
+    assert m.tile_stats()["record_bytes"] < 8 * m.n < 4 * m.info()["nnz"] / 6
+    x2, c2, _ = meshes.relabel(x, c, seed=4)
+    recs2 = F.Mesh(x2, c2, "f32", host_only=True).tile_records(False)
+    assert sum(len(r["xend"]) for r in recs2) > 0.95 * rows
+
+
 def test_ring1_symmetric_shares_adjoint_tiles():
     x, c = meshes.jittered_tri_grid(20, 20, seed=2)
     m = F.Mesh(x, c, "f32", host_only=True)
