@@ -146,7 +146,9 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
  *               uint32 words[nw]  stencil rows of the explicit rows, three
  *                                 10-bit slots per word (bits 0-9, 10-19,
  *                                 20-29), ascending, each row padded to a
- *                                 multiple of 3 with the row's own slot
+ *                                 multiple of 3 with the row's own slot;
+ *                                 bits 30-31 of a row's last word: its
+ *                                 padding count
  *               uint32 runs[nr]   per run of consecutive caller indices:
  *                                 caller index of its first slot minus that
  *                                 slot

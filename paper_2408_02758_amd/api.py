@@ -151,7 +151,7 @@ class Mesh:
             run_of = np.cumsum(starts) - 1
             idx = (r["runs"][run_of].astype(np.uint64) + np.arange(S, dtype=np.uint64)) % (1 << 32)
             w = r["words"]
-            ent_x = np.stack([w & 0x3FF, (w >> 10) & 0x3FF, w >> 20], 1).reshape(-1).astype(np.int64)
+            ent_x = np.stack([w & 0x3FF, (w >> 10) & 0x3FF, (w >> 20) & 0x3FF], 1).reshape(-1).astype(np.int64)
             xend = r["xend"].astype(np.int64)
             expl = np.flatnonzero(bits(r["xmask"], P))
             rows, ends, pos = [], [], 0

@@ -386,8 +386,9 @@ bool tile_fits(int dim, bool f64, int64_t P, int64_t H, int64_t nw)
 {
     if (P + H > kMaxStaged || nw > kMaxTileWords) return false;
     const RecLayout r = rec_layout((uint32_t)P, (uint32_t)H, (uint32_t)nw, (uint32_t)(P + H), (uint32_t)P);
-    const size_t slot = std::max(fwd_slot_bytes(dim, f64), bwd_slot_bytes(dim, f64));
-    return tile_lds_bytes(slot, (int)(P + H), r.bytes) <= kLdsBudget;
+    const int S = (int)(P + H);
+    if (dim == 3 && S > bwd3_capacity(f64)) return false;
+    return std::max(fwd_points_bytes(dim, f64, S), bwd_points_bytes(dim, f64, S)) + r.bytes <= kLdsBudget;
 }
 
 // The record of one tile (layout in ftle_internal.h): own points [b, e) of
@@ -441,13 +442,15 @@ void tile_record(const Csr& a, const std::vector<int32_t>& perm, int64_t b, int6
             }
         }
         std::sort(row.begin(), row.end());
-        while (row.size() % 3) row.push_back(l);
+        const uint32_t pad = (3 - row.size() % 3) % 3;
+        for (uint32_t k = 0; k < pad; ++k) row.push_back(l);
         nwf += (uint32_t)row.size() / 3;
         bool shift = l > 0 && row.size() == prev.size();
         for (size_t k = 0; shift && k < row.size(); ++k) shift = row[k] == prev[k] + 1u;
         if (!shift) {
             expl[l] = 1;
             for (size_t k = 0; k < row.size(); k += 3) words.push_back(row[k] | row[k + 1] << 10 | row[k + 2] << 20);
+            if (!row.empty()) words.back() |= pad << 30;   // the last word's padding entries
             xend.push_back((uint16_t)words.size());
         }
         prev.swap(row);

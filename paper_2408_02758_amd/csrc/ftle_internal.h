@@ -23,7 +23,8 @@ namespace ftle {
 //   uint32 words[nw]   stencil rows of the explicit rows (below): three
 //                      10-bit local indices per word, in bits 0-9, 10-19 and
 //                      20-29; a row's entries ascend and are padded to a
-//                      multiple of 3 with the row's own slot
+//                      multiple of 3 with the row's own slot; bits 30-31 of
+//                      a row's last word hold its padding count (0-2)
 //   uint32 runs[nr]    run r (a maximal stretch of slots with consecutive
 //                      caller indices): caller index of its first slot minus
 //                      that slot, so that slot l of run r is point runs[r] + l
@@ -87,21 +88,30 @@ __host__ __device__ inline RecLayout rec_layout(const TileMeta& m)
     return rec_layout(m.P, m.H, m.nw, m.nr, m.nx);
 }
 
-// LDS bytes per staged point, in units of the value size e (4 or 8 bytes):
-//   forward  2D: 4e, one slot (x0, x1, phi0, phi1)
-//            3D: 6e, two arrays: (phi1, phi2) slots of 2e at the start of
-//                LDS, then (x0, x1, x2, phi0) slots of 4e
-//   adjoint  2D: 8e, one slot (x0, x1, w0, w1) (h0, h1, -, -)
-//            3D: 9e, three arrays: w2 slots of e, then (x0, x1, x2, h0)
-//                slots of 4e, then (h1, h2, w0, w1) slots of 4e
-// Each array holds round_up(P + H, 4) slots, so every array and the record
-// copy after them start 16-byte aligned.
+// LDS of a tile's staged points, with e the value size (4 or 8 bytes) and S
+// the staged points:
+//   forward  2D: one array of round_up(S, 4) slots (x0, x1, phi0, phi1), 4e
+//            3D: three arrays of kMaxStaged slots of 2e: (x0, x1), (x2, phi0),
+//                (phi1, phi2); the fixed array stride lets one per-neighbour
+//                address reach all three through the instruction's offset
+//   adjoint  2D: one array of round_up(S, 4) slots (x0, x1, w0, w1)
+//                (h0, h1, -, -), 8e
+//            3D: three arrays of bwd3_capacity slots: (x0, x1, x2, h0) and
+//                (h1, h2, w0, w1) (4e each, the second at a fixed offset
+//                from the first), then w2 (e)
+// so that every array and the record copy after them start 16-byte aligned.
 __host__ __device__ inline size_t elem_bytes(bool f64) { return f64 ? 8 : 4; }
-__host__ __device__ inline size_t fwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 4 : 6); }
-__host__ __device__ inline size_t bwd_slot_bytes(int dim, bool f64) { return elem_bytes(f64) * (dim == 2 ? 8 : 9); }
-__host__ __device__ inline size_t tile_lds_bytes(size_t slot_bytes, int staged, size_t rec_bytes)
+__host__ __device__ inline size_t fwd_points_bytes(int dim, bool f64, int staged)
 {
-    return (size_t)round_up(staged, 4) * slot_bytes + rec_bytes;
+    return dim == 2 ? (size_t)round_up(staged, 4) * 4 * elem_bytes(f64) : (size_t)kMaxStaged * 6 * elem_bytes(f64);
+}
+// Staged points a 3D adjoint tile holds (its arrays have that many slots;
+// float64 tiles are cut smaller to stay in the LDS budget).
+__host__ __device__ constexpr int bwd3_capacity(bool f64) { return f64 ? 512 : kMaxStaged; }
+__host__ __device__ inline size_t bwd_points_bytes(int dim, bool f64, int staged)
+{
+    return dim == 2 ? (size_t)round_up(staged, 4) * 8 * elem_bytes(f64)
+                    : (size_t)bwd3_capacity(f64) * 9 * elem_bytes(f64);
 }
 
 // One tile set: the tiles of one stencil (the forward stencil, or its

@@ -139,23 +139,27 @@ __device__ inline int xcd_tile(int bid, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Staged points in LDS.  Staged slot l (l is the stencil's local index) has
-// o = l * unit; with e = sizeof(T) and R = round_up(P + H, 4):
-//   forward 2D: (x0, x1, phi0, phi1) at o                     (unit 4e)
-//   forward 3D: (phi1, phi2) at o, (x0, x1, x2, phi0) at
-//               2 o + 2eR                                     (unit 2e)
-//   adjoint 2D: (x0, x1, w0, w1) (h0, h1, -, -) at 2 o
-//   adjoint 3D: w2 at o / 2, (x0, x1, x2, h0) at 2 o + eR,
-//               (h1, h2, w0, w1) at 2 o + 5eR
-// so that 16-byte reads are 16-byte aligned, no LDS is padding in 3D, and
-// neighbouring points sit in neighbouring banks.  A copy of the tile's record
-// follows.
+// Staged points in LDS, from the launch's base address lds0; staged slot l
+// (l is the stencil's local index), e = sizeof(T):
+//   forward 2D: (x0, x1, phi0, phi1) at 4e l
+//   forward 3D: (x0, x1), (x2, phi0), (phi1, phi2) at 2e l + {0, 1, 2} F,
+//               F = 2e kMaxStaged (a fixed stride: one address per neighbour
+//               reaches all three through the instruction's offset field)
+//   adjoint 2D: (x0, x1, w0, w1) (h0, h1, -, -) at 8e l
+//   adjoint 3D: (x0, x1, x2, h0), (h1, h2, w0, w1) at 4e l + {0, 1} A and
+//               w2 at 2 A + e l, A = 4e bwd3_capacity
+// so that 16-byte reads are 16-byte aligned and neighbouring points sit in
+// neighbouring banks.  A copy of the tile's record follows.
 // ---------------------------------------------------------------------------
 template <int D, typename T> struct Layout {
     static constexpr uint32_t e = sizeof(T);
     static constexpr uint32_t unit = (D == 2 ? 4 : 2) * e;
-    static constexpr uint32_t fwd = (D == 2 ? 4 : 6) * e;   // LDS bytes per staged point
-    static constexpr uint32_t bwd = (D == 2 ? 8 : 9) * e;
+    static constexpr uint32_t stride = kMaxStaged * 2 * e;   // 3D forward: array stride
+    static constexpr uint32_t bunit = 4 * e;                                   // 3D adjoint: slot of the 4-value arrays
+    static constexpr uint32_t bstride = (uint32_t)bwd3_capacity(e == 8) * bunit;   // and their stride
+    // LDS address of the record copy after the staged points
+    static __device__ uint32_t fwd_rec(uint32_t lds0, int S) { return lds0 + (uint32_t)fwd_points_bytes(D, e == 8, S); }
+    static __device__ uint32_t bwd_rec(uint32_t lds0, int S) { return lds0 + (uint32_t)bwd_points_bytes(D, e == 8, S); }
 };
 
 // Copy of a tile's record (n16 chunks of 16 bytes) into LDS as a direct
@@ -196,23 +200,51 @@ __device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
 
 // Walk of one row of the padded stencil, WPS words (3 WPS neighbours) per
 // step: the words' LDS loads, then the neighbours' slot loads, then the
-// arithmetic; a final single word.  visit(l...) gets the neighbours' local
-// indices.
-template <int WPS, typename F>
+// arithmetic; a final single word.  visit(pad, l...) gets the local indices
+// and the padding count of the step's last word (its bits 30-31): a zero
+// constant except for the row's last word when PAD.
+template <int K> using IntK = std::integral_constant<int, K>;
+
+template <int WPS, bool PAD, typename F>
 __device__ inline void walk_row(uint32_t words, int s, int e, F&& visit)
 {
-    auto ix = [](uint32_t w, int k) { return k == 2 ? w >> 20 : (w >> (10 * k)) & 0x3ffu; };
-    int k = s;
+    // one bit-field extract per entry; written as an instruction because the
+    // compiler otherwise merges the extract into the caller's address scaling
+    // as shift, mask and add (three operations instead of extract + shift-add)
+    auto ix = [](uint32_t w, auto k) {
+        uint32_t r;
+        asm("v_bfe_u32 %0, %1, %2, 10" : "=v"(r) : "v"(w), "i"(10 * decltype(k)::value));
+        return r;
+    };
+    using Zero = std::integral_constant<uint32_t, 0>;
+    uint32_t a = words + 4u * s;   // the loop runs on the LDS address
+    // PAD: the last word goes separately, with its padding count; no other
+    // word holds padding
+    const uint32_t end = words + 4u * e - (PAD && e > s ? 4u : 0u);
     if constexpr (WPS == 2) {
-        for (; k + 2 <= e; k += 2) {
-            const uint32_t w0 = lds_ld<uint32_t>(words + 4u * k), w1 = lds_ld<uint32_t>(words + 4u * k + 4u);
-            visit(ix(w0, 0), ix(w0, 1), ix(w0, 2), ix(w1, 0), ix(w1, 1), ix(w1, 2));
+        for (; a + 8u <= end; a += 8u) {
+            const uint32_t w0 = lds_ld<uint32_t>(a), w1 = lds_ld<uint32_t>(a + 4u);
+            visit(Zero{}, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}), ix(w1, IntK<0>{}),
+                  ix(w1, IntK<1>{}), ix(w1, IntK<2>{}));
         }
     }
-    for (; k < e; ++k) {
-        const uint32_t w0 = lds_ld<uint32_t>(words + 4u * k);
-        visit(ix(w0, 0), ix(w0, 1), ix(w0, 2));
+    for (; a < end; a += 4u) {
+        const uint32_t w0 = lds_ld<uint32_t>(a);
+        visit(Zero{}, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
     }
+    if (PAD && e > s) {
+        const uint32_t w0 = lds_ld<uint32_t>(a);
+        visit(w0 >> 30, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
+    }
+}
+
+// Entry k of the N a walk step visits holds a neighbour, not the row's
+// padding (the last pad entries of the row's last word).  The padding's
+// arithmetic is skipped by a branch that whole waves take when their rows
+// end alike (in 3D: 14 neighbours, one padding entry).
+template <int N, typename P> __device__ inline bool entry_live(int k, P pad)
+{
+    return k < N - 2 || (uint32_t)(N - k) > (uint32_t)pad;
 }
 
 // Decoding of a tile record held in LDS at address rec (layout R).
@@ -356,17 +388,16 @@ __device__ inline void fwd_stage(uint32_t rec, const RecLayout& R, const T* __re
             xv[k] = rec_at<WIDE, Packed3<T>>(x, u[k], sizeof(Packed3<T>));
             fv[k] = rec_at<WIDE, Packed3<T>>(flow, u[k], sizeof(Packed3<T>));
         }
-        const uint32_t abase = lds0 + (uint32_t)round_up(S, 4) * 2 * sizeof(T);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
-            lds_st(2 * o + abase, V4{xv[k].a, xv[k].b, xv[k].c, fv[k].a});
-            lds_st(lds0 + o, V2{fv[k].b, fv[k].c});
+            const uint32_t o = lds0 + (uint32_t)min(base + k * B, S - 1) * L::unit;
+            lds_st(o, V2{xv[k].a, xv[k].b});
+            lds_st(o + L::stride, V2{xv[k].c, fv[k].a});
+            lds_st(o + 2 * L::stride, V2{fv[k].b, fv[k].c});
         }
     }
 }
 
-template <int K> using IntK = std::integral_constant<int, K>;
 
 // Rounds over S staged slots: full rounds of kMaxK slots per thread, then one
 // round of the K (1..kMaxK) the rest needs.  K is workgroup-uniform, so the
@@ -403,7 +434,7 @@ __device__ __forceinline__ void fwd_stage_tile(const TileMeta m, const uint4* __
     using L = Layout<D, T>;
     const int S = (int)m.P + (int)m.H;
     const RecLayout R = rec_layout(m);
-    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the record
+    const uint32_t recl = L::fwd_rec(lds0, S);   // LDS address of the record
     dma_segment<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
     __syncthreads();
@@ -424,9 +455,8 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
     const int P = (int)m.P;
     const int S = P + (int)m.H;
     const RecLayout R = rec_layout(m);
-    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::fwd;   // LDS address of the record
+    const uint32_t recl = L::fwd_rec(lds0, S);   // LDS address of the record
     const uint32_t words = recl;
-    const uint32_t abase = lds0 + (uint32_t)round_up(S, 4) * 2 * sizeof(T);   // 3D: (x0, x1, x2, phi0) array
     uint32_t redone = 0;   // points of this lane that took the float64 recompute
     for (int l = tid; l < P; l += B) {
         const RowRef row = row_ref(recl, R, l);
@@ -455,9 +485,12 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
             };
             const uint32_t b0 = lds0 + sh;
             auto at = [&](uint32_t j) { return lds_ld<V4>(b0 + j * L::unit); };
-            walk_row<2>(words, s, e, [&](auto... o) {
+            walk_row<2, false>(words, s, e, [&](auto pad, auto... o) {
+                constexpr int N = sizeof...(o);
                 const V4 q[] = {at(o)...};
-                for (const V4& v : q) acc(v);
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    if (entry_live<N>(k, pad)) acc(q[k]);
             });
             u = slot_point(recl, R, l);
             const T det = m00 * m11 - m01 * m01;
@@ -492,18 +525,17 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                 if constexpr (TAPE == 2) rec_put<WIDE>(tape + (size_t)n * 4, u, sizeof(T), h0 * s0 + h1 * s1);
             }
         } else {
-            const V4 c0 = lds_ld<V4>(2 * oself + abase);
-            const V2 c1 = lds_ld<V2>(lds0 + oself);
+            const V2 ca = lds_ld<V2>(lds0 + oself), cb = lds_ld<V2>(lds0 + oself + L::stride);
+            const V2 cc = lds_ld<V2>(lds0 + oself + 2 * L::stride);
             T m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
             T b00 = 0, b01 = 0, b02 = 0, b10 = 0, b11 = 0, b12 = 0, b20 = 0, b21 = 0, b22 = 0;
             T s0 = 0, s1 = 0, s2 = 0;
             struct Q {
-                V4 a;
-                V2 b;
+                V2 a, b, c;
             };
             auto acc = [&](const Q q) {
-                const T dx0 = q.a.x - c0.x, dx1 = q.a.y - c0.y, dx2 = q.a.z - c0.z;
-                const T df0 = q.a.w - c0.w, df1 = q.b.x - c1.x, df2 = q.b.y - c1.y;
+                const T dx0 = q.a.x - ca.x, dx1 = q.a.y - ca.y, dx2 = q.b.x - cb.x;
+                const T df0 = q.b.y - cb.y, df1 = q.c.x - cc.x, df2 = q.c.y - cc.y;
                 m00 = dfma(dx0, dx0, m00);
                 m01 = dfma(dx0, dx1, m01);
                 m02 = dfma(dx0, dx2, m02);
@@ -525,16 +557,18 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                     s2 += dx2;
                 }
             };
-            // one per-lane base: slot j of the (phi1, phi2) array at t = b0 + j unit,
-            // of the (x0, x1, x2, phi0) array at 2 t + (abase - 2 lds0)
-            const uint32_t b0 = lds0 + sh, kx = abase - 2 * lds0;
+            // one address per neighbour; the other two arrays at fixed offsets
+            const uint32_t b0 = lds0 + sh;
             auto at = [&](uint32_t j) {
                 const uint32_t t = b0 + j * L::unit;
-                return Q{lds_ld<V4>(2 * t + kx), lds_ld<V2>(t)};
+                return Q{lds_ld<V2>(t), lds_ld<V2>(t + L::stride), lds_ld<V2>(t + 2 * L::stride)};
             };
-            walk_row<1>(words, s, e, [&](auto... o) {
+            walk_row<1, true>(words, s, e, [&](auto pad, auto... o) {
+                constexpr int N = sizeof...(o);
                 const Q q[] = {at(o)...};
-                for (const Q& v : q) acc(v);
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    if (entry_live<N>(k, pad)) acc(q[k]);
             });
             u = slot_point(recl, R, l);
             // adjugate of M (symmetric)
@@ -680,14 +714,14 @@ __device__ inline void bwd_stage(uint32_t rec, const RecLayout& R, const T* __re
             pv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k], sizeof(Packed3<T>));
             hv[k] = rec_at<WIDE, Packed3<T>>(tape, 2 * u[k] + 1, sizeof(Packed3<T>));
         }
-        const uint32_t r4 = (uint32_t)round_up(S, 4) * sizeof(T), c1 = lds0 + r4, c2 = lds0 + 5 * r4;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
+            const uint32_t sl = (uint32_t)min(base + k * B, S - 1);
+            const uint32_t o = lds0 + sl * L::bunit;
             const T gg = isfinite(gu[k]) ? gu[k] : T(0);
-            lds_st(2 * o + c1, V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a});
-            lds_st(2 * o + c2, V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b});
-            lds_st(lds0 + (o >> 1), gg * pv[k].c);
+            lds_st(o, V4{xv[k].a, xv[k].b, xv[k].c, hv[k].a});
+            lds_st(o + L::bstride, V4{hv[k].b, hv[k].c, gg * pv[k].a, gg * pv[k].b});
+            lds_st(lds0 + 2 * L::bstride + sl * sizeof(T), gg * pv[k].c);
         }
     }
 }
@@ -702,7 +736,7 @@ __device__ __forceinline__ void bwd_stage_tile(const TileMeta m, const uint4* __
     using L = Layout<D, T>;
     const int S = (int)m.P + (int)m.H;
     const RecLayout R = rec_layout(m);
-    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the record
+    const uint32_t recl = L::bwd_rec(lds0, S);   // LDS address of the record
     dma_segment<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
     __syncthreads();
@@ -725,10 +759,10 @@ __device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const T* __re
     const int P = (int)m.P;
     const int S = P + (int)m.H;
     const RecLayout R = rec_layout(m);
-    const uint32_t recl = lds0 + (uint32_t)round_up(S, 4) * L::bwd;   // LDS address of the record
+    const uint32_t recl = L::bwd_rec(lds0, S);   // LDS address of the record
     const uint32_t words = recl;
-    // 2D: the slot array at lds0; 3D: w2 at lds0 and the two 4-value arrays
-    const uint32_t r4 = (uint32_t)round_up(S, 4) * sizeof(T), c0 = lds0, c1 = lds0 + r4, c2 = lds0 + 5 * r4;
+    // 2D: the slot array at lds0; 3D: the two 4-value arrays, then w2
+    const uint32_t c0 = lds0, cw = lds0 + 2 * L::bstride;
     for (int l = tid; l < P; l += B) {
         const RowRef row = row_ref(recl, R, l);
         const int s = row.s, e = row.e;
@@ -749,9 +783,13 @@ __device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const T* __re
                 const uint32_t o = j * L::unit;
                 return Q{lds_ld<V4>(b0 + 2 * o), lds_ld<V2>(b0 + 2 * o + 4 * sizeof(T))};
             };
-            walk_row<1>(words, s, e, [&](auto... o) {
+            walk_row<1, true>(words, s, e, [&](auto pad, auto... o) {
+                constexpr int N = sizeof...(o);
                 const Q q[] = {at(o)...};
-                for (const Q& v : q) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (!entry_live<N>(k, pad)) continue;
+                    const Q& v = q[k];
                     const T d0 = cj.x - v.a.x, d1 = cj.y - v.a.y;
                     const T t = v.h.x * d0 + v.h.y * d1;
                     a0 = dfma(v.a.z, t, a0);
@@ -768,22 +806,28 @@ __device__ __forceinline__ void bwd_compute_tile(const TileMeta m, const T* __re
             }
             rec_put<WIDE>(grad, u, sizeof(V2), V2{a0 - sig * cj.z, a1 - sig * cj.w});
         } else {
-            const V4 cj = lds_ld<V4>(2 * oself + c1);
-            const V4 cb = lds_ld<V4>(2 * oself + c2);
-            const T cw2 = lds_ld<T>(c0 + (oself >> 1));
+            const V4 cj = lds_ld<V4>(lds0 + (uint32_t)l * L::bunit);
+            const V4 cb = lds_ld<V4>(lds0 + (uint32_t)l * L::bunit + L::bstride);
+            const T cw2 = lds_ld<T>(cw + (uint32_t)l * sizeof(T));
             T a0 = 0, a1 = 0, a2 = 0, s0 = 0, s1 = 0, s2 = 0;
             struct Q {
                 V4 a, b;
                 T c;
             };
-            const uint32_t b0 = c0 + (sh >> 1), b1 = c1 + 2 * sh, b2 = c2 + 2 * sh;
+            // per neighbour one address into the 4-value arrays (the second at
+            // a fixed offset) and one into w2
+            const uint32_t bq = lds0 + (uint32_t)row.shift * L::bunit, bw = cw + (uint32_t)row.shift * sizeof(T);
             auto at = [&](uint32_t j) {
-                const uint32_t o = j * L::unit;
-                return Q{lds_ld<V4>(2 * o + b1), lds_ld<V4>(2 * o + b2), lds_ld<T>(b0 + (o >> 1))};
+                const uint32_t t = bq + j * L::bunit;
+                return Q{lds_ld<V4>(t), lds_ld<V4>(t + L::bstride), lds_ld<T>(bw + j * sizeof(T))};
             };
-            walk_row<1>(words, s, e, [&](auto... o) {
+            walk_row<1, true>(words, s, e, [&](auto pad, auto... o) {
+                constexpr int N = sizeof...(o);
                 const Q q[] = {at(o)...};
-                for (const Q& v : q) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    if (!entry_live<N>(k, pad)) continue;
+                    const Q& v = q[k];
                     const T d0 = cj.x - v.a.x, d1 = cj.y - v.a.y, d2 = cj.z - v.a.z;
                     const T t = v.a.w * d0 + v.b.x * d1 + v.b.y * d2;
                     a0 = dfma(v.b.z, t, a0);
@@ -869,12 +913,12 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict_
 template <int D, typename T>
 size_t fwd_lds(const DevTiles& t)
 {
-    return tile_lds_bytes(Layout<D, T>::fwd, t.max_staged, (size_t)t.max_rec);
+    return fwd_points_bytes(D, sizeof(T) == 8, t.max_staged) + (size_t)t.max_rec;
 }
 template <int D, typename T>
 size_t bwd_lds(const DevTiles& t)
 {
-    return tile_lds_bytes(Layout<D, T>::bwd, t.max_staged, (size_t)t.max_rec);
+    return bwd_points_bytes(D, sizeof(T) == 8, t.max_staged) + (size_t)t.max_rec;
 }
 
 template <int D, typename T, int B, bool WIDE>

@@ -169,11 +169,14 @@ def test_record_index_arrays_are_consistent(name, dim, x, cells, stencil):
             xe = r["xend"].astype(np.int64)
             assert np.all(np.diff(np.concatenate([[0], xe])) > 0) and int(xe[-1]) == len(r["words"])
             w = r["words"]
-            ent = np.stack([w & 0x3FF, (w >> 10) & 0x3FF, w >> 20], 1).reshape(-1)
+            ent = np.stack([w & 0x3FF, (w >> 10) & 0x3FF, (w >> 20) & 0x3FF], 1).reshape(-1)
             for k, l in enumerate(expl):
-                row = ent[3 * (int(xe[k - 1]) if k else 0):3 * int(xe[k])].astype(np.int64)
+                w0, w1 = (int(xe[k - 1]) if k else 0), int(xe[k])
+                row = ent[3 * w0:3 * w1].astype(np.int64)
                 body = row[row != l]   # the padding is the row's own slot, never a neighbour
                 assert np.all(np.diff(body) >= 0) and np.all(row[len(body):] == l)
+                # bits 30-31: the padding count, in the row's last word only
+                assert np.all(w[w0:w1 - 1] >> 30 == 0) and int(w[w1 - 1]) >> 30 == len(row) - len(body)
 
 
 def test_grid_numbered_records_compress():
