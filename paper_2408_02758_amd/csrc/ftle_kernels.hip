@@ -202,7 +202,7 @@ __device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
 // step: the words' LDS loads, then the neighbours' slot loads, then the
 // arithmetic; a final single word.  visit(pad, l...) gets the local indices
 // and the padding count of the step's last word (its bits 30-31): a zero
-// constant except for the row's last word when PAD.
+// constant except for the row's last word, visited first when PAD.
 template <int K> using IntK = std::integral_constant<int, K>;
 
 template <int WPS, bool PAD, typename F>
@@ -218,9 +218,19 @@ __device__ inline void walk_row(uint32_t words, int s, int e, F&& visit)
     };
     using Zero = std::integral_constant<uint32_t, 0>;
     uint32_t a = words + 4u * s;   // the loop runs on the LDS address
-    // PAD: the last word goes separately, with its padding count; no other
-    // word holds padding
-    const uint32_t end = words + 4u * e - (PAD && e > s ? 4u : 0u);
+    uint32_t end = words + 4u * e;
+    if constexpr (PAD) {
+        // the row's last word first, with its padding count (no other word
+        // holds padding); an empty row visits a placeholder word of three
+        // slot-0 entries, all padding (pad 3; its reads stay inside the
+        // staged points).  Unconditional, so that the accumulators enter the
+        // loop as values, not as constants the compiler materialises on both
+        // of its edges.
+        const bool any = e > s;
+        end -= any ? 4u : 0u;
+        const uint32_t w0 = any ? lds_ld<uint32_t>(end) : 0u;
+        visit(any ? w0 >> 30 : 3u, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
+    }
     if constexpr (WPS == 2) {
         for (; a + 8u <= end; a += 8u) {
             const uint32_t w0 = lds_ld<uint32_t>(a), w1 = lds_ld<uint32_t>(a + 4u);
@@ -232,19 +242,16 @@ __device__ inline void walk_row(uint32_t words, int s, int e, F&& visit)
         const uint32_t w0 = lds_ld<uint32_t>(a);
         visit(Zero{}, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
     }
-    if (PAD && e > s) {
-        const uint32_t w0 = lds_ld<uint32_t>(a);
-        visit(w0 >> 30, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
-    }
 }
 
 // Entry k of the N a walk step visits holds a neighbour, not the row's
-// padding (the last pad entries of the row's last word).  The padding's
+// padding (the last pad entries of the row's last word; pad 3: all of an
+// empty row's placeholder word).  The padding's
 // arithmetic is skipped by a branch that whole waves take when their rows
 // end alike (in 3D: 14 neighbours, one padding entry).
 template <int N, typename P> __device__ inline bool entry_live(int k, P pad)
 {
-    return k < N - 2 || (uint32_t)(N - k) > (uint32_t)pad;
+    return k < N - 3 || (uint32_t)(N - k) > (uint32_t)pad;
 }
 
 // Decoding of a tile record held in LDS at address rec (layout R).
