@@ -524,8 +524,11 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                     v1 = T(0);
                 }
                 const bool use = ok && (lam > T(0)) && isfinite(f);
-                const T sc = use ? T(2) * inv2T * drcp(lam) : T(0);
-                const T p0 = (j00 * v0 + j01 * v1) * sc, p1 = (j10 * v0 + j11 * v1) * sc;
+                // a point without a usable FTLE (rank-deficient stencil, non-
+                // finite values) puts zeros on the tape: selects, not products
+                // with zero, since J may hold NaN there
+                const T sc = T(2) * inv2T * drcp(lam);
+                const T p0 = use ? (j00 * v0 + j01 * v1) * sc : T(0), p1 = use ? (j10 * v0 + j11 * v1) * sc : T(0);
                 const T h0 = use ? (m11 * v0 - m01 * v1) * id : T(0);
                 const T h1 = use ? (m00 * v1 - m01 * v0) * id : T(0);
                 rec_put<WIDE>(tape, u, sizeof(V4), V4{p0, p1, h0, h1});
@@ -633,14 +636,17 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                     v0 = T(1); v1 = T(0); v2 = T(0);
                 }
                 const bool use = ok && (lam > T(0)) && isfinite(f);
-                const T sc = use ? T(2) * inv2T * drcp(lam) : T(0);
-                const T hs = use ? id : T(0);
-                const T h0 = (a00 * v0 + a01 * v1 + a02 * v2) * hs;
-                const T h1 = (a01 * v0 + a11 * v1 + a12 * v2) * hs;
-                const T h2 = (a02 * v0 + a12 * v1 + a22 * v2) * hs;
+                // a point without a usable FTLE (rank-deficient stencil, non-
+                // finite values) puts zeros on the tape: selects, not products
+                // with zero, since J and v may hold NaN there
+                const T sc = T(2) * inv2T * drcp(lam);
+                const T h0 = use ? (a00 * v0 + a01 * v1 + a02 * v2) * id : T(0);
+                const T h1 = use ? (a01 * v0 + a11 * v1 + a12 * v2) * id : T(0);
+                const T h2 = use ? (a02 * v0 + a12 * v1 + a22 * v2) * id : T(0);
                 rec_put<WIDE>(tape, 2 * u, sizeof(Packed3<T>),
-                              Packed3<T>{(j00 * v0 + j01 * v1 + j02 * v2) * sc, (j10 * v0 + j11 * v1 + j12 * v2) * sc,
-                                         (j20 * v0 + j21 * v1 + j22 * v2) * sc});
+                              Packed3<T>{use ? (j00 * v0 + j01 * v1 + j02 * v2) * sc : T(0),
+                                         use ? (j10 * v0 + j11 * v1 + j12 * v2) * sc : T(0),
+                                         use ? (j20 * v0 + j21 * v1 + j22 * v2) * sc : T(0)});
                 rec_put<WIDE>(tape, 2 * u + 1, sizeof(Packed3<T>), Packed3<T>{h0, h1, h2});
                 if constexpr (TAPE == 2) rec_put<WIDE>(tape + (size_t)n * 6, u, sizeof(T), h0 * s0 + h1 * s1 + h2 * s2);
             }

@@ -254,6 +254,77 @@ def test_adjoint_vs_oracle(dim, dtype, stencil):
         check("adjoint fwd", out.cpu().numpy().astype(np.float64), fref, gap, T)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("relabel", [True, False])
+def test_3d_records_worst_case_and_empty_rows(dtype, relabel):
+    """Compressed records at their worst and at edges: a 3D grid plus a
+    cluster of points in no cell (empty rows) and one point whose only cell is
+    flat (a rank-deficient stencil of points that are themselves fine).
+    Relabelled at random: every row explicit, one index run per slot, the
+    empty rows scattered.  In grid order: the empty rows are consecutive
+    slots, stored as shifts of one another.  Forward and adjoint against the
+    oracle: the flat point's NaN FTLE adds nothing to its neighbours'
+    gradients."""
+    x0, c0, phi0, T = _grad_case(3, dtype, 14)
+    n0 = x0.shape[0]
+    extra = 5
+    xe = (np.asarray(x0, np.float64).max(0) + 3.0 + 0.01 * np.arange(extra)[:, None]).astype(x0.dtype)
+    # flat cell: three top-face corners of the grid and a new point in their plane
+    top = np.nonzero(x0[:, 2] == x0[:, 2].max())[0]
+    b, c, d = top[0], top[1], top[14]   # (0,0), (1,0), (0,1) of the top face
+    xf = (x0[b] + 0.5 * (x0[b] - x0[c]) + 0.5 * (x0[b] - x0[d]))[None, :].astype(x0.dtype)
+    x1 = np.concatenate([x0, xe, xf])
+    nf = x1.shape[0] - 1
+    c1 = np.concatenate([c0, np.array([[b, c, d, nf]], np.int32)])
+    phi1 = torch.cat([phi0, torch.as_tensor(np.concatenate([2.0 * xe, 2.0 * xf]), dtype=phi0.dtype,
+                                            device=phi0.device)]).contiguous()
+    if relabel:
+        x, cells, p = meshes.relabel(x1, c1, seed=11)
+    else:
+        x, cells, p = x1, c1, np.arange(x1.shape[0])
+    phi = torch.empty_like(phi1)
+    phi[torch.as_tensor(p, device=phi1.device)] = phi1
+    x = x.astype(x0.dtype)
+    m = F.Mesh(x, cells, dtype)
+    recs = m.tile_records()
+    if relabel:
+        assert sum(len(r["xend"]) for r in recs) > 0.9 * x.shape[0]
+    else:   # the empty rows after the first are shifts
+        iso = set(range(n0 + 1, n0 + extra))
+        shifts = 0
+        for (idx, rowend, _, P, _), r in zip(m.tiles(), recs):
+            for l in range(P):
+                if int(idx[l]) in iso and not (int(r["xmask"][l // 32]) >> (l % 32)) & 1:
+                    shifts += 1
+        assert shifts == extra - 1
+    g = torch.as_tensor(np.random.default_rng(7).standard_normal(x.shape[0]), dtype=phi.dtype, device=DEV)
+    out, tape = m.forward_tape(phi, T)
+    got_g = m.backward_tape(tape, g).cpu().numpy()
+    st = oracle.ring1(3, x.shape[0], cells)
+    xd, pd = x.astype(np.float64), phi.cpu().numpy().astype(np.float64)
+    fref, gap, _ = oracle.ftle(3, xd, pd, st, T, diagnostics=True)
+    assert np.isnan(fref[p[n0:]]).all() and np.isfinite(fref[p[[b, c, d]]]).all()
+    got_f = out.cpu().numpy().astype(np.float64)
+    if dtype == "f64":
+        check_f64("records 3D", got_f, fref, gap, T, 3)
+    else:
+        check_f32("records 3D", got_f, fref, gap, T)
+    ref = oracle.ftle_grad(3, xd, pd, st, T, g.cpu().numpy().astype(np.float64))
+    # points with an ill-defined top eigenvector (finite FTLE, nearly repeated
+    # top eigenvalue) and their neighbours are excluded; NaN points are not
+    bad = np.zeros(x.shape[0], bool)
+    for i in np.nonzero(np.isfinite(fref) & ~(gap >= 1e-6))[0]:
+        bad[i] = True
+        bad[st.col[st.row_ptr[i]:st.row_ptr[i + 1]]] = True
+    assert np.isfinite(got_g).all()
+    err = np.abs(got_g - ref)[~bad].max() / np.abs(ref).max()
+    print(f"[records 3D {dtype} relabel={relabel}] adjoint max err/scale = {err:.3e}, excluded {bad.sum()}",
+          flush=True)
+    assert err <= (1e-10 if dtype == "f64" else 2e-4)
+    assert not bad[p[[b, c, d, nf]]].any()
+    assert np.all(got_g[p[n0:nf]] == 0)
+
+
 def test_adjoint_fd_16cubed_f64():
     """GPU float64 adjoint against central differences (h = 1e-6) of the oracle's FTLE."""
     x, cells, phi, T = _grad_case(3, "f64", 16)
