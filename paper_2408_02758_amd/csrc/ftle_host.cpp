@@ -196,12 +196,14 @@ struct TileSet {
     int64_t halo_total = 0;
     void* d_meta = nullptr;
     void* d_rec = nullptr;
+    void* d_minv = nullptr;   // 3D forward tile set: inverse normal matrices (caller order)
 
     DevTiles dev() const
     {
         DevTiles d;
         d.meta = static_cast<const TileMeta*>(d_meta);
         d.rec = static_cast<const uint4*>(d_rec);
+        d.minv = d_minv;
         d.n_tiles = (int)meta.size();
         d.max_staged = max_staged;
         d.max_rec = max_rec;
@@ -378,6 +380,51 @@ int64_t padded_words(const Csr& a, int64_t b, int64_t e)
     int64_t t = 0;
     for (int64_t r = b; r < e; ++r) t += (a.row_ptr[r + 1] - a.row_ptr[r] + 2) / 3;
     return t;
+}
+
+// The least-squares normal matrix of a 3D point i depends on the mesh alone:
+// M_i = sum over its stencil row of (x_j - x_i)(x_j - x_i)^T (with repeated
+// entries repeated).  Its inverse is formed once, in float64, for the tape
+// forward: six values (00, 01, 02, 11, 12, 22) per point in caller order, in
+// the mesh dtype, all NaN where M fails the rank test det M > tau (tr M / 3)^3
+// (tau = 1e-5 for float32 meshes, 1e-12 for float64, as in the kernels).
+std::vector<unsigned char> normal_inverse3(const Csr& a, const std::vector<int32_t>& perm,
+                                           const std::vector<double>& xd, bool f64)
+{
+    const int64_t n = (int64_t)perm.size();
+    std::vector<unsigned char> out((size_t)n * 6 * (f64 ? 8 : 4));
+    const double tau = f64 ? 1e-12 : 1e-5;
+    parallel_for(n, [&](int64_t b, int64_t e, int) {
+        for (int64_t r = b; r < e; ++r) {
+            const int64_t i = perm[r];
+            const double* xi = &xd[(size_t)i * 3];
+            double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+            for (int32_t p = a.row_ptr[r]; p < a.row_ptr[r + 1]; ++p) {
+                const double* xj = &xd[(size_t)perm[a.col[p]] * 3];
+                const double d0 = xj[0] - xi[0], d1 = xj[1] - xi[1], d2 = xj[2] - xi[2];
+                m00 += d0 * d0;
+                m01 += d0 * d1;
+                m02 += d0 * d2;
+                m11 += d1 * d1;
+                m12 += d1 * d2;
+                m22 += d2 * d2;
+            }
+            const double a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
+            const double a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
+            const double det = m00 * a00 + m01 * a01 + m02 * a02;
+            const double tr3 = (m00 + m11 + m22) / 3.0;
+            double v[6] = {a00 / det, a01 / det, a02 / det, a11 / det, a12 / det, a22 / det};
+            if (!(det > tau * tr3 * tr3 * tr3))
+                for (double& t : v) t = std::nan("");
+            for (int k = 0; k < 6; ++k) {
+                if (f64)
+                    reinterpret_cast<double*>(out.data())[i * 6 + k] = v[k];
+                else
+                    reinterpret_cast<float*>(out.data())[i * 6 + k] = (float)v[k];
+            }
+        }
+    });
+    return out;
 }
 
 // nw: the padded stencil words of all P rows.  The record is checked at its
@@ -593,7 +640,8 @@ void free_tiles(TileSet& t)
 {
     if (t.d_meta) (void)hipFree(t.d_meta);
     if (t.d_rec) (void)hipFree(t.d_rec);
-    t.d_meta = t.d_rec = nullptr;
+    if (t.d_minv) (void)hipFree(t.d_minv);
+    t.d_meta = t.d_rec = t.d_minv = nullptr;
 }
 
 void upload_tiles(TileSet& t)
@@ -863,6 +911,8 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
         // coordinates in user order, stored in the mesh dtype
         m->x_user.resize((size_t)n * dim * m->elem());
         std::memcpy(m->x_user.data(), coords, m->x_user.size());
+        std::vector<unsigned char> minv;
+        if (dim == 3 && !m->host_only) minv = normal_inverse3(m->csr, m->perm, xd, f64);
 
         if (!m->host_only) {
             int dev = 0;
@@ -870,6 +920,7 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
             m->device = dev;
             try {
                 upload_tiles(m->fwd);
+                if (!minv.empty()) m->fwd.d_minv = dev_upload(minv.data(), minv.size());
                 if (!m->symmetric) upload_tiles(m->bwd);
                 m->d_x = dev_upload(m->x_user.data(), m->x_user.size());
                 m->d_hits = static_cast<unsigned long long*>(dev_upload(nullptr, sizeof(unsigned long long)));

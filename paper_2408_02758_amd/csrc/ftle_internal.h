@@ -119,6 +119,7 @@ __host__ __device__ inline size_t bwd_points_bytes(int dim, bool f64, int staged
 struct DevTiles {
     const TileMeta* meta;
     const uint4* rec;
+    const void* minv;   // 3D forward tiles: per point (caller order) the six values of M^-1, else null
     int n_tiles;
     int max_staged;   // max over tiles of P + H
     int max_rec;      // max over tiles of the record bytes

@@ -452,9 +452,10 @@ __device__ __forceinline__ void fwd_stage_tile(const TileMeta m, const uint4* __
 
 // The compute of a staged forward tile by B threads (tid in [0, B)).
 template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
-__device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T, T* __restrict__ out,
-                                                 T* __restrict__ tape, const int64_t n, const float eig_tau,
-                                                 unsigned long long* hits, const uint32_t lds0, const int tid)
+__device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T* __restrict__ minv, const T inv2T,
+                                                 T* __restrict__ out, T* __restrict__ tape, const int64_t n,
+                                                 const float eig_tau, unsigned long long* hits, const uint32_t lds0,
+                                                 const int tid)
 {
     using V2 = vec2_t<T>;
     using V4 = vec4_t<T>;
@@ -535,6 +536,21 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                 if constexpr (TAPE == 2) rec_put<WIDE>(tape + (size_t)n * 4, u, sizeof(T), h0 * s0 + h1 * s1);
             }
         } else {
+            // The tape kernels take M^-1 from the mesh (host-computed in float64
+            // from the coordinates alone; NaN where M is rank deficient) and
+            // accumulate B only: 6 FMAs per neighbour and the adjugate fewer.
+            // The plain forward forms M itself, which measured faster where
+            // the launch is bound by memory as much as by arithmetic.
+            constexpr bool kMinv = TAPE != 0;
+            Packed3<T> ia{}, ib{};
+            auto load_minv = [&] {
+                u = slot_point(recl, R, l);
+                ia = rec_at<WIDE, Packed3<T>>(minv, 2 * u, sizeof(Packed3<T>));
+                ib = rec_at<WIDE, Packed3<T>>(minv, 2 * u + 1, sizeof(Packed3<T>));
+            };
+            // loaded before the walk, after it when the walk also sums the
+            // differences (registers)
+            if constexpr (TAPE == 1) load_minv();
             const V2 ca = lds_ld<V2>(lds0 + oself), cb = lds_ld<V2>(lds0 + oself + L::stride);
             const V2 cc = lds_ld<V2>(lds0 + oself + 2 * L::stride);
             T m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
@@ -546,12 +562,14 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
             auto acc = [&](const Q q) {
                 const T dx0 = q.a.x - ca.x, dx1 = q.a.y - ca.y, dx2 = q.b.x - cb.x;
                 const T df0 = q.b.y - cb.y, df1 = q.c.x - cc.x, df2 = q.c.y - cc.y;
-                m00 = dfma(dx0, dx0, m00);
-                m01 = dfma(dx0, dx1, m01);
-                m02 = dfma(dx0, dx2, m02);
-                m11 = dfma(dx1, dx1, m11);
-                m12 = dfma(dx1, dx2, m12);
-                m22 = dfma(dx2, dx2, m22);
+                if constexpr (!kMinv) {
+                    m00 = dfma(dx0, dx0, m00);
+                    m01 = dfma(dx0, dx1, m01);
+                    m02 = dfma(dx0, dx2, m02);
+                    m11 = dfma(dx1, dx1, m11);
+                    m12 = dfma(dx1, dx2, m12);
+                    m22 = dfma(dx2, dx2, m22);
+                }
                 b00 = dfma(df0, dx0, b00);
                 b01 = dfma(df0, dx1, b01);
                 b02 = dfma(df0, dx2, b02);
@@ -580,14 +598,24 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                 for (int k = 0; k < N; ++k)
                     if (entry_live<N>(k, pad)) acc(q[k]);
             });
-            u = slot_point(recl, R, l);
-            // adjugate of M (symmetric)
-            const T a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
-            const T a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
-            const T det = m00 * a00 + m01 * a01 + m02 * a02;
-            const T tr3 = (m00 + m11 + m22) * T(1.0 / 3.0);
-            const bool ok = det > rank_tau<T>() * tr3 * tr3 * tr3;
-            const T id = drcp(det);
+            if constexpr (TAPE == 2) load_minv();
+            if constexpr (!kMinv) u = slot_point(recl, R, l);
+            // M^-1 = A id: A the adjugate of M (symmetric) and id = 1 / det M,
+            // or A = M^-1 itself and id = 1
+            T a00, a01, a02, a11, a12, a22, id;
+            bool ok;
+            if constexpr (kMinv) {
+                a00 = ia.a, a01 = ia.b, a02 = ia.c, a11 = ib.a, a12 = ib.b, a22 = ib.c;
+                id = T(1);
+                ok = !isnan(a00);
+            } else {
+                a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
+                a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
+                const T det = m00 * a00 + m01 * a01 + m02 * a02;
+                const T tr3 = (m00 + m11 + m22) * T(1.0 / 3.0);
+                ok = det > rank_tau<T>() * tr3 * tr3 * tr3;
+                id = drcp(det);
+            }
             const T j00 = (b00 * a00 + b01 * a01 + b02 * a02) * id;
             const T j01 = (b00 * a01 + b01 * a11 + b02 * a12) * id;
             const T j02 = (b00 * a02 + b01 * a12 + b02 * a22) * id;
@@ -608,7 +636,7 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
                 lam = lam_max3_poly(c00, c01, c02, c11, c12, c22, r);
                 // Top pair nearly equal: c'(r) amplifies float rounding in r;
                 // redo the tensor and the eigenvalue in double from J.
-                const bool redo = ok && (r < -1.0f + eig_tau);
+                const bool redo = ok && (r + 1.0f < eig_tau);   // (r + 1: no loop-invariant register)
                 if (redo) {
                     lam = lam_max3_f64_from_J(j00, j01, j02, j10, j11, j12, j20, j21, j22);
                     ++redone;
@@ -659,14 +687,15 @@ __device__ __forceinline__ void fwd_compute_tile(const TileMeta m, const T inv2T
 // One tile of the forward pass by the whole workgroup of B threads.
 template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
 __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restrict__ rec,
-                                         const T* __restrict__ x, const T* __restrict__ flow, const T inv2T,
-                                         T* __restrict__ out, T* __restrict__ tape, const int64_t n,
-                                         const float eig_tau, unsigned long long* hits, const uint32_t lds0)
+                                         const T* __restrict__ x, const T* __restrict__ minv,
+                                         const T* __restrict__ flow, const T inv2T, T* __restrict__ out,
+                                         T* __restrict__ tape, const int64_t n, const float eig_tau,
+                                         unsigned long long* hits, const uint32_t lds0)
 {
     fwd_stage_tile<D, T, B, WIDE>(m, rec, x, flow, lds0, (int)threadIdx.x);
     __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
     __syncthreads();
-    fwd_compute_tile<D, T, OUT, TAPE, B, WIDE>(m, inv2T, out, tape, n, eig_tau, hits, lds0, (int)threadIdx.x);
+    fwd_compute_tile<D, T, OUT, TAPE, B, WIDE>(m, minv, inv2T, out, tape, n, eig_tau, hits, lds0, (int)threadIdx.x);
 }
 
 // float: at most 64 VGPRs (8 waves per SIMD), so that the LDS, not the
@@ -674,11 +703,11 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
 template <int D, typename T, bool OUT, int TAPE, int B, bool WIDE>
 __global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
 fwd_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int n_tiles, const T* __restrict__ x,
-           const T* __restrict__ flow, T inv2T, T* __restrict__ out, T* __restrict__ tape, int64_t n, float eig_tau,
-           unsigned long long* hits)
+           const T* __restrict__ minv, const T* __restrict__ flow, T inv2T, T* __restrict__ out, T* __restrict__ tape,
+           int64_t n, float eig_tau, unsigned long long* hits)
 {
     const int t = xcd_tile(blockIdx.x, n_tiles);
-    fwd_tile<D, T, OUT, TAPE, B, WIDE>(meta[t], rec, x, flow, inv2T, out, tape, n, eig_tau, hits, 0u);
+    fwd_tile<D, T, OUT, TAPE, B, WIDE>(meta[t], rec, x, minv, flow, inv2T, out, tape, n, eig_tau, hits, 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -890,7 +919,7 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict_
     if (tiles_per_pop == 0) {
         // flat launch: one work item per workgroup, dealt XCD-contiguously
         const BatchItem it = items[xcd_tile(blockIdx.x, n_items)];
-        fwd_tile<D, T, true, 0, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
+        fwd_tile<D, T, true, 0, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x), nullptr,
                                              static_cast<const T*>(call.flow[it.mesh]), (T)call.inv2T[it.mesh],
                                              static_cast<T*>(call.out[it.mesh]), nullptr, 0, eig_tau, it.fp64_hits,
                                              kBatchedLdsHead);
@@ -905,7 +934,7 @@ __global__ void __launch_bounds__(B) batched_kernel(const BatchItem* __restrict_
         const int lim = min(base + tiles_per_pop, n_items);
         for (int i = base; i < lim; ++i) {
             const BatchItem it = items[i];
-            fwd_tile<D, T, true, 0, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x),
+            fwd_tile<D, T, true, 0, B, WIDE>(it.meta, it.rec, static_cast<const T*>(it.x), nullptr,
                                                  static_cast<const T*>(call.flow[it.mesh]), (T)call.inv2T[it.mesh],
                                                  static_cast<T*>(call.out[it.mesh]), nullptr, 0, eig_tau,
                                                  it.fp64_hits, kBatchedLdsHead);
@@ -947,7 +976,8 @@ hipError_t fwd_launch_b(const DevTiles& tiles, const void* x, const void* flow, 
     T* tp = static_cast<T*>(tape);
 #define FTLE_FWD_LAUNCH(OUT, TAPE)                                                                              \
     hipLaunchKernelGGL((fwd_kernel<D, T, OUT, TAPE, B, WIDE>), grid, blk, lds, stream, tiles.meta, tiles.rec,   \
-                       tiles.n_tiles, xp, fp, (T)inv2T, op, tp, n, (float)eig_tau, hits)
+                       tiles.n_tiles, xp, static_cast<const T*>(tiles.minv), fp, (T)inv2T, op, tp, n,             \
+                       (float)eig_tau, hits)
     if (!tape)
         FTLE_FWD_LAUNCH(true, 0);
     else if (out && tape_sigma)
