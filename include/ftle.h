@@ -199,8 +199,11 @@ ftle_status ftle_tape_bytes(ftle_mesh_t mesh, int64_t* bytes);
  * Forward FTLE that also records, per point, what the adjoint needs
  * (p = J v / (|T| lambda), h = M^{-1} v, with v the unit top eigenvector of
  * C, and for a non-symmetric stencil sigma = h . sum_j (x_j - x_i), which
- * the adjoint otherwise forms itself).  The tape's layout is internal.  Same
- * arguments as ftle_forward plus
+ * the adjoint otherwise forms itself).  The tape's layout is internal.  In
+ * 3D the M^{-1} of every point is the mesh's, formed once in float64 when
+ * the mesh is created, so that out agrees with ftle_forward's to rounding
+ * (not bit for bit).  Points without a usable FTLE put zeros on the tape.
+ * Same arguments as ftle_forward plus
  *   tape     device pointer of ftle_tape_bytes() bytes, caller-owned, overwritten
  */
 ftle_status ftle_forward_tape(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
