@@ -56,6 +56,13 @@ def alg_bytes_bwd(n, nnz, dim, s=4):
     return 4 * (n + 1) + 4 * nnz + 3 * dim * s * n + s * n
 
 
+def alg_bytes_ell(n, dim, s=4):
+    """The paper's own layout for its axis stencil (Section 2.2, Table 1): a
+    fixed-width list of 2*dim 32-bit neighbour indices per point (-1 where a
+    side has none), no row pointers, then x and phi read and FTLE written."""
+    return n * (4 * 2 * dim + 2 * dim * s + s)
+
+
 def format_bytes_fwd(mesh, dim, s=4):
     st = mesh.tile_stats()
     return st["record_bytes"] + 2 * dim * s * mesh.n + s * mesh.n
@@ -182,7 +189,7 @@ def cpu_baseline(w, threads):
                       f"(stencil built beforehand), float64, OpenMP {threads} threads"}
 
 
-def error_vs_oracle(w, got, sel=None):
+def error_vs_oracle(w, got, sel=None, stencil="ring1"):
     """Error of a float32 GPU FTLE field against the FP64 oracle on the same
     (float32-rounded) inputs: max |error| over finite points, and the relative
     error where the top eigenvalue is separated (gap >= 1e-3) and |ln lambda|
@@ -191,6 +198,8 @@ def error_vs_oracle(w, got, sel=None):
 
     import oracle
     st = oracle.ring1(w.dim, w.n, w.cells)
+    if stencil == "axis":
+        st = oracle.axis(w.dim, w.coords.astype(np.float64), st)
     ref, gap, _ = oracle.ftle(w.dim, w.coords.astype(np.float64), w.flow_numpy().astype(np.float64), st, w.T,
                               sel=sel, diagnostics=True)
     g = np.asarray(got, dtype=np.float64)
@@ -250,7 +259,8 @@ def main():
     ap.add_argument("--copies", type=int, default=3, help="input copies rotated between steps")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of: fwd3d,fwdbwd,batched (the 2D headline always runs)")
+    ap.add_argument("--only", default="",
+                    help="comma list of: fwd3d,fwdbwd,batched,axis (the 2D headline always runs)")
     ap.add_argument("--cache", default="", help="directory to keep generated workloads in (npz)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy of this many MiB (counter calibration)")
@@ -402,6 +412,30 @@ def main():
     for v in variants.values():
         v["roofline"]["frac_of_copy_probe"] = round(v["roofline"]["achieved"] / copy_gbps, 4)
     if variants:
+        if want("axis"):
+            # the paper's stencil (one nearest neighbour per side of each axis),
+            # measured against the paper's fixed-width list (alg_bytes_ell)
+            for dim, name, wl in ((2, "axis_2d_2048", lambda: w2),
+                                  (3, "axis_3d_160", lambda: cached("abc_3d", lambda: configs.abc_3d(dev),
+                                                                    args.cache, dev))):
+                log(f"{name}: building meshes")
+                wa = wl()
+                ma = [F.Mesh(wa.coords, wa.cells, "f32", stencil="axis") for _ in range(R)]
+                fa = [wa.flow.to(dev).clone().contiguous() for _ in range(R)]
+                oa = [torch.empty(wa.n, dtype=torch.float32, device=dev) for _ in range(R)]
+                fns = [lambda k=k: ma[k].forward(fa[k], wa.T, out=oa[k]) for k in range(R)]
+                t = time_steps(fns, steps_v, args.warmup, torch)
+                Be = alg_bytes_ell(wa.n, dim)
+                variants[name] = {
+                    "workload": f"{dim}D plain FTLE forward with the paper's axis stencil (2*dim nearest neighbours "
+                                f"along the axes, Section 2.2), on the {'2048^2' if dim == 2 else '160^3'} workload",
+                    "points": wa.n, "nnz": ma[0].info()["nnz"], "ms_per_step": round(t, 5),
+                    "points_per_s": round(wa.n / (t * 1e-3), 1),
+                    "roofline": dict(roofline(Be, t), alg_bytes_per_launch=Be, alg_model="paper's fixed-width list",
+                                     format_bytes_per_launch=format_bytes_fwd(ma[0], dim))}
+                log(f"{name}: {t * 1e3:.2f} us/step")
+                keep[name] = (wa, oa[0].cpu().numpy())
+                del fns, ma, fa, oa
         result["variants"] = variants
 
     if not args.no_cpu_baseline:
@@ -423,6 +457,13 @@ def main():
             err["fwd_bwd_96"] = {"ftle": error_vs_oracle(wd, outd0), "grad": grad_error_vs_oracle(wd, g0, grad0)}
         if "batched" in keep:
             err["batched_48"] = {w.name: error_vs_oracle(w, got) for w, got in keep["batched"]}
+        if "axis_2d_2048" in keep:
+            wa, got = keep["axis_2d_2048"]
+            err["axis_2d_2048"] = error_vs_oracle(wa, got, stencil="axis")
+        if "axis_3d_160" in keep:
+            wa, got = keep["axis_3d_160"]
+            err["axis_3d_160_sample"] = error_vs_oracle(wa, got, sel=np.sort(rng.choice(wa.n, 200000, replace=False)),
+                                                        stencil="axis")
         result["error_vs_fp64"] = err
 
     print(json.dumps(result), flush=True)

@@ -104,6 +104,24 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
                              int64_t n_cells, const int32_t* cells, unsigned flags,
                              ftle_mesh_t* out);
 
+/*
+ * Build a mesh from a caller-supplied stencil instead of cells: the
+ * neighbour list of Section 2.2 computed elsewhere (the paper's alternative
+ * input mode).  Row i of (row_ptr, col) lists the neighbours of point i by
+ * caller index, in any order; a repeated entry counts twice in the least
+ * squares, -1 entries (the fixed-width list's absent sides) and i itself are
+ * dropped.  The rest is as ftle_create_mesh: the stencil need not be
+ * symmetric (the adjoint then gathers over its transpose).
+ *   row_ptr  host, n_points+1 int64, row_ptr[0] = 0, non-decreasing; copied
+ *   col      host, row_ptr[n_points] int32 in [-1, n_points); copied
+ *   flags    FTLE_NO_REORDER, FTLE_HOST_ONLY, FTLE_TILE(k)
+ * Errors: as ftle_create_mesh; BAD_MESH for a decreasing row_ptr, a
+ * row_ptr[0] other than 0 or an entry out of range.
+ */
+ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                                      const int64_t* row_ptr, const int32_t* col, unsigned flags,
+                                      ftle_mesh_t* out);
+
 /* Release a mesh and its device memory (waits for the device).  NULL is a no-op. */
 void ftle_destroy_mesh(ftle_mesh_t mesh);
 

@@ -28,6 +28,7 @@ class Mesh:
     coords: (N, dim) array; cells: (ncells, dim+1) int32 point indices.
     dtype: "f32" or "f64" (storage and arithmetic of every call).
     stencil: "ring1" (all vertices sharing a cell) or "axis" (the 4/6-slot list).
+    Mesh.from_csr builds one from a caller-supplied neighbour list instead.
     """
 
     def __init__(self, coords, cells, dtype: str = "f32", stencil: str = "ring1", reorder: bool = True,
@@ -53,13 +54,48 @@ class Mesh:
         ncells = cells.shape[0] if cells.size else 0
         check(L.ftle_create_mesh(dim, coords.shape[0], coords.ctypes.data, code, ncells,
                                  cells.ctypes.data if ncells else None, flags, ctypes.byref(h)))
+        self._init(h, dim, coords.shape[0], dtype, host_only)
+
+    def _init(self, h, dim, n, dtype, host_only):
+        code, _, tdt = _DT[dtype]
         self._h = h
         self.dim = dim
-        self.n = coords.shape[0]
+        self.n = n
         self.dtype = dtype
         self.torch_dtype = tdt
         self._code = code
         self.host_only = host_only
+
+    @classmethod
+    def from_csr(cls, coords, row_ptr, col, dtype: str = "f32", reorder: bool = True, tile_log2: int = 0,
+                 host_only: bool = False):
+        """Mesh from a caller-supplied stencil: row i of (row_ptr, col) lists the
+        neighbours of point i (caller indices, any order; -1 entries and i itself
+        are dropped, repeats count twice)."""
+        if dtype not in _DT:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        L = _lib.load()
+        code, npdt, _ = _DT[dtype]
+        coords = np.ascontiguousarray(np.asarray(coords), dtype=npdt)
+        if coords.ndim != 2 or coords.shape[1] not in (2, 3):
+            raise ValueError("coords must have shape (N, 2) or (N, 3)")
+        row_ptr = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int64)
+        col = np.ascontiguousarray(np.asarray(col), dtype=np.int32)
+        if row_ptr.shape != (coords.shape[0] + 1,):
+            raise ValueError("row_ptr must have N+1 entries")
+        flags = 0
+        if not reorder:
+            flags |= _lib.NO_REORDER
+        if host_only:
+            flags |= _lib.HOST_ONLY
+        flags |= _lib.tile_flag(tile_log2)
+        h = ctypes.c_void_p()
+        check(L.ftle_create_mesh_from_csr(coords.shape[1], coords.shape[0], coords.ctypes.data, code,
+                                          row_ptr.ctypes.data, col.ctypes.data if col.size else None, flags,
+                                          ctypes.byref(h)))
+        m = cls.__new__(cls)
+        m._init(h, coords.shape[1], coords.shape[0], dtype, host_only)
+        return m
 
     # -- lifetime ---------------------------------------------------------
     def close(self):

@@ -762,36 +762,160 @@ int caller_order_axis(int dim, int64_t n, const double* x, const double* unit)
     return f;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Common part of the two mesh constructors: the Morton order of the points,
+// the stencil (from `stencil`, given the Morton permutation and its inverse,
+// returning the CSR over Morton positions), the tiles and the upload.
+template <typename StencilFn>
+ftle_mesh_t build_mesh(int dim, int64_t n, const void* coords, ftle_dtype dtype, unsigned flags, int tile_log2,
+                       const std::vector<double>& xd, StencilFn&& stencil)
+{
+    const bool f64 = dtype == FTLE_F64;
+    std::unique_ptr<ftle_mesh_s> m(new ftle_mesh_s);
+    m->dim = dim;
+    m->n = n;
+    m->dtype = dtype;
+    m->flags = flags;
+    m->host_only = (flags & FTLE_HOST_ONLY) != 0;
+    m->tile_points = tile_log2 ? (1 << tile_log2) : 512;
+    // launch shapes measured best on MI355X for 512-point tiles: two points
+    // per lane in 2D, one in 3D (whose per-lane registers cap occupancy)
+    m->fwd_block = (dim == 2) ? 256 : 512;
+    m->bwd_block = (dim == 2) ? 256 : 512;
+    // Morton order: quantise to the bounding box, interleave, stable sort
+    m->perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) m->perm[i] = (int32_t)i;
+    if (!(flags & FTLE_NO_REORDER) && n > 1) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t i = 0; i < n; ++i)
+            for (int d = 0; d < dim; ++d) {
+                lo[d] = std::min(lo[d], xd[i * dim + d]);
+                hi[d] = std::max(hi[d], xd[i * dim + d]);
+            }
+        // Quantise each axis in units of the mean point spacing, with
+        // `sub` fractional bits.  The unit is the span over n^(1/dim) - 1/2
+        // points and the offset 0.2 unit, so that floor() sends point i of
+        // an m-point lattice to i (i (1 + 1/(2m-2)) + 0.2 < i + 1) and also
+        // keeps cell-centred points jittered by up to +-0.3 spacing inside
+        // their own cell.  On such grids the integer parts are the grid
+        // indices, runs of 2^(k*dim) consecutive codes are aligned blocks
+        // and tiles have minimal halos; the fractional bits keep irregular
+        // meshes finely ordered.
+        const int bits = (dim == 2) ? 31 : 21;
+        const double per_axis = std::max(2.0, std::pow((double)n, 1.0 / dim));
+        double unit[3] = {1, 1, 1};
+        double range = 1.0;
+        for (int d = 0; d < dim; ++d) {
+            const double span = hi[d] - lo[d];
+            unit[d] = span > 0 ? span / (per_axis - 0.5) : 1.0;
+            range = std::max(range, span / unit[d] + 1.0);
+        }
+        // Caller order that walks one axis (consecutive caller indices one
+        // spacing apart along it and fixed along the others, as in a
+        // structured grid stored row by row): the other axes' codes move up
+        // one bit, so a run of 512 codes is a block long along that axis
+        // (32 x 16 in 2D, 16 x 8 x 4 instead of 8^3 in 3D) and a tile's
+        // points form longer caller-order runs.  (Longer blocks, 64 x 8 in
+        // 2D, grow the halo more than they gain.)
+        const int fast = caller_order_axis(dim, n, xd.data(), unit);
+        const int shift_bits = fast >= 0 ? 1 : 0;
+        int sub = 8;
+        while (sub > 0 && std::ldexp(range, sub + shift_bits) >= std::ldexp(1.0, bits)) --sub;
+        const double qmax = std::ldexp(1.0, bits - shift_bits) - 1.0;
+        std::vector<uint64_t> key(n);
+        parallel_for(n, [&](int64_t b, int64_t e, int) {
+            for (int64_t i = b; i < e; ++i) {
+                uint64_t code = 0;
+                for (int d = 0; d < dim; ++d) {
+                    const double t = std::floor(((xd[i * dim + d] - lo[d]) / unit[d] + 0.2) * std::ldexp(1.0, sub));
+                    uint64_t q = (uint64_t)std::min(qmax, std::max(0.0, t));
+                    if (fast >= 0 && d != fast) q <<= shift_bits;
+                    code |= (dim == 2 ? spread2(q) : spread3(q)) << d;
+                }
+                key[i] = code;
+            }
+        });
+        radix_sort_pairs(key, m->perm);
+    }
+    std::vector<int32_t> inv(n);
+    for (int64_t r = 0; r < n; ++r) inv[m->perm[r]] = (int32_t)r;
+
+    m->csr = stencil(m->perm, inv);
+    Csr tr = transpose(m->csr, n);
+    m->symmetric = csr_equal(tr, m->csr);
+    m->fwd = build_tiles(dim, f64, n, m->tile_points, m->csr, m->perm);
+    if (!m->symmetric) m->bwd = build_tiles(dim, f64, n, m->tile_points, tr, m->perm);
+    // coordinates in user order, stored in the mesh dtype
+    m->x_user.resize((size_t)n * dim * m->elem());
+    std::memcpy(m->x_user.data(), coords, m->x_user.size());
+    std::vector<unsigned char> minv;
+    if (dim == 3 && !m->host_only) minv = normal_inverse3(m->csr, m->perm, xd, f64);
+
+    if (!m->host_only) {
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        m->device = dev;
+        try {
+            upload_tiles(m->fwd);
+            if (!minv.empty()) m->fwd.d_minv = dev_upload(minv.data(), minv.size());
+            if (!m->symmetric) upload_tiles(m->bwd);
+            m->d_x = dev_upload(m->x_user.data(), m->x_user.size());
+            m->d_hits = static_cast<unsigned long long*>(dev_upload(nullptr, sizeof(unsigned long long)));
+            check_hip(hipMemset(m->d_hits, 0, sizeof(unsigned long long)), "hipMemset");
+            check_hip(hipEventCreateWithFlags(&m->work_done, hipEventDisableTiming), "hipEventCreate");
+        } catch (...) {
+            release_device(m.get());
+            throw;
+        }
+    }
+    return m.release();
+}
+
+// Shared validation of (dim, n_points, coords, dtype, flags); returns the
+// coordinates as float64 and the tile exponent.
+std::vector<double> checked_coords(int dim, int64_t n_points, const void* coords, ftle_dtype dtype, unsigned flags,
+                                   unsigned allowed, int* tile_log2)
+{
+    if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+    if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points must be >= 1");
+    if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+    if (!coords) fail(FTLE_ERR_INVALID_ARG, "coords is NULL");
+    if (flags & ~allowed) fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
+    *tile_log2 = (int)((flags >> 8) & 0xff);
+    if (*tile_log2 != 0 && (*tile_log2 < 5 || *tile_log2 > 11))
+        fail(FTLE_ERR_INVALID_ARG, "FTLE_TILE(k) needs 5 <= k <= 11");
+    const bool f64 = dtype == FTLE_F64;
+    std::vector<double> xd((size_t)n_points * dim);
+    for (int64_t i = 0; i < n_points * dim; ++i) {
+        const double v = f64 ? static_cast<const double*>(coords)[i] : (double)static_cast<const float*>(coords)[i];
+        if (!std::isfinite(v)) fail(FTLE_ERR_INVALID_ARG, "coordinate " + std::to_string(i / dim) + " is not finite");
+        xd[i] = v;
+    }
+    return xd;
+}
+
+}  // namespace
+
+extern "C" {
+
 ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
                              int64_t n_cells, const int32_t* cells, unsigned flags, ftle_mesh_t* out)
 {
     return guarded([&] {
         if (!out) fail(FTLE_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
-        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
-        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
-        if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points must be >= 1");
-        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
-        if (!coords) fail(FTLE_ERR_INVALID_ARG, "coords is NULL");
+        int tile_log2 = 0;
+        const unsigned known = FTLE_STENCIL_AXIS | FTLE_NO_REORDER | FTLE_HOST_ONLY | FTLE_TILE(0xff);
+        const std::vector<double> xd = checked_coords(dim, n_points, coords, dtype, flags, known, &tile_log2);
         if (n_cells < 0) fail(FTLE_ERR_INVALID_ARG, "n_cells < 0");
         if (n_cells > 0 && !cells) fail(FTLE_ERR_INVALID_ARG, "cells is NULL");
-        const unsigned known = FTLE_STENCIL_AXIS | FTLE_NO_REORDER | FTLE_HOST_ONLY | FTLE_TILE(0xff);
-        if (flags & ~known) fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
-        const int tile_log2 = (int)((flags >> 8) & 0xff);
-        if (tile_log2 != 0 && (tile_log2 < 5 || tile_log2 > 11))
-            fail(FTLE_ERR_INVALID_ARG, "FTLE_TILE(k) needs 5 <= k <= 11");
         const int64_t n = n_points;
         const int k = dim + 1;
         if (n_cells > INT64_MAX / k) fail(FTLE_ERR_INVALID_ARG, "n_cells too large");
-
-        // validate coordinates
-        const bool f64 = dtype == FTLE_F64;
-        std::vector<double> xd((size_t)n * dim);
-        for (int64_t i = 0; i < n * dim; ++i) {
-            const double v = f64 ? static_cast<const double*>(coords)[i] : (double)static_cast<const float*>(coords)[i];
-            if (!std::isfinite(v)) fail(FTLE_ERR_INVALID_ARG, "coordinate " + std::to_string(i / dim) + " is not finite");
-            xd[i] = v;
-        }
         // validate cells
         std::atomic<int64_t> bad_cell{-1};
         std::atomic<int> bad_kind{0};
@@ -817,124 +941,72 @@ ftle_status ftle_create_mesh(int dim, int64_t n_points, const void* coords, ftle
             fail(FTLE_ERR_BAD_MESH, std::string(bad_kind == 1 ? "cell index out of range" : "repeated vertex") +
                                         " in cell " + std::to_string(bad_cell.load()));
 
-        std::unique_ptr<ftle_mesh_s> m(new ftle_mesh_s);
-        m->dim = dim;
-        m->n = n;
-        m->dtype = dtype;
-        m->flags = flags;
-        m->host_only = (flags & FTLE_HOST_ONLY) != 0;
-        m->tile_points = tile_log2 ? (1 << tile_log2) : 512;
-        // launch shapes measured best on MI355X for 512-point tiles: two points
-        // per lane in 2D, one in 3D (whose per-lane registers cap occupancy)
-        m->fwd_block = (dim == 2) ? 256 : 512;
-        m->bwd_block = (dim == 2) ? 256 : 512;
-
-        // Morton order: quantise to the bounding box, interleave, stable sort
-        m->perm.resize(n);
-        for (int64_t i = 0; i < n; ++i) m->perm[i] = (int32_t)i;
-        if (!(flags & FTLE_NO_REORDER) && n > 1) {
-            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-            for (int64_t i = 0; i < n; ++i)
-                for (int d = 0; d < dim; ++d) {
-                    lo[d] = std::min(lo[d], xd[i * dim + d]);
-                    hi[d] = std::max(hi[d], xd[i * dim + d]);
-                }
-            // Quantise each axis in units of the mean point spacing, with
-            // `sub` fractional bits.  The unit is the span over n^(1/dim) - 1/2
-            // points and the offset 0.2 unit, so that floor() sends point i of
-            // an m-point lattice to i (i (1 + 1/(2m-2)) + 0.2 < i + 1) and also
-            // keeps cell-centred points jittered by up to +-0.3 spacing inside
-            // their own cell.  On such grids the integer parts are the grid
-            // indices, runs of 2^(k*dim) consecutive codes are aligned blocks
-            // and tiles have minimal halos; the fractional bits keep irregular
-            // meshes finely ordered.
-            const int bits = (dim == 2) ? 31 : 21;
-            const double per_axis = std::max(2.0, std::pow((double)n, 1.0 / dim));
-            double unit[3] = {1, 1, 1};
-            double range = 1.0;
-            for (int d = 0; d < dim; ++d) {
-                const double span = hi[d] - lo[d];
-                unit[d] = span > 0 ? span / (per_axis - 0.5) : 1.0;
-                range = std::max(range, span / unit[d] + 1.0);
-            }
-            // Caller order that walks one axis (consecutive caller indices one
-            // spacing apart along it and fixed along the others, as in a
-            // structured grid stored row by row): the other axes' codes move up
-            // one bit, so a run of 512 codes is a block long along that axis
-            // (32 x 16 in 2D, 16 x 8 x 4 instead of 8^3 in 3D) and a tile's
-            // points form longer caller-order runs.  (Longer blocks, 64 x 8 in
-            // 2D, grow the halo more than they gain.)
-            const int fast = caller_order_axis(dim, n, xd.data(), unit);
-            const int shift_bits = fast >= 0 ? 1 : 0;
-            int sub = 8;
-            while (sub > 0 && std::ldexp(range, sub + shift_bits) >= std::ldexp(1.0, bits)) --sub;
-            const double qmax = std::ldexp(1.0, bits - shift_bits) - 1.0;
-            std::vector<uint64_t> key(n);
-            parallel_for(n, [&](int64_t b, int64_t e, int) {
-                for (int64_t i = b; i < e; ++i) {
-                    uint64_t code = 0;
-                    for (int d = 0; d < dim; ++d) {
-                        const double t = std::floor(((xd[i * dim + d] - lo[d]) / unit[d] + 0.2) * std::ldexp(1.0, sub));
-                        uint64_t q = (uint64_t)std::min(qmax, std::max(0.0, t));
-                        if (fast >= 0 && d != fast) q <<= shift_bits;
-                        code |= (dim == 2 ? spread2(q) : spread3(q)) << d;
-                    }
-                    key[i] = code;
-                }
-            });
-            radix_sort_pairs(key, m->perm);
-        }
-        std::vector<int32_t> inv(n);
-        for (int64_t r = 0; r < n; ++r) inv[m->perm[r]] = (int32_t)r;
-
-        // cells in Morton positions, then the stencil
-        std::vector<int32_t> mc((size_t)n_cells * k);
-        parallel_for(n_cells * k, [&](int64_t b, int64_t e, int) {
-            for (int64_t i = b; i < e; ++i) mc[i] = inv[cells[i]];
-        });
-        Csr ring = build_ring1(dim, n, n_cells, mc);
-        mc.clear();
-        mc.shrink_to_fit();
-        if (flags & FTLE_STENCIL_AXIS) {
-            std::vector<double> xm((size_t)n * dim);
-            for (int64_t r = 0; r < n; ++r)
-                for (int d = 0; d < dim; ++d) xm[r * dim + d] = xd[(size_t)m->perm[r] * dim + d];
-            m->csr = build_axis<double>(dim, n, ring, xm.data(), m->perm);
-        } else {
-            m->csr = std::move(ring);
-        }
-        Csr tr = transpose(m->csr, n);
-        m->symmetric = csr_equal(tr, m->csr);
-        m->fwd = build_tiles(dim, f64, n, m->tile_points, m->csr, m->perm);
-        if (!m->symmetric) m->bwd = build_tiles(dim, f64, n, m->tile_points, tr, m->perm);
-
-        // coordinates in user order, stored in the mesh dtype
-        m->x_user.resize((size_t)n * dim * m->elem());
-        std::memcpy(m->x_user.data(), coords, m->x_user.size());
-        std::vector<unsigned char> minv;
-        if (dim == 3 && !m->host_only) minv = normal_inverse3(m->csr, m->perm, xd, f64);
-
-        if (!m->host_only) {
-            int dev = 0;
-            check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
-            m->device = dev;
-            try {
-                upload_tiles(m->fwd);
-                if (!minv.empty()) m->fwd.d_minv = dev_upload(minv.data(), minv.size());
-                if (!m->symmetric) upload_tiles(m->bwd);
-                m->d_x = dev_upload(m->x_user.data(), m->x_user.size());
-                m->d_hits = static_cast<unsigned long long*>(dev_upload(nullptr, sizeof(unsigned long long)));
-                check_hip(hipMemset(m->d_hits, 0, sizeof(unsigned long long)), "hipMemset");
-                check_hip(hipEventCreateWithFlags(&m->work_done, hipEventDisableTiming), "hipEventCreate");
-            } catch (...) {
-                release_device(m.get());
-                throw;
-            }
-        }
-        *out = m.release();
+        *out = build_mesh(dim, n, coords, dtype, flags, tile_log2, xd,
+                          [&](const std::vector<int32_t>& perm, const std::vector<int32_t>& inv) {
+                              // cells in Morton positions, then the stencil
+                              std::vector<int32_t> mc((size_t)n_cells * k);
+                              parallel_for(n_cells * k, [&](int64_t b, int64_t e, int) {
+                                  for (int64_t i = b; i < e; ++i) mc[i] = inv[cells[i]];
+                              });
+                              Csr ring = build_ring1(dim, n, n_cells, mc);
+                              mc.clear();
+                              mc.shrink_to_fit();
+                              if (!(flags & FTLE_STENCIL_AXIS)) return ring;
+                              std::vector<double> xm((size_t)n * dim);
+                              for (int64_t r = 0; r < n; ++r)
+                                  for (int d = 0; d < dim; ++d) xm[r * dim + d] = xd[(size_t)perm[r] * dim + d];
+                              return build_axis<double>(dim, n, ring, xm.data(), perm);
+                          });
     });
 }
 
+ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                                      const int64_t* row_ptr, const int32_t* col, unsigned flags,
+                                      ftle_mesh_t* out)
+{
+    return guarded([&] {
+        if (!out) fail(FTLE_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        int tile_log2 = 0;
+        const unsigned known = FTLE_NO_REORDER | FTLE_HOST_ONLY | FTLE_TILE(0xff);
+        const std::vector<double> xd = checked_coords(dim, n_points, coords, dtype, flags, known, &tile_log2);
+        if (!row_ptr) fail(FTLE_ERR_INVALID_ARG, "row_ptr is NULL");
+        const int64_t n = n_points;
+        if (row_ptr[0] != 0) fail(FTLE_ERR_BAD_MESH, "row_ptr[0] must be 0");
+        for (int64_t i = 0; i < n; ++i)
+            if (row_ptr[i + 1] < row_ptr[i]) fail(FTLE_ERR_BAD_MESH, "row_ptr decreases at row " + std::to_string(i));
+        if (row_ptr[n] > 0 && !col) fail(FTLE_ERR_INVALID_ARG, "col is NULL");
+        for (int64_t p = 0; p < row_ptr[n]; ++p)
+            if (col[p] < -1 || col[p] >= n)
+                fail(FTLE_ERR_BAD_MESH, "col[" + std::to_string(p) + "] out of range");
+        *out = build_mesh(dim, n, coords, dtype, flags, tile_log2, xd,
+                          [&](const std::vector<int32_t>& perm, const std::vector<int32_t>& inv) {
+                              // rows in Morton positions, ascending; -1 and the point itself dropped
+                              Csr c;
+                              c.row_ptr.assign(n + 1, 0);
+                              int64_t total = 0;
+                              for (int64_t r = 0; r < n; ++r) {
+                                  const int64_t i = perm[r];
+                                  for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+                                      total += (col[p] >= 0 && col[p] != i) ? 1 : 0;
+                                  if (total > INT32_MAX)
+                                      fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
+                                  c.row_ptr[r + 1] = (int32_t)total;
+                              }
+                              c.col.resize(total);
+                              parallel_for(n, [&](int64_t b, int64_t e, int) {
+                                  for (int64_t r = b; r < e; ++r) {
+                                      const int64_t i = perm[r];
+                                      int32_t q = c.row_ptr[r];
+                                      for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+                                          if (col[p] >= 0 && col[p] != i) c.col[q++] = inv[col[p]];
+                                      std::sort(c.col.begin() + c.row_ptr[r], c.col.begin() + q);
+                                  }
+                              });
+                              return c;
+                          });
+    });
+}
 
 ftle_status ftle_mesh_info(ftle_mesh_t mesh, int* dim, int64_t* n_points, int64_t* nnz, int* dtype)
 {

@@ -325,6 +325,48 @@ def test_3d_records_worst_case_and_empty_rows(dtype, relabel):
     assert np.all(got_g[p[n0:nf]] == 0)
 
 
+@pytest.mark.parametrize("dim,dtype", [(2, "f32"), (3, "f32"), (3, "f64")])
+def test_from_csr_knn_vs_oracle(dim, dtype):
+    """A caller-supplied, non-symmetric stencil (the k nearest neighbours):
+    forward and adjoint (gather over the transposed stencil, sigma from the
+    tape) against the oracle on the same stencil; and the cells' own stencil
+    given as a list reproduces the cells mesh bit for bit."""
+    from scipy.spatial import cKDTree
+    x, cells, phi, T = _grad_case(dim, dtype)
+    k = 6 if dim == 2 else 10
+    _, nb = cKDTree(np.asarray(x, np.float64)).query(np.asarray(x, np.float64), k + 1)
+    nb = np.ascontiguousarray(nb[:, 1:], dtype=np.int32).ravel()
+    row_ptr = np.arange(x.shape[0] + 1, dtype=np.int64) * k
+    m = F.Mesh.from_csr(x, row_ptr, nb, dtype)
+    st = oracle.Stencil(row_ptr, nb)
+    xd, pd = x.astype(np.float64), phi.cpu().numpy().astype(np.float64)
+    fref, gap, _ = oracle.ftle(dim, xd, pd, st, T, diagnostics=True)
+    g = torch.as_tensor(np.random.default_rng(8).standard_normal(x.shape[0]), dtype=phi.dtype, device=DEV)
+    out, tape = m.forward_tape(phi, T)
+    f = m.forward(phi, T).cpu().numpy().astype(np.float64)
+    grad = m.backward_tape(tape, g).cpu().numpy()
+    check = check_f64 if dtype == "f64" else check_f32
+    if dtype == "f64":
+        check("knn fwd", f, fref, gap, T, dim)
+        check("knn tape fwd", out.cpu().numpy(), fref, gap, T, dim)
+    else:
+        check("knn fwd", f, fref, gap, T)
+        check("knn tape fwd", out.cpu().numpy().astype(np.float64), fref, gap, T)
+    ref = oracle.ftle_grad(dim, xd, pd, st, T, g.cpu().numpy().astype(np.float64))
+    bad = np.zeros(x.shape[0], bool)
+    for i in np.nonzero(np.isfinite(fref) & ~(gap >= 1e-6))[0]:
+        bad[i] = True
+        bad[st.col[st.row_ptr[i]:st.row_ptr[i + 1]]] = True
+    err = np.abs(grad - ref)[~bad].max() / np.abs(ref).max()
+    print(f"[knn {dim}D {dtype}] adjoint max err/scale = {err:.3e}, excluded {bad.sum()}", flush=True)
+    assert err <= (1e-10 if dtype == "f64" else 2e-4)
+    # the cells' stencil as a list: the same mesh
+    ring = oracle.ring1(dim, x.shape[0], cells)
+    mr = F.Mesh.from_csr(x, ring.row_ptr, ring.col, dtype)
+    mc = F.Mesh(x, cells, dtype)
+    assert torch.equal(torch.nan_to_num(mr.forward(phi, T), nan=7.0), torch.nan_to_num(mc.forward(phi, T), nan=7.0))
+
+
 def test_adjoint_fd_16cubed_f64():
     """GPU float64 adjoint against central differences (h = 1e-6) of the oracle's FTLE."""
     x, cells, phi, T = _grad_case(3, "f64", 16)

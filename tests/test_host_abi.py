@@ -195,6 +195,62 @@ def test_grid_numbered_records_compress():
     assert sum(len(r["xend"]) for r in recs2) > 0.95 * rows
 
 
+def _rows_as_sets(m):
+    row_ptr, col, perm = m.csr()
+    return {int(perm[r]): sorted(int(perm[c]) for c in col[row_ptr[r]:row_ptr[r + 1]]) for r in range(m.n)}
+
+
+@pytest.mark.parametrize("stencil", ["ring1", "axis"])
+def test_from_csr_matches_cells(stencil):
+    """A mesh built from the oracle's own stencil (the caller-supplied list of
+    the paper's alternative input mode) equals the one built from the cells:
+    same stencil, same tile records."""
+    x, c = meshes.jittered_tri_grid(37, 23, seed=3)
+    st = oracle.ring1(2, x.shape[0], c)
+    if stencil == "axis":
+        st = oracle.axis(2, x, st)
+    m1 = F.Mesh(x, c, "f32", stencil=stencil, host_only=True)
+    m2 = F.Mesh.from_csr(x, st.row_ptr, st.col, "f32", host_only=True)
+    assert _rows_as_sets(m1) == _rows_as_sets(m2)
+    for adjoint in (False, True):
+        for a, b in zip(m1.tile_records(adjoint), m2.tile_records(adjoint)):
+            assert a.keys() == b.keys()
+            for k in a:
+                assert np.array_equal(a[k], b[k]) if isinstance(a[k], np.ndarray) else a[k] == b[k]
+
+
+def test_from_csr_drops_absent_and_self_keeps_repeats():
+    x = np.random.default_rng(1).uniform(size=(40, 3))
+    rows = [[(i + 1) % 40, (i + 2) % 40, -1, i, (i + 1) % 40] for i in range(40)]
+    row_ptr = np.arange(41) * 5
+    m = F.Mesh.from_csr(x, row_ptr, np.array(rows, np.int32).ravel(), "f64", host_only=True, tile_log2=5)
+    got = _rows_as_sets(m)
+    assert all(got[i] == sorted([(i + 1) % 40, (i + 1) % 40, (i + 2) % 40]) for i in range(40))
+    assert m.info()["nnz"] == 3 * 40
+
+
+def test_from_csr_validation(L):
+    INVALID, BAD = 1, 2
+    x = np.zeros((4, 2), np.float32)
+    col = np.array([1, 2, 0, 3], np.int32)
+
+    def make(row_ptr, col=col, flags=_lib.HOST_ONLY, dim=2):
+        h = ctypes.c_void_p()
+        rp = np.asarray(row_ptr if row_ptr is not None else [0], np.int64)
+        return L.ftle_create_mesh_from_csr(dim, 4, x.ctypes.data, 0, rp.ctypes.data if row_ptr is not None else None,
+                                           col.ctypes.data if col is not None else None, flags, ctypes.byref(h))
+
+    assert make([0, 1, 2, 3, 4]) == 0
+    assert make(None) == INVALID
+    assert make([0, 1, 2, 3, 4], col=None) == INVALID
+    assert make([1, 1, 2, 3, 4]) == BAD
+    assert make([0, 2, 1, 3, 4]) == BAD
+    assert make([0, 1, 2, 3, 4], col=np.array([1, 2, 0, 4], np.int32)) == BAD
+    assert make([0, 1, 2, 3, 4], col=np.array([1, 2, -2, 3], np.int32)) == BAD
+    assert make([0, 1, 2, 3, 4], flags=_lib.HOST_ONLY | _lib.STENCIL_AXIS) == INVALID
+    assert make([0, 1, 2, 3, 4], dim=5) == INVALID
+
+
 def test_ring1_symmetric_shares_adjoint_tiles():
     x, c = meshes.jittered_tri_grid(20, 20, seed=2)
     m = F.Mesh(x, c, "f32", host_only=True)
