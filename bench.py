@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -233,6 +234,12 @@ def grad_error_vs_oracle(w, g_in, grad):
             "max_err_over_max_grad": float(np.abs(got - ref)[~bad].max() / np.abs(ref).max())}
 
 
+def oracle_advect(x0, t0, T):
+    """The FP64 oracle's RK4 double-gyre flow map (dt = 0.01) of the given particles."""
+    import oracle
+    return oracle.advect_rk4("double_gyre", x0, t0, T, 0.01)
+
+
 def copy_probe_gbps(torch, dev, mib=1024, reps=10):
     """Bandwidth of a plain elementwise kernel (torch.neg: mib MiB read + mib MiB written)."""
     src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
@@ -260,7 +267,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of: fwd3d,fwdbwd,batched,axis (the 2D headline always runs)")
+                    help="comma list of: fwd3d,fwdbwd,batched,axis,advect (the 2D headline always runs)")
     ap.add_argument("--cache", default="", help="directory to keep generated workloads in (npz)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy of this many MiB (counter calibration)")
@@ -436,6 +443,26 @@ def main():
                 log(f"{name}: {t * 1e3:.2f} us/step")
                 keep[name] = (wa, oa[0].cpu().numpy())
                 del fns, ma, fa, oa
+        if want("advect"):
+            # the step before the path: the 2048^2 double-gyre flow map by RK4 on
+            # the GPU (float64 arithmetic, float32 output), as the headline's
+            # input was generated (T = 15, dt = 0.01: 1500 steps per particle)
+            log("advect_2d_2048: RK4 flow map on the GPU")
+            x0 = torch.as_tensor(w2.coords, dtype=torch.float32, device=dev).contiguous()
+            t0 = float(w2.extra.get("t0", 0.0))
+            phi = torch.empty_like(x0)
+            F.advect_rk4("double_gyre", x0, t0, w2.T, 0.01, out=phi)
+            t = time_steps([lambda: F.advect_rk4("double_gyre", x0, t0, w2.T, 0.01, out=phi)], 3, 1, torch)
+            nsteps = math.ceil(abs(w2.T) / 0.01 - 1e-9)
+            variants["advect_2d_2048"] = {
+                "workload": "RK4 flow map of the 2048^2 jittered grid in the double gyre, t0 = 0, T = 15, dt = 0.01 "
+                            "(float64 arithmetic, float32 output)",
+                "points": w2.n, "steps_per_point": nsteps, "ms_per_step": round(t, 4),
+                "points_per_s": round(w2.n / (t * 1e-3), 1),
+                "particle_steps_per_s": round(w2.n * nsteps / (t * 1e-3), 1)}
+            log(f"advect_2d_2048: {t:.2f} ms per flow map")
+            keep["advect"] = (w2, x0.cpu().numpy(), t0, phi.cpu().numpy())
+            del x0, phi
         result["variants"] = variants
 
     if not args.no_cpu_baseline:
@@ -457,6 +484,12 @@ def main():
             err["fwd_bwd_96"] = {"ftle": error_vs_oracle(wd, outd0), "grad": grad_error_vs_oracle(wd, g0, grad0)}
         if "batched" in keep:
             err["batched_48"] = {w.name: error_vs_oracle(w, got) for w, got in keep["batched"]}
+        if "advect" in keep:
+            wa, x0, t0, phi = keep["advect"]
+            sel = np.sort(rng.choice(wa.n, 20000, replace=False))
+            ref = oracle_advect(x0[sel].astype(np.float64), t0, wa.T)
+            err["advect_2d_2048_sample"] = {"points": int(sel.size),
+                                            "max_abs_err": float(np.abs(phi[sel].astype(np.float64) - ref).max())}
         if "axis_2d_2048" in keep:
             wa, got = keep["axis_2d_2048"]
             err["axis_2d_2048"] = error_vs_oracle(wa, got, stencil="axis")

@@ -122,6 +122,35 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
                                       const int64_t* row_ptr, const int32_t* col, unsigned flags,
                                       ftle_mesh_t* out);
 
+/* Analytic flows of ftle_advect_rk4. */
+typedef enum {
+    /* double gyre (Shadden, Lekien and Marsden 2005), 2D; params A, eps, omega
+     * (default 0.1, 0.25, 2 pi / 10) */
+    FTLE_FLOW_DOUBLE_GYRE = 0,
+    /* steady ABC flow, 3D; params A, B, C (default sqrt 3, sqrt 2, 1) */
+    FTLE_FLOW_ABC = 1
+} ftle_flow;
+
+/*
+ * Flow map phi = x(t0 + T) of particles starting at x0 at time t0, by the
+ * classical fourth-order Runge-Kutta method in float64 (the step before the
+ * FTLE path: the paper's inputs are precomputed flow maps).  Each particle
+ * takes max(1, ceil(|T|/dt - 1e-9)) steps of T/steps.
+ *   flow     FTLE_FLOW_* (2D double gyre, 3D ABC)
+ *   params   host, 3 doubles, or NULL for the defaults above
+ *   n        particles (>= 0)
+ *   x0       device, n x dim of dtype (dim 2 or 3 by the flow)
+ *   t0s, Ts  device, n doubles each: per-particle start time and duration
+ *            (many meshes' windows in one call), or NULL to use t0 / T
+ *   dt       largest step (> 0)
+ *   phi      device, n x dim of dtype, caller-owned, overwritten; not x0
+ * Errors: INVALID_ARG (flow, dtype, n < 0, null pointer with n > 0, dt <= 0,
+ * non-finite t0, T or parameter), DEVICE.
+ */
+ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const void* x0, ftle_dtype dtype,
+                            const double* t0s, const double* Ts, double t0, double T, double dt, void* phi,
+                            ftle_stream_t stream);
+
 /* Release a mesh and its device memory (waits for the device).  NULL is a no-op. */
 void ftle_destroy_mesh(ftle_mesh_t mesh);
 

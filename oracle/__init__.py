@@ -62,6 +62,8 @@ class _Lib:
         lib.oracle_ftle_grad.restype = None
         lib.oracle_ftle_grad.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp, ctypes.c_double,
                                          vp, vp]
+        lib.oracle_advect_rk4.restype = None
+        lib.oracle_advect_rk4.argtypes = [ctypes.c_int, vp, i64, vp, vp, vp, ctypes.c_double, vp]
         lib.oracle_jacobi_eig3.restype = None
         lib.oracle_jacobi_eig3.argtypes = [vp, vp, vp]
         lib.oracle_set_threads.restype = None
@@ -193,3 +195,24 @@ def jacobi_eig3(m, lib=None):
     vecs = np.empty((3, 3))
     lib.oracle_jacobi_eig3(_p(m), _p(vals), _p(vecs))
     return vals, vecs
+
+
+FLOWS = {"double_gyre": (0, 2, (0.1, 0.25, 2.0 * np.pi / 10.0)),
+         "abc": (1, 3, (np.sqrt(3.0), np.sqrt(2.0), 1.0))}
+
+
+def advect_rk4(flow: str, x0, t0, T, dt: float, params=None, lib=None):
+    """Flow map x(t0 + T) of the analytic flow ("double_gyre": params A, eps,
+    omega; "abc": params A, B, C) by classical RK4 in float64: per point
+    max(1, ceil(|T|/dt - 1e-9)) steps of T/steps.  t0 and T: scalars or per-point
+    arrays."""
+    lib = _load(lib)
+    kind, dim, default = FLOWS[flow]
+    prm = _f64(default if params is None else params)
+    x = _f64(x0).reshape(-1, dim)
+    n = x.shape[0]
+    t0a = _f64(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
+    Ta = _f64(np.broadcast_to(np.asarray(T, dtype=np.float64), (n,)))
+    out = np.empty_like(x)
+    lib.oracle_advect_rk4(kind, _p(prm), n, _p(x), _p(t0a), _p(Ta), float(dt), _p(out))
+    return out

@@ -436,3 +436,66 @@ void oracle_ftle_grad(int dim, int64_t n, const double* x, const double* phi,
     free(H);
     free(use);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Flow maps by advection (the step before the FTLE path: the paper's inputs */
+/* are precomputed flow maps, Section 2.2)                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Velocity of an analytic flow at point p, time t.
+ *  kind 0, the double gyre (Shadden, Lekien and Marsden, Physica D 212,
+ *    2005), params A, eps, omega: stream function
+ *    psi = A sin(pi f(x, t)) sin(pi y), f = eps sin(omega t) x^2 +
+ *    (1 - 2 eps sin(omega t)) x; velocity (-dpsi/dy, dpsi/dx).
+ *  kind 1, the steady ABC flow, params A, B, C:
+ *    (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x).
+ */
+static void velocity(int kind, const double* prm, const double* p, double t, double* v)
+{
+    const double pi = 3.14159265358979323846;
+    if (kind == 0) {
+        const double A = prm[0], eps = prm[1], om = prm[2];
+        const double s = sin(om * t);
+        const double a = eps * s, b = 1.0 - 2.0 * eps * s;
+        const double f = a * p[0] * p[0] + b * p[0];
+        const double dfdx = 2.0 * a * p[0] + b;
+        v[0] = -pi * A * sin(pi * f) * cos(pi * p[1]);
+        v[1] = pi * A * cos(pi * f) * sin(pi * p[1]) * dfdx;
+    } else {
+        const double A = prm[0], B = prm[1], C = prm[2];
+        v[0] = A * sin(p[2]) + C * cos(p[1]);
+        v[1] = B * sin(p[0]) + A * cos(p[2]);
+        v[2] = C * sin(p[1]) + B * cos(p[0]);
+    }
+}
+
+/*
+ * Flow map phi_i = x_i(t0_i + T_i) by the classical fourth-order Runge-Kutta
+ * method: steps = max(1, ceil(|T_i| / dt - 1e-9)) steps of h = T_i / steps.
+ * x0, phi: n x dim; t0, T: n values each.
+ */
+void oracle_advect_rk4(int kind, const double* prm, int64_t n, const double* x0, const double* t0,
+                       const double* T, double dt, double* phi)
+{
+    const int D = kind == 0 ? 2 : 3;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double p[3], q[3], k1[3], k2[3], k3[3], k4[3];
+        for (int d = 0; d < D; ++d) p[d] = x0[i * D + d];
+        double steps = ceil(fabs(T[i]) / dt - 1e-9);
+        if (steps < 1.0) steps = 1.0;
+        const double h = T[i] / steps;
+        for (int64_t s = 0; s < (int64_t)steps; ++s) {
+            const double t = t0[i] + (double)s * h;
+            velocity(kind, prm, p, t, k1);
+            for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k1[d];
+            velocity(kind, prm, q, t + 0.5 * h, k2);
+            for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k2[d];
+            velocity(kind, prm, q, t + 0.5 * h, k3);
+            for (int d = 0; d < D; ++d) q[d] = p[d] + h * k3[d];
+            velocity(kind, prm, q, t + h, k4);
+            for (int d = 0; d < D; ++d) p[d] += h / 6.0 * (k1[d] + 2.0 * k2[d] + 2.0 * k3[d] + k4[d]);
+        }
+        for (int d = 0; d < D; ++d) phi[i * D + d] = p[d];
+    }
+}

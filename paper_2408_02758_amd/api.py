@@ -359,6 +359,39 @@ class FTLEFunction(torch.autograd.Function):
         return grad, None, None
 
 
+_FLOWS = {"double_gyre": (0, 2), "abc": (1, 3)}
+
+
+def advect_rk4(flow: str, x0: torch.Tensor, t0, T, dt: float, params=None, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """Flow map x(t0 + T) of particles at x0 (device tensor, (N, 2) for
+    "double_gyre" or (N, 3) for "abc", float32 or float64) by RK4 on the GPU.
+    t0 and T: floats, or float64 device tensors of N per-particle values."""
+    kind, dim = _FLOWS[flow]
+    if not (x0.is_cuda and x0.is_contiguous() and x0.dim() == 2 and x0.shape[1] == dim):
+        raise ValueError(f"x0 must be a contiguous device tensor of shape (N, {dim})")
+    code = {torch.float32: 0, torch.float64: 1}.get(x0.dtype)
+    if code is None:
+        raise ValueError("x0 must be float32 or float64")
+    n = x0.shape[0]
+
+    def per_point(v, name):
+        if isinstance(v, torch.Tensor):
+            if not (v.is_cuda and v.dtype == torch.float64 and v.is_contiguous() and v.shape == (n,)):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of {n} values")
+            return ctypes.c_void_p(v.data_ptr()), 0.0
+        return None, float(v)
+
+    t0p, t0s = per_point(t0, "t0")
+    Tp, Ts = per_point(T, "T")
+    if out is None:
+        out = torch.empty_like(x0)
+    prm = None if params is None else (ctypes.c_double * 3)(*[float(v) for v in params])
+    check(_lib.load().ftle_advect_rk4(kind, prm, n, ctypes.c_void_p(x0.data_ptr()), code, t0p, Tp, t0s, Ts,
+                                      float(dt), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
 def force_wide_offsets(on: bool) -> None:
     """Testing aid: make every later launch take the 64-bit offset path (see ftle_force_wide_offsets)."""
     check(_lib.load().ftle_force_wide_offsets(int(bool(on))))

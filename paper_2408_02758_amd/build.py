@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libftle.so")
-SOURCES = [os.path.join(CSRC, "ftle_kernels.hip"), os.path.join(CSRC, "ftle_host.cpp")]
+SOURCES = [os.path.join(CSRC, "ftle_kernels.hip"), os.path.join(CSRC, "ftle_advect.hip"),
+           os.path.join(CSRC, "ftle_host.cpp")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

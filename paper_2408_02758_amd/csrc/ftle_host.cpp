@@ -1426,6 +1426,37 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
     });
 }
 
+ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const void* x0, ftle_dtype dtype,
+                            const double* t0s, const double* Ts, double t0, double T, double dt, void* phi,
+                            ftle_stream_t stream)
+{
+    return guarded([&] {
+        if (flow != FTLE_FLOW_DOUBLE_GYRE && flow != FTLE_FLOW_ABC) fail(FTLE_ERR_INVALID_ARG, "unknown flow");
+        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        if (n < 0) fail(FTLE_ERR_INVALID_ARG, "n < 0");
+        if (n > 0 && (!x0 || !phi)) fail(FTLE_ERR_INVALID_ARG, "x0 or phi is NULL");
+        if (!(dt > 0.0) || !std::isfinite(dt)) fail(FTLE_ERR_INVALID_ARG, "dt must be positive and finite");
+        if (!std::isfinite(t0) || !std::isfinite(T)) fail(FTLE_ERR_INVALID_ARG, "t0 and T must be finite");
+        double prm[3];
+        if (params) {
+            for (int k = 0; k < 3; ++k) {
+                if (!std::isfinite(params[k])) fail(FTLE_ERR_INVALID_ARG, "non-finite flow parameter");
+                prm[k] = params[k];
+            }
+        } else if (flow == FTLE_FLOW_DOUBLE_GYRE) {
+            prm[0] = 0.1, prm[1] = 0.25, prm[2] = 2.0 * 3.14159265358979323846 / 10.0;
+        } else {
+            prm[0] = std::sqrt(3.0), prm[1] = std::sqrt(2.0), prm[2] = 1.0;
+        }
+        if (n == 0) return;
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        check_hip(launch_advect(flow, prm, dtype == FTLE_F64, n, x0, t0s, Ts, t0, T, dt, phi,
+                                static_cast<hipStream_t>(stream)),
+                  "advect launch");
+    });
+}
+
 ftle_status ftle_batched_config(int n, const ftle_mesh_t* meshes, int* block, int* tiles_per_pop, int* grid)
 {
     return guarded([&] {

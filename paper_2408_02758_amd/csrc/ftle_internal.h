@@ -167,6 +167,11 @@ hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, cons
 // Block sizes (threads per workgroup) the kernels are compiled for.
 inline bool supported_block(int b) { return b == 128 || b == 256 || b == 512; }
 
+// Flow maps by RK4 advection (ftle_advect.hip): kind 0 double gyre, 1 ABC;
+// per-point t0s / Ts when not null, else t0 / T for every particle.
+hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, const void* x0, const double* t0s,
+                         const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream);
+
 hipError_t launch_batched(int dim, bool f64, bool wide, const BatchItem* items, int n_items, int tiles_per_pop,
                           unsigned* queue, const BatchCall& call, size_t lds, double eig_tau, int block, int grid,
                           hipStream_t stream);

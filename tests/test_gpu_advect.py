@@ -1,0 +1,75 @@
+"""GPU RK4 flow maps (ftle_advect_rk4) against the FP64 oracle, and the
+sliding-window pipeline: one advection call over several meshes' windows
+feeding one batched FTLE call.
+
+Tolerance: both sides step the same RK4 in float64; they differ only in the
+rounding of the velocity's sines and cosines (the GPU forms sin(pi f) as
+sinpi(f)), which the flow's stretching amplifies by at most exp(lambda T)
+(lambda < 1 on these flows): 1e-9 absolute over T = 15 is ample.  Float32
+output adds its own rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_02758_amd as F
+from workloads import meshes
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.mark.parametrize("flow,dim", [("double_gyre", 2), ("abc", 3)])
+def test_advect_vs_oracle(flow, dim):
+    if dim == 2:
+        x, _ = meshes.jittered_tri_grid(64, 48, seed=4)
+        t0, T, dt = 0.5, 15.0, 0.01
+    else:
+        x, _ = meshes.kuhn_tet_grid(14)
+        t0, T, dt = 0.0, 10.0, 0.02
+    ref = oracle.advect_rk4(flow, x, t0, T, dt)
+    x64 = torch.as_tensor(x, dtype=torch.float64, device=DEV)
+    got = F.advect_rk4(flow, x64, t0, T, dt).cpu().numpy()
+    err = np.abs(got - ref).max()
+    print(f"[advect {flow} f64] max |d| = {err:.3e}", flush=True)
+    assert err < 1e-9
+    got32 = F.advect_rk4(flow, x64.float().contiguous(), t0, T, dt).cpu().numpy().astype(np.float64)
+    ref32 = oracle.advect_rk4(flow, x.astype(np.float32).astype(np.float64), t0, T, dt)
+    assert np.all(np.abs(got32 - ref32) <= 1e-9 + 2 ** -23 * np.abs(ref32))
+    # backward in time, and T = 0
+    back = F.advect_rk4(flow, torch.as_tensor(ref, device=DEV), t0 + T, -T, dt).cpu().numpy()
+    assert np.abs(back - x).max() < 1e-6
+    assert torch.equal(F.advect_rk4(flow, x64, 1.0, 0.0, dt), x64)
+
+
+def test_windows_pipeline_vs_oracle():
+    """Three meshes, each with its own window (t0, T), advected in one call with
+    per-particle times, then their FTLE in one batched call; against the
+    oracle's flow maps and FTLE."""
+    sides, t0s, Ts = (30, 41, 25), (0.0, 2.5, 7.0), (15.0, 10.0, -12.0)
+    geo = [meshes.jittered_tri_grid(s, s, seed=100 + k) for k, s in enumerate(sides)]
+    counts = [g[0].shape[0] for g in geo]
+    allx = np.concatenate([g[0] for g in geo])
+    t0p = np.repeat(t0s, counts)
+    Tp = np.repeat(Ts, counts)
+    xd = torch.as_tensor(allx, dtype=torch.float64, device=DEV)
+    phi = F.advect_rk4("double_gyre", xd, torch.as_tensor(t0p, device=DEV), torch.as_tensor(Tp, device=DEV), 0.01)
+    ref_phi = oracle.advect_rk4("double_gyre", allx, t0p, Tp, 0.01)
+    assert np.abs(phi.cpu().numpy() - ref_phi).max() < 1e-9
+    # the same as one call per window, bit for bit
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for k in range(3):
+        one = F.advect_rk4("double_gyre", xd[off[k]:off[k + 1]].contiguous(), t0s[k], Ts[k], 0.01)
+        assert torch.equal(one, phi[off[k]:off[k + 1]])
+    ms = [F.Mesh(g[0], g[1], "f64") for g in geo]
+    flows_k = [phi[off[k]:off[k + 1]].contiguous() for k in range(3)]
+    outs = F.batched(ms, flows_k, list(Ts))
+    for k, (g, out) in enumerate(zip(geo, outs)):
+        st = oracle.ring1(2, g[0].shape[0], g[1])
+        ref = oracle.ftle(2, g[0], ref_phi[off[k]:off[k + 1]], st, Ts[k])
+        got = out.cpu().numpy()
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        # the flow maps differ by < 1e-9; the stencil differences amplify that by 1/spacing
+        assert np.abs(got[fin] - ref[fin]).max() < 1e-6
