@@ -2,11 +2,13 @@
 //
 // Mesh creation does, on the CPU, what Section 2.2 of de Castro et al.
 // assigns to the host processor: it determines every point's neighbours once
-// and stores them as a list of integer indices that the accelerator then
-// reads in a fixed order.  On top of that it orders the points along a
-// Morton curve and cuts the order into LDS-sized tiles (see
-// ftle_internal.h for the tile record layout), so the GPU reads every index
-// sequentially and every coordinate and flow-map value about once.
+// (from the cells, or takes them from the caller) and stores them as a list
+// of integer indices that the accelerator then reads in a fixed order.  On
+// top of that it orders the points along a Morton curve and cuts the order
+// into LDS-sized tiles with compressed records (see ftle_internal.h for the
+// layout), so the GPU reads every index sequentially and every coordinate and
+// flow-map value about once.  The flow-map advection entry point
+// (ftle_advect_rk4) is validated here too.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -14,15 +14,18 @@
 //    batched gathers, so each value comes from HBM about once, and the
 //    stencil walk reads LDS only.
 //  - The neighbour list (Section 2.2: precomputed on the host, read in a
-//    fixed order) is stored per tile as 10-bit indices of the neighbours'
-//    staged slots, three per 32-bit word: a third of the bytes of a 32-bit
-//    list, copied to LDS once.  Rows are padded to a multiple of three with
-//    the point itself (which adds exact zeros), so the walk reads three
-//    neighbours per 32-bit LDS load with no per-entry branch.
+//    fixed order) is stored per tile, compressed (ftle_internal.h): the
+//    staged points' caller indices as runs of consecutive indices, and the
+//    stencil as 10-bit indices of the neighbours' staged slots, three per
+//    32-bit word, kept only for rows that are not the previous row shifted
+//    by one slot.  The record is copied to LDS whole and decoded there.
+//    Rows are padded to a multiple of three with the point itself (which
+//    adds exact zeros), so the walk reads three neighbours per 32-bit LDS
+//    load with no per-entry select.
 //  - A lane computes one point at a time (a workgroup of B lanes walks its
 //    tile's P points in steps of B); Jacobian, tensor, eigenvalue and
-//    logarithm stay in registers.  No MFMA: per point the work is a few dozen multiply-adds
-//    over a gathered stencil, not a dense contraction.
+//    logarithm stay in registers.  No MFMA: per point the work is a few
+//    dozen multiply-adds over a gathered stencil, not a dense contraction.
 //  - Consecutive workgroup ids land on different XCDs; tiles are remapped so
 //    that each XCD walks a contiguous stretch of the Morton order and halo
 //    reuse happens in its own L2.
@@ -169,7 +172,7 @@ template <int D, typename T> struct Layout {
 // in flight while the wave issues other instructions.  The caller waits
 // (vmcnt 0) and synchronises the workgroup before reading dst.
 template <int B>
-__device__ inline void dma_segment(const uint4* __restrict__ src, uint32_t dst, int n16, int tid)
+__device__ inline void dma_record(const uint4* __restrict__ src, uint32_t dst, int n16, int tid)
 {
     const int lane = tid & 63;
     for (int c0 = tid - lane; c0 < n16; c0 += B) {   // wave-uniform chunk base
@@ -442,7 +445,7 @@ __device__ __forceinline__ void fwd_stage_tile(const TileMeta m, const uint4* __
     const int S = (int)m.P + (int)m.H;
     const RecLayout R = rec_layout(m);
     const uint32_t recl = L::fwd_rec(lds0, S);   // LDS address of the record
-    dma_segment<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
+    dma_record<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
     __syncthreads();
     stage_points<B>(S, [&](auto kc, int r0) {
@@ -693,7 +696,7 @@ __device__ __forceinline__ void fwd_tile(const TileMeta m, const uint4* __restri
                                          unsigned long long* hits, const uint32_t lds0)
 {
     fwd_stage_tile<D, T, B, WIDE>(m, rec, x, flow, lds0, (int)threadIdx.x);
-    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
+    __builtin_amdgcn_s_waitcnt(0);   // the staging loads have landed in LDS
     __syncthreads();
     fwd_compute_tile<D, T, OUT, TAPE, B, WIDE>(m, minv, inv2T, out, tape, n, eig_tau, hits, lds0, (int)threadIdx.x);
 }
@@ -779,7 +782,7 @@ __device__ __forceinline__ void bwd_stage_tile(const TileMeta m, const uint4* __
     const int S = (int)m.P + (int)m.H;
     const RecLayout R = rec_layout(m);
     const uint32_t recl = L::bwd_rec(lds0, S);   // LDS address of the record
-    dma_segment<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
+    dma_record<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
     __syncthreads();
     stage_points<B>(S, [&](auto kc, int r0) {
@@ -895,7 +898,7 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
 {
     const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
     bwd_stage_tile<D, T, B, WIDE>(m, rec, x, tape, g, 0u, (int)threadIdx.x);
-    __builtin_amdgcn_s_waitcnt(0);   // the segment DMA has landed in LDS
+    __builtin_amdgcn_s_waitcnt(0);   // the staging loads have landed in LDS
     __syncthreads();
     bwd_compute_tile<D, T, B, WIDE, SIG>(m, tape, n, grad, 0u, (int)threadIdx.x);
 }
