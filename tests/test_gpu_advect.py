@@ -37,9 +37,11 @@ def test_advect_vs_oracle(flow, dim):
     got32 = F.advect_rk4(flow, x64.float().contiguous(), t0, T, dt).cpu().numpy().astype(np.float64)
     ref32 = oracle.advect_rk4(flow, x.astype(np.float32).astype(np.float64), t0, T, dt)
     assert np.all(np.abs(got32 - ref32) <= 1e-9 + 2 ** -23 * np.abs(ref32))
-    # backward in time, and T = 0
+    # backward in time returns the start up to the RK4 truncation error, which
+    # the flow's stretching amplifies (1.3e-6 for the ABC flow at dt = 0.02 over
+    # T = 10 and back); and T = 0 is the identity
     back = F.advect_rk4(flow, torch.as_tensor(ref, device=DEV), t0 + T, -T, dt).cpu().numpy()
-    assert np.abs(back - x).max() < 1e-6
+    assert np.abs(back - x).max() < 1e-5
     assert torch.equal(F.advect_rk4(flow, x64, 1.0, 0.0, dt), x64)
 
 
