@@ -232,6 +232,16 @@ def cpu_baseline(w, threads):
                       f"(stencil built beforehand), float64, OpenMP {threads} threads"}
 
 
+def stencil_vs_oracle(w, row_ptr, col):
+    """The GPU-built one-ring stencil against the oracle's, entry for entry."""
+    import numpy as np
+
+    import oracle
+    ref = oracle.ring1(w.dim, w.n, w.cells)
+    return {"row_ptr_equal": bool(np.array_equal(row_ptr, ref.row_ptr)),
+            "col_equal": bool(np.array_equal(col, ref.col)), "nnz": int(ref.col.size)}
+
+
 def error_vs_oracle(w, got, sel=None, stencil="ring1"):
     """Error of a float32 GPU FTLE field against the FP64 oracle on the same
     (float32-rounded) inputs: max |error| over finite points, and the relative
@@ -309,7 +319,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of: fwd3d,fwdbwd,batched,axis,advect (the 2D headline always runs)")
+                    help="comma list of: fwd3d,fwdbwd,batched,axis,neighbours,advect (the 2D headline always runs)")
     ap.add_argument("--cache", default="", help="directory to keep generated workloads in (npz)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy of this many MiB (counter calibration)")
@@ -482,6 +492,29 @@ def main():
                 log(f"{name}: {t * 1e3:.2f} us/step")
                 keep[name] = (wa, oa[0].cpu().numpy())
                 del fns, ma, fa, oa
+        if want("neighbours"):
+            # the one-ring stencil built on the GPU from the cells (edge pairs,
+            # radix sort, deduplication, CSR), each call allocating its sort
+            # buffers and returning the entry count to the host
+            for name, wk in (("ring1_csr_2d_2048", lambda: w2),
+                             ("ring1_csr_3d_160", lambda: cached("abc_3d", lambda: configs.abc_3d(dev), args.cache,
+                                                                   dev))):
+                wn = wk()
+                log(f"{name}: one-ring stencil on the GPU")
+                cells_d = torch.as_tensor(wn.cells, dtype=torch.int32, device=dev).contiguous()
+                rp, col = F.ring1_csr(wn.dim, wn.n, cells_d)
+                t = time_steps([lambda: F.ring1_csr(wn.dim, wn.n, cells_d)], 5, 1, torch)
+                Bn = 4 * cells_d.numel() + 8 * (wn.n + 1) + 4 * col.numel()
+                variants[name] = {
+                    "workload": f"one-ring CSR of the {'2048^2 triangle' if wn.dim == 2 else '160^3 tetrahedron'} "
+                                "mesh from its cells on the GPU",
+                    "points": wn.n, "cells": int(cells_d.shape[0]), "nnz": int(col.numel()),
+                    "ms_per_step": round(t, 4), "points_per_s": round(wn.n / (t * 1e-3), 1),
+                    "roofline": dict(roofline(Bn, t), alg_bytes_per_launch=Bn,
+                                     alg_model="cells read once, CSR written once")}
+                log(f"{name}: {t:.2f} ms per stencil")
+                keep[name] = (wn, rp.cpu().numpy(), col.cpu().numpy())
+                del cells_d, rp, col, wn
         if want("advect"):
             # the step before the path: the 2048^2 double-gyre flow map by RK4 on
             # the GPU (float64 arithmetic, float32 output), as the headline's
@@ -527,6 +560,9 @@ def main():
             err["fwd_bwd_96"] = {"ftle": error_vs_oracle(wd, outd0), "grad": grad_error_vs_oracle(wd, g0, grad0)}
         if "batched" in keep:
             err["batched_48"] = {w.name: error_vs_oracle(w, got) for w, got in keep["batched"]}
+        for name in ("ring1_csr_2d_2048", "ring1_csr_3d_160"):
+            if name in keep:
+                err[name] = stencil_vs_oracle(*keep[name])
         if "advect" in keep:
             wa, x0, t0, phi = keep["advect"]
             sel = np.sort(rng.choice(wa.n, 20000, replace=False))

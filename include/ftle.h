@@ -122,6 +122,34 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
                                       const int64_t* row_ptr, const int32_t* col, unsigned flags,
                                       ftle_mesh_t* out);
 
+/*
+ * The one-ring stencil of a cell mesh, built on the device: row i lists, in
+ * ascending order and once each, every other point that shares a cell with
+ * point i (the neighbour determination that Section 2.2 keeps off the
+ * accelerator; the same stencil ftle_create_mesh builds on the host).  Edge
+ * extraction, a radix sort and a deduplication of the (i, j) pairs, then the
+ * CSR arrays.  The result feeds ftle_create_mesh_from_csr.
+ *   dim          2 (triangles) or 3 (tetrahedra)
+ *   n_points     1 <= n_points <= 2^31-1
+ *   n_cells      >= 0
+ *   cells        device, n_cells x (dim+1) int32 point indices; a point
+ *                repeated inside a cell adds no pair with itself
+ *   row_ptr      device, n_points+1 int64, caller-owned, overwritten
+ *   col          device, col_capacity int32, caller-owned; receives *nnz entries
+ *   col_capacity n_cells * dim * (dim+1) always suffices
+ *   nnz          host, receives the entry count (also when it exceeds
+ *                col_capacity)
+ * The call allocates its sort buffers on the device for its duration (two
+ * arrays of 8 bytes per cell pair) and returns after the stream has finished
+ * the work.
+ * Errors: INVALID_ARG (dim, n_points < 1, n_cells < 0, null pointer),
+ * BAD_MESH (a cell index outside [0, n_points), found on the device; row_ptr
+ * and col are then not written), UNSUPPORTED (n_points > 2^31-1, *nnz >
+ * col_capacity: row_ptr and col not written), OOM, DEVICE.
+ */
+ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
+                           int32_t* col, int64_t col_capacity, int64_t* nnz, ftle_stream_t stream);
+
 /* Analytic flows of ftle_advect_rk4. */
 typedef enum {
     /* double gyre (Shadden, Lekien and Marsden 2005), 2D; params A, eps, omega

@@ -392,6 +392,25 @@ def advect_rk4(flow: str, x0: torch.Tensor, t0, T, dt: float, params=None, out: 
     return out
 
 
+def ring1_csr(dim: int, n_points: int, cells: torch.Tensor, stream=None):
+    """The one-ring stencil of a cell mesh built on the GPU (ftle_ring1_csr):
+    cells is a contiguous int32 device tensor (n_cells, dim + 1); returns
+    (row_ptr int64 (n_points + 1,), col int32 (nnz,)) on the same device,
+    every other point sharing a cell with point i, ascending, once each.
+    Mesh.from_csr takes them (on the host) to build the mesh."""
+    if not (cells.is_cuda and cells.dtype == torch.int32 and cells.is_contiguous() and cells.dim() == 2
+            and cells.shape[1] == dim + 1):
+        raise ValueError(f"cells must be a contiguous int32 device tensor of shape (n_cells, {dim + 1})")
+    n_cells = cells.shape[0]
+    row_ptr = torch.empty(int(n_points) + 1, dtype=torch.int64, device=cells.device)
+    col = torch.empty(max(1, n_cells * dim * (dim + 1)), dtype=torch.int32, device=cells.device)
+    nnz = ctypes.c_int64(0)
+    check(_lib.load().ftle_ring1_csr(dim, int(n_points), n_cells, ctypes.c_void_p(cells.data_ptr()),
+                                     ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                                     col.numel(), ctypes.byref(nnz), _stream_handle(stream)))
+    return row_ptr, col[:nnz.value]
+
+
 def force_wide_offsets(on: bool) -> None:
     """Testing aid: make every later launch take the 64-bit offset path (see ftle_force_wide_offsets)."""
     check(_lib.load().ftle_force_wide_offsets(int(bool(on))))
@@ -403,4 +422,4 @@ def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
 
 
 __all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError",
-           "force_wide_offsets"]
+           "force_wide_offsets", "advect_rk4", "ring1_csr"]

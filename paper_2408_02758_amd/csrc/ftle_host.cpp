@@ -1459,6 +1459,68 @@ ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const voi
     });
 }
 
+ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
+                           int32_t* col, int64_t col_capacity, int64_t* nnz, ftle_stream_t stream)
+{
+    // device buffers of one call, released on every exit
+    struct Scratch {
+        uint64_t* keys = nullptr;
+        uint64_t* tmp = nullptr;
+        void* work = nullptr;
+        int64_t* count = nullptr;
+        int* err = nullptr;
+        ~Scratch()
+        {
+            for (void* p : {(void*)keys, (void*)tmp, work, (void*)count, (void*)err})
+                if (p) (void)hipFree(p);
+        }
+    };
+    return guarded([&] {
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points < 1");
+        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+        if (n_cells < 0) fail(FTLE_ERR_INVALID_ARG, "n_cells < 0");
+        if (!row_ptr || !nnz || (n_cells > 0 && (!cells || !col)) || col_capacity < 0)
+            fail(FTLE_ERR_INVALID_ARG, "null pointer or negative capacity");
+        const int64_t per = (int64_t)(dim + 1) * dim;   // directed pairs per cell
+        if (n_cells > INT64_MAX / per) fail(FTLE_ERR_UNSUPPORTED, "too many cells");
+        const int64_t edges = n_cells * per;
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        Scratch b;
+        check_hip(hipMalloc((void**)&b.count, sizeof(int64_t)), "hipMalloc");
+        check_hip(hipMalloc((void**)&b.err, sizeof(int)), "hipMalloc");
+        const int zero = 0;
+        check_hip(hipMemcpyAsync(b.err, &zero, sizeof(int), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        int64_t n_unique = 0;
+        if (edges > 0) {
+            const size_t work = ring1_device_scratch_bytes(edges);
+            check_hip(hipMalloc((void**)&b.keys, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
+            check_hip(hipMalloc((void**)&b.tmp, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
+            check_hip(hipMalloc(&b.work, work ? work : 16), "hipMalloc (sort scratch)");
+            check_hip(launch_emit_edges(dim, cells, n_cells, n_points, b.keys, b.err, s), "edge extraction");
+            check_hip(sort_unique_keys(b.keys, b.tmp, edges, n_points, b.work, work, b.count, s), "sort / unique");
+            check_hip(hipMemcpyAsync(&n_unique, b.count, sizeof(int64_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        }
+        int err = 0;
+        check_hip(hipMemcpyAsync(&err, b.err, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+        if (err) fail(FTLE_ERR_BAD_MESH, "cell index outside [0, n_points)");
+        // the unique keys end with at most one sentinel (a repeated point in a cell)
+        int64_t count = n_unique;
+        if (count > 0) {
+            uint64_t last = 0;
+            check_hip(hipMemcpy(&last, b.keys + (count - 1), sizeof(uint64_t), hipMemcpyDeviceToHost), "hipMemcpy");
+            if ((last >> ring1_key_bits(n_points)) >= (uint64_t)n_points) --count;
+        }
+        *nnz = count;
+        if (count > col_capacity) fail(FTLE_ERR_UNSUPPORTED, "col_capacity below the stencil's entry count (in *nnz)");
+        check_hip(launch_csr_from_keys(b.keys, count, n_points, row_ptr, col, s), "CSR from keys");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
 ftle_status ftle_batched_config(int n, const ftle_mesh_t* meshes, int* block, int* tiles_per_pop, int* grid)
 {
     return guarded([&] {

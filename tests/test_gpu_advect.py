@@ -75,3 +75,18 @@ def test_windows_pipeline_vs_oracle():
         assert np.array_equal(np.isnan(got), np.isnan(ref))
         # the flow maps differ by < 1e-9; the stencil differences amplify that by 1/spacing
         assert np.abs(got[fin] - ref[fin]).max() < 1e-6
+
+
+def test_advect_large_start_time_and_ragged_steps():
+    """Double gyre from a start time far from 0 (a large phase omega t) over a
+    duration that is not a whole number of steps, forward and backward: the
+    kernel's time factor (advanced by rotations, evaluated directly every few
+    steps) against the oracle's direct evaluation at every stage."""
+    x, _ = meshes.jittered_tri_grid(20, 15, seed=9)
+    x64 = torch.as_tensor(x, dtype=torch.float64, device=DEV)
+    for t0, T in ((12345.6, 7.305), (-987.25, -3.3333)):
+        ref = oracle.advect_rk4("double_gyre", x, t0, T, 0.01)
+        got = F.advect_rk4("double_gyre", x64, t0, T, 0.01).cpu().numpy()
+        err = np.abs(got - ref).max()
+        print(f"[advect double_gyre t0={t0} T={T}] max |d| = {err:.3e}", flush=True)
+        assert err < 1e-9
