@@ -251,6 +251,25 @@ def test_from_csr_validation(L):
     assert make([0, 1, 2, 3, 4], dim=5) == INVALID
 
 
+def test_ring1_csr_validation(L):
+    """ftle_ring1_csr rejects bad arguments before touching a device (the
+    pointers below are never dereferenced)."""
+    INVALID, UNSUPPORTED = 1, 4
+    fake = ctypes.c_void_p(16)
+    nnz = ctypes.c_int64(0)
+
+    def call(dim=2, n=10, n_cells=3, cells=fake, row_ptr=fake, col=fake, cap=18, nnz_p=ctypes.byref(nnz)):
+        return L.ftle_ring1_csr(dim, n, n_cells, cells, row_ptr, col, cap, nnz_p, None)
+
+    assert call(dim=1) == INVALID and call(dim=4) == INVALID
+    assert call(n=0) == INVALID and call(n=-5) == INVALID
+    assert call(n=1 << 31) == UNSUPPORTED
+    assert call(n_cells=-1) == INVALID
+    assert call(cells=None) == INVALID and call(row_ptr=None) == INVALID and call(col=None) == INVALID
+    assert call(nnz_p=None) == INVALID and call(cap=-1) == INVALID
+    assert L.ftle_last_error()
+
+
 def test_ring1_symmetric_shares_adjoint_tiles():
     x, c = meshes.jittered_tri_grid(20, 20, seed=2)
     m = F.Mesh(x, c, "f32", host_only=True)
