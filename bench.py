@@ -326,7 +326,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the FTLE hot path is "
-              "built and measured on a single MI355X; see DESIGN.md for how it would shard.", flush=True)
+              "built and measured on a single MI355X (meshes would be split into Morton ranges, one per GPU, "
+              "with a one-ring halo exchange of the flow map).", flush=True)
         sys.exit(2)
 
     import numpy as np

@@ -1,6 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle, on the GPU.
 
-Tolerances (see the design doc for the derivation):
+Tolerances (from the float32 arithmetic: short sums of products over at most
+~16 neighbours, an adjugate solve with cond(M) <= 10 on these meshes, and
+the hardware log2's ~1 ulp; the observed errors sit two orders below):
   float64 meshes: |f_gpu - f_ref| <= 1e-12 + 1e-10 |f_ref|    (3D: 1e-9 where the
                   top eigenvalue pair is closer than 1e-3 relative, where the
                   trigonometric formula loses half the digits)
