@@ -59,6 +59,11 @@ def alg_bytes_fwd(n, nnz, dim, s=4):
     return 4 * (n + 1) + 4 * nnz + 2 * dim * s * n + s * n
 
 
+def alg_bytes_fwd_f16(n, nnz, dim):
+    """As alg_bytes_fwd with the flow map held as binary16 displacements."""
+    return 4 * (n + 1) + 4 * nnz + dim * 4 * n + dim * 2 * n + 4 * n
+
+
 def alg_bytes_bwd(n, nnz, dim, s=4):
     return 4 * (n + 1) + 4 * nnz + 3 * dim * s * n + s * n
 
@@ -319,7 +324,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of: fwd3d,fwdbwd,batched,axis,neighbours,advect (the 2D headline always runs)")
+                    help="comma list of: f16,fwd3d,fwdbwd,batched,axis,neighbours,advect (the 2D headline always runs)")
     ap.add_argument("--cache", default="", help="directory to keep generated workloads in (npz)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain elementwise copy of this many MiB (counter calibration)")
@@ -392,6 +397,23 @@ def main():
     # ---- variants ----------------------------------------------------------
     if not args.no_variants:
         steps_v = max(10, args.steps // 2)
+        if want("f16"):
+            # the headline with the flow map stored as binary16 displacements
+            # (4 bytes per point instead of 8), float32 arithmetic
+            log("f16 flow storage: 2048^2 forward")
+            d16 = [meshes2[k].encode_flow_f16(flows2[k]) for k in range(R)]
+            fns = [lambda k=k: meshes2[k].forward_f16(d16[k], w2.T, out=outs2[k]) for k in range(R)]
+            t = time_steps(fns, args.steps, args.warmup, torch)
+            Bh = alg_bytes_fwd_f16(w2.n, nnz2, 2)
+            variants["fwd_2d_2048_f16flow"] = {
+                "workload": "2D forward on the 2048^2 workload with the flow map stored as binary16 displacements "
+                            "phi - x (float32 arithmetic on the decoded map)",
+                "points": w2.n, "nnz": nnz2, "ms_per_step": round(t, 5), "points_per_s": round(w2.n / (t * 1e-3), 1),
+                "roofline": dict(roofline(Bh, t), alg_bytes_per_launch=Bh,
+                                 traffic=traffic_for(traffic, f"fwd16_kernel<{meshes2[0].blocks()[0]}>"))}
+            log(f"f16 flow storage: {t * 1e3:.2f} us/step")
+            keep["f16"] = outs2[0].cpu().numpy()
+            del d16, fns
         if want("fwd3d"):
             log("generating 160^3 ABC workload")
             w3 = cached("abc_3d", lambda: configs.abc_3d(dev), args.cache, dev)
@@ -561,6 +583,10 @@ def main():
             err["fwd_bwd_96"] = {"ftle": error_vs_oracle(wd, outd0), "grad": grad_error_vs_oracle(wd, g0, grad0)}
         if "batched" in keep:
             err["batched_48"] = {w.name: error_vs_oracle(w, got) for w, got in keep["batched"]}
+        if "f16" in keep:
+            # against the oracle on the original float32 flow map: the accuracy
+            # the binary16 storage gives up (its parity on the decoded map is tested)
+            err["f16flow_2d_2048_vs_float32_flow"] = error_vs_oracle(w2, keep["f16"])
         for name in ("ring1_csr_2d_2048", "ring1_csr_3d_160"):
             if name in keep:
                 err[name] = stencil_vs_oracle(*keep[name])

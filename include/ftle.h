@@ -265,6 +265,29 @@ ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, d
                          void* out, ftle_stream_t stream);
 
 /*
+ * Half-precision flow-map storage, 2D float32 meshes (the precision-for-
+ * bandwidth trade Section 1.1 allows: 4 bytes of flow map per point, not 8).
+ * The flow map is held as the displacement d = phi - x of each point,
+ * rounded to binary16; the forward decodes phi' = x + d in float32 and
+ * computes the float32 FTLE of phi' (as ftle_forward would of phi').
+ * ftle_encode_flow_f16:
+ *   flow     device, n_points x 2 float32, phi in user order
+ *   delta    device, n_points x 2 binary16, caller-owned, overwritten with
+ *            binary16(phi - x) (the float32 difference rounded to nearest
+ *            even; beyond +-65504 it is +-inf, and the FTLE there not finite)
+ * ftle_forward_f16:
+ *   delta    device, n_points x 2 binary16, as ftle_encode_flow_f16 writes it
+ *   T, out   as ftle_forward (out float32)
+ * The FTLE of phi' differs from that of phi by the displacement's rounding
+ * (2^-11 relative to |d|) over the neighbour spacing: a trade of accuracy
+ * for bytes, not a float32 result.
+ * Errors: INVALID_ARG (NULL pointer, T), UNSUPPORTED (3D or float64 mesh,
+ * n_points >= 2^29, host-only mesh), DEVICE.
+ */
+ftle_status ftle_encode_flow_f16(ftle_mesh_t mesh, const void* flow, void* delta, ftle_stream_t stream);
+ftle_status ftle_forward_f16(ftle_mesh_t mesh, const void* delta, double T, void* out, ftle_stream_t stream);
+
+/*
  * Bytes of the adjoint tape written by ftle_forward_tape (2*dim+1 values of
  * dtype per point).
  */

@@ -216,3 +216,20 @@ def advect_rk4(flow: str, x0, t0, T, dt: float, params=None, lib=None):
     out = np.empty_like(x)
     lib.oracle_advect_rk4(kind, _p(prm), n, _p(x), _p(t0a), _p(Ta), float(dt), _p(out))
     return out
+
+
+def encode_flow_f16(coords, flow):
+    """Half-precision flow-map storage (the paper's precision-for-speed trade,
+    Section 1.1): the displacement phi - x taken in float32, then rounded to
+    binary16, each step to nearest even (IEEE 754; numpy's float32 arithmetic
+    and float32 -> float16 conversion)."""
+    x32 = np.asarray(coords, dtype=np.float32)
+    p32 = np.asarray(flow, dtype=np.float32)
+    with np.errstate(over="ignore"):
+        return (p32 - x32).astype(np.float16)
+
+
+def decode_flow_f16(coords, delta):
+    """The flow map the stored displacements stand for: x + d in float32 (one
+    rounding), d widened exactly from binary16."""
+    return np.asarray(coords, dtype=np.float32) + np.asarray(delta, dtype=np.float16).astype(np.float32)

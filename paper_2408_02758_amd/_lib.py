@@ -39,6 +39,8 @@ SIGNATURES = {
     "ftle_create_mesh": (_int, [_int, _i64, _vp, _int, _i64, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_create_mesh_from_csr": (_int, [_int, _i64, _vp, _int, _vp, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_ring1_csr": (_int, [_int, _i64, _i64, _vp, _vp, _vp, _i64, _P(_i64), _vp]),
+    "ftle_encode_flow_f16": (_int, [_vp, _vp, _vp, _vp]),
+    "ftle_forward_f16": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),
     "ftle_advect_rk4": (_int, [_int, _vp, _i64, _vp, _int, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, _vp, _vp]),
     "ftle_destroy_mesh": (None, [_vp]),

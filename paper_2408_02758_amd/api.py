@@ -239,6 +239,31 @@ class Mesh:
                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
+    def encode_flow_f16(self, flow: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """binary16(phi - x), the half-precision storage of a float32 flow map
+        (2D float32 meshes; ftle_encode_flow_f16)."""
+        self._check_flow(flow)
+        if out is None:
+            out = torch.empty(self.n, 2, dtype=torch.float16, device=flow.device)
+        if not (out.is_cuda and out.dtype == torch.float16 and out.is_contiguous() and tuple(out.shape) == (self.n, 2)):
+            raise ValueError(f"out must be a contiguous float16 device tensor of shape ({self.n}, 2)")
+        check(_lib.load().ftle_encode_flow_f16(self._h, ctypes.c_void_p(flow.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def forward_f16(self, delta: torch.Tensor, T: float, out: torch.Tensor | None = None, stream=None):
+        """Float32 FTLE of the flow map x + delta, delta the binary16
+        displacements encode_flow_f16 writes (ftle_forward_f16)."""
+        if not (isinstance(delta, torch.Tensor) and delta.is_cuda and delta.dtype == torch.float16
+                and delta.is_contiguous() and tuple(delta.shape) == (self.n, 2)):
+            raise ValueError(f"delta must be a contiguous float16 device tensor of shape ({self.n}, 2)")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device=delta.device)
+        self._check_flow(out, "out", (self.n,))
+        check(_lib.load().ftle_forward_f16(self._h, ctypes.c_void_p(delta.data_ptr()), float(T),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
     def forward_tape(self, flow: torch.Tensor, T: float, out=None, tape=None, stream=None):
         self._check_flow(flow)
         if out is None:

@@ -1093,6 +1093,42 @@ ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, d
     });
 }
 
+namespace {
+void check_f16_mesh(ftle_mesh_t mesh)
+{
+    check_mesh(mesh);
+    if (mesh->dim != 2 || mesh->f64())
+        fail(FTLE_ERR_UNSUPPORTED, "half-precision flow maps are for 2D float32 meshes");
+    if (mesh->n >= ((int64_t)1 << 29)) fail(FTLE_ERR_UNSUPPORTED, "mesh too large for half-precision flow maps");
+}
+}  // namespace
+
+ftle_status ftle_encode_flow_f16(ftle_mesh_t mesh, const void* flow, void* delta, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_f16_mesh(mesh);
+        if (!flow || !delta) fail(FTLE_ERR_INVALID_ARG, "flow or delta is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        check_hip(launch_encode_f16(mesh->d_x, flow, delta, mesh->n, static_cast<hipStream_t>(stream)),
+                  "encode launch");
+    });
+}
+
+ftle_status ftle_forward_f16(ftle_mesh_t mesh, const void* delta, double T, void* out, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_f16_mesh(mesh);
+        check_T(T);
+        if (!delta || !out) fail(FTLE_ERR_INVALID_ARG, "delta or out is NULL");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        check_hip(launch_forward_f16(mesh->fwd.dev(), mesh->d_x, delta, 0.5 / std::fabs(T), out, mesh->n, eig_tau(),
+                                     mesh->d_hits, mesh->fwd_block, static_cast<hipStream_t>(stream)),
+                  "forward (half-precision flow) launch");
+    });
+}
+
 ftle_status ftle_tape_bytes(ftle_mesh_t mesh, int64_t* bytes)
 {
     return guarded([&] {

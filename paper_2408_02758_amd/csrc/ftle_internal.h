@@ -160,6 +160,12 @@ hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* 
                           double inv2T, void* out, void* tape, bool tape_sigma, int64_t n, double eig_tau,
                           unsigned long long* hits, int block, hipStream_t stream);
 
+// Half-precision flow-map storage (2D, float32 meshes): the forward from
+// binary16 displacements d = phi - x, and the encoding of a float32 flow map.
+hipError_t launch_forward_f16(const DevTiles& tiles, const void* x, const void* delta, double inv2T, void* out,
+                              int64_t n, double eig_tau, unsigned long long* hits, int block, hipStream_t stream);
+hipError_t launch_encode_f16(const void* x, const void* flow, void* delta, int64_t n, hipStream_t stream);
+
 hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
                                   const void* tape, bool tape_sigma, int64_t n, const void* g, void* grad,
                                   int block, hipStream_t stream);

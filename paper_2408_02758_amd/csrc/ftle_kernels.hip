@@ -30,6 +30,7 @@
 //    that each XCD walks a contiguous stretch of the Morton order and halo
 //    reuse happens in its own L2.
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
 #include <cmath>
 #include <cstdint>
@@ -1098,6 +1099,97 @@ hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* 
                    : fwd_launch<2, float>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream);
     return f64 ? fwd_launch<3, double>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream)
                : fwd_launch<3, float>(tiles, x, flow, inv2T, out, tape, ts, n, eig_tau, hits, block, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Half-precision flow-map storage (2D meshes, float32 arithmetic).  The flow
+// map is held as the displacement d = phi - x, rounded to binary16: 4 bytes
+// per point instead of 8.  The staging decodes phi' = x + d in float32 (one
+// rounding); from there the tile runs the float32 forward unchanged, so the
+// result is the float32 FTLE of the decoded map phi'.
+// ---------------------------------------------------------------------------
+template <int B, int K>
+__device__ inline void fwd16_stage(uint32_t rec, const RecLayout& R, const float* __restrict__ x,
+                                   const __half2* __restrict__ d, int S, int r0, int tid)
+{
+    using L = Layout<2, float>;
+    const int base = r0 + tid;
+    uint32_t u[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = slot_point(rec, R, min(base + k * B, S - 1));
+    float2 xv[K];
+    __half2 dv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        xv[k] = rec_at<false, float2>(x, u[k], sizeof(float2));
+        dv[k] = rec_at<false, __half2>(d, u[k], sizeof(__half2));
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float2 dd = __half22float2(dv[k]);
+        const uint32_t o = (uint32_t)min(base + k * B, S - 1) * L::unit;
+        lds_st(o, float4{xv[k].x, xv[k].y, xv[k].x + dd.x, xv[k].y + dd.y});
+    }
+}
+
+template <int B>
+__global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(8)))
+fwd16_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int n_tiles, const float* __restrict__ x,
+             const __half2* __restrict__ d, float inv2T, float* __restrict__ out, int64_t n, float eig_tau,
+             unsigned long long* hits)
+{
+    using L = Layout<2, float>;
+    const TileMeta m = meta[xcd_tile(blockIdx.x, n_tiles)];
+    const int S = (int)m.P + (int)m.H;
+    const RecLayout R = rec_layout(m);
+    const uint32_t recl = L::fwd_rec(0u, S);
+    const int tid = (int)threadIdx.x;
+    dma_record<B>(rec + m.rec_off, recl, (int)(R.bytes / 16), tid);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the record has landed in LDS
+    __syncthreads();
+    stage_points<B>(S, [&](auto kc, int r0) { fwd16_stage<B, decltype(kc)::value>(recl, R, x, d, S, r0, tid); });
+    __builtin_amdgcn_s_waitcnt(0);   // the staging loads have landed in LDS
+    __syncthreads();
+    fwd_compute_tile<2, float, true, 0, B, false>(m, nullptr, inv2T, out, nullptr, n, eig_tau, hits, 0u, tid);
+}
+
+// d = binary16(phi - x), the float32 difference rounded to nearest even.
+__global__ void __launch_bounds__(256) encode16_kernel(const float2* __restrict__ x, const float2* __restrict__ phi,
+                                                       __half2* __restrict__ d, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 a = x[i], b = phi[i];
+    d[i] = __floats2half2_rn(b.x - a.x, b.y - a.y);
+}
+
+hipError_t launch_forward_f16(const DevTiles& tiles, const void* x, const void* delta, double inv2T, void* out,
+                              int64_t n, double eig_tau, unsigned long long* hits, int block, hipStream_t stream)
+{
+    if (tiles.n_tiles == 0) return hipSuccess;
+    const size_t lds = fwd_lds<2, float>(tiles);
+    const float* xp = static_cast<const float*>(x);
+    const __half2* dp = static_cast<const __half2*>(delta);
+    float* op = static_cast<float*>(out);
+#define FTLE_FWD16_LAUNCH(BB)                                                                                    \
+    hipLaunchKernelGGL((fwd16_kernel<BB>), dim3(tiles.n_tiles), dim3(BB), lds, stream, tiles.meta, tiles.rec,    \
+                       tiles.n_tiles, xp, dp, (float)inv2T, op, n, (float)eig_tau, hits)
+    switch (block) {
+    case 128: FTLE_FWD16_LAUNCH(128); break;
+    case 512: FTLE_FWD16_LAUNCH(512); break;
+    default: FTLE_FWD16_LAUNCH(256); break;
+    }
+#undef FTLE_FWD16_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_f16(const void* x, const void* flow, void* delta, int64_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(encode16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       static_cast<const float2*>(x), static_cast<const float2*>(flow), static_cast<__half2*>(delta),
+                       n);
+    return hipGetLastError();
 }
 
 hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
