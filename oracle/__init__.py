@@ -7,8 +7,11 @@ and of its adjoint.  It exists to check the GPU library; only the tests, the
 smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
 code with the GPU library and does not import it.
 
-Parity status of each function (what pins it) is listed in the test module
-``tests/test_oracle_pins.py``.
+It also holds the two steps around the path that the library offers on the
+GPU: RK4 flow maps of analytic flows, and the binary16 storage of a flow map
+(numpy).  What pins each function is in the test modules
+``tests/test_oracle_pins.py``, ``tests/test_oracle_advect.py`` and
+``tests/test_oracle_f16.py``.
 """
 from __future__ import annotations
 
