@@ -1500,14 +1500,13 @@ ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int
 {
     // device buffers of one call, released on every exit
     struct Scratch {
-        uint64_t* keys = nullptr;
-        uint64_t* tmp = nullptr;
+        uint64_t* keys = nullptr;   // the pair keys; after the sort, the flags and positions
+        uint64_t* sorted = nullptr;
         void* work = nullptr;
-        int64_t* count = nullptr;
         int* err = nullptr;
         ~Scratch()
         {
-            for (void* p : {(void*)keys, (void*)tmp, work, (void*)count, (void*)err})
+            for (void* p : {(void*)keys, (void*)sorted, work, (void*)err})
                 if (p) (void)hipFree(p);
         }
     };
@@ -1519,40 +1518,42 @@ ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int
         if (!row_ptr || !nnz || (n_cells > 0 && (!cells || !col)) || col_capacity < 0)
             fail(FTLE_ERR_INVALID_ARG, "null pointer or negative capacity");
         const int64_t per = (int64_t)(dim + 1) * dim;   // directed pairs per cell
-        if (n_cells > INT64_MAX / per) fail(FTLE_ERR_UNSUPPORTED, "too many cells");
+        if (n_cells > (int64_t)UINT32_MAX / per) fail(FTLE_ERR_UNSUPPORTED, "more than 2^32-1 cell pairs");
         const int64_t edges = n_cells * per;
         int dev = 0;
         check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
         const hipStream_t s = static_cast<hipStream_t>(stream);
         Scratch b;
-        check_hip(hipMalloc((void**)&b.count, sizeof(int64_t)), "hipMalloc");
         check_hip(hipMalloc((void**)&b.err, sizeof(int)), "hipMalloc");
         const int zero = 0;
         check_hip(hipMemcpyAsync(b.err, &zero, sizeof(int), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-        int64_t n_unique = 0;
+        // flags and positions (uint32 each) reuse the key array once the keys are sorted
+        uint32_t* flag = nullptr;
+        uint32_t* pos = nullptr;
+        uint32_t tail[2] = {0, 0};   // flag and position of the last sorted key
         if (edges > 0) {
             const size_t work = ring1_device_scratch_bytes(edges);
             check_hip(hipMalloc((void**)&b.keys, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
-            check_hip(hipMalloc((void**)&b.tmp, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
+            check_hip(hipMalloc((void**)&b.sorted, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
             check_hip(hipMalloc(&b.work, work ? work : 16), "hipMalloc (sort scratch)");
+            flag = reinterpret_cast<uint32_t*>(b.keys);
+            pos = flag + edges;
             check_hip(launch_emit_edges(dim, cells, n_cells, n_points, b.keys, b.err, s), "edge extraction");
-            check_hip(sort_unique_keys(b.keys, b.tmp, edges, n_points, b.work, work, b.count, s), "sort / unique");
-            check_hip(hipMemcpyAsync(&n_unique, b.count, sizeof(int64_t), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+            check_hip(sort_and_mark_keys(b.keys, b.sorted, edges, n_points, b.work, work, flag, pos, s),
+                      "sort / deduplication");
+            check_hip(hipMemcpyAsync(&tail[0], flag + (edges - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync");
+            check_hip(hipMemcpyAsync(&tail[1], pos + (edges - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                      "hipMemcpyAsync");
         }
         int err = 0;
         check_hip(hipMemcpyAsync(&err, b.err, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
         check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
         if (err) fail(FTLE_ERR_BAD_MESH, "cell index outside [0, n_points)");
-        // the unique keys end with at most one sentinel (a repeated point in a cell)
-        int64_t count = n_unique;
-        if (count > 0) {
-            uint64_t last = 0;
-            check_hip(hipMemcpy(&last, b.keys + (count - 1), sizeof(uint64_t), hipMemcpyDeviceToHost), "hipMemcpy");
-            if ((last >> ring1_key_bits(n_points)) >= (uint64_t)n_points) --count;
-        }
+        const int64_t count = (int64_t)tail[0] + (int64_t)tail[1];
         *nnz = count;
         if (count > col_capacity) fail(FTLE_ERR_UNSUPPORTED, "col_capacity below the stencil's entry count (in *nnz)");
-        check_hip(launch_csr_from_keys(b.keys, count, n_points, row_ptr, col, s), "CSR from keys");
+        check_hip(launch_csr_from_keys(b.sorted, flag, pos, edges, count, n_points, row_ptr, col, s), "CSR from keys");
         check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     });
 }

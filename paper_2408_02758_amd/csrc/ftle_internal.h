@@ -179,15 +179,17 @@ hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, co
                          const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream);
 
 // One-ring stencil on the device (ftle_neighbours.hip): edge keys from the
-// cells, their sort and deduplication, and the CSR arrays from the unique keys.
+// cells, their sort and deduplication, and the CSR arrays from the kept keys.
 size_t ring1_device_scratch_bytes(int64_t n_edges);
 int ring1_key_bits(int64_t n);   // b: a key is i * 2^b + j
 hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int64_t n, uint64_t* keys, int* err,
                              hipStream_t stream);
-hipError_t sort_unique_keys(uint64_t* keys, uint64_t* tmp_keys, int64_t n_edges, int64_t n, void* scratch,
-                            size_t scratch_bytes, int64_t* d_n_unique, hipStream_t stream);
-hipError_t launch_csr_from_keys(const uint64_t* keys, int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col,
-                                hipStream_t stream);
+// sorted <- keys sorted; flag[p] = key p kept (first of its run, not the
+// sentinel); pos = exclusive sum of flag (flag and pos may share keys' memory).
+hipError_t sort_and_mark_keys(uint64_t* keys, uint64_t* sorted, int64_t n_edges, int64_t n, void* scratch,
+                              size_t scratch_bytes, uint32_t* flag, uint32_t* pos, hipStream_t stream);
+hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t n_edges,
+                                int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t stream);
 
 hipError_t launch_batched(int dim, bool f64, bool wide, const BatchItem* items, int n_items, int tiles_per_pop,
                           unsigned* queue, const BatchCall& call, size_t lds, double eig_tau, int block, int grid,

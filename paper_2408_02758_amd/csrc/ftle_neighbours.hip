@@ -9,9 +9,11 @@
 //      becomes a sentinel key n * 2^b that sorts after every real key, and an
 //      index outside [0, n) raises the error flag and becomes the sentinel too;
 //   2. a radix sort of the keys over their 2 b bits (hipCUB);
-//   3. deduplication (hipCUB unique);
-//   4. the CSR arrays from the sorted unique keys: entry p's column is its
-//      low b bits, and row r starts at the first entry whose row is >= r.
+//   3. deduplication: a flag per sorted key that is the first of its run of
+//      equal keys and not the sentinel, and the exclusive sum of the flags
+//      (hipCUB), which is each kept key's CSR position;
+//   4. the CSR arrays: a kept key's column is its low b bits, and row r
+//      starts at the first kept key whose row is >= r.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -36,7 +38,9 @@ __global__ void __launch_bounds__(256) emit_edges(const int32_t* __restrict__ ce
     for (int a = 0; a < K; ++a) bad |= (v[a] < 0) || ((int64_t)v[a] >= n);
     if (bad) *err = 1;   // every writer stores the same value
     const uint64_t sentinel = (uint64_t)n << b;
-    uint64_t* out = keys + c * (K * (K - 1));
+    // pair o of every cell in one contiguous stretch: each store instruction
+    // writes consecutive keys for consecutive cells (the sort ignores order)
+    uint64_t* out = keys + c;
     int o = 0;
 #pragma unroll
     for (int a = 0; a < K; ++a)
@@ -44,25 +48,39 @@ __global__ void __launch_bounds__(256) emit_edges(const int32_t* __restrict__ ce
         for (int c2 = 0; c2 < K; ++c2) {
             if (a == c2) continue;
             const bool real = !bad && v[a] != v[c2];
-            out[o++] = real ? ((uint64_t)(uint32_t)v[a] << b) | (uint32_t)v[c2] : sentinel;
+            out[(int64_t)(o++) * n_cells] = real ? ((uint64_t)(uint32_t)v[a] << b) | (uint32_t)v[c2] : sentinel;
         }
 }
 
-// Entries p < nnz of the sorted unique keys (all rows < n): the column, and
-// the starts of the rows from the previous entry's row + 1 up to this one's;
-// the last entry also closes the rows after its own up to n.
-__global__ void __launch_bounds__(256) csr_from_keys(const uint64_t* __restrict__ keys, int64_t nnz, int64_t n,
-                                                     int b, int64_t* __restrict__ row_ptr, int32_t* __restrict__ col)
+// flag[p] = 1 where sorted key p is the first of its run and below the sentinel.
+__global__ void __launch_bounds__(256) mark_first(const uint64_t* __restrict__ keys, int64_t m, uint64_t sentinel,
+                                                  uint32_t* __restrict__ flag)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nnz) return;
+    if (p >= m) return;
     const uint64_t k = keys[p];
+    flag[p] = (k < sentinel && (p == 0 || keys[p - 1] != k)) ? 1u : 0u;
+}
+
+// Kept key p (flag set) goes to CSR position pos[p]: its column, and the
+// starts of the rows from the previous key's row + 1 up to its own (the
+// previous key, kept or not, has the previous kept key's row); the last kept
+// key also closes the rows after its own up to n.
+__global__ void __launch_bounds__(256) csr_from_keys(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ flag,
+                                                     const uint32_t* __restrict__ pos, int64_t m, int64_t nnz,
+                                                     int64_t n, int b, int64_t* __restrict__ row_ptr,
+                                                     int32_t* __restrict__ col)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m || !flag[p]) return;
+    const uint64_t k = keys[p];
+    const int64_t q = pos[p];
     const int64_t r = (int64_t)(k >> b);
     const int64_t rp = p == 0 ? -1 : (int64_t)(keys[p - 1] >> b);
-    col[p] = (int32_t)(k & ((1ull << b) - 1));
-    for (int64_t q = rp + 1; q <= r; ++q) row_ptr[q] = p;
-    if (p == nnz - 1)
-        for (int64_t q = r + 1; q <= n; ++q) row_ptr[q] = nnz;
+    col[q] = (int32_t)(k & ((1ull << b) - 1));
+    for (int64_t t = rp + 1; t <= r; ++t) row_ptr[t] = q;
+    if (q == nnz - 1)
+        for (int64_t t = r + 1; t <= n; ++t) row_ptr[t] = nnz;
 }
 
 __global__ void __launch_bounds__(256) fill_zero(int64_t* __restrict__ a, int64_t m)
@@ -84,12 +102,12 @@ int ring1_key_bits(int64_t n)
 
 size_t ring1_device_scratch_bytes(int64_t n_edges)
 {
-    size_t sort_bytes = 0, unique_bytes = 0;
+    size_t sort_bytes = 0, scan_bytes = 0;
     hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                       (int64_t)n_edges, 0, 64, (hipStream_t)0);
-    hipcub::DeviceSelect::Unique(nullptr, unique_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                 (int64_t*)nullptr, (int64_t)n_edges, (hipStream_t)0);
-    return sort_bytes > unique_bytes ? sort_bytes : unique_bytes;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                     (int64_t)n_edges, (hipStream_t)0);
+    return sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
 }
 
 hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int64_t n, uint64_t* keys, int* err,
@@ -105,26 +123,29 @@ hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int
     return hipGetLastError();
 }
 
-hipError_t sort_unique_keys(uint64_t* keys, uint64_t* tmp_keys, int64_t n_edges, int64_t n, void* scratch,
-                            size_t scratch_bytes, int64_t* d_n_unique, hipStream_t stream)
+hipError_t sort_and_mark_keys(uint64_t* keys, uint64_t* sorted, int64_t n_edges, int64_t n, void* scratch,
+                              size_t scratch_bytes, uint32_t* flag, uint32_t* pos, hipStream_t stream)
 {
     // keys i * 2^b + j with i <= n (the sentinel's row) and j < n use 2 b bits
-    const int end_bit = 2 * ring1_key_bits(n);
+    const int b = ring1_key_bits(n);
     size_t bytes = scratch_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortKeys(scratch, bytes, keys, tmp_keys, n_edges, 0, end_bit, stream);
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(scratch, bytes, keys, sorted, n_edges, 0, 2 * b, stream);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mark_first, dim3(blocks_for(n_edges)), dim3(256), 0, stream, sorted, n_edges,
+                       (uint64_t)n << b, flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     bytes = scratch_bytes;
-    return hipcub::DeviceSelect::Unique(scratch, bytes, tmp_keys, keys, d_n_unique, n_edges, stream);
+    return hipcub::DeviceScan::ExclusiveSum(scratch, bytes, flag, pos, n_edges, stream);
 }
 
-hipError_t launch_csr_from_keys(const uint64_t* keys, int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col,
-                                hipStream_t stream)
+hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t n_edges,
+                                int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t stream)
 {
     if (nnz == 0) {
         hipLaunchKernelGGL(fill_zero, dim3(blocks_for(n + 1)), dim3(256), 0, stream, row_ptr, n + 1);
     } else {
-        hipLaunchKernelGGL(csr_from_keys, dim3(blocks_for(nnz)), dim3(256), 0, stream, keys, nnz, n,
-                           ring1_key_bits(n), row_ptr, col);
+        hipLaunchKernelGGL(csr_from_keys, dim3(blocks_for(n_edges)), dim3(256), 0, stream, sorted, flag, pos, n_edges,
+                           nnz, n, ring1_key_bits(n), row_ptr, col);
     }
     return hipGetLastError();
 }
