@@ -3,8 +3,10 @@
 Headline: forward FTLE on the 2048x2048 jittered triangulated double-gyre
 mesh (4,194,304 points, float32), points/s.  Also measured in the same run
 and reported under "variants": the 160^3 ABC tetrahedral forward, the 96^3
-forward+adjoint, the 48-mesh batched forward, the axis stencil on the 2048^2
-and 160^3 meshes, and the RK4 flow map of the 2048^2 mesh.
+forward+adjoint, the 48-mesh batched forward, the headline with its flow map
+held as binary16 displacements, the axis stencil on the 2048^2 and 160^3
+meshes, the one-ring stencil built on the GPU from those meshes' cells, and
+the RK4 flow map of the 2048^2 mesh.
 
 Every timed step reads inputs already resident in HBM.  Each workload is held
 in several independent copies (mesh records, coordinates, flow map, output)
