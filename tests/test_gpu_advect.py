@@ -90,3 +90,18 @@ def test_advect_large_start_time_and_ragged_steps():
         err = np.abs(got - ref).max()
         print(f"[advect double_gyre t0={t0} T={T}] max |d| = {err:.3e}", flush=True)
         assert err < 1e-9
+
+
+def test_advect_full_2048_sampled():
+    """The measured flow map: all 4,194,304 particles of the 2048^2 jittered
+    grid (float32 in and out, as the benchmark times it), 3,000 of them
+    against the oracle's RK4 on the same float32 starting points."""
+    x, _ = meshes.jittered_tri_grid(2048, 2048, seed=7)
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    phi = F.advect_rk4("double_gyre", torch.as_tensor(x32, device=DEV), 0.0, 15.0, 0.01).cpu().numpy()
+    sel = np.unique(np.concatenate([np.random.default_rng(2).choice(x32.shape[0], 3000, replace=False),
+                                    np.arange(32), np.arange(x32.shape[0] - 32, x32.shape[0])]))
+    ref = oracle.advect_rk4("double_gyre", x32[sel].astype(np.float64), 0.0, 15.0, 0.01)
+    err = np.abs(phi[sel].astype(np.float64) - ref)
+    print(f"[advect 2048^2 sampled] max |d| = {err.max():.3e}", flush=True)
+    assert np.all(err <= 1e-9 + 2.0 ** -23 * np.abs(ref))
