@@ -171,10 +171,11 @@ ADVECT_PROFILE = os.path.join(ROOT, "profiles", "ftle_advect_rk4.txt")
 ADVECT_SRC = os.path.join(ROOT, "paper_2408_02758_amd", "csrc", "ftle_advect.hip")
 
 
-def advect_counts():
-    """Float64 FLOPs and VALU instructions per launch of the 2048^2 double-gyre
-    flow map, from the committed rocprofv3 summary, or {} when that summary was
-    taken from another version of the kernel source."""
+def advect_counts(flow="double_gyre"):
+    """Float64 FLOPs and VALU instructions per launch of the measured flow map
+    ("double_gyre": the 2048^2 grid; "abc": the 160^3 grid), from the committed
+    rocprofv3 summary, or {} when that summary was taken from another version
+    of the kernel source."""
     import hashlib
     if not os.path.exists(ADVECT_PROFILE):
         return {}
@@ -188,7 +189,10 @@ def advect_counts():
     with open(ADVECT_SRC, "rb") as f:
         if meta.get("advect_source_sha256") != hashlib.sha256(f.read()).hexdigest():
             return {}
-    return {"flops": float(meta["fp64_flops_per_launch"]), "valu": float(meta["valu_insts_per_launch"])}
+    key = "dg" if flow == "double_gyre" else "abc"
+    if f"{key}_fp64_flops_per_launch" not in meta:
+        return {}
+    return {"flops": float(meta[f"{key}_fp64_flops_per_launch"]), "valu": float(meta[f"{key}_valu_insts_per_launch"])}
 
 
 def alu_roofline(counts, ms):
@@ -293,10 +297,10 @@ def grad_error_vs_oracle(w, g_in, grad):
             "max_err_over_max_grad": float(np.abs(got - ref)[~bad].max() / np.abs(ref).max())}
 
 
-def oracle_advect(x0, t0, T):
-    """The FP64 oracle's RK4 double-gyre flow map (dt = 0.01) of the given particles."""
+def oracle_advect(x0, t0, T, flow="double_gyre", dt=0.01):
+    """The FP64 oracle's RK4 flow map of the given particles."""
     import oracle
-    return oracle.advect_rk4("double_gyre", x0, t0, T, 0.01)
+    return oracle.advect_rk4(flow, x0, t0, T, dt)
 
 
 def copy_probe_gbps(torch, dev, mib=1024, reps=10):
@@ -561,6 +565,24 @@ def main():
             log(f"advect_2d_2048: {t:.2f} ms per flow map")
             keep["advect"] = (w2, x0.cpu().numpy(), t0, phi.cpu().numpy())
             del x0, phi
+            # the 160^3 ABC flow map (T = 10, dt = 0.02: 500 steps per particle)
+            w3a = cached("abc_3d", lambda: configs.abc_3d(dev), args.cache, dev)
+            log("advect_3d_160: RK4 flow map on the GPU")
+            x0 = torch.as_tensor(w3a.coords, dtype=torch.float32, device=dev).contiguous()
+            phi = torch.empty_like(x0)
+            F.advect_rk4("abc", x0, 0.0, w3a.T, 0.02, out=phi)
+            t = time_steps([lambda: F.advect_rk4("abc", x0, 0.0, w3a.T, 0.02, out=phi)], 3, 1, torch)
+            nsteps = math.ceil(abs(w3a.T) / 0.02 - 1e-9)
+            variants["advect_3d_160"] = {
+                "workload": "RK4 flow map of the 160^3 Kuhn grid in the ABC flow, t0 = 0, T = 10, dt = 0.02 "
+                            "(float64 arithmetic, float32 output)",
+                "points": w3a.n, "steps_per_point": nsteps, "ms_per_step": round(t, 4),
+                "points_per_s": round(w3a.n / (t * 1e-3), 1),
+                "particle_steps_per_s": round(w3a.n * nsteps / (t * 1e-3), 1),
+                "roofline": alu_roofline(advect_counts("abc"), t)}
+            log(f"advect_3d_160: {t:.2f} ms per flow map")
+            keep["advect_abc"] = (w3a, x0.cpu().numpy(), phi.cpu().numpy())
+            del x0, phi, w3a
         for v in variants.values():
             if v["roofline"]["bound"] == "hbm":
                 v["roofline"]["frac_of_copy_probe"] = round(v["roofline"]["achieved"] / copy_gbps, 4)
@@ -598,6 +620,12 @@ def main():
             ref = oracle_advect(x0[sel].astype(np.float64), t0, wa.T)
             err["advect_2d_2048_sample"] = {"points": int(sel.size),
                                             "max_abs_err": float(np.abs(phi[sel].astype(np.float64) - ref).max())}
+        if "advect_abc" in keep:
+            wa, x0, phi = keep["advect_abc"]
+            sel = np.sort(rng.choice(wa.n, 20000, replace=False))
+            ref = oracle_advect(x0[sel].astype(np.float64), 0.0, wa.T, "abc", 0.02)
+            err["advect_3d_160_sample"] = {"points": int(sel.size),
+                                           "max_abs_err": float(np.abs(phi[sel].astype(np.float64) - ref).max())}
         if "axis_2d_2048" in keep:
             wa, got = keep["axis_2d_2048"]
             err["axis_2d_2048"] = error_vs_oracle(wa, got, stencil="axis")
