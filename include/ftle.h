@@ -126,7 +126,8 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
  * The one-ring stencil of a cell mesh, built on the device: row i lists, in
  * ascending order and once each, every other point that shares a cell with
  * point i (the neighbour determination that Section 2.2 keeps off the
- * accelerator; the same stencil ftle_create_mesh builds on the host).  Edge
+ * accelerator and the Conclusions name as future work; the same stencil
+ * ftle_create_mesh builds on the host).  Edge
  * extraction, a radix sort and a deduplication of the (i, j) pairs, then the
  * CSR arrays.  The result feeds ftle_create_mesh_from_csr.
  *   dim          2 (triangles) or 3 (tetrahedra)

@@ -1,7 +1,8 @@
 // The one-ring stencil of a cell mesh built on the GPU: the neighbour
-// determination that precedes the FTLE path (Section 2.2 keeps it off the
-// accelerator and names moving it as future work).  Every point's neighbours
-// are the other points sharing a cell with it, ascending, each once.
+// determination that precedes the FTLE path (Section 2.2 keeps it on the host,
+// off the accelerator; the Conclusions list accelerating it as future work).
+// Every point's neighbours are the other points sharing a cell with it,
+// ascending, each once.
 //
 //   1. edge extraction: each cell of K = dim + 1 points emits its K (K - 1)
 //      directed pairs (i, j) as 64-bit keys i * 2^b + j, with b the bit
