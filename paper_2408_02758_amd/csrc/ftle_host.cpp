@@ -1532,7 +1532,8 @@ ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int
         uint32_t* pos = nullptr;
         uint32_t tail[2] = {0, 0};   // flag and position of the last sorted key
         if (edges > 0) {
-            const size_t work = ring1_device_scratch_bytes(edges);
+            size_t work = 0;
+            check_hip(ring1_device_scratch_bytes(edges, &work), "sort scratch size");
             check_hip(hipMalloc((void**)&b.keys, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
             check_hip(hipMalloc((void**)&b.sorted, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
             check_hip(hipMalloc(&b.work, work ? work : 16), "hipMalloc (sort scratch)");

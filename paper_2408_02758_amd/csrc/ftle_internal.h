@@ -180,7 +180,7 @@ hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, co
 
 // One-ring stencil on the device (ftle_neighbours.hip): edge keys from the
 // cells, their sort and deduplication, and the CSR arrays from the kept keys.
-size_t ring1_device_scratch_bytes(int64_t n_edges);
+hipError_t ring1_device_scratch_bytes(int64_t n_edges, size_t* bytes);
 int ring1_key_bits(int64_t n);   // b: a key is i * 2^b + j
 hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int64_t n, uint64_t* keys, int* err,
                              hipStream_t stream);

@@ -101,14 +101,16 @@ int ring1_key_bits(int64_t n)
     return b;
 }
 
-size_t ring1_device_scratch_bytes(int64_t n_edges)
+hipError_t ring1_device_scratch_bytes(int64_t n_edges, size_t* bytes)
 {
     size_t sort_bytes = 0, scan_bytes = 0;
-    hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                      (int64_t)n_edges, 0, 64, (hipStream_t)0);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                     (int64_t)n_edges, (hipStream_t)0);
-    return sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (const uint64_t*)nullptr,
+                                                     (uint64_t*)nullptr, (int64_t)n_edges, 0, 64, (hipStream_t)0);
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                         (int64_t)n_edges, (hipStream_t)0);
+    *bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
+    return e;
 }
 
 hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int64_t n, uint64_t* keys, int* err,
