@@ -164,7 +164,9 @@ typedef enum {
  * Flow map phi = x(t0 + T) of particles starting at x0 at time t0, by the
  * classical fourth-order Runge-Kutta method in float64 (the step before the
  * FTLE path: the paper's inputs are precomputed flow maps).  Each particle
- * takes max(1, ceil(|T|/dt - 1e-9)) steps of T/steps.
+ * takes max(1, ceil(|T|/dt - 1e-9)) steps of T/steps, at most 10^7: a
+ * particle whose per-particle duration Ts[i] is not finite or needs more
+ * steps gets NaN.
  *   flow     FTLE_FLOW_* (2D double gyre, 3D ABC)
  *   params   host, 3 doubles, or NULL for the defaults above
  *   n        particles (>= 0)
@@ -174,7 +176,8 @@ typedef enum {
  *   dt       largest step (> 0)
  *   phi      device, n x dim of dtype, caller-owned, overwritten; not x0
  * Errors: INVALID_ARG (flow, dtype, n < 0, null pointer with n > 0, dt <= 0,
- * non-finite t0, T or parameter), DEVICE.
+ * non-finite t0, T or parameter, a common T needing more than 10^7 steps),
+ * DEVICE.
  */
 ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const void* x0, ftle_dtype dtype,
                             const double* t0s, const double* Ts, double t0, double T, double dt, void* phi,
@@ -337,8 +340,8 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
  * CU) or a flat grid of one workgroup per tile -- and keeps the fastest;
  * later calls only update the graph node's arguments.  Each output equals
  * ftle_forward's bit for bit (same tile body).  Calls with one list of meshes
- * share its queue counters: they are ordered on one stream; concurrent calls
- * with the same list on different streams race.
+ * share its queue counters: a call on another stream than the previous call
+ * with that list waits (on the device) for the previous launch.
  *   n         1 <= n <= 64 meshes
  *   meshes    host array of n handles (all dim and dtype equal)
  *   flows     host array of n device pointers (flow maps, user order)
@@ -375,6 +378,44 @@ ftle_status ftle_mesh_fp64_hits(ftle_mesh_t mesh, int64_t* hits, int reset);
  * it was built with.  Always returns FTLE_OK.
  */
 ftle_status ftle_force_wide_offsets(int on);
+
+/*
+ * Testing aid: the threshold of the 3D float32 eigenvalue recompute.  The
+ * trigonometric eigenvalue formula (lambda = q + 2 p cos(acos(r)/3)) loses
+ * accuracy where r -> -1, i.e. where the two largest eigenvalues of C nearly
+ * coincide; points with r + 1 < tau redo C = J^T J and the formula in
+ * float64 from the float32 Jacobian (ftle_mesh_fp64_hits counts them).
+ *   tau  >= 0: the new threshold (0 disables the recompute; any tau > 2
+ *        sends every point with a usable stencil through it, since
+ *        r + 1 <= 2); < 0: back to the default (the FTLE_EIG_TAU environment
+ *        variable, read once, else 2e-3).
+ * Process-wide; it applies to forward, tape-forward, adjoint and batched
+ * launches enqueued after the call.
+ * Errors: INVALID_ARG for a NaN or infinite tau.
+ */
+ftle_status ftle_set_eig_threshold(double tau);
+
+/* The threshold ftle_set_eig_threshold set, or the default.
+ * Errors: INVALID_ARG for a NULL tau. */
+ftle_status ftle_get_eig_threshold(double* tau);
+
+/*
+ * Testing aid: pin the launch shape of ftle_batched instead of autotuning it,
+ * so that every form can be checked against ftle_forward.
+ *   block          0: unpin (lists of meshes without a chosen shape are
+ *                  autotuned again; the others keep theirs); else 128, 256
+ *                  or 512 threads per workgroup
+ *   tiles_per_pop  0: the flat grid (one workgroup per tile); 1..64: the
+ *                  persistent grid draining the atomic queue, that many
+ *                  tiles per pop
+ *   per_cu_cap     persistent grid only: at most this many resident
+ *                  workgroups per CU (1..32; ignored when tiles_per_pop is 0)
+ * Process-wide: the next ftle_batched call of every list of meshes adopts the
+ * pinned shape (rebuilding its cached graph) until it is unpinned.
+ * ftle_batched_config reports the shape in use.
+ * Errors: INVALID_ARG for a value outside these ranges.
+ */
+ftle_status ftle_batched_pin_config(int block, int tiles_per_pop, int per_cu_cap);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* ftle_last_error(void);

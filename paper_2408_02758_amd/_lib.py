@@ -59,6 +59,9 @@ SIGNATURES = {
     "ftle_batched_config": (_int, [_int, _vp, _P(_int), _P(_int), _P(_int)]),
     "ftle_mesh_fp64_hits": (_int, [_vp, _P(_i64), _int]),
     "ftle_force_wide_offsets": (_int, [_int]),
+    "ftle_set_eig_threshold": (_int, [_dbl]),
+    "ftle_get_eig_threshold": (_int, [_P(_dbl)]),
+    "ftle_batched_pin_config": (_int, [_int, _int, _int]),
     "ftle_last_error": (ctypes.c_char_p, []),
     "ftle_version": (ctypes.c_char_p, []),
 }

@@ -441,10 +441,30 @@ def force_wide_offsets(on: bool) -> None:
     check(_lib.load().ftle_force_wide_offsets(int(bool(on))))
 
 
+def set_eig_threshold(tau: float) -> None:
+    """Testing aid: threshold of the 3D float32 eigenvalue recompute (r + 1 < tau
+    goes through float64; tau > 2 sends every point, 0 none, < 0 restores the
+    default; see ftle_set_eig_threshold)."""
+    check(_lib.load().ftle_set_eig_threshold(float(tau)))
+
+
+def eig_threshold() -> float:
+    t = ctypes.c_double()
+    check(_lib.load().ftle_get_eig_threshold(ctypes.byref(t)))
+    return t.value
+
+
+def pin_batched_config(block: int = 0, tiles_per_pop: int = 0, per_cu_cap: int = 0) -> None:
+    """Testing aid: pin the batched launch shape (block 0 unpins; tiles_per_pop 0
+    is the flat grid; see ftle_batched_pin_config)."""
+    check(_lib.load().ftle_batched_pin_config(int(block), int(tiles_per_pop), int(per_cu_cap)))
+
+
 def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
     """Differentiable FTLE of a flow map on a mesh."""
     return FTLEFunction.apply(flow, mesh, T)
 
 
 __all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError",
-           "force_wide_offsets", "advect_rk4", "ring1_csr"]
+           "force_wide_offsets", "set_eig_threshold", "eig_threshold", "pin_batched_config", "advect_rk4",
+           "ring1_csr"]

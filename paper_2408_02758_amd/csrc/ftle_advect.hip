@@ -10,7 +10,9 @@
 //  - the steady Arnold-Beltrami-Childress flow
 //    (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x).
 //
-// A particle takes max(1, ceil(|T|/dt - 1e-9)) steps of T/steps from t0.
+// A particle takes max(1, ceil(|T|/dt - 1e-9)) steps of T/steps from t0; a
+// particle whose duration is not finite or needs more than kMaxAdvectSteps
+// steps gets NaN without stepping (the host rejects such a common T).
 // The work is arithmetic (transcendentals) on registers: one 2-3 value load
 // and one store per particle.
 #include <hip/hip_runtime.h>
@@ -76,6 +78,11 @@ __global__ void __launch_bounds__(256) advect_kernel(FlowParams pr, int64_t n, c
     const double ti = t0s ? t0s[i] : t0;
     const double Ti = Ts ? Ts[i] : Tall;
     const double steps = fmax(1.0, ceil(fabs(Ti) / dt - 1e-9));
+    if (!(steps <= (double)kMaxAdvectSteps)) {   // also NaN and inf
+#pragma unroll
+        for (int d = 0; d < D; ++d) phi[i * D + d] = (T)NAN;
+        return;
+    }
     const double h = Ti / steps;
     const int64_t ns = (int64_t)steps;
     double rs = 0.0, rc = 1.0, sw = 0.0, cw = 1.0;   // rotation by omega h / 2; factor pair at the step's start

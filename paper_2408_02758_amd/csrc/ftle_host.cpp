@@ -682,7 +682,19 @@ double env_double(const char* name, double dflt)
 }
 
 // r < -1 + tau selects the float64 eigenvalue recompute (3D, float32 meshes).
-double eig_tau() { static const double t = env_double("FTLE_EIG_TAU", 2e-3); return t; }
+// The default comes from FTLE_EIG_TAU (read once) or is 2e-3;
+// ftle_set_eig_threshold replaces it at run time.
+double default_eig_tau()
+{
+    static const double t = env_double("FTLE_EIG_TAU", 2e-3);
+    return t;
+}
+std::atomic<double> g_eig_tau{-1.0};   // < 0: the default
+double eig_tau()
+{
+    const double t = g_eig_tau.load(std::memory_order_relaxed);
+    return t < 0.0 ? default_eig_tau() : t;
+}
 
 void check_mesh(ftle_mesh_t m)
 {
@@ -735,6 +747,22 @@ ftle_status ftle_force_wide_offsets(int on)
 {
     set_force_wide(on != 0);
     return FTLE_OK;
+}
+
+ftle_status ftle_set_eig_threshold(double tau)
+{
+    return guarded([&] {
+        if (std::isnan(tau) || std::isinf(tau)) fail(FTLE_ERR_INVALID_ARG, "tau must be finite");
+        g_eig_tau.store(tau < 0.0 ? -1.0 : tau, std::memory_order_relaxed);
+    });
+}
+
+ftle_status ftle_get_eig_threshold(double* tau)
+{
+    return guarded([&] {
+        if (!tau) fail(FTLE_ERR_INVALID_ARG, "tau is NULL");
+        *tau = eig_tau();
+    });
 }
 
 // The axis along which the caller's point order advances, or -1: over a
@@ -1234,8 +1262,8 @@ struct BatchPlan {
     unsigned* d_queue = nullptr;  // 2 counters
     int n_items = 0;
     size_t lds = 0;
-    // chosen launch shape
-    int block = 256, tiles_per_pop = 1, grid = 0;
+    // chosen launch shape (cap: resident workgroups per CU of a persistent grid)
+    int block = 256, tiles_per_pop = 1, grid = 0, cap = 0;
     bool tuned = false;
     // graph
     hipGraph_t graph = nullptr;
@@ -1244,10 +1272,22 @@ struct BatchPlan {
     std::vector<unsigned char> arg_storage;
     void* args[6] = {};
     BatchCall last{};          // arguments the graph node holds now
+    double last_tau = -1.0;    // eigen threshold the graph node holds now
+    // the queue counters are reused by every launch: a launch on another
+    // stream than the previous one waits for it
+    hipEvent_t done = nullptr;
+    hipStream_t done_stream = nullptr;
+    bool launched = false;
 };
 
 std::mutex g_batch_mu;
 std::map<std::vector<ftle_mesh_t>, std::unique_ptr<BatchPlan>> g_plans;
+
+// Launch shape pinned by ftle_batched_pin_config (block 0: not pinned).
+struct PinnedShape {
+    int block = 0, tiles_per_pop = 0, cap = 0;
+};
+PinnedShape g_pin;   // guarded by g_batch_mu
 
 BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
 {
@@ -1297,6 +1337,7 @@ BatchPlan* get_plan(int n, const ftle_mesh_t* meshes)
     p->d_items = dev_upload(flat.data(), flat.size() * sizeof(BatchItem));
     p->d_queue = static_cast<unsigned*>(dev_upload(nullptr, 2 * sizeof(unsigned)));
     check_hip(hipMemset(p->d_queue, 0, 2 * sizeof(unsigned)), "hipMemset");
+    check_hip(hipEventCreateWithFlags(&p->done, hipEventDisableTiming), "hipEventCreateWithFlags");
     check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
     BatchPlan* raw = p.get();
     g_plans[key] = std::move(p);
@@ -1351,6 +1392,7 @@ void autotune(BatchPlan* p, const BatchCall& call, hipStream_t s)
                     p->block = b;
                     p->tiles_per_pop = k;
                     p->grid = grid;
+                    p->cap = k == 0 ? 0 : cap;
                 }
             }
     (void)hipEventDestroy(e0);
@@ -1375,10 +1417,32 @@ void build_graph(BatchPlan* p, const BatchCall& call)
     check_hip(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
 }
 
-void free_plan(BatchPlan* p)
+void drop_graph(BatchPlan* p)
 {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->node = nullptr;
+}
+
+// Adopt the pinned launch shape (the graph is rebuilt on the next launch).
+void apply_pin(BatchPlan* p, const PinnedShape& pin)
+{
+    const int cap = pin.tiles_per_pop == 0 ? 0 : pin.cap;
+    if (p->tuned && p->block == pin.block && p->tiles_per_pop == pin.tiles_per_pop && p->cap == cap) return;
+    p->block = pin.block;
+    p->tiles_per_pop = pin.tiles_per_pop;
+    p->cap = cap;
+    p->grid = pin.tiles_per_pop == 0 ? p->n_items : resident_grid(p, pin.block, cap);
+    p->tuned = true;
+    drop_graph(p);
+}
+
+void free_plan(BatchPlan* p)
+{
+    drop_graph(p);
+    if (p->done) (void)hipEventDestroy(p->done);
     if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_queue) (void)hipFree(p->d_queue);
 }
@@ -1441,15 +1505,22 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
             call.inv2T[k] = 0.5 / std::fabs(T[k]);
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
-        if (!p->tuned) autotune(p, call, s);
+        // the previous launch of this plan may still use the queue counters
+        if (p->launched && p->done_stream != s) check_hip(hipStreamWaitEvent(s, p->done, 0), "hipStreamWaitEvent");
+        if (g_pin.block)
+            apply_pin(p, g_pin);
+        else if (!p->tuned)
+            autotune(p, call, s);
+        const double tau = eig_tau();
         if (!p->exec) {
             build_graph(p, call);
             p->last = call;
+            p->last_tau = tau;
         }
-        if (std::memcmp(&p->last, &call, sizeof(BatchCall)) != 0) {
-            // new pointers or times: update the graph's kernel node in place
+        if (std::memcmp(&p->last, &call, sizeof(BatchCall)) != 0 || p->last_tau != tau) {
+            // new pointers, times or threshold: update the graph's kernel node in place
             batched_kernel_args(static_cast<const BatchItem*>(p->d_items), p->n_items, p->tiles_per_pop, p->d_queue,
-                                call, eig_tau(), p->arg_storage.data(), p->args);
+                                call, tau, p->arg_storage.data(), p->args);
             hipKernelNodeParams kp{};
             kp.func = const_cast<void*>(batched_kernel_symbol(p->dim, p->f64, p->block, p->wide));
             kp.gridDim = dim3(p->grid);
@@ -1459,8 +1530,12 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
             kp.extra = nullptr;
             check_hip(hipGraphExecKernelNodeSetParams(p->exec, p->node, &kp), "hipGraphExecKernelNodeSetParams");
             p->last = call;
+            p->last_tau = tau;
         }
         check_hip(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
+        check_hip(hipEventRecord(p->done, s), "hipEventRecord");
+        p->done_stream = s;
+        p->launched = true;
     });
 }
 
@@ -1475,6 +1550,8 @@ ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const voi
         if (n > 0 && (!x0 || !phi)) fail(FTLE_ERR_INVALID_ARG, "x0 or phi is NULL");
         if (!(dt > 0.0) || !std::isfinite(dt)) fail(FTLE_ERR_INVALID_ARG, "dt must be positive and finite");
         if (!std::isfinite(t0) || !std::isfinite(T)) fail(FTLE_ERR_INVALID_ARG, "t0 and T must be finite");
+        if (!Ts && !(std::ceil(std::fabs(T) / dt - 1e-9) <= (double)kMaxAdvectSteps))
+            fail(FTLE_ERR_INVALID_ARG, "|T| / dt exceeds the step limit (10^7 steps per particle)");
         double prm[3];
         if (params) {
             for (int k = 0; k < 3; ++k) {
@@ -1556,6 +1633,20 @@ ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int
         if (count > col_capacity) fail(FTLE_ERR_UNSUPPORTED, "col_capacity below the stencil's entry count (in *nnz)");
         check_hip(launch_csr_from_keys(b.sorted, flag, pos, edges, count, n_points, row_ptr, col, s), "CSR from keys");
         check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    });
+}
+
+ftle_status ftle_batched_pin_config(int block, int tiles_per_pop, int per_cu_cap)
+{
+    return guarded([&] {
+        if (block != 0) {
+            if (!supported_block(block)) fail(FTLE_ERR_INVALID_ARG, "block must be 0, 128, 256 or 512");
+            if (tiles_per_pop < 0 || tiles_per_pop > 64) fail(FTLE_ERR_INVALID_ARG, "tiles_per_pop must be in [0, 64]");
+            if (tiles_per_pop > 0 && (per_cu_cap < 1 || per_cu_cap > 32))
+                fail(FTLE_ERR_INVALID_ARG, "per_cu_cap must be in [1, 32]");
+        }
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        g_pin = block ? PinnedShape{block, tiles_per_pop, tiles_per_pop ? per_cu_cap : 0} : PinnedShape{};
     });
 }
 

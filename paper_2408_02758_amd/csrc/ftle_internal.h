@@ -174,7 +174,9 @@ hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, cons
 inline bool supported_block(int b) { return b == 128 || b == 256 || b == 512; }
 
 // Flow maps by RK4 advection (ftle_advect.hip): kind 0 double gyre, 1 ABC;
-// per-point t0s / Ts when not null, else t0 / T for every particle.
+// per-point t0s / Ts when not null, else t0 / T for every particle.  At most
+// kMaxAdvectSteps steps per particle.
+constexpr int64_t kMaxAdvectSteps = 10000000;
 hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, const void* x0, const double* t0s,
                          const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream);
 

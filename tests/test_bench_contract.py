@@ -35,3 +35,50 @@ def test_rooflines():
     a = bench.alu_roofline({"flops": 78.6e12 * 1e-3, "valu": bench.VALU_ISSUE_PEAK * 1e-3}, 1.0)
     assert a["bound"] == "alu" and a["frac"] == 1.0 and a["valu_issue_frac"] == 1.0
     assert bench.alu_roofline({}, 1.0)["achieved"] is None
+
+
+def test_profiling_runs_need_a_filled_cache(tmp_path):
+    """Under --require-cache a workload missing from --cache ends the run before
+    any GPU work (profilers must not see the workload generator's kernels)."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--require-cache", "--cache", str(tmp_path),
+                        "--only", "fwd3d,batched"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 3
+    assert "--fill-cache" in r.stderr and "abc_3d" in r.stderr and "batched_2d" in r.stderr
+    loads = bench.Workloads(str(tmp_path), "cpu", require=True)
+    (tmp_path / "scale_2d.npz").write_bytes(b"")
+    loads.check(["scale_2d"])
+    try:
+        loads.check(["scale_2d", "diff_3d"])
+    except bench.MissingWorkload as e:
+        assert "diff_3d" in str(e)
+    else:
+        raise AssertionError("missing workload not reported")
+    assert bench.needed_workloads(False, ["axis"]) == ["scale_2d", "abc_3d"]
+
+
+def test_profile_summaries_from_rocprof_csv(tmp_path):
+    """The kernel-trace and counter summarizers on rocprofv3-shaped CSV files:
+    durations per kernel, and counters scaled so that the first copy-probe
+    dispatch reads exactly its size."""
+    kt = tmp_path / "kt" / "host" / "1"
+    kt.mkdir(parents=True)
+    with open(kt / "kt_kernel_trace.csv", "w") as f:
+        f.write('"Kind","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
+        f.write('"KERNEL_DISPATCH","fwd_kernel<2, float, true, 0, 256, false>","1000","33000"\n')
+        f.write('"KERNEL_DISPATCH","fwd_kernel<2, float, true, 0, 256, false>","50000","80000"\n')
+        f.write('"KERNEL_DISPATCH","void at::native::neg_kernel","90000","99000"\n')
+    lines = bench.summarize_trace(str(tmp_path / "kt"), "main")
+    assert len(lines) == 1 and "avg_us: 31.00" in lines[0] and "calls: 2" in lines[0]
+    for counter, probe, val in (("FETCH_SIZE", 131072.0, 50000.0), ("WRITE_SIZE", 262144.0, 16384.0)):
+        d = tmp_path / counter / "h" / "2"
+        d.mkdir(parents=True)
+        with open(d / "pmc_counter_collection.csv", "w") as f:
+            f.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+            f.write(f'"1","at::native::neg_kernel","{counter}","{probe}"\n')
+            f.write(f'"2","fwd_kernel<2, float, true, 0, 256, false>","{counter}","{val}"\n')
+            f.write(f'"3","fwd_kernel<2, float, true, 0, 256, false>","{counter}","{val}"\n')
+    lines = bench.summarize_counters(str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"), "main")
+    assert len(lines) == 1
+    row = dict(p.split(": ", 1) for p in lines[0].split(" | "))
+    assert float(row["fetch_factor"]) == 2.0 and float(row["write_factor"]) == 1.0
+    assert row["dispatches"] == "2" and float(row["fetch_kib"]) == 50000.0

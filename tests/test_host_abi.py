@@ -416,3 +416,31 @@ def test_tiles_follow_caller_order_axis():
     m2 = F.Mesh(x2, c2, "f32", host_only=True)
     assert m2.info()["nnz"] == m.info()["nnz"]
     assert all(P + H <= 1024 for _, _, _, P, H in m2.tiles(False))
+
+
+def test_testing_aids_validation(L):
+    """The run-time eigen threshold and the pinned batched shape reject bad
+    values before any device work; valid values round-trip."""
+    INVALID = 1
+    t = ctypes.c_double()
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        assert L.ftle_set_eig_threshold(bad) == INVALID
+    assert L.ftle_get_eig_threshold(None) == INVALID
+    assert L.ftle_set_eig_threshold(0.5) == 0
+    assert L.ftle_get_eig_threshold(ctypes.byref(t)) == 0 and t.value == 0.5
+    assert L.ftle_set_eig_threshold(-1.0) == 0
+    assert L.ftle_get_eig_threshold(ctypes.byref(t)) == 0 and t.value == pytest.approx(2e-3)
+    for block, k, cap in ((64, 1, 4), (256, -1, 4), (256, 65, 4), (256, 2, 0), (512, 1, 33)):
+        assert L.ftle_batched_pin_config(block, k, cap) == INVALID, (block, k, cap)
+    assert L.ftle_batched_pin_config(256, 0, 0) == 0   # flat grid: the cap is ignored
+    assert L.ftle_batched_pin_config(0, 0, 0) == 0
+
+
+def test_advect_step_limit(L):
+    """A common duration that needs more than 10^7 RK4 steps is rejected on the
+    host (the pointers are never dereferenced)."""
+    INVALID = 1
+    fake = ctypes.c_void_p(16)
+    assert L.ftle_advect_rk4(0, None, 10, fake, 0, None, None, 0.0, 1e15, 1e-2, fake, None) == INVALID
+    assert b"step limit" in L.ftle_last_error()
+    assert L.ftle_advect_rk4(1, None, 10, fake, 0, None, None, 0.0, -1.00000001e5, 1e-2, fake, None) == INVALID
