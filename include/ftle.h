@@ -332,6 +332,26 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
                           const void* grad_ftle, void* grad_flow, ftle_stream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ftle_backward
+ * with its tape in a fixed 128 MiB device array that the library holds on
+ * each GPU it runs on (until the process ends) instead of a workspace it
+ * allocates.  The call allocates nothing, on the device or the host; its
+ * results equal ftle_backward's bit for bit (same kernels).
+ *   arguments as ftle_backward
+ * Limit: the tape, n_points * (2 dim + 1) values of dtype, must fit 128 MiB
+ * (3D float32: up to 4,793,490 points; 2D float32: 6,710,886; 3D float64:
+ * 2,396,745; 2D float64: 3,355,443).
+ * Every call on one GPU shares that GPU's array and leaves its tape there:
+ * calls that overlap on one GPU (on different streams, or from several host
+ * threads) race; order them on one stream.
+ * Errors: as ftle_backward; UNSUPPORTED for a mesh whose tape exceeds the
+ * limit (checked before any device work).
+ */
+ftle_status ftle_backward_noalloc(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
+                                  const void* grad_ftle, void* grad_flow, ftle_stream_t stream);
+
+/*
  * Batched forward FTLE over independent meshes (same dim and dtype), in one
  * launch over a work list of (mesh, tile) items, replayed from a cached HIP
  * graph.  The first call for a given list of meshes builds the work list,

@@ -299,6 +299,19 @@ class Mesh:
                                         ctypes.c_void_p(grad_flow.data_ptr()), _stream_handle(stream)))
         return grad_flow
 
+    def backward_noalloc(self, flow: torch.Tensor, T: float, grad_ftle: torch.Tensor, grad_flow: torch.Tensor,
+                         stream=None):
+        """ftle_backward with its tape in the library's fixed per-GPU scratch:
+        the call allocates nothing (grad_flow must be given).  Calls that
+        overlap on one GPU race; order them on one stream."""
+        self._check_flow(flow)
+        self._check_flow(grad_ftle, "grad_ftle", (self.n,))
+        self._check_flow(grad_flow, "grad_flow")
+        check(_lib.load().ftle_backward_noalloc(self._h, ctypes.c_void_p(flow.data_ptr()), self._code, float(T),
+                                                ctypes.c_void_p(grad_ftle.data_ptr()),
+                                                ctypes.c_void_p(grad_flow.data_ptr()), _stream_handle(stream)))
+        return grad_flow
+
     def fp64_hits(self, reset: bool = False) -> int:
         h = ctypes.c_int64()
         check(_lib.load().ftle_mesh_fp64_hits(self._h, ctypes.byref(h), int(reset)))

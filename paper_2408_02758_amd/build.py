@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libftle.so")
 SOURCES = [os.path.join(CSRC, "ftle_kernels.hip"), os.path.join(CSRC, "ftle_advect.hip"),
-           os.path.join(CSRC, "ftle_neighbours.hip"), os.path.join(CSRC, "ftle_host.cpp")]
+           os.path.join(CSRC, "ftle_neighbours.hip"), os.path.join(CSRC, "ftle_noalloc.hip"),
+           os.path.join(CSRC, "ftle_host.cpp")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

@@ -1230,6 +1230,35 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
     });
 }
 
+ftle_status ftle_backward_noalloc(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
+                                  const void* grad_ftle, void* grad_flow, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_mesh(mesh);
+        check_dtype(mesh, dtype);
+        check_T(T);
+        if (!flow || !grad_ftle || !grad_flow) fail(FTLE_ERR_INVALID_ARG, "flow, grad_ftle or grad_flow is NULL");
+        const size_t bytes = (size_t)mesh->n * (2 * mesh->dim + 1) * mesh->elem();
+        if (bytes > kNoAllocScratchBytes)
+            fail(FTLE_ERR_UNSUPPORTED, "the adjoint tape (" + std::to_string(bytes) +
+                                           " bytes) exceeds the fixed scratch of ftle_backward_noalloc (" +
+                                           std::to_string(kNoAllocScratchBytes) + " bytes)");
+        need_device(mesh);
+        DeviceScope ds(mesh->device);
+        void* tape = nullptr;
+        check_hip(noalloc_scratch(mesh->device, &tape), "hipGetSymbolAddress (scratch)");
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        // the tape forward writes every point's tape entry, so nothing is cleared first
+        check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, 0.5 / std::fabs(T),
+                                 nullptr, tape, !mesh->symmetric, mesh->n, eig_tau(), mesh->d_hits,
+                                 mesh->fwd_block, s),
+                  "adjoint tape launch");
+        check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, tape,
+                                         !mesh->symmetric, mesh->n, grad_ftle, grad_flow, mesh->bwd_block, s),
+                  "adjoint launch");
+    });
+}
+
 ftle_status ftle_mesh_fp64_hits(ftle_mesh_t mesh, int64_t* hits, int reset)
 {
     return guarded([&] {

@@ -193,6 +193,12 @@ hipError_t sort_and_mark_keys(uint64_t* keys, uint64_t* sorted, int64_t n_edges,
 hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t n_edges,
                                 int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t stream);
 
+// The allocation-free adjoint (ftle_noalloc.hip): its tape lives in a fixed
+// device array of kNoAllocScratchBytes per GPU; noalloc_scratch gives that
+// array's address on `device`, which must be current.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+hipError_t noalloc_scratch(int device, void** ptr);
+
 hipError_t launch_batched(int dim, bool f64, bool wide, const BatchItem* items, int n_items, int tiles_per_pop,
                           unsigned* queue, const BatchCall& call, size_t lds, double eig_tau, int block, int grid,
                           hipStream_t stream);

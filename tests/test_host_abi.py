@@ -444,3 +444,25 @@ def test_advect_step_limit(L):
     assert L.ftle_advect_rk4(0, None, 10, fake, 0, None, None, 0.0, 1e15, 1e-2, fake, None) == INVALID
     assert b"step limit" in L.ftle_last_error()
     assert L.ftle_advect_rk4(1, None, 10, fake, 0, None, None, 0.0, -1.00000001e5, 1e-2, fake, None) == INVALID
+
+
+def test_backward_noalloc_limit_checked_first(L):
+    """ftle_backward_noalloc rejects a mesh whose tape exceeds its fixed 128 MiB
+    scratch before any device work (here a host-only 3D float64 mesh one point
+    over the limit), and validates its arguments like ftle_backward."""
+    INVALID, UNSUP = 1, 4
+    n = (128 << 20) // (7 * 8) + 1
+    x = np.random.default_rng(0).random((n, 3))
+    h = ctypes.c_void_p()
+    assert L.ftle_create_mesh(3, n, x.ctypes.data, 1, 0, None, _lib.HOST_ONLY, ctypes.byref(h)) == 0
+    p = ctypes.c_void_p(16)   # never dereferenced
+    assert L.ftle_backward_noalloc(h, p, 1, 1.0, p, p, None) == UNSUP
+    assert b"scratch" in L.ftle_last_error()
+    assert L.ftle_backward_noalloc(h, p, 1, 0.0, p, p, None) == INVALID
+    assert L.ftle_backward_noalloc(h, p, 0, 1.0, p, p, None) == 3
+    L.ftle_destroy_mesh(h)
+    st, h2 = _create(L)   # small host-only mesh: within the limit, then refused as host-only
+    assert L.ftle_backward_noalloc(h2, p, 0, 1.0, p, p, None) == UNSUP
+    assert b"HOST_ONLY" in L.ftle_last_error()
+    assert L.ftle_backward_noalloc(h2, p, 0, 1.0, None, p, None) == INVALID
+    L.ftle_destroy_mesh(h2)
