@@ -59,9 +59,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X float64 vector, published (256 CUs x 1
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions/s: 4 SIMDs per CU, 4 cycles each
 
 # variant groups of --only, and the cached workloads each needs
-GROUPS = ("f16", "fp64", "fwd3d", "fwdbwd", "batched", "axis", "neighbours", "advect")
+GROUPS = ("f16", "fp64", "fwd3d", "fwdbwd", "batched", "axis", "ell", "neighbours", "advect")
 GROUP_WORKLOADS = {"headline": ["scale_2d"], "f16": ["scale_2d"], "fp64": ["scale_2d"], "fwd3d": ["abc_3d"],
                    "fwdbwd": ["diff_3d"], "batched": ["batched_2d"], "axis": ["scale_2d", "abc_3d"],
+                   "ell": ["scale_2d", "abc_3d"],
                    "neighbours": ["scale_2d", "abc_3d"], "advect": ["scale_2d", "abc_3d"]}
 
 # The commands that made the summaries under profiles/ (run from the
@@ -71,7 +72,7 @@ PROFILE_RECIPE = [
     # kernel durations: the ring-1 rows, then the axis rows (same kernel names)
     "timeout -k 10 600 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_main -o kt --output-format csv -- "
     "python -u bench.py --require-cache --cache gpurun_out/wc --steps 30 --no-cpu-baseline --no-sustained "
-    "--batched-shape 256,0,0 --only f16,fp64,fwd3d,fwdbwd,batched",
+    "--batched-shape 256,0,0 --only f16,fp64,fwd3d,fwdbwd,batched,ell",
     "timeout -k 10 600 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_axis -o kt --output-format csv -- "
     "python -u bench.py --require-cache --cache gpurun_out/wc --steps 30 --no-cpu-baseline --no-sustained "
     "--no-headline --only axis",
@@ -79,7 +80,7 @@ PROFILE_RECIPE = [
     # starting with a 256 MiB copy whose counts calibrate the counters
     "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_main -o pmc --output-format csv -- "
     "python -u bench.py --require-cache --cache gpurun_out/wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
-    "--no-sustained --batched-shape 256,0,0 --copy-probe-mib 256 --only f16,fp64,fwd3d,fwdbwd,batched",
+    "--no-sustained --batched-shape 256,0,0 --copy-probe-mib 256 --only f16,fp64,fwd3d,fwdbwd,batched,ell",
     "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_axis -o pmc --output-format csv -- "
     "python -u bench.py --require-cache --cache gpurun_out/wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
     "--no-sustained --no-headline --copy-probe-mib 256 --only axis",
@@ -240,47 +241,63 @@ def time_steps(fns, steps, warmup, torch):
 
 
 class ClockSampler:
-    """Samples the GPU's shader clock from sysfs (the hwmon freq1_input file of
-    the device's PCI function, in Hz) every ~2 ms while active: a file read, no
-    process.  Reports min / median / max MHz, or why it recorded nothing."""
+    """Samples the GPU's shader clock while active: the current level of the
+    device's pp_dpm_sclk sysfs file (the line marked '*'), with the board
+    power from its hwmon power1_input, every ~5 ms (file reads, no process).
+    Reports min / median / max, or why nothing was recorded."""
 
     def __init__(self, torch):
-        self.path, self.reason = None, None
+        self.sclk = self.power = self.reason = None
+        cards = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
         try:
             p = torch.cuda.get_device_properties(0)
             bdf = f"{p.pci_domain_id:04x}:{p.pci_bus_id:02x}:{p.pci_device_id:02x}.0"
-            cands = sorted(glob.glob(f"/sys/bus/pci/devices/{bdf}/hwmon/hwmon*/freq1_input"))
-            if cands:
-                self.path = cands[0]
-            else:
-                self.reason = f"no hwmon freq1_input under /sys/bus/pci/devices/{bdf}"
-        except Exception as e:  # noqa: BLE001 - the clock is informational
-            self.reason = f"device properties unavailable: {e}"
-        self.samples = []
+        except Exception:  # noqa: BLE001 - the clock is informational
+            bdf = None
+        match = [c for c in cards if bdf and os.path.realpath(os.path.dirname(c)).endswith(bdf)]
+        if match or len(cards) == 1:
+            self.sclk = (match or cards)[0]
+            pw = sorted(glob.glob(os.path.join(os.path.dirname(self.sclk), "hwmon", "hwmon*", "power1_input")))
+            self.power = pw[0] if pw else None
+        else:
+            self.reason = f"{len(cards)} pp_dpm_sclk files, none for PCI device {bdf}"
+        self.samples, self.watts = [], []
         self._stop = threading.Event()
         self._thread = None
 
-    def _read(self):
-        with open(self.path) as f:
-            return int(f.read().strip()) / 1e6
+    @staticmethod
+    def _read_sclk(path):
+        with open(path) as f:
+            for ln in f:
+                if ln.rstrip().endswith("*"):
+                    return float(ln.split(":", 1)[1].strip().rstrip("*").strip().lower().rstrip("mhz"))
+        return None
+
+    def _sample(self):
+        v = self._read_sclk(self.sclk)
+        if v is not None:
+            self.samples.append(v)
+        if self.power:
+            with open(self.power) as f:
+                self.watts.append(int(f.read().strip()) / 1e6)
 
     def __enter__(self):
-        self.samples = []
-        if self.path:
+        self.samples, self.watts = [], []
+        if self.sclk:
             try:
-                self._read()
+                self._sample()
             except (OSError, ValueError) as e:
-                self.reason, self.path = f"{self.path}: {e}", None
-        if self.path:
+                self.reason, self.sclk = f"{self.sclk}: {e}", None
+        if self.sclk:
             self._stop.clear()
 
             def run():
                 while not self._stop.is_set():
                     try:
-                        self.samples.append(self._read())
+                        self._sample()
                     except (OSError, ValueError):
                         pass
-                    self._stop.wait(0.002)
+                    self._stop.wait(0.005)
             self._thread = threading.Thread(target=run, daemon=True)
             self._thread.start()
         return self
@@ -295,8 +312,11 @@ class ClockSampler:
         if not self.samples:
             return {"recorded": False, "reason": self.reason or "no samples"}
         s = sorted(self.samples)
-        return {"recorded": True, "source": self.path, "samples": len(s), "min_mhz": round(s[0], 1),
-                "median_mhz": round(statistics.median(s), 1), "max_mhz": round(s[-1], 1)}
+        out = {"recorded": True, "source": self.sclk, "samples": len(s), "min_mhz": s[0],
+               "median_mhz": statistics.median(s), "max_mhz": s[-1]}
+        if self.watts:
+            out["median_power_w"] = round(statistics.median(self.watts), 1)
+        return out
 
 
 def sustained(fns, torch, alg_bytes, clock, steps=200, warmup=50):
@@ -447,6 +467,34 @@ def _field(row, *names):
     raise KeyError(names)
 
 
+def short_kernel_name(name):
+    """A kernel's name without return type, namespaces and argument list:
+    'void ftle::(anonymous namespace)::fwd_kernel<2, float, ...>(...)' ->
+    'fwd_kernel<2, float, ...>'."""
+    s = name.strip()
+    if s.startswith("void "):
+        s = s[5:]
+    depth, cut = 0, len(s)
+    for k, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and not s[max(0, k - 2):k].endswith("::"):
+            cut = k
+            break
+    s = s[:cut]
+    depth, start = 0, 0
+    for k, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == ":" and depth == 0 and k + 1 < len(s) and s[k + 1] == ":":
+            start = k + 2
+    return s[start:].strip()
+
+
 FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "fused", "csr", "edges", "advect", "mark_first")
 
 
@@ -455,7 +503,7 @@ def summarize_trace(directory, run):
     (us), from rocprofv3 --kernel-trace CSV output under directory."""
     per = {}
     for r in _csv_rows(directory, "kernel_trace.csv"):
-        name = _field(r, "Kernel_Name", "Kernel-Name")
+        name = short_kernel_name(_field(r, "Kernel_Name", "Kernel-Name"))
         t = (int(_field(r, "End_Timestamp")) - int(_field(r, "Start_Timestamp"))) / 1e3
         per.setdefault(name, []).append(t)
     lines = []
@@ -477,7 +525,7 @@ def summarize_counters(fetch_dir, write_dir, run, probe_mib=256):
         for r in _csv_rows(directory, "counter_collection.csv"):
             if _field(r, "Counter_Name") != counter:
                 continue
-            name = _field(r, "Kernel_Name")
+            name = short_kernel_name(_field(r, "Kernel_Name"))
             disp = int(_field(r, "Dispatch_Id"))
             if disp not in vals.setdefault(name, {}):
                 vals[name][disp] = 0.0
@@ -533,6 +581,16 @@ class Stencils:
         key = (w.name, w.n)
         if key not in self._memo:
             self._memo[key] = oracle.ring1(w.dim, w.n, w.cells)
+        return self._memo[key]
+
+    def axis(self, w):
+        """The oracle's fixed-width axis list (a Stencil of 2*dim slots per point)."""
+        import numpy as np
+
+        import oracle
+        key = ("axis", w.name, w.n)
+        if key not in self._memo:
+            self._memo[key] = oracle.axis(w.dim, w.coords.astype(np.float64), self.get(w))
         return self._memo[key]
 
 
@@ -608,9 +666,7 @@ def error_vs_oracle(stencils, w, got, sel=None, stencil="ring1"):
     import numpy as np
 
     import oracle
-    st = stencils.get(w)
-    if stencil == "axis":
-        st = oracle.axis(w.dim, w.coords.astype(np.float64), st)
+    st = stencils.axis(w) if stencil == "axis" else stencils.get(w)
     ref, gap, _ = oracle.ftle(w.dim, w.coords.astype(np.float64), w.flow_numpy().astype(np.float64), st, w.T,
                               sel=sel, diagnostics=True)
     g = np.asarray(got, dtype=np.float64)
@@ -774,7 +830,7 @@ def main():
         del src, dst
 
     # ---- headline: 2D forward at 2048^2 ------------------------------------
-    w2 = loads.get("scale_2d") if (headline or any(g in groups for g in ("f16", "fp64", "axis", "neighbours",
+    w2 = loads.get("scale_2d") if (headline or any(g in groups for g in ("f16", "fp64", "axis", "ell", "neighbours",
                                                                           "advect"))) else None
     copy_gbps = None
     if headline:
@@ -976,6 +1032,40 @@ def main():
             log(f"{name}: {t * 1e3:.2f} us/step")
             keep[name] = (wa, oa[0].cpu().numpy())
             del fns, ma, fa, oa
+    if want("ell"):
+        # the paper's fixed-width list itself (2*dim int32 per point, -1 where
+        # absent, no row pointers, caller order), built on the GPU from the
+        # device one-ring stencil, and the forward that streams it: direct
+        # gathers (the paper's layout without reuse) and LDS-staged blocks
+        for dim, name in ((2, "ell_2d_2048"), (3, "ell_3d_160")):
+            we = w2 if dim == 2 else loads.get("abc_3d")
+            log(f"{name}: the axis list on the GPU")
+            xs, fs, ls, os_ = [], [], [], []
+            for _ in range(R):
+                cells_d = torch.as_tensor(we.cells, dtype=torch.int32, device=dev).contiguous()
+                rp, col = F.ring1_csr(dim, we.n, cells_d)
+                x_d = torch.as_tensor(we.coords, device=dev).contiguous()
+                ls.append(F.axis_ell(x_d, rp, col))
+                xs.append(x_d)
+                fs.append(we.flow.to(dev).clone().contiguous())
+                os_.append(torch.empty(we.n, dtype=torch.float32, device=dev))
+                del cells_d, rp, col
+            Be = alg_bytes_ell(we.n, dim)
+            for staged in (False, True):
+                fns = [lambda k=k: F.forward_ell(xs[k], ls[k], fs[k], we.T, staged=staged, out=os_[k])
+                       for k in range(R)]
+                t = time_steps(fns, steps_v, args.warmup, torch)
+                key = f"{name}_{'staged' if staged else 'direct'}"
+                variants[key] = {
+                    "workload": f"{dim}D FTLE forward from the paper's fixed-width axis list (2*dim int32 per point, "
+                                f"-1 where absent, caller order) on the {'2048^2' if dim == 2 else '160^3'} workload, "
+                                + ("each workgroup's 256 points staged in LDS" if staged else "direct gathers"),
+                    "points": we.n, "ms_per_step": round(t, 5), "points_per_s": round(we.n / (t * 1e-3), 1),
+                    "roofline": hbm_roofline(Be, t, "main", [f"ell_kernel<{dim}, float, {str(staged).lower()}, 256>"],
+                                             traffic, traced, {"alg_model": "paper's fixed-width list"})}
+                log(f"{key}: {t * 1e3:.2f} us/step")
+                keep[key] = (we, os_[0].cpu().numpy(), ls[0].cpu().numpy())
+            del fns, xs, fs, ls, os_
     if want("neighbours"):
         # the one-ring stencil built on the GPU from the cells (edge pairs,
         # radix sort, deduplication, CSR), each call allocating its sort
@@ -1096,6 +1186,13 @@ def main():
             ref = oracle_advect(x0[sel].astype(np.float64), 0.0, wa.T, "abc", 0.02)
             err["advect_3d_160_sample"] = {"points": int(sel.size),
                                            "max_abs_err": float(np.abs(phi[sel].astype(np.float64) - ref).max())}
+        for key in ("ell_2d_2048_direct", "ell_2d_2048_staged", "ell_3d_160_direct", "ell_3d_160_staged"):
+            if key in keep:
+                we, got, lst = keep[key]
+                sel = None if we.dim == 2 else np.sort(rng.choice(we.n, 200000, replace=False))
+                e = error_vs_oracle(stencils, we, got, sel=sel, stencil="axis")
+                e["list_equals_oracle"] = bool(np.array_equal(lst.ravel(), stencils.axis(we).col))
+                err[key] = e
         if "axis_2d_2048" in keep:
             wa, got = keep["axis_2d_2048"]
             err["axis_2d_2048"] = error_vs_oracle(stencils, wa, got, stencil="axis")

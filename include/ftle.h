@@ -269,6 +269,45 @@ ftle_status ftle_forward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, d
                          void* out, ftle_stream_t stream);
 
 /*
+ * The paper's own neighbour list (Section 2.2; Table 1's 128 / 192 index bits
+ * per point) as the kernel's input, with no mesh object: per point exactly
+ * 2*dim int32 indices, one per signed axis direction in the order -x, +x,
+ * -y, +y (2D), then -z, +z (3D), -1 where a side has no neighbour, row-major
+ * n_points x 2*dim in the caller's point order, no row pointers.
+ * ftle_axis_ell builds the list on the device from a one-ring stencil: for
+ * each side, among the stencil's neighbours j with s (x_j - x_i)_d > 0, the
+ * one with the largest cosine s (x_j - x_i)_d / |x_j - x_i|, ties to the
+ * smaller index (the FTLE_STENCIL_AXIS stencil as a fixed-width list), in
+ * float64.
+ *   coords    device, n_points x dim of dtype
+ *   row_ptr   device, n_points+1 int64; col device int32 (as ftle_ring1_csr
+ *             writes them; rows in any order; entries outside [0, n_points)
+ *             and i itself are skipped)
+ *   ell       device, n_points x 2*dim int32, caller-owned, overwritten;
+ *             16-byte aligned in 2D, 8-byte aligned in 3D
+ * ftle_forward_ell computes FTLE from such a list, one lane per point, in the
+ * caller's point order (no reordering, no tiles): least squares over the
+ * present slots, C = J^T J, its largest eigenvalue, ln sqrt(lambda) / |T|.
+ *   coords, ell  as above (entries outside [0, n_points) and i itself are
+ *             treated as absent)
+ *   flow      device, n_points x dim of dtype; out device, n_points of dtype
+ *   flags     FTLE_ELL_DIRECT: every neighbour gathered from global memory
+ *             (the paper's layout without reuse); FTLE_ELL_STAGED: each
+ *             workgroup's block of 256 consecutive points staged in LDS first,
+ *             neighbours inside the block read there
+ * Points with fewer than dim usable neighbours, or neighbours that do not
+ * span the space, get NaN; the 3D float32 eigenvalue takes the float64
+ * recompute as ftle_forward does (not counted).
+ * Errors: INVALID_ARG (dim, dtype, n_points < 0, NULL pointer, T, flag,
+ * alignment), UNSUPPORTED (n_points > 2^31-1), DEVICE.
+ */
+enum { FTLE_ELL_DIRECT = 0, FTLE_ELL_STAGED = 1 };
+ftle_status ftle_axis_ell(int dim, int64_t n_points, const void* coords, ftle_dtype dtype, const int64_t* row_ptr,
+                          const int32_t* col, int32_t* ell, ftle_stream_t stream);
+ftle_status ftle_forward_ell(int dim, int64_t n_points, const void* coords, ftle_dtype dtype, const int32_t* ell,
+                             const void* flow, double T, void* out, unsigned flags, ftle_stream_t stream);
+
+/*
  * Half-precision flow-map storage, 2D float32 meshes (the precision-for-
  * bandwidth trade Section 1.1 allows: 4 bytes of flow map per point, not 8).
  * The flow map is held as the displacement d = phi - x of each point,

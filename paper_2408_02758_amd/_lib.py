@@ -18,6 +18,7 @@ F32, F64 = 0, 1
 STENCIL_RING1, STENCIL_AXIS = 0, 1
 NO_REORDER = 1 << 4
 HOST_ONLY = 1 << 5
+ELL_DIRECT, ELL_STAGED = 0, 1
 
 
 def tile_flag(k: int) -> int:
@@ -39,6 +40,8 @@ SIGNATURES = {
     "ftle_create_mesh": (_int, [_int, _i64, _vp, _int, _i64, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_create_mesh_from_csr": (_int, [_int, _i64, _vp, _int, _vp, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_ring1_csr": (_int, [_int, _i64, _i64, _vp, _vp, _vp, _i64, _P(_i64), _vp]),
+    "ftle_axis_ell": (_int, [_int, _i64, _vp, _int, _vp, _vp, _vp, _vp]),
+    "ftle_forward_ell": (_int, [_int, _i64, _vp, _int, _vp, _vp, _dbl, _vp, ctypes.c_uint, _vp]),
     "ftle_encode_flow_f16": (_int, [_vp, _vp, _vp, _vp]),
     "ftle_forward_f16": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),
     "ftle_advect_rk4": (_int, [_int, _vp, _i64, _vp, _int, _vp, _vp, ctypes.c_double, ctypes.c_double,

@@ -449,6 +449,52 @@ def ring1_csr(dim: int, n_points: int, cells: torch.Tensor, stream=None):
     return row_ptr, col[:nnz.value]
 
 
+def _device_points(t: torch.Tensor, name: str, n: int, dim: int):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype in (torch.float32, torch.float64)
+            and tuple(t.shape) == (n, dim)):
+        raise ValueError(f"{name} must be a contiguous float32/float64 device tensor of shape ({n}, {dim})")
+
+
+def axis_ell(coords: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, stream=None) -> torch.Tensor:
+    """The paper's fixed-width list (n, 2*dim) int32 built on the GPU from a
+    one-ring stencil (ftle_axis_ell): per signed axis direction the neighbour
+    with the largest cosine, -1 where there is none."""
+    n, dim = coords.shape
+    _device_points(coords, "coords", n, dim)
+    if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.is_contiguous() and row_ptr.shape == (n + 1,)):
+        raise ValueError("row_ptr must be a contiguous int64 device tensor of n+1 entries")
+    if not (col.is_cuda and col.dtype == torch.int32 and col.is_contiguous()):
+        raise ValueError("col must be a contiguous int32 device tensor")
+    ell = torch.empty(n, 2 * dim, dtype=torch.int32, device=coords.device)
+    code = _lib.F64 if coords.dtype == torch.float64 else _lib.F32
+    check(_lib.load().ftle_axis_ell(dim, n, ctypes.c_void_p(coords.data_ptr()), code,
+                                    ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                                    ctypes.c_void_p(ell.data_ptr()), _stream_handle(stream)))
+    return ell
+
+
+def forward_ell(coords: torch.Tensor, ell: torch.Tensor, flow: torch.Tensor, T: float, staged: bool = False,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """FTLE from the paper's fixed-width list (ftle_forward_ell): coords and
+    flow (n, dim) device tensors of one dtype, ell (n, 2*dim) int32 (-1 where
+    absent).  staged: each workgroup's block of points staged in LDS."""
+    n, dim = coords.shape
+    _device_points(coords, "coords", n, dim)
+    _device_points(flow, "flow", n, dim)
+    if flow.dtype != coords.dtype:
+        raise ValueError("flow and coords must have the same dtype")
+    if not (ell.is_cuda and ell.dtype == torch.int32 and ell.is_contiguous() and tuple(ell.shape) == (n, 2 * dim)):
+        raise ValueError(f"ell must be a contiguous int32 device tensor of shape ({n}, {2 * dim})")
+    if out is None:
+        out = torch.empty(n, dtype=coords.dtype, device=coords.device)
+    code = _lib.F64 if coords.dtype == torch.float64 else _lib.F32
+    check(_lib.load().ftle_forward_ell(dim, n, ctypes.c_void_p(coords.data_ptr()), code,
+                                       ctypes.c_void_p(ell.data_ptr()), ctypes.c_void_p(flow.data_ptr()), float(T),
+                                       ctypes.c_void_p(out.data_ptr()),
+                                       _lib.ELL_STAGED if staged else _lib.ELL_DIRECT, _stream_handle(stream)))
+    return out
+
+
 def force_wide_offsets(on: bool) -> None:
     """Testing aid: make every later launch take the 64-bit offset path (see ftle_force_wide_offsets)."""
     check(_lib.load().ftle_force_wide_offsets(int(bool(on))))
@@ -480,4 +526,4 @@ def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
 
 __all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError",
            "force_wide_offsets", "set_eig_threshold", "eig_threshold", "pin_batched_config", "advect_rk4",
-           "ring1_csr"]
+           "ring1_csr", "axis_ell", "forward_ell"]

@@ -1665,6 +1665,49 @@ ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int
     });
 }
 
+ftle_status ftle_forward_ell(int dim, int64_t n_points, const void* coords, ftle_dtype dtype, const int32_t* ell,
+                             const void* flow, double T, void* out, unsigned flags, ftle_stream_t stream)
+{
+    return guarded([&] {
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        if (n_points < 0) fail(FTLE_ERR_INVALID_ARG, "n_points < 0");
+        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+        check_T(T);
+        if (flags & ~(unsigned)FTLE_ELL_STAGED) fail(FTLE_ERR_INVALID_ARG, "unknown flag");
+        if (n_points > 0 && (!coords || !ell || !flow || !out)) fail(FTLE_ERR_INVALID_ARG, "NULL pointer");
+        if (reinterpret_cast<uintptr_t>(ell) % (dim == 2 ? 16 : 8) != 0)
+            fail(FTLE_ERR_INVALID_ARG, "ell must be 16-byte (2D) or 8-byte (3D) aligned");
+        if (n_points == 0) return;
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        check_hip(launch_forward_ell(dim, dtype == FTLE_F64, (flags & FTLE_ELL_STAGED) != 0, coords, flow, ell,
+                                     n_points, 0.5 / std::fabs(T), out, eig_tau(), nullptr, 256,
+                                     static_cast<hipStream_t>(stream)),
+                  "forward (axis list) launch");
+    });
+}
+
+ftle_status ftle_axis_ell(int dim, int64_t n_points, const void* coords, ftle_dtype dtype, const int64_t* row_ptr,
+                          const int32_t* col, int32_t* ell, ftle_stream_t stream)
+{
+    return guarded([&] {
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        if (n_points < 0) fail(FTLE_ERR_INVALID_ARG, "n_points < 0");
+        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+        if (n_points > 0 && (!coords || !row_ptr || !col || !ell)) fail(FTLE_ERR_INVALID_ARG, "NULL pointer");
+        if (reinterpret_cast<uintptr_t>(ell) % (dim == 2 ? 16 : 8) != 0)
+            fail(FTLE_ERR_INVALID_ARG, "ell must be 16-byte (2D) or 8-byte (3D) aligned");
+        if (n_points == 0) return;
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        check_hip(launch_axis_ell(dim, dtype == FTLE_F64, coords, row_ptr, col, n_points, ell,
+                                  static_cast<hipStream_t>(stream)),
+                  "axis list launch");
+    });
+}
+
 ftle_status ftle_batched_pin_config(int block, int tiles_per_pop, int per_cu_cap)
 {
     return guarded([&] {

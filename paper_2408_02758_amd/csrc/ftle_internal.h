@@ -193,6 +193,15 @@ hipError_t sort_and_mark_keys(uint64_t* keys, uint64_t* sorted, int64_t n_edges,
 hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t n_edges,
                                 int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t stream);
 
+// The paper's fixed-width axis list (ftle_ell.hip): the forward from it (one
+// lane per caller point; staged: each workgroup's block of points in LDS),
+// and its construction from a one-ring CSR.
+hipError_t launch_forward_ell(int dim, bool f64, bool staged, const void* x, const void* flow, const int32_t* ell,
+                              int64_t n, double inv2T, void* out, double eig_tau, unsigned long long* hits,
+                              int block, hipStream_t stream);
+hipError_t launch_axis_ell(int dim, bool f64, const void* x, const int64_t* row_ptr, const int32_t* col, int64_t n,
+                           int32_t* ell, hipStream_t stream);
+
 // The allocation-free adjoint (ftle_noalloc.hip): its tape lives in a fixed
 // device array of kNoAllocScratchBytes per GPU; noalloc_scratch gives that
 // array's address on `device`, which must be current.

@@ -1,4 +1,4 @@
-"""Coefficients of the float32 3x3 eigenvalue step in ftle_kernels.hip.
+"""Coefficients of the float32 3x3 eigenvalue step in ftle_device_math.h.
 
 The largest eigenvalue of a symmetric 3x3 tensor is q + 2 p c, where c is
 the largest root of 4 c^3 - 3 c = r, i.e. c = cos(acos(r) / 3) (the

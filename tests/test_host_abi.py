@@ -466,3 +466,32 @@ def test_backward_noalloc_limit_checked_first(L):
     assert b"HOST_ONLY" in L.ftle_last_error()
     assert L.ftle_backward_noalloc(h2, p, 0, 1.0, None, p, None) == INVALID
     L.ftle_destroy_mesh(h2)
+
+
+def test_axis_list_entries_validation(L):
+    """ftle_forward_ell and ftle_axis_ell reject bad arguments before any
+    device work (the pointers are never dereferenced); n_points = 0 is a no-op."""
+    INVALID, UNSUP = 1, 4
+    p = ctypes.c_void_p(256)
+    odd = ctypes.c_void_p(260)   # 4-byte aligned only
+
+    def fwd(dim=2, n=10, x=p, dt=0, ell=p, fl=p, T=1.0, out=p, flags=0):
+        return L.ftle_forward_ell(dim, n, x, dt, ell, fl, T, out, flags, None)
+
+    assert fwd(dim=1) == INVALID and fwd(dim=4) == INVALID and fwd(dt=2) == INVALID
+    assert fwd(n=-1) == INVALID and fwd(n=1 << 31) == UNSUP
+    for T in (0.0, float("nan"), float("inf")):
+        assert fwd(T=T) == INVALID
+    assert fwd(flags=2) == INVALID
+    assert fwd(x=None) == INVALID and fwd(ell=None) == INVALID and fwd(fl=None) == INVALID and fwd(out=None) == INVALID
+    assert fwd(ell=odd) == INVALID and fwd(dim=3, ell=odd) == INVALID
+    assert b"aligned" in L.ftle_last_error()
+    assert fwd(n=0, x=None, ell=None, fl=None, out=None) == 0
+
+    def ax(dim=2, n=10, x=p, dt=0, rp=p, col=p, ell=p):
+        return L.ftle_axis_ell(dim, n, x, dt, rp, col, ell, None)
+
+    assert ax(dim=5) == INVALID and ax(dt=3) == INVALID and ax(n=-2) == INVALID and ax(n=1 << 31) == UNSUP
+    assert ax(x=None) == INVALID and ax(rp=None) == INVALID and ax(col=None) == INVALID and ax(ell=None) == INVALID
+    assert ax(ell=odd) == INVALID
+    assert ax(n=0, x=None, rp=None, col=None, ell=None) == 0
