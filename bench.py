@@ -68,21 +68,21 @@ GROUP_WORKLOADS = {"headline": ["scale_2d"], "f16": ["scale_2d"], "fp64": ["scal
 # The commands that made the summaries under profiles/ (run from the
 # repository root; the first fills the workload cache without a profiler).
 PROFILE_RECIPE = [
-    "python -u bench.py --fill-cache --cache gpurun_out/wc",
+    "python -u bench.py --fill-cache --cache /tmp/ftle_wc",
     # kernel durations: the ring-1 rows, then the axis rows (same kernel names)
     "timeout -k 10 600 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_main -o kt --output-format csv -- "
-    "python -u bench.py --require-cache --cache gpurun_out/wc --steps 30 --no-cpu-baseline --no-sustained "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 30 --no-cpu-baseline --no-sustained "
     "--batched-shape 256,0,0 --only f16,fp64,fwd3d,fwdbwd,batched,ell",
     "timeout -k 10 600 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_axis -o kt --output-format csv -- "
-    "python -u bench.py --require-cache --cache gpurun_out/wc --steps 30 --no-cpu-baseline --no-sustained "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 30 --no-cpu-baseline --no-sustained "
     "--no-headline --only axis",
     # HBM traffic: one counter per run (FETCH_SIZE, then WRITE_SIZE), each run
     # starting with a 256 MiB copy whose counts calibrate the counters
     "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_main -o pmc --output-format csv -- "
-    "python -u bench.py --require-cache --cache gpurun_out/wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
     "--no-sustained --batched-shape 256,0,0 --copy-probe-mib 256 --only f16,fp64,fwd3d,fwdbwd,batched,ell",
     "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_axis -o pmc --output-format csv -- "
-    "python -u bench.py --require-cache --cache gpurun_out/wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
     "--no-sustained --no-headline --copy-probe-mib 256 --only axis",
 ]
 
@@ -556,6 +556,33 @@ def summarize_counters(fetch_dir, write_dir, run, probe_mib=256):
     return lines
 
 
+PROFILE_BATCHED_SHAPE = "256,0,0"
+
+
+def profile_header(kind):
+    """Header of a committed profile summary: what it holds, the commands that
+    made it (PROFILE_RECIPE, then the summarizer), the hash of the kernel
+    sources it was taken from and the batched launch shape pinned in it."""
+    if kind == "trace":
+        title = "rocprofv3 --kernel-trace: per-kernel durations (us) of the FTLE kernels, one MI355X (gfx950)"
+        cmds = PROFILE_RECIPE[:3] + ["python bench.py --profile-header trace",
+                                    "python bench.py --summarize-trace gpurun_out/kt_main main",
+                                    "python bench.py --summarize-trace gpurun_out/kt_axis axis"]
+    else:
+        title = ("rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE: HBM KiB per dispatch of the FTLE kernels, one MI355X "
+                 "(gfx950); each counter scaled by the factor that makes a 256 MiB copy (torch.neg) read its size")
+        cmds = [PROFILE_RECIPE[0]] + [c.replace("{counter}", k) for c in PROFILE_RECIPE[3:]
+                                      for k in ("FETCH_SIZE", "WRITE_SIZE")]
+        cmds += ["python bench.py --profile-header counters",
+                 "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_main gpurun_out/pmc_WRITE_SIZE_main main",
+                 "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_axis gpurun_out/pmc_WRITE_SIZE_axis axis"]
+    lines = [f"# {title}", "# commands, from the repository root:"] + [f"#   {c}" for c in cmds]
+    lines += ["# run 'main': the ring-1, float64, binary16, forward+adjoint, batched and axis-list rows; run 'axis': "
+              "the axis-stencil rows (same kernel names as the ring-1 ones)",
+              f"kernel_sources_sha256 = {kernel_sources_sha256()}", f"batched_shape = {PROFILE_BATCHED_SHAPE}"]
+    return "\n".join(lines)
+
+
 # ---------------------------------------------------------------------------
 # the FP64 oracle on the host: baseline timings and the error of the GPU fields
 # ---------------------------------------------------------------------------
@@ -766,6 +793,8 @@ def main():
                     help="print the kernel-trace summary lines of rocprofv3 CSV output in DIR and exit")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "RUN"),
                     help="print the FETCH_SIZE / WRITE_SIZE summary lines of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--profile-header", choices=("trace", "counters"),
+                    help="print the header of a profile summary (commands, source hash) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the FTLE hot path is "
@@ -777,6 +806,9 @@ def main():
         return
     if args.summarize_counters:
         print("\n".join(summarize_counters(*args.summarize_counters)))
+        return
+    if args.profile_header:
+        print(profile_header(args.profile_header))
         return
 
     only = [g for g in args.only.split(",") if g]

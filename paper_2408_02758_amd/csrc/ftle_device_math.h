@@ -1,8 +1,9 @@
-// Per-point arithmetic shared by the FTLE kernels (ftle_kernels.hip,
-// ftle_ell.hip): precision-explicit helpers, the rank threshold of the
-// least-squares solve, and the closed-form largest eigenvalue of a symmetric
-// 3x3 tensor with its float64 recompute.  Device code only; every function
-// has internal linkage, so each translation unit has its own copy.
+// Device helpers shared by the FTLE kernels (ftle_kernels.hip, ftle_ell.hip):
+// the XCD-aware workgroup order, precision-explicit arithmetic, the rank
+// threshold of the least-squares solve, and the closed-form largest
+// eigenvalue of a symmetric 3x3 tensor with its float64 recompute.  Device
+// code only; every function has internal linkage, so each translation unit
+// has its own copy.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,6 +12,17 @@
 
 namespace ftle {
 namespace {
+
+// Workgroup id -> tile.  The hardware deals consecutive ids round-robin to
+// the 8 XCDs; this gives XCD x the contiguous tile range
+// [x*q + min(x, r), ...) with q = n / 8, r = n % 8 (a bijection on [0, n)).
+__device__ inline int xcd_tile(int bid, int n)
+{
+    constexpr int kXcd = 8;
+    const int x = bid % kXcd, s = bid / kXcd;
+    const int q = n / kXcd, r = n % kXcd;
+    return x * q + min(x, r) + s;
+}
 
 // Precision-explicit math (no silent promotion of float code to double).
 // The float versions use the hardware reciprocal, square root and base-2

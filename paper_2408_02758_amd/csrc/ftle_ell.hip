@@ -124,10 +124,16 @@ __device__ inline T ell_epilogue3(const T (&m)[6], const T (&b)[9], T inv2T, flo
     return ok ? log_scaled(lam, inv2T) : quiet_nan<T>();
 }
 
-// One lane per caller point i.  STAGED: the workgroup's block [b0, b0 + B)
-// of points is first copied to LDS (x then phi, D values each) and neighbours
-// inside it are read there.  Slots outside [0, n) (the list's -1) and the
-// point itself are skipped.
+// One lane per caller point.  Workgroups take blocks of B consecutive
+// points, XCD by XCD in contiguous ranges (xcd_tile), so that a point's
+// neighbours in the caller's numbering (the next grid line or plane) are
+// mostly in the same XCD's L2.  Slots outside [0, n) (the list's -1) and the
+// point itself are replaced by the point itself, whose differences are exact
+// zeros: every lane issues all its loads at once, with no branch between
+// them.  STAGED: the block's points are first copied to LDS (x then phi, D
+// values each) and a neighbour inside the block is read there (the global
+// load then reads the lane's own point, already in cache).  (Two or four
+// points per lane, to keep more loads in flight, measured no faster.)
 template <int D, typename T, bool STAGED, int B>
 __global__ void __launch_bounds__(B) ell_kernel(const T* __restrict__ x, const T* __restrict__ flow,
                                                   const int32_t* __restrict__ ell, int64_t n, T inv2T,
@@ -137,7 +143,7 @@ __global__ void __launch_bounds__(B) ell_kernel(const T* __restrict__ x, const T
     T* sx = reinterpret_cast<T*>(ell_lds);   // STAGED: [B][D] coordinates, then [B][D] flow map
     T* sf = sx + B * D;
     const int tid = (int)threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * B;
+    const int64_t b0 = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * B;
     const int64_t i = b0 + tid;
     if constexpr (STAGED) {
         // coalesced copy of the block's coordinates and flow map
@@ -149,36 +155,36 @@ __global__ void __launch_bounds__(B) ell_kernel(const T* __restrict__ x, const T
         __syncthreads();
     }
     if (i >= n) return;
-    auto point = [&](int64_t j, Pt<D, T>& pj, Pt<D, T>& fj) {
-        if constexpr (STAGED) {
-            const uint64_t o = (uint64_t)(j - b0);
-            if (o < (uint64_t)B) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    pj.v[d] = sx[o * D + d];
-                    fj.v[d] = sf[o * D + d];
-                }
-                return;
-            }
-        }
-        pj = load_pt<D, T>(x, j);
-        fj = load_pt<D, T>(flow, j);
-    };
-    Pt<D, T> xi, fi;
-    point(i, xi, fi);
+    const Pt<D, T> xi = load_pt<D, T>(x, i), fi = load_pt<D, T>(flow, i);
     int32_t s[2 * D];
     load_slots<D>(ell, i, s);
+    Pt<D, T> xj[2 * D], fj[2 * D];
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        const int64_t j = ((uint64_t)(int64_t)s[k] < (uint64_t)n) ? (int64_t)s[k] : i;
+        if constexpr (STAGED) {
+            const uint64_t o = (uint64_t)(j - b0);
+            const bool in = o < (uint64_t)B;
+            const int64_t g = in ? i : j;
+            const uint32_t l = in ? (uint32_t)o : (uint32_t)tid;
+            const Pt<D, T> xg = load_pt<D, T>(x, g), fg = load_pt<D, T>(flow, g);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                xj[k].v[d] = in ? sx[l * D + d] : xg.v[d];
+                fj[k].v[d] = in ? sf[l * D + d] : fg.v[d];
+            }
+        } else {
+            xj[k] = load_pt<D, T>(x, j);
+            fj[k] = load_pt<D, T>(flow, j);
+        }
+    }
     T f;
     if constexpr (D == 2) {
         T m00 = 0, m01 = 0, m11 = 0, b00 = 0, b01 = 0, b10 = 0, b11 = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int64_t j = s[k];
-            if ((uint64_t)j >= (uint64_t)n || j == i) continue;
-            Pt<2, T> xj, fj;
-            point(j, xj, fj);
-            const T dx0 = xj.v[0] - xi.v[0], dx1 = xj.v[1] - xi.v[1];
-            const T df0 = fj.v[0] - fi.v[0], df1 = fj.v[1] - fi.v[1];
+            const T dx0 = xj[k].v[0] - xi.v[0], dx1 = xj[k].v[1] - xi.v[1];
+            const T df0 = fj[k].v[0] - fi.v[0], df1 = fj[k].v[1] - fi.v[1];
             m00 = dfma(dx0, dx0, m00);
             m01 = dfma(dx0, dx1, m01);
             m11 = dfma(dx1, dx1, m11);
@@ -193,15 +199,11 @@ __global__ void __launch_bounds__(B) ell_kernel(const T* __restrict__ x, const T
         T b[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const int64_t j = s[k];
-            if ((uint64_t)j >= (uint64_t)n || j == i) continue;
-            Pt<3, T> xj, fj;
-            point(j, xj, fj);
             T dx[3], df[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                dx[d] = xj.v[d] - xi.v[d];
-                df[d] = fj.v[d] - fi.v[d];
+                dx[d] = xj[k].v[d] - xi.v[d];
+                df[d] = fj[k].v[d] - fi.v[d];
             }
             m[0] = dfma(dx[0], dx[0], m[0]);
             m[1] = dfma(dx[0], dx[1], m[1]);
@@ -278,10 +280,11 @@ __global__ void __launch_bounds__(256) axis_ell_kernel(const T* __restrict__ x, 
     }
 }
 
-template <int D, typename T, int B>
-hipError_t ell_launch_b(bool staged, const void* x, const void* flow, const int32_t* ell, int64_t n, double inv2T,
-                        void* out, double eig_tau, unsigned long long* hits, hipStream_t stream)
+template <int D, typename T>
+hipError_t ell_launch(bool staged, const void* x, const void* flow, const int32_t* ell, int64_t n, double inv2T,
+                      void* out, double eig_tau, unsigned long long* hits, hipStream_t stream)
 {
+    constexpr int B = 256;
     const dim3 grid((unsigned)((n + B - 1) / B)), blk(B);
     const T* xp = static_cast<const T*>(x);
     const T* fp = static_cast<const T*>(flow);
@@ -295,29 +298,18 @@ hipError_t ell_launch_b(bool staged, const void* x, const void* flow, const int3
     return hipGetLastError();
 }
 
-template <int D, typename T>
-hipError_t ell_launch(bool staged, const void* x, const void* flow, const int32_t* ell, int64_t n, double inv2T,
-                      void* out, double eig_tau, unsigned long long* hits, int block, hipStream_t stream)
-{
-    switch (block) {
-    case 128: return ell_launch_b<D, T, 128>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream);
-    case 512: return ell_launch_b<D, T, 512>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream);
-    default: return ell_launch_b<D, T, 256>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream);
-    }
-}
-
 }  // namespace
 
 hipError_t launch_forward_ell(int dim, bool f64, bool staged, const void* x, const void* flow, const int32_t* ell,
                               int64_t n, double inv2T, void* out, double eig_tau, unsigned long long* hits,
-                              int block, hipStream_t stream)
+                              hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
     if (dim == 2)
-        return f64 ? ell_launch<2, double>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, block, stream)
-                   : ell_launch<2, float>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, block, stream);
-    return f64 ? ell_launch<3, double>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, block, stream)
-               : ell_launch<3, float>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, block, stream);
+        return f64 ? ell_launch<2, double>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream)
+                   : ell_launch<2, float>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream);
+    return f64 ? ell_launch<3, double>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream)
+               : ell_launch<3, float>(staged, x, flow, ell, n, inv2T, out, eig_tau, hits, stream);
 }
 
 hipError_t launch_axis_ell(int dim, bool f64, const void* x, const int64_t* row_ptr, const int32_t* col, int64_t n,

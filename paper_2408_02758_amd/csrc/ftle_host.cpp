@@ -1682,7 +1682,7 @@ ftle_status ftle_forward_ell(int dim, int64_t n_points, const void* coords, ftle
         int dev = 0;
         check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
         check_hip(launch_forward_ell(dim, dtype == FTLE_F64, (flags & FTLE_ELL_STAGED) != 0, coords, flow, ell,
-                                     n_points, 0.5 / std::fabs(T), out, eig_tau(), nullptr, 256,
+                                     n_points, 0.5 / std::fabs(T), out, eig_tau(), nullptr,
                                      static_cast<hipStream_t>(stream)),
                   "forward (axis list) launch");
     });

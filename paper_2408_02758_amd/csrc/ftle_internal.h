@@ -198,7 +198,7 @@ hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, co
 // and its construction from a one-ring CSR.
 hipError_t launch_forward_ell(int dim, bool f64, bool staged, const void* x, const void* flow, const int32_t* ell,
                               int64_t n, double inv2T, void* out, double eig_tau, unsigned long long* hits,
-                              int block, hipStream_t stream);
+                              hipStream_t stream);
 hipError_t launch_axis_ell(int dim, bool f64, const void* x, const int64_t* row_ptr, const int32_t* col, int64_t n,
                            int32_t* ell, hipStream_t stream);
 

@@ -93,17 +93,6 @@ template <typename T> struct LdsIo<HIP_vector_type<T, 4>> {
 template <typename V> __device__ inline V lds_ld(uint32_t a) { return LdsIo<V>::ld(a); }
 template <typename V> __device__ inline void lds_st(uint32_t a, const V v) { LdsIo<V>::st(a, v); }
 
-// Workgroup id -> tile.  The hardware deals consecutive ids round-robin to
-// the 8 XCDs; this gives XCD x the contiguous tile range
-// [x*q + min(x, r), ...) with q = n / 8, r = n % 8 (a bijection on [0, n)).
-__device__ inline int xcd_tile(int bid, int n)
-{
-    constexpr int kXcd = 8;
-    const int x = bid % kXcd, s = bid / kXcd;
-    const int q = n / kXcd, r = n % kXcd;
-    return x * q + min(x, r) + s;
-}
-
 // ---------------------------------------------------------------------------
 // Staged points in LDS, from the launch's base address lds0; staged slot l
 // (l is the stencil's local index), e = sizeof(T):
