@@ -999,22 +999,6 @@ def main():
             "roofline": rld}
         log(f"fwd+bwd: {t * 1e3:.2f} us/step")
         keep["fwdbwd"] = (wd, outd[0].cpu().numpy(), gw.cpu().numpy(), gradd[0].cpu().numpy())
-        # the same outputs from one persistent launch (the loss weights known up front)
-        fns = [lambda k=k: msd[k].forward_backward(fld[k], wd.T, gw, out=outd[k], grad_flow=gradd[k])
-               for k in range(R)]
-        t = time_steps(fns, steps_v, args.warmup, torch)
-        info = msd[0].fused_info()
-        rlf = hbm_roofline(Bd, t, "main", [f"fused_kernel<3, float, {fb}>"], traffic, traced)
-        if not args.no_sustained:
-            log("timing fused forward+adjoint, sustained")
-            rlf["sustained"] = sustained(fns, torch, Bd, clock)
-        variants["fwd_bwd_3d_96_fused"] = {
-            "workload": "the same forward + adjoint in one persistent launch (ftle_forward_backward: forward tiles "
-                        "publish their tape per tile, adjoint tiles wait for the tiles they stage)",
-            "points": wd.n, "nnz": nnzd, "ms_per_step": round(t, 5), "points_per_s": round(wd.n / (t * 1e-3), 1),
-            "launch": info, "roofline": rlf}
-        log(f"fused fwd+bwd: {t * 1e3:.2f} us/step ({info})")
-        keep["fwdbwd_fused"] = (wd, outd[0].cpu().numpy(), gw.cpu().numpy(), gradd[0].cpu().numpy())
         del fns, msd, fld, outd, taped, gradd
     if want("batched"):
         wb = loads.get("batched_2d")
@@ -1210,10 +1194,6 @@ def main():
             wd, outd0, g0, grad0 = keep["fwdbwd"]
             err["fwd_bwd_96"] = {"ftle": error_vs_oracle(stencils, wd, outd0),
                                  "grad": grad_error_vs_oracle(stencils, wd, g0, grad0)}
-        if "fwdbwd_fused" in keep:
-            wd, outd0, g0, grad0 = keep["fwdbwd_fused"]
-            err["fwd_bwd_96_fused"] = {"ftle": error_vs_oracle(stencils, wd, outd0),
-                                       "grad": grad_error_vs_oracle(stencils, wd, g0, grad0)}
         if "batched" in keep:
             err["batched_48"] = {w.name: error_vs_oracle(stencils, w, got) for w, got in keep["batched"]}
         if "fp64" in keep:

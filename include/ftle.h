@@ -371,37 +371,6 @@ ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, 
                           const void* grad_ftle, void* grad_flow, ftle_stream_t stream);
 
 /*
- * FTLE and its adjoint together, for a loss whose derivative in the FTLE is
- * known before the forward pass (L = sum_i g_i FTLE_i with fixed weights g):
- * out as ftle_forward's and grad_flow as ftle_backward's, bit for bit equal
- * to ftle_forward_tape followed by ftle_backward_tape.  For a symmetric
- * stencil (RING1, AXIS from cells) it is one persistent launch: forward tiles
- * write FTLE and the tape and publish it per tile; adjoint tiles wait only
- * for the forward tiles that own the points they stage, so the adjoint of
- * the first tiles runs while the last forward tiles finish.  Otherwise (or
- * when 64-bit offsets are needed) two launches.  The tape lives in the
- * mesh's adjoint workspace, shared with ftle_backward (calls on one mesh are
- * ordered on the device).
- *   flow, dtype, T     as ftle_forward
- *   grad_ftle          device, n_points of dtype: g
- *   out                device, n_points of dtype: FTLE, overwritten
- *   grad_flow          device, n_points x dim of dtype: dL/dphi, overwritten
- * Errors: as ftle_forward and ftle_backward.
- */
-ftle_status ftle_forward_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
-                                  const void* grad_ftle, void* out, void* grad_flow, ftle_stream_t stream);
-
-/*
- * The launch form of ftle_forward_backward on this mesh: one_launch 1 when it
- * is the persistent single launch; grid its workgroups (0 before the first
- * call); late_waits the number of dependency waits that ran out of their
- * bound since the mesh was created (0 unless something is wrong; the
- * outputs of such a launch are not to be trusted; synchronises the device).
- * Any output pointer may be NULL.
- */
-ftle_status ftle_mesh_fused_info(ftle_mesh_t mesh, int* one_launch, int* grid, int64_t* late_waits);
-
-/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): ftle_backward
  * with its tape in a fixed 128 MiB device array that the library holds on

@@ -59,8 +59,6 @@ SIGNATURES = {
     "ftle_backward_tape": (_int, [_vp, _vp, _int, _vp, _vp, _vp]),
     "ftle_backward": (_int, [_vp, _vp, _int, _dbl, _vp, _vp, _vp]),
     "ftle_backward_noalloc": (_int, [_vp, _vp, _int, _dbl, _vp, _vp, _vp]),
-    "ftle_forward_backward": (_int, [_vp, _vp, _int, _dbl, _vp, _vp, _vp, _vp]),
-    "ftle_mesh_fused_info": (_int, [_vp, _P(_int), _P(_int), _P(_i64)]),
     "ftle_batched": (_int, [_int, _vp, _vp, _vp, _vp, _int, _vp]),
     "ftle_batched_config": (_int, [_int, _vp, _P(_int), _P(_int), _P(_int)]),
     "ftle_mesh_fp64_hits": (_int, [_vp, _P(_i64), _int]),

@@ -299,29 +299,6 @@ class Mesh:
                                         ctypes.c_void_p(grad_flow.data_ptr()), _stream_handle(stream)))
         return grad_flow
 
-    def forward_backward(self, flow: torch.Tensor, T: float, grad_ftle: torch.Tensor, out=None, grad_flow=None,
-                         stream=None):
-        """FTLE and dL/dflow for L = sum_i g_i FTLE_i with g known up front
-        (ftle_forward_backward: one persistent launch for symmetric stencils)."""
-        self._check_flow(flow)
-        self._check_flow(grad_ftle, "grad_ftle", (self.n,))
-        if out is None:
-            out = torch.empty(self.n, dtype=self.torch_dtype, device=flow.device)
-        if grad_flow is None:
-            grad_flow = torch.empty(self.n, self.dim, dtype=self.torch_dtype, device=flow.device)
-        self._check_flow(out, "out", (self.n,))
-        self._check_flow(grad_flow, "grad_flow")
-        check(_lib.load().ftle_forward_backward(self._h, ctypes.c_void_p(flow.data_ptr()), self._code, float(T),
-                                                ctypes.c_void_p(grad_ftle.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                                ctypes.c_void_p(grad_flow.data_ptr()), _stream_handle(stream)))
-        return out, grad_flow
-
-    def fused_info(self):
-        """{'one_launch', 'grid', 'late_waits'} of ftle_forward_backward on this mesh."""
-        one, grid, late = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
-        check(_lib.load().ftle_mesh_fused_info(self._h, ctypes.byref(one), ctypes.byref(grid), ctypes.byref(late)))
-        return {"one_launch": bool(one.value), "grid": grid.value, "late_waits": late.value}
-
     def backward_noalloc(self, flow: torch.Tensor, T: float, grad_ftle: torch.Tensor, grad_flow: torch.Tensor,
                          stream=None):
         """ftle_backward with its tape in the library's fixed per-GPU scratch:

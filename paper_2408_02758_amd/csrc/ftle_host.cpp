@@ -233,18 +233,6 @@ struct ftle_mesh_s {
     void* d_work = nullptr;        // adjoint workspace (tape) of ftle_backward
     hipEvent_t work_done = nullptr;
     hipStream_t work_stream = nullptr;
-    // forward+adjoint in one launch (ftle_forward_backward): built on first use
-    struct Fused {
-        bool ready = false;
-        int32_t* d_dep_ptr = nullptr;   // per tile, the tiles owning the points it stages
-        int32_t* d_dep = nullptr;
-        unsigned* d_flags = nullptr;    // per tile, the epoch of the last launch that published its tape
-        unsigned* d_queue = nullptr;    // next item, finished workgroups
-        unsigned* d_err = nullptr;      // launches whose dependency wait ran out
-        unsigned epoch = 0;
-        int grid = 0;
-        size_t lds = 0;
-    } fused;
     std::mutex mu;
 
     bool f64() const { return dtype == FTLE_F64; }
@@ -676,10 +664,6 @@ void release_device(ftle_mesh_s* m)
     if (m->d_x) (void)hipFree(m->d_x);
     if (m->d_hits) (void)hipFree(m->d_hits);
     if (m->d_work) (void)hipFree(m->d_work);
-    for (void* p : {(void*)m->fused.d_dep_ptr, (void*)m->fused.d_dep, (void*)m->fused.d_flags,
-                    (void*)m->fused.d_queue, (void*)m->fused.d_err})
-        if (p) (void)hipFree(p);
-    m->fused = ftle_mesh_s::Fused{};
     if (m->work_done) (void)hipEventDestroy(m->work_done);
     m->d_x = nullptr;
     m->d_hits = nullptr;
@@ -1272,140 +1256,6 @@ ftle_status ftle_backward_noalloc(ftle_mesh_t mesh, const void* flow, ftle_dtype
         check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, tape,
                                          !mesh->symmetric, mesh->n, grad_ftle, grad_flow, mesh->bwd_block, s),
                   "adjoint launch");
-    });
-}
-
-}  // extern "C"
-
-namespace {
-
-// The dependency lists of the fused launch: tile t stages its own points and
-// their one-ring halo; each staged point's tape is written by the tile that
-// owns it (tiles are consecutive Morton ranges).
-void build_fused(ftle_mesh_t m)
-{
-    const TileSet& ts = m->fwd;
-    const int nt = (int)ts.meta.size();
-    std::vector<int64_t> begin(nt + 1, 0);
-    for (int t = 0; t < nt; ++t) begin[t + 1] = begin[t] + ts.meta[t].P;
-    if (begin[nt] != m->n) fail(FTLE_ERR_DEVICE, "internal error: tiles do not cover the mesh");
-    std::vector<int32_t> ptr(nt + 1, 0), dep;
-    std::vector<uint32_t> stamp((size_t)m->n, 0);
-    std::vector<int32_t> halo, own;
-    for (int t = 0; t < nt; ++t) {
-        tile_halo(m->csr, m->perm, begin[t], begin[t + 1], stamp, (uint32_t)(t + 1), halo);
-        own.assign(1, t);
-        for (int32_t r : halo) own.push_back((int32_t)(std::upper_bound(begin.begin(), begin.end(), (int64_t)r) -
-                                                       begin.begin() - 1));
-        std::sort(own.begin(), own.end());
-        own.erase(std::unique(own.begin(), own.end()), own.end());
-        dep.insert(dep.end(), own.begin(), own.end());
-        ptr[t + 1] = (int32_t)dep.size();
-    }
-    ftle_mesh_s::Fused& f = m->fused;
-    f.d_dep_ptr = static_cast<int32_t*>(dev_upload(ptr.data(), ptr.size() * sizeof(int32_t)));
-    f.d_dep = static_cast<int32_t*>(dev_upload(dep.data(), dep.size() * sizeof(int32_t)));
-    f.d_flags = static_cast<unsigned*>(dev_upload(nullptr, (size_t)nt * sizeof(unsigned)));
-    f.d_queue = static_cast<unsigned*>(dev_upload(nullptr, 2 * sizeof(unsigned)));
-    f.d_err = static_cast<unsigned*>(dev_upload(nullptr, sizeof(unsigned)));
-    check_hip(hipMemset(f.d_flags, 0, (size_t)nt * sizeof(unsigned)), "hipMemset");
-    check_hip(hipMemset(f.d_queue, 0, 2 * sizeof(unsigned)), "hipMemset");
-    check_hip(hipMemset(f.d_err, 0, sizeof(unsigned)), "hipMemset");
-    f.lds = fused_lds_bytes(m->dim, m->f64(), ts.dev());
-    int per_cu = 0, cus = 0;
-    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_kernel_symbol(m->dim, m->f64(), m->fwd_block),
-                                                           m->fwd_block, f.lds),
-              "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-    check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device), "hipDeviceGetAttribute");
-    f.grid = std::max(1, std::min(2 * nt, std::max(1, per_cu) * cus));
-    f.ready = true;
-}
-
-}  // namespace
-
-extern "C" {
-
-ftle_status ftle_forward_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
-                                  const void* grad_ftle, void* out, void* grad_flow, ftle_stream_t stream)
-{
-    return guarded([&] {
-        check_mesh(mesh);
-        check_dtype(mesh, dtype);
-        check_T(T);
-        if (!flow || !grad_ftle || !out || !grad_flow) fail(FTLE_ERR_INVALID_ARG, "NULL pointer argument");
-        need_device(mesh);
-        DeviceScope ds(mesh->device);
-        std::lock_guard<std::mutex> lk(mesh->mu);
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        if (!mesh->d_work) {
-            const size_t bytes = (size_t)mesh->n * (2 * mesh->dim + 1) * mesh->elem();
-            check_hip(hipMalloc(&mesh->d_work, bytes), "hipMalloc (adjoint workspace)");
-        } else if (mesh->work_stream != s) {
-            // the previous call on another stream may still use the workspace
-            check_hip(hipStreamWaitEvent(s, mesh->work_done, 0), "hipStreamWaitEvent");
-        }
-        const double inv2T = 0.5 / std::fabs(T);
-        if (!mesh->symmetric || batched_needs_wide(mesh->dim, mesh->f64(), mesh->n)) {
-            // the adjoint's tiles differ from the forward's, or 64-bit offsets: two launches
-            check_hip(launch_forward(mesh->dim, mesh->f64(), mesh->fwd.dev(), mesh->d_x, flow, inv2T, out,
-                                     mesh->d_work, !mesh->symmetric, mesh->n, eig_tau(), mesh->d_hits,
-                                     mesh->fwd_block, s),
-                      "tape forward launch");
-            check_hip(launch_backward_gather(mesh->dim, mesh->f64(), mesh->adj_tiles().dev(), mesh->d_x, mesh->d_work,
-                                             !mesh->symmetric, mesh->n, grad_ftle, grad_flow, mesh->bwd_block, s),
-                      "adjoint launch");
-        } else {
-            if (!mesh->fused.ready) build_fused(mesh);
-            ftle_mesh_s::Fused& f = mesh->fused;
-            if (++f.epoch == 0) {   // after 2^32 - 1 launches: clear the flags and start over
-                check_hip(hipMemsetAsync(f.d_flags, 0, mesh->fwd.meta.size() * sizeof(unsigned), s), "hipMemsetAsync");
-                f.epoch = 1;
-            }
-            FusedCall c{};
-            c.tiles = mesh->fwd.dev();
-            c.dep_ptr = f.d_dep_ptr;
-            c.dep = f.d_dep;
-            c.x = mesh->d_x;
-            c.flow = flow;
-            c.inv2T = inv2T;
-            c.g = grad_ftle;
-            c.out = out;
-            c.tape = mesh->d_work;
-            c.grad = grad_flow;
-            c.n = mesh->n;
-            c.eig_tau = eig_tau();
-            c.hits = mesh->d_hits;
-            c.queue = f.d_queue;
-            c.flags = f.d_flags;
-            c.epoch = f.epoch;
-            c.err = f.d_err;
-            c.grid = f.grid;
-            c.lds = f.lds;
-            check_hip(launch_fused(mesh->dim, mesh->f64(), c, mesh->fwd_block, s), "fused forward+adjoint launch");
-        }
-        check_hip(hipEventRecord(mesh->work_done, s), "hipEventRecord");
-        mesh->work_stream = s;
-    });
-}
-
-ftle_status ftle_mesh_fused_info(ftle_mesh_t mesh, int* one_launch, int* grid, int64_t* late_waits)
-{
-    return guarded([&] {
-        check_mesh(mesh);
-        need_device(mesh);
-        DeviceScope ds(mesh->device);
-        std::lock_guard<std::mutex> lk(mesh->mu);
-        const bool one = mesh->symmetric && !batched_needs_wide(mesh->dim, mesh->f64(), mesh->n);
-        if (one_launch) *one_launch = one ? 1 : 0;
-        if (grid) *grid = mesh->fused.ready ? mesh->fused.grid : 0;
-        if (late_waits) {
-            unsigned e = 0;
-            if (mesh->fused.ready) {
-                check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
-                check_hip(hipMemcpy(&e, mesh->fused.d_err, sizeof(e), hipMemcpyDeviceToHost), "hipMemcpy");
-            }
-            *late_waits = e;
-        }
     });
 }
 

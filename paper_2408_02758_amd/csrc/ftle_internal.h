@@ -160,38 +160,6 @@ hipError_t launch_forward(int dim, bool f64, const DevTiles& tiles, const void* 
                           double inv2T, void* out, void* tape, bool tape_sigma, int64_t n, double eig_tau,
                           unsigned long long* hits, int block, hipStream_t stream);
 
-// Forward and adjoint in one persistent launch (symmetric stencils only):
-// the tiles of the forward stencil, each tile's dependency list (the tiles
-// owning the points it stages, itself included; dep_ptr has n_tiles + 1
-// entries), the tape workspace, per-tile flags, the two queue counters
-// (zero before the first launch; each launch leaves them zero), the call's
-// epoch (nonzero, different from the flags' values of every earlier launch
-// that has not been cleared) and an error word (set if a wait ran out).
-struct FusedCall {
-    DevTiles tiles;
-    const int32_t* dep_ptr;
-    const int32_t* dep;
-    const void* x;
-    const void* flow;
-    double inv2T;
-    const void* g;
-    void* out;
-    void* tape;
-    void* grad;
-    int64_t n;
-    double eig_tau;
-    unsigned long long* hits;
-    unsigned* queue;
-    unsigned* flags;
-    unsigned epoch;
-    unsigned* err;
-    int grid;
-    size_t lds;
-};
-size_t fused_lds_bytes(int dim, bool f64, const DevTiles& t);
-const void* fused_kernel_symbol(int dim, bool f64, int block);
-hipError_t launch_fused(int dim, bool f64, const FusedCall& c, int block, hipStream_t stream);
-
 // Half-precision flow-map storage (2D, float32 meshes): the forward from
 // binary16 displacements d = phi - x, and the encoding of a float32 flow map.
 hipError_t launch_forward_f16(const DevTiles& tiles, const void* x, const void* delta, double inv2T, void* out,

@@ -32,7 +32,6 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
-#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -785,87 +784,6 @@ __global__ void __launch_bounds__(B) bwd_kernel(const TileMeta* __restrict__ met
 }
 
 // ---------------------------------------------------------------------------
-// Forward and adjoint in one persistent launch (symmetric stencils: the
-// adjoint's tiles are the forward's).  A resident grid drains one atomic
-// queue whose first n_tiles items are the forward tiles (FTLE and tape of the
-// tile's own points) and whose next n_tiles items are the adjoint tiles.  An
-// adjoint tile reads the tape of every point it stages, written by the
-// forward tiles that own them (its dependency list, built with the mesh):
-// each forward tile publishes its tape with a release store of the call's
-// epoch into its flag, and an adjoint tile's first wave waits for its
-// dependencies' flags and acquires before the workgroup stages the tape.
-// Every forward item precedes every adjoint item in the queue, so an adjoint
-// tile only ever waits for forward tiles that running workgroups have already
-// taken, and those wait for nothing: every wait ends.  The wait is bounded
-// anyway (kSpinLimit polls); a lane that runs out counts itself in *err and
-// goes on.  queue[0]
-// is the next item, queue[1] counts finished workgroups; the last workgroup
-// to finish zeroes both for the next launch.
-// ---------------------------------------------------------------------------
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-template <int D, typename T, int B>
-__global__ void __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (D == 3 ? 6 : 8) : 1)))
-fused_kernel(const TileMeta* __restrict__ meta, const uint4* __restrict__ rec, int n_tiles,
-             const int32_t* __restrict__ dep_ptr, const int32_t* __restrict__ dep, const T* __restrict__ x,
-             const T* __restrict__ minv, const T* __restrict__ flow, T inv2T, const T* __restrict__ g,
-             T* __restrict__ out, T* tape, T* __restrict__ grad, int64_t n, float eig_tau,
-             unsigned long long* hits, unsigned* queue, unsigned* flags, unsigned epoch, unsigned* err)
-{
-    constexpr uint32_t lds0 = kBatchedLdsHead;   // the item word sits in the first 16 bytes of LDS
-    const int tid = (int)threadIdx.x;
-    for (;;) {
-        if (tid == 0) lds_st(0u, (int)atomicAdd(&queue[0], 1u));
-        __syncthreads();
-        // workgroup-uniform: a scalar, so that the tile's metadata is one scalar load
-        const int item = __builtin_amdgcn_readfirstlane(lds_ld<int>(0u));
-        __syncthreads();
-        if (item >= 2 * n_tiles) break;
-        if (item < n_tiles) {
-            fwd_tile<D, T, true, 1, B, false>(meta[item], rec, x, minv, flow, inv2T, out, tape, n, eig_tau, hits,
-                                              lds0);
-            __syncthreads();   // every lane's tape stores come before the flag
-            if (tid == 0) __hip_atomic_store(&flags[item], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const int a = item - n_tiles;
-            if (tid < 64) {
-                const int d1 = dep_ptr[a + 1];
-                bool late = false;
-                for (int k = dep_ptr[a] + tid; k < d1; k += 64) {
-                    const unsigned* f = &flags[dep[k]];
-                    for (uint32_t spin = 0;
-                         __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch; ++spin) {
-                        if (spin >= kSpinLimit) {
-                            late = true;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                }
-                if (late) atomicAdd(err, 1u);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            __syncthreads();
-            const TileMeta m = meta[a];
-            bwd_stage_tile<D, T, B, false>(m, rec, x, tape, g, lds0, tid);
-            __builtin_amdgcn_s_waitcnt(0);   // the staging loads have landed in LDS
-            __syncthreads();
-            bwd_compute_tile<D, T, B, false, false>(m, tape, n, grad, lds0, tid);
-        }
-        __syncthreads();   // the next item reuses the LDS
-    }
-    if (tid == 0) {
-        __threadfence();
-        const unsigned done = atomicAdd(&queue[1], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(&queue[0], 0u);
-            atomicExch(&queue[1], 0u);
-            __threadfence();
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Batched forward over (mesh, tile) work items, running the same tile body as
 // fwd_kernel (results are bit-identical).  Two launch forms:
 //  - persistent (tiles_per_pop > 0): a resident grid drains an atomic queue,
@@ -1026,45 +944,6 @@ hipError_t bwd_launch(const DevTiles& tiles, const void* x, const void* tape, bo
     }
 }
 
-template <int D, typename T, int B>
-const void* fused_symbol_b()
-{
-    return reinterpret_cast<const void*>(&fused_kernel<D, T, B>);
-}
-
-template <int D, typename T>
-const void* fused_symbol(int block)
-{
-    switch (block) {
-    case 128: return fused_symbol_b<D, T, 128>();
-    case 256: return fused_symbol_b<D, T, 256>();
-    case 512: return fused_symbol_b<D, T, 512>();
-    default: return nullptr;
-    }
-}
-
-template <int D, typename T, int B>
-hipError_t fused_launch_b(const FusedCall& c, hipStream_t stream)
-{
-    hipLaunchKernelGGL((fused_kernel<D, T, B>), dim3(c.grid), dim3(B), c.lds, stream, c.tiles.meta, c.tiles.rec,
-                       c.tiles.n_tiles, c.dep_ptr, c.dep, static_cast<const T*>(c.x),
-                       static_cast<const T*>(c.tiles.minv), static_cast<const T*>(c.flow), (T)c.inv2T,
-                       static_cast<const T*>(c.g), static_cast<T*>(c.out), static_cast<T*>(c.tape),
-                       static_cast<T*>(c.grad), c.n, (float)c.eig_tau, c.hits, c.queue, c.flags, c.epoch, c.err);
-    return hipGetLastError();
-}
-
-template <int D, typename T>
-hipError_t fused_launch(const FusedCall& c, int block, hipStream_t stream)
-{
-    switch (block) {
-    case 128: return fused_launch_b<D, T, 128>(c, stream);
-    case 256: return fused_launch_b<D, T, 256>(c, stream);
-    case 512: return fused_launch_b<D, T, 512>(c, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 struct BatchArgs {
     const BatchItem* items;
     int n_items;
@@ -1190,24 +1069,6 @@ hipError_t launch_encode_f16(const void* x, const void* flow, void* delta, int64
                        static_cast<const float2*>(x), static_cast<const float2*>(flow), static_cast<__half2*>(delta),
                        n);
     return hipGetLastError();
-}
-
-size_t fused_lds_bytes(int dim, bool f64, const DevTiles& t)
-{
-    return std::max(fwd_lds_bytes(dim, f64, t), bwd_lds_bytes(dim, f64, t)) + kBatchedLdsHead;
-}
-
-const void* fused_kernel_symbol(int dim, bool f64, int block)
-{
-    if (dim == 2) return f64 ? fused_symbol<2, double>(block) : fused_symbol<2, float>(block);
-    return f64 ? fused_symbol<3, double>(block) : fused_symbol<3, float>(block);
-}
-
-hipError_t launch_fused(int dim, bool f64, const FusedCall& c, int block, hipStream_t stream)
-{
-    if (c.tiles.n_tiles == 0) return hipSuccess;
-    if (dim == 2) return f64 ? fused_launch<2, double>(c, block, stream) : fused_launch<2, float>(c, block, stream);
-    return f64 ? fused_launch<3, double>(c, block, stream) : fused_launch<3, float>(c, block, stream);
 }
 
 hipError_t launch_backward_gather(int dim, bool f64, const DevTiles& tiles, const void* x,
