@@ -495,7 +495,8 @@ def short_kernel_name(name):
     return s[start:].strip()
 
 
-FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "fused", "csr", "edges", "advect", "mark_first")
+FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "incidence", "scan_tiles", "scan_partials",
+                    "add_partials", "ring_rows", "long_rows", "advect")
 
 
 def summarize_trace(directory, run):
@@ -1099,14 +1100,17 @@ def main():
                 keep[key] = (we, os_[0].cpu().numpy(), ls[0].cpu().numpy())
             del fns, xs, fs, ls, os_
     if want("neighbours"):
-        # the one-ring stencil built on the GPU from the cells (edge pairs,
-        # radix sort, deduplication, CSR), each call allocating its sort
-        # buffers and returning the entry count to the host
+        # the one-ring stencil built on the GPU from the cells (incidence
+        # counts and lists, each point's distinct neighbours sorted in LDS,
+        # CSR), with a caller-held workspace, returning the entry count to
+        # the host
         for name, wn in (("ring1_csr_2d_2048", w2), ("ring1_csr_3d_160", loads.get("abc_3d"))):
             log(f"{name}: one-ring stencil on the GPU")
             cells_d = torch.as_tensor(wn.cells, dtype=torch.int32, device=dev).contiguous()
-            rp, col = F.ring1_csr(wn.dim, wn.n, cells_d)
-            t = time_steps([lambda: F.ring1_csr(wn.dim, wn.n, cells_d)], 5, 1, torch)
+            ws = torch.empty(F.ring1_workspace_bytes(wn.dim, wn.n, cells_d.shape[0]), dtype=torch.uint8, device=dev)
+            colbuf = torch.empty(cells_d.shape[0] * wn.dim * (wn.dim + 1), dtype=torch.int32, device=dev)
+            rp, col = F.ring1_csr(wn.dim, wn.n, cells_d, workspace=ws, col=colbuf)
+            t = time_steps([lambda: F.ring1_csr(wn.dim, wn.n, cells_d, workspace=ws, col=colbuf)], 10, 2, torch)
             Bn = 4 * cells_d.numel() + 8 * (wn.n + 1) + 4 * col.numel()
             variants[name] = {
                 "workload": f"one-ring CSR of the {'2048^2 triangle' if wn.dim == 2 else '160^3 tetrahedron'} "
@@ -1117,7 +1121,7 @@ def main():
                                  alg_model="cells read once, CSR written once")}
             log(f"{name}: {t:.2f} ms per stencil")
             keep[name] = (wn, rp.cpu().numpy(), col.cpu().numpy())
-            del cells_d, rp, col
+            del cells_d, rp, col, ws, colbuf
     if want("advect"):
         # the step before the path: the 2048^2 double-gyre flow map by RK4 on
         # the GPU (float64 arithmetic, float32 output), as the headline's

@@ -127,12 +127,13 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
  * ascending order and once each, every other point that shares a cell with
  * point i (the neighbour determination that Section 2.2 keeps off the
  * accelerator and the Conclusions name as future work; the same stencil
- * ftle_create_mesh builds on the host).  Edge
- * extraction, a radix sort and a deduplication of the (i, j) pairs, then the
- * CSR arrays.  The result feeds ftle_create_mesh_from_csr.
+ * ftle_create_mesh builds on the host).  Hand-written kernels: incidence
+ * counts and their scan, each point's incident cells, then each point's
+ * distinct neighbours sorted in LDS, counted, scanned into row_ptr and
+ * written.  The result feeds ftle_create_mesh_from_csr.
  *   dim          2 (triangles) or 3 (tetrahedra)
  *   n_points     1 <= n_points <= 2^31-1
- *   n_cells      >= 0
+ *   n_cells      >= 0, at most (2^32-1) / (dim+1)
  *   cells        device, n_cells x (dim+1) int32 point indices; a point
  *                repeated inside a cell adds no pair with itself
  *   row_ptr      device, n_points+1 int64, caller-owned, overwritten
@@ -140,16 +141,23 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
  *   col_capacity n_cells * dim * (dim+1) always suffices
  *   nnz          host, receives the entry count (also when it exceeds
  *                col_capacity)
- * The call allocates its sort buffers on the device for its duration (two
- * arrays of 8 bytes per cell pair) and returns after the stream has finished
+ * ftle_ring1_csr allocates its workspace (ftle_ring1_csr_workspace bytes,
+ * about 4 bytes per cell corner and 16 per point) for the duration of the
+ * call; ftle_ring1_csr_ws takes it from the caller (device memory of at
+ * least that size, overwritten).  Both return after the stream has finished
  * the work.
- * Errors: INVALID_ARG (dim, n_points < 1, n_cells < 0, null pointer),
- * BAD_MESH (a cell index outside [0, n_points), found on the device; row_ptr
- * and col are then not written), UNSUPPORTED (n_points > 2^31-1, *nnz >
- * col_capacity: row_ptr and col not written), OOM, DEVICE.
+ * Errors: INVALID_ARG (dim, n_points < 1, n_cells < 0, null pointer, too
+ * small a workspace), BAD_MESH (a cell index outside [0, n_points), found on
+ * the device; row_ptr and col are then not written), UNSUPPORTED
+ * (n_points > 2^31-1, too many cells, a point whose incident cells list more
+ * than 4096 points, *nnz > col_capacity: col not written), OOM, DEVICE.
  */
 ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
                            int32_t* col, int64_t col_capacity, int64_t* nnz, ftle_stream_t stream);
+ftle_status ftle_ring1_csr_workspace(int dim, int64_t n_points, int64_t n_cells, int64_t* bytes);
+ftle_status ftle_ring1_csr_ws(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
+                              int32_t* col, int64_t col_capacity, int64_t* nnz, void* workspace,
+                              int64_t workspace_bytes, ftle_stream_t stream);
 
 /* Analytic flows of ftle_advect_rk4. */
 typedef enum {

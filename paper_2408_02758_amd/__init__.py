@@ -5,5 +5,5 @@ C ABI in include/ftle.h.  This package only marshals arguments to it.
 """
 from .api import (BatchedCall, FTLEError, FTLEFunction, Mesh, advect_rk4, batched, batched_config,  # noqa: F401
                   axis_ell, eig_threshold, force_wide_offsets, forward_ell, ftle, pin_batched_config, ring1_csr,
-                  set_eig_threshold)
+                  ring1_workspace_bytes, set_eig_threshold)
 from ._lib import LIB_PATH, load  # noqa: F401

@@ -40,6 +40,8 @@ SIGNATURES = {
     "ftle_create_mesh": (_int, [_int, _i64, _vp, _int, _i64, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_create_mesh_from_csr": (_int, [_int, _i64, _vp, _int, _vp, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_ring1_csr": (_int, [_int, _i64, _i64, _vp, _vp, _vp, _i64, _P(_i64), _vp]),
+    "ftle_ring1_csr_workspace": (_int, [_int, _i64, _i64, _P(_i64)]),
+    "ftle_ring1_csr_ws": (_int, [_int, _i64, _i64, _vp, _vp, _vp, _i64, _P(_i64), _vp, _i64, _vp]),
     "ftle_axis_ell": (_int, [_int, _i64, _vp, _int, _vp, _vp, _vp, _vp]),
     "ftle_forward_ell": (_int, [_int, _i64, _vp, _int, _vp, _vp, _dbl, _vp, ctypes.c_uint, _vp]),
     "ftle_encode_flow_f16": (_int, [_vp, _vp, _vp, _vp]),

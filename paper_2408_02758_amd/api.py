@@ -430,22 +430,43 @@ def advect_rk4(flow: str, x0: torch.Tensor, t0, T, dt: float, params=None, out: 
     return out
 
 
-def ring1_csr(dim: int, n_points: int, cells: torch.Tensor, stream=None):
+def ring1_workspace_bytes(dim: int, n_points: int, n_cells: int) -> int:
+    """Device workspace bytes of ring1_csr(..., workspace=...) (ftle_ring1_csr_workspace)."""
+    b = ctypes.c_int64()
+    check(_lib.load().ftle_ring1_csr_workspace(dim, int(n_points), int(n_cells), ctypes.byref(b)))
+    return b.value
+
+
+def ring1_csr(dim: int, n_points: int, cells: torch.Tensor, stream=None, workspace: torch.Tensor | None = None,
+              col: torch.Tensor | None = None):
     """The one-ring stencil of a cell mesh built on the GPU (ftle_ring1_csr):
     cells is a contiguous int32 device tensor (n_cells, dim + 1); returns
     (row_ptr int64 (n_points + 1,), col int32 (nnz,)) on the same device,
     every other point sharing a cell with point i, ascending, once each.
-    Mesh.from_csr takes them (on the host) to build the mesh."""
+    workspace: a device tensor of at least ring1_workspace_bytes bytes to use
+    instead of an allocation inside the call (ftle_ring1_csr_ws); col: the
+    output buffer (int32, its size the capacity).  Mesh.from_csr takes the
+    result (on the host) to build the mesh."""
     if not (cells.is_cuda and cells.dtype == torch.int32 and cells.is_contiguous() and cells.dim() == 2
             and cells.shape[1] == dim + 1):
         raise ValueError(f"cells must be a contiguous int32 device tensor of shape (n_cells, {dim + 1})")
     n_cells = cells.shape[0]
     row_ptr = torch.empty(int(n_points) + 1, dtype=torch.int64, device=cells.device)
-    col = torch.empty(max(1, n_cells * dim * (dim + 1)), dtype=torch.int32, device=cells.device)
+    if col is None:
+        col = torch.empty(max(1, n_cells * dim * (dim + 1)), dtype=torch.int32, device=cells.device)
+    if not (col.is_cuda and col.dtype == torch.int32 and col.is_contiguous()):
+        raise ValueError("col must be a contiguous int32 device tensor")
     nnz = ctypes.c_int64(0)
-    check(_lib.load().ftle_ring1_csr(dim, int(n_points), n_cells, ctypes.c_void_p(cells.data_ptr()),
-                                     ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col.data_ptr()),
-                                     col.numel(), ctypes.byref(nnz), _stream_handle(stream)))
+    L = _lib.load()
+    args = [dim, int(n_points), n_cells, ctypes.c_void_p(cells.data_ptr()), ctypes.c_void_p(row_ptr.data_ptr()),
+            ctypes.c_void_p(col.data_ptr()), col.numel(), ctypes.byref(nnz)]
+    if workspace is None:
+        check(L.ftle_ring1_csr(*args, _stream_handle(stream)))
+    else:
+        if not (workspace.is_cuda and workspace.is_contiguous()):
+            raise ValueError("workspace must be a contiguous device tensor")
+        check(L.ftle_ring1_csr_ws(*args, ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel() * workspace.element_size(), _stream_handle(stream)))
     return row_ptr, col[:nnz.value]
 
 
@@ -526,4 +547,4 @@ def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
 
 __all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError",
            "force_wide_offsets", "set_eig_threshold", "eig_threshold", "pin_batched_config", "advect_rk4",
-           "ring1_csr", "axis_ell", "forward_ell"]
+           "ring1_csr", "ring1_workspace_bytes", "axis_ell", "forward_ell"]

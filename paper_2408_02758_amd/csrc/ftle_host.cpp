@@ -1601,67 +1601,83 @@ ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const voi
     });
 }
 
+namespace {
+
+void check_ring1_args(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, const int64_t* row_ptr,
+                      const int32_t* col, int64_t col_capacity, const int64_t* nnz)
+{
+    if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+    if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points < 1");
+    if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+    if (n_cells < 0) fail(FTLE_ERR_INVALID_ARG, "n_cells < 0");
+    if (!row_ptr || !nnz || (n_cells > 0 && (!cells || !col)) || col_capacity < 0)
+        fail(FTLE_ERR_INVALID_ARG, "null pointer or negative capacity");
+    if (n_cells > (int64_t)UINT32_MAX / (dim + 1)) fail(FTLE_ERR_UNSUPPORTED, "more than 2^32-1 cell corners");
+}
+
+void ring1_run(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr, int32_t* col,
+               int64_t col_capacity, int64_t* nnz, void* workspace, hipStream_t s)
+{
+    int bad = 0, too_long = 0;
+    int64_t count = 0;
+    check_hip(ring1_build(dim, cells, n_cells, n_points, workspace, row_ptr, col, col_capacity, &count, &bad,
+                          &too_long, s),
+              "one-ring stencil");
+    if (bad) fail(FTLE_ERR_BAD_MESH, "cell index outside [0, n_points)");
+    if (too_long) fail(FTLE_ERR_UNSUPPORTED, "a point's incident cells list more than 4096 points");
+    *nnz = count;
+    if (count > col_capacity) fail(FTLE_ERR_UNSUPPORTED, "col_capacity below the stencil's entry count (in *nnz)");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+}  // namespace
+
+ftle_status ftle_ring1_csr_workspace(int dim, int64_t n_points, int64_t n_cells, int64_t* bytes)
+{
+    return guarded([&] {
+        if (!bytes) fail(FTLE_ERR_INVALID_ARG, "bytes is NULL");
+        int64_t dummy = 0;
+        check_ring1_args(dim, n_points, n_cells, n_cells ? reinterpret_cast<const int32_t*>(16) : nullptr,
+                         reinterpret_cast<const int64_t*>(16), n_cells ? reinterpret_cast<const int32_t*>(16) : nullptr,
+                         0, &dummy);
+        *bytes = (int64_t)ring1_workspace_bytes(dim, n_points, n_cells);
+    });
+}
+
+ftle_status ftle_ring1_csr_ws(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
+                              int32_t* col, int64_t col_capacity, int64_t* nnz, void* workspace,
+                              int64_t workspace_bytes, ftle_stream_t stream)
+{
+    return guarded([&] {
+        check_ring1_args(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz);
+        if (!workspace) fail(FTLE_ERR_INVALID_ARG, "workspace is NULL");
+        if (workspace_bytes < (int64_t)ring1_workspace_bytes(dim, n_points, n_cells))
+            fail(FTLE_ERR_INVALID_ARG, "workspace smaller than ftle_ring1_csr_workspace's size");
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        ring1_run(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz, workspace,
+                  static_cast<hipStream_t>(stream));
+    });
+}
+
 ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
                            int32_t* col, int64_t col_capacity, int64_t* nnz, ftle_stream_t stream)
 {
-    // device buffers of one call, released on every exit
-    struct Scratch {
-        uint64_t* keys = nullptr;   // the pair keys; after the sort, the flags and positions
-        uint64_t* sorted = nullptr;
-        void* work = nullptr;
-        int* err = nullptr;
+    struct Scratch {   // released on every exit
+        void* p = nullptr;
         ~Scratch()
         {
-            for (void* p : {(void*)keys, (void*)sorted, work, (void*)err})
-                if (p) (void)hipFree(p);
+            if (p) (void)hipFree(p);
         }
     };
     return guarded([&] {
-        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
-        if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points < 1");
-        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
-        if (n_cells < 0) fail(FTLE_ERR_INVALID_ARG, "n_cells < 0");
-        if (!row_ptr || !nnz || (n_cells > 0 && (!cells || !col)) || col_capacity < 0)
-            fail(FTLE_ERR_INVALID_ARG, "null pointer or negative capacity");
-        const int64_t per = (int64_t)(dim + 1) * dim;   // directed pairs per cell
-        if (n_cells > (int64_t)UINT32_MAX / per) fail(FTLE_ERR_UNSUPPORTED, "more than 2^32-1 cell pairs");
-        const int64_t edges = n_cells * per;
+        check_ring1_args(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz);
         int dev = 0;
         check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
-        const hipStream_t s = static_cast<hipStream_t>(stream);
-        Scratch b;
-        check_hip(hipMalloc((void**)&b.err, sizeof(int)), "hipMalloc");
-        const int zero = 0;
-        check_hip(hipMemcpyAsync(b.err, &zero, sizeof(int), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-        // flags and positions (uint32 each) reuse the key array once the keys are sorted
-        uint32_t* flag = nullptr;
-        uint32_t* pos = nullptr;
-        uint32_t tail[2] = {0, 0};   // flag and position of the last sorted key
-        if (edges > 0) {
-            size_t work = 0;
-            check_hip(ring1_device_scratch_bytes(edges, &work), "sort scratch size");
-            check_hip(hipMalloc((void**)&b.keys, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
-            check_hip(hipMalloc((void**)&b.sorted, (size_t)edges * sizeof(uint64_t)), "hipMalloc (edge keys)");
-            check_hip(hipMalloc(&b.work, work ? work : 16), "hipMalloc (sort scratch)");
-            flag = reinterpret_cast<uint32_t*>(b.keys);
-            pos = flag + edges;
-            check_hip(launch_emit_edges(dim, cells, n_cells, n_points, b.keys, b.err, s), "edge extraction");
-            check_hip(sort_and_mark_keys(b.keys, b.sorted, edges, n_points, b.work, work, flag, pos, s),
-                      "sort / deduplication");
-            check_hip(hipMemcpyAsync(&tail[0], flag + (edges - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s),
-                      "hipMemcpyAsync");
-            check_hip(hipMemcpyAsync(&tail[1], pos + (edges - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, s),
-                      "hipMemcpyAsync");
-        }
-        int err = 0;
-        check_hip(hipMemcpyAsync(&err, b.err, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-        if (err) fail(FTLE_ERR_BAD_MESH, "cell index outside [0, n_points)");
-        const int64_t count = (int64_t)tail[0] + (int64_t)tail[1];
-        *nnz = count;
-        if (count > col_capacity) fail(FTLE_ERR_UNSUPPORTED, "col_capacity below the stencil's entry count (in *nnz)");
-        check_hip(launch_csr_from_keys(b.sorted, flag, pos, edges, count, n_points, row_ptr, col, s), "CSR from keys");
-        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+        Scratch w;
+        check_hip(hipMalloc(&w.p, ring1_workspace_bytes(dim, n_points, n_cells)), "hipMalloc (stencil workspace)");
+        ring1_run(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz, w.p,
+                  static_cast<hipStream_t>(stream));
     });
 }
 

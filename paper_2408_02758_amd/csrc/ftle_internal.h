@@ -180,18 +180,18 @@ constexpr int64_t kMaxAdvectSteps = 10000000;
 hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, const void* x0, const double* t0s,
                          const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream);
 
-// One-ring stencil on the device (ftle_neighbours.hip): edge keys from the
-// cells, their sort and deduplication, and the CSR arrays from the kept keys.
-hipError_t ring1_device_scratch_bytes(int64_t n_edges, size_t* bytes);
-int ring1_key_bits(int64_t n);   // b: a key is i * 2^b + j
-hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int64_t n, uint64_t* keys, int* err,
-                             hipStream_t stream);
-// sorted <- keys sorted; flag[p] = key p kept (first of its run, not the
-// sentinel); pos = exclusive sum of flag (flag and pos may share keys' memory).
-hipError_t sort_and_mark_keys(uint64_t* keys, uint64_t* sorted, int64_t n_edges, int64_t n, void* scratch,
-                              size_t scratch_bytes, uint32_t* flag, uint32_t* pos, hipStream_t stream);
-hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t n_edges,
-                                int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t stream);
+// One-ring stencil on the device (ftle_neighbours.hip): incidence counts,
+// their scan, incidence lists, then each point's distinct neighbours counted,
+// scanned into row_ptr and written to col.  The workspace
+// (ring1_workspace_bytes) is device memory the call may overwrite.  On return
+// *bad_mesh (a cell index outside [0, n): nothing written) or *too_long (a
+// point whose incident cells list more than 4096 points) may be set;
+// otherwise *nnz holds the entry count, and row_ptr / col are written when it
+// is at most col_capacity.  Synchronises the stream.
+size_t ring1_workspace_bytes(int dim, int64_t n, int64_t n_cells);
+hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace, int64_t* row_ptr,
+                       int32_t* col, int64_t col_capacity, int64_t* nnz, int* bad_mesh, int* too_long,
+                       hipStream_t stream);
 
 // The paper's fixed-width axis list (ftle_ell.hip): the forward from it (one
 // lane per caller point; staged: each workgroup's block of points in LDS),

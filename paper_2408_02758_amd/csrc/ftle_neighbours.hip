@@ -2,21 +2,24 @@
 // determination that precedes the FTLE path (Section 2.2 keeps it on the host,
 // off the accelerator; the Conclusions list accelerating it as future work).
 // Every point's neighbours are the other points sharing a cell with it,
-// ascending, each once.
+// ascending, each once.  Hand-written kernels, no library sort:
 //
-//   1. edge extraction: each cell of K = dim + 1 points emits its K (K - 1)
-//      directed pairs (i, j) as 64-bit keys i * 2^b + j, with b the bit
-//      length of n; a pair with i = j (a point repeated inside a cell)
-//      becomes a sentinel key n * 2^b that sorts after every real key, and an
-//      index outside [0, n) raises the error flag and becomes the sentinel too;
-//   2. a radix sort of the keys over their 2 b bits (hipCUB);
-//   3. deduplication: a flag per sorted key that is the first of its run of
-//      equal keys and not the sentinel, and the exclusive sum of the flags
-//      (hipCUB), which is each kept key's CSR position;
-//   4. the CSR arrays: a kept key's column is its low b bits, and row r
-//      starts at the first kept key whose row is >= r.
+//   1. incidence counts: each cell adds one to the count of each of its K =
+//      dim + 1 points (an index outside [0, n) raises the error flag);
+//   2. an exclusive scan of the counts gives each point's incidence offset
+//      (scan_tiles / scan_partials / add_partials: 2048-element tiles, the
+//      tiles' sums scanned by one workgroup, then added back);
+//   3. incidence lists: each cell appends its index to the list of each of its
+//      points (atomic cursors; the order inside a list does not matter);
+//   4. rows: one lane per point walks its incident cells and inserts their
+//      other points into a short sorted list of distinct indices in LDS (a
+//      lane's list is interleaved with its workgroup's, so that a list step
+//      is one conflict-free LDS access); the first pass only counts them,
+//      the counts are scanned into the row pointers, and the second pass
+//      writes the lists.  A point with more than kRowCap distinct neighbours
+//      is handed to a workgroup of its own (long_rows: its candidates sorted
+//      by a bitonic network in LDS, duplicates dropped by a flag scan).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cstdint>
 
@@ -25,132 +28,379 @@
 namespace ftle {
 namespace {
 
+constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
+constexpr int kRowThreads = 128;   // lanes per workgroup of the row passes
+constexpr int kRowCap = 32;        // distinct neighbours a lane keeps in LDS
+constexpr int kLongCap = 4096;     // candidates (with repeats) of a long row
+
+inline unsigned blocks_for(int64_t m, int per = 256) { return (unsigned)((m + per - 1) / per); }
+
+// The points of cell c (tetrahedra: one 16-byte load when the array is
+// 16-byte aligned, a workgroup-uniform test).
 template <int K>
-__global__ void __launch_bounds__(256) emit_edges(const int32_t* __restrict__ cells, int64_t n_cells, int64_t n,
-                                                  int b, uint64_t* __restrict__ keys, int* __restrict__ err)
+__device__ inline void load_cell(const int32_t* __restrict__ cells, int64_t c, int32_t (&v)[K])
+{
+    if (K == 4 && (reinterpret_cast<uintptr_t>(cells) & 15) == 0) {
+        const int4 q = reinterpret_cast<const int4*>(cells)[c];
+        v[0] = q.x, v[1] = q.y, v[2] = q.z;
+        if constexpr (K == 4) v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int a = 0; a < K; ++a) v[a] = cells[c * K + a];
+    }
+}
+
+// 1. one per (cell, point) occurrence; a cell with an index outside [0, n)
+// sets *err and adds nothing.
+template <int K>
+__global__ void __launch_bounds__(256) count_incidence(const int32_t* __restrict__ cells, int64_t n_cells, int64_t n,
+                                                       uint32_t* __restrict__ cnt, int* __restrict__ err)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     int32_t v[K];
-#pragma unroll
-    for (int a = 0; a < K; ++a) v[a] = cells[c * K + a];
+    load_cell<K>(cells, c, v);
     bool bad = false;
 #pragma unroll
-    for (int a = 0; a < K; ++a) bad |= (v[a] < 0) || ((int64_t)v[a] >= n);
-    if (bad) *err = 1;   // every writer stores the same value
-    const uint64_t sentinel = (uint64_t)n << b;
-    // pair o of every cell in one contiguous stretch: each store instruction
-    // writes consecutive keys for consecutive cells (the sort ignores order)
-    uint64_t* out = keys + c;
-    int o = 0;
+    for (int a = 0; a < K; ++a) bad |= (uint64_t)(int64_t)v[a] >= (uint64_t)n;
+    if (bad) {
+        *err = 1;   // every writer stores the same value
+        return;
+    }
 #pragma unroll
-    for (int a = 0; a < K; ++a)
+    for (int a = 0; a < K; ++a) atomicAdd(&cnt[v[a]], 1u);
+}
+
+// 3. cell c into the incidence list of each of its points (cur: each point's
+// next free position, starting at its offset).
+template <int K>
+__global__ void __launch_bounds__(256) fill_incidence(const int32_t* __restrict__ cells, int64_t n_cells,
+                                                      uint32_t* __restrict__ cur, int32_t* __restrict__ inc)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    int32_t v[K];
+    load_cell<K>(cells, c, v);
 #pragma unroll
-        for (int c2 = 0; c2 < K; ++c2) {
-            if (a == c2) continue;
-            const bool real = !bad && v[a] != v[c2];
-            out[(int64_t)(o++) * n_cells] = real ? ((uint64_t)(uint32_t)v[a] << b) | (uint32_t)v[c2] : sentinel;
-        }
+    for (int a = 0; a < K; ++a) inc[atomicAdd(&cur[v[a]], 1u)] = (int32_t)c;
 }
 
-// flag[p] = 1 where sorted key p is the first of its run and below the sentinel.
-__global__ void __launch_bounds__(256) mark_first(const uint64_t* __restrict__ keys, int64_t m, uint64_t sentinel,
-                                                  uint32_t* __restrict__ flag)
+// ---------------------------------------------------------------------------
+// Exclusive scan of m uint32 counts into out[0..m) (Out: uint32 or int64),
+// with out[m] = the total.  scan_tiles scans each 2048-element tile and
+// writes its sum to partial[tile]; scan_partials scans the partial sums in
+// one workgroup (chunks of 1024 with a carry) and writes the total to
+// out[m]; add_partials adds each tile's offset.
+// ---------------------------------------------------------------------------
+template <typename Out>
+__device__ inline Out block_inclusive_scan(Out v, Out* s, int tid, int nthreads)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m) return;
-    const uint64_t k = keys[p];
-    flag[p] = (k < sentinel && (p == 0 || keys[p - 1] != k)) ? 1u : 0u;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < nthreads; off <<= 1) {
+        const Out t = tid >= off ? s[tid - off] : Out(0);
+        __syncthreads();
+        s[tid] += t;
+        __syncthreads();
+    }
+    return s[tid];
 }
 
-// Kept key p (flag set) goes to CSR position pos[p]: its column, and the
-// starts of the rows from the previous key's row + 1 up to its own (the
-// previous key, kept or not, has the previous kept key's row); the last kept
-// key also closes the rows after its own up to n.
-__global__ void __launch_bounds__(256) csr_from_keys(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ flag,
-                                                     const uint32_t* __restrict__ pos, int64_t m, int64_t nnz,
-                                                     int64_t n, int b, int64_t* __restrict__ row_ptr,
-                                                     int32_t* __restrict__ col)
+template <typename Out>
+__global__ void __launch_bounds__(kScanThreads) scan_tiles(const uint32_t* in, int64_t m, Out* out,
+                                                             Out* __restrict__ partial)   // in and out may coincide
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= m || !flag[p]) return;
-    const uint64_t k = keys[p];
-    const int64_t q = pos[p];
-    const int64_t r = (int64_t)(k >> b);
-    const int64_t rp = p == 0 ? -1 : (int64_t)(keys[p - 1] >> b);
-    col[q] = (int32_t)(k & ((1ull << b) - 1));
-    for (int64_t t = rp + 1; t <= r; ++t) row_ptr[t] = q;
-    if (q == nnz - 1)
-        for (int64_t t = r + 1; t <= n; ++t) row_ptr[t] = nnz;
+    __shared__ Out s[kScanThreads];
+    const int tid = (int)threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
+    Out v[kScanItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < m ? (Out)in[base + k] : Out(0);
+        sum += v[k];
+    }
+    const Out incl = block_inclusive_scan<Out>(sum, s, tid, kScanThreads);
+    Out run = incl - sum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) out[base + k] = run;
+        run += v[k];
+    }
+    if (tid == kScanThreads - 1) partial[blockIdx.x] = incl;
 }
 
-__global__ void __launch_bounds__(256) fill_zero(int64_t* __restrict__ a, int64_t m)
+template <typename Out>
+__global__ void __launch_bounds__(1024) scan_partials(Out* __restrict__ partial, int64_t np, Out* __restrict__ total)
+{
+    __shared__ Out s[1024];
+    const int tid = (int)threadIdx.x;
+    Out carry = 0;
+    for (int64_t c0 = 0; c0 < np; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        const Out v = i < np ? partial[i] : Out(0);
+        const Out incl = block_inclusive_scan<Out>(v, s, tid, 1024);
+        if (i < np) partial[i] = carry + incl - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+    if (tid == 0) *total = carry;
+}
+
+template <typename Out>
+__global__ void __launch_bounds__(256) add_partials(Out* __restrict__ out, int64_t m, const Out* __restrict__ partial)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) a[i] = 0;
+    if (i < m) out[i] += partial[i / kScanTile];
 }
 
-inline unsigned blocks_for(int64_t m) { return (unsigned)((m + 255) / 256); }
+template <typename Out>
+hipError_t exclusive_scan(const uint32_t* in, int64_t m, Out* out, Out* partial, hipStream_t stream)
+{
+    const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+    if (tiles > 0)
+        hipLaunchKernelGGL((scan_tiles<Out>), dim3((unsigned)tiles), dim3(kScanThreads), 0, stream, in, m, out,
+                           partial);
+    hipLaunchKernelGGL((scan_partials<Out>), dim3(1), dim3(1024), 0, stream, partial, tiles, out + m);
+    if (tiles > 1)
+        hipLaunchKernelGGL((add_partials<Out>), dim3(blocks_for(m)), dim3(256), 0, stream, out, m,
+                           (const Out*)partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 4. rows.  Lane r (point r) keeps its distinct neighbours, ascending, in
+// lst[k * kRowThreads + lane], k < kRowCap.  WRITE = false: deg[r] = their
+// count; a point with more is appended to longs (deg[r] = 0 for now).
+// WRITE = true: the list goes to col[row_ptr[r] ...]; long points are
+// skipped (long_rows writes them).
+// ---------------------------------------------------------------------------
+template <int K, bool WRITE>
+__global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restrict__ cells,
+                                                         const int32_t* __restrict__ inc,
+                                                         const uint32_t* __restrict__ off, int64_t n,
+                                                         uint32_t* __restrict__ deg, const int64_t* __restrict__ row_ptr,
+                                                         int32_t* __restrict__ col, uint32_t* __restrict__ longs,
+                                                         uint32_t* __restrict__ n_long)
+{
+    __shared__ int32_t lst[kRowCap * kRowThreads];
+    const int t = (int)threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * kRowThreads + t;
+    if (r >= n) return;
+    int32_t* my = lst + t;   // entry k at my[k * kRowThreads]
+    int cnt = 0;
+    bool over = false;
+    const uint32_t p1 = off[r + 1];
+    for (uint32_t p = off[r]; p < p1 && !over; ++p) {
+        int32_t v[K];
+        load_cell<K>(cells, inc[p], v);
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int32_t u = v[a];
+            if (u == (int32_t)r) continue;
+            int k = cnt;   // insertion point: after every entry below u
+            while (k > 0 && my[(k - 1) * kRowThreads] > u) --k;
+            if (k > 0 && my[(k - 1) * kRowThreads] == u) continue;   // already listed
+            if (cnt == kRowCap) {
+                over = true;
+                break;
+            }
+            for (int j = cnt; j > k; --j) my[j * kRowThreads] = my[(j - 1) * kRowThreads];
+            my[k * kRowThreads] = u;
+            ++cnt;
+        }
+    }
+    if constexpr (!WRITE) {
+        if (over) longs[atomicAdd(n_long, 1u)] = (uint32_t)r;
+        deg[r] = over ? 0u : (uint32_t)cnt;
+    } else {
+        if (over) return;
+        int32_t* out = col + row_ptr[r];
+        for (int k = 0; k < cnt; ++k) out[k] = my[k * kRowThreads];
+    }
+}
+
+// A long row by a workgroup of 256 lanes: its candidates (the points of its
+// incident cells, the point itself as a filler) sorted by a bitonic network
+// in LDS, then one flag per first occurrence and their exclusive sum.  More
+// than kLongCap candidates: *err |= 2 (the stencil is not built).  The
+// workgroups loop over the long rows (their number is only known on the
+// device).
+template <int K, bool WRITE>
+__global__ void __launch_bounds__(256) long_rows(const int32_t* __restrict__ cells, const int32_t* __restrict__ inc,
+                                                 const uint32_t* __restrict__ off, const uint32_t* __restrict__ longs,
+                                                 const uint32_t* __restrict__ n_long, uint32_t* __restrict__ deg,
+                                                 const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                 int* __restrict__ err)
+{
+    constexpr int kT = 256, kPer = kLongCap / kT;
+    constexpr int32_t kFill = INT32_MAX;
+    __shared__ int32_t s[kLongCap];
+    __shared__ uint32_t part[kT];
+    const int t = (int)threadIdx.x;
+    const uint32_t nl = *n_long;
+    for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+        const int64_t r = longs[li];
+        const uint32_t p0 = off[r], m = (off[r + 1] - p0) * K;
+        if (m > (uint32_t)kLongCap) {
+            if (t == 0) atomicOr(err, 2);
+            continue;
+        }
+        int p2 = 1;
+        while (p2 < (int)m) p2 <<= 1;
+        for (int i = t; i < p2; i += kT) {
+            int32_t u = kFill;
+            if (i < (int)m) {
+                u = cells[(int64_t)inc[p0 + i / K] * K + i % K];
+                if (u == (int32_t)r) u = kFill;
+            }
+            s[i] = u;
+        }
+        __syncthreads();
+        for (int size = 2; size <= p2; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = t; i < p2; i += kT) {
+                    const int j = i ^ stride;
+                    if (j > i) {
+                        const bool up = (i & size) == 0;
+                        const int32_t a = s[i], b = s[j];
+                        if ((a > b) == up) {
+                            s[i] = b;
+                            s[j] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // lane t owns entries [t kPer, (t + 1) kPer): first occurrences, then their exclusive sum
+        uint32_t c = 0;
+        for (int k = 0; k < kPer; ++k) {
+            const int i = t * kPer + k;
+            c += (i < p2 && s[i] != kFill && (i == 0 || s[i] != s[i - 1])) ? 1u : 0u;
+        }
+        const uint32_t incl = block_inclusive_scan<uint32_t>(c, part, t, kT);
+        if constexpr (!WRITE) {
+            if (t == kT - 1) deg[r] = incl;
+        } else {
+            int32_t* out = col + row_ptr[r] + (incl - c);
+            for (int k = 0; k < kPer; ++k) {
+                const int i = t * kPer + k;
+                if (i < p2 && s[i] != kFill && (i == 0 || s[i] != s[i - 1])) *out++ = s[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kLongGrid = 256;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-int ring1_key_bits(int64_t n)
+// Workspace of ring1_build, carved in this order: incidence counts and
+// offsets (n + 1), cursors (n), incidence lists (K n_cells), distinct counts
+// (n + 1), long rows (n), scan partial sums, error and long-row counters.
+size_t ring1_workspace_bytes(int dim, int64_t n, int64_t n_cells)
 {
-    int b = 0;
-    for (uint64_t v = (uint64_t)n; v; v >>= 1) ++b;
-    return b;
+    const int K = dim + 1;
+    const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile + 1;
+    return align256(4 * (size_t)(n + 1)) + align256(4 * (size_t)n) + align256(4 * (size_t)K * n_cells) +
+           align256(4 * (size_t)(n + 1)) + align256(4 * (size_t)n) + align256(8 * (size_t)tiles) + 256;
 }
 
-hipError_t ring1_device_scratch_bytes(int64_t n_edges, size_t* bytes)
+hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace, int64_t* row_ptr,
+                       int32_t* col, int64_t col_capacity, int64_t* nnz, int* bad_mesh, int* too_long,
+                       hipStream_t stream)
 {
-    size_t sort_bytes = 0, scan_bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortKeys(nullptr, sort_bytes, (const uint64_t*)nullptr,
-                                                     (uint64_t*)nullptr, (int64_t)n_edges, 0, 64, (hipStream_t)0);
-    if (e != hipSuccess) return e;
-    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                         (int64_t)n_edges, (hipStream_t)0);
-    *bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
-    return e;
-}
-
-hipError_t launch_emit_edges(int dim, const int32_t* cells, int64_t n_cells, int64_t n, uint64_t* keys, int* err,
-                             hipStream_t stream)
-{
-    if (n_cells == 0) return hipSuccess;
-    if (dim == 2)
-        hipLaunchKernelGGL(emit_edges<3>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, n,
-                           ring1_key_bits(n), keys, err);
-    else
-        hipLaunchKernelGGL(emit_edges<4>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, n,
-                           ring1_key_bits(n), keys, err);
-    return hipGetLastError();
-}
-
-hipError_t sort_and_mark_keys(uint64_t* keys, uint64_t* sorted, int64_t n_edges, int64_t n, void* scratch,
-                              size_t scratch_bytes, uint32_t* flag, uint32_t* pos, hipStream_t stream)
-{
-    // keys i * 2^b + j with i <= n (the sentinel's row) and j < n use 2 b bits
-    const int b = ring1_key_bits(n);
-    size_t bytes = scratch_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortKeys(scratch, bytes, keys, sorted, n_edges, 0, 2 * b, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mark_first, dim3(blocks_for(n_edges)), dim3(256), 0, stream, sorted, n_edges,
-                       (uint64_t)n << b, flag);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    bytes = scratch_bytes;
-    return hipcub::DeviceScan::ExclusiveSum(scratch, bytes, flag, pos, n_edges, stream);
-}
-
-hipError_t launch_csr_from_keys(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t n_edges,
-                                int64_t nnz, int64_t n, int64_t* row_ptr, int32_t* col, hipStream_t stream)
-{
-    if (nnz == 0) {
-        hipLaunchKernelGGL(fill_zero, dim3(blocks_for(n + 1)), dim3(256), 0, stream, row_ptr, n + 1);
-    } else {
-        hipLaunchKernelGGL(csr_from_keys, dim3(blocks_for(n_edges)), dim3(256), 0, stream, sorted, flag, pos, n_edges,
-                           nnz, n, ring1_key_bits(n), row_ptr, col);
+    const int K = dim + 1;
+    unsigned char* w = static_cast<unsigned char*>(workspace);
+    auto carve = [&](size_t bytes) {
+        void* p = w;
+        w += align256(bytes);
+        return p;
+    };
+    uint32_t* cnt = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
+    uint32_t* cur = static_cast<uint32_t*>(carve(4 * (size_t)n));
+    int32_t* inc = static_cast<int32_t*>(carve(4 * (size_t)K * n_cells));
+    uint32_t* deg = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
+    uint32_t* longs = static_cast<uint32_t*>(carve(4 * (size_t)n));
+    const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile + 1;
+    void* partial = carve(8 * (size_t)tiles);
+    int* err = static_cast<int*>(carve(256));
+    uint32_t* n_long = reinterpret_cast<uint32_t*>(err + 1);
+    hipError_t e;
+#define FTLE_CHECK(x)                          \
+    if ((e = (x)) != hipSuccess) return e;
+    FTLE_CHECK(hipMemsetAsync(cnt, 0, 4 * (size_t)(n + 1), stream));
+    FTLE_CHECK(hipMemsetAsync(err, 0, 8, stream));
+    if (n_cells > 0) {
+        if (dim == 2)
+            hipLaunchKernelGGL(count_incidence<3>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, n,
+                               cnt, err);
+        else
+            hipLaunchKernelGGL(count_incidence<4>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, n,
+                               cnt, err);
+        FTLE_CHECK(hipGetLastError());
     }
-    return hipGetLastError();
+    int flags = 0;
+    FTLE_CHECK(hipMemcpyAsync(&flags, err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    FTLE_CHECK(hipStreamSynchronize(stream));
+    if (flags) {
+        *bad_mesh = 1;
+        return hipSuccess;
+    }
+    // 2. offsets (cnt becomes off, in place: the tile scan reads a value before writing it)
+    FTLE_CHECK(exclusive_scan<uint32_t>(cnt, n, cnt, static_cast<uint32_t*>(partial), stream));
+    // 3. incidence lists
+    FTLE_CHECK(hipMemcpyAsync(cur, cnt, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream));
+    if (n_cells > 0) {
+        if (dim == 2)
+            hipLaunchKernelGGL(fill_incidence<3>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, cur,
+                               inc);
+        else
+            hipLaunchKernelGGL(fill_incidence<4>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, cur,
+                               inc);
+        FTLE_CHECK(hipGetLastError());
+    }
+    // 4. distinct counts, their offsets, then the lists
+    const dim3 rg(blocks_for(n, kRowThreads)), rb(kRowThreads);
+    if (dim == 2) {
+        hipLaunchKernelGGL((ring_rows<3, false>), rg, rb, 0, stream, cells, inc, cnt, n, deg, nullptr, nullptr, longs,
+                           n_long);
+        hipLaunchKernelGGL((long_rows<3, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
+                           n_long, deg, nullptr, nullptr, err);
+    } else {
+        hipLaunchKernelGGL((ring_rows<4, false>), rg, rb, 0, stream, cells, inc, cnt, n, deg, nullptr, nullptr, longs,
+                           n_long);
+        hipLaunchKernelGGL((long_rows<4, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
+                           n_long, deg, nullptr, nullptr, err);
+    }
+    FTLE_CHECK(hipGetLastError());
+    FTLE_CHECK(exclusive_scan<int64_t>(deg, n, row_ptr, static_cast<int64_t*>(partial), stream));
+    int64_t total = 0;
+    FTLE_CHECK(hipMemcpyAsync(&total, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    FTLE_CHECK(hipMemcpyAsync(&flags, err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    FTLE_CHECK(hipStreamSynchronize(stream));
+    *nnz = total;
+    if (flags & 2) {
+        *too_long = 1;
+        return hipSuccess;
+    }
+    if (total > col_capacity || total == 0) return hipSuccess;
+    if (dim == 2) {
+        hipLaunchKernelGGL((ring_rows<3, true>), rg, rb, 0, stream, cells, inc, cnt, n, deg, row_ptr, col, longs,
+                           n_long);
+        hipLaunchKernelGGL((long_rows<3, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
+                           n_long, deg, row_ptr, col, err);
+    } else {
+        hipLaunchKernelGGL((ring_rows<4, true>), rg, rb, 0, stream, cells, inc, cnt, n, deg, row_ptr, col, longs,
+                           n_long);
+        hipLaunchKernelGGL((long_rows<4, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
+                           n_long, deg, row_ptr, col, err);
+    }
+    FTLE_CHECK(hipGetLastError());
+#undef FTLE_CHECK
+    return hipSuccess;
 }
 
 }  // namespace ftle

@@ -98,3 +98,47 @@ def test_mesh_from_device_stencil_matches_cells():
     a = m_cells.forward(phi, 2.0).cpu().numpy()
     b = m_csr.forward(phi, 2.0).cpu().numpy()
     assert np.array_equal(a, b, equal_nan=True)
+
+
+def test_ring1_csr_long_rows_and_workspace():
+    """Points with more distinct neighbours than a lane keeps in LDS go to the
+    long-row path: a fan of 70 triangles around one point (70 neighbours), and
+    a point shared by 300 triangles of a star (600 candidates); with a
+    caller-held workspace, and with cells that are not 16-byte aligned."""
+    k = 70
+    fan = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], dtype=np.int32)
+    rp, col = assert_same(2, k + 1, fan)
+    assert rp[1] - rp[0] == k
+    m = 300
+    star = np.array([[0, 1 + 2 * i, 2 + 2 * i] for i in range(m)], dtype=np.int32)
+    x, grid = meshes.jittered_tri_grid(30, 20, seed=2)
+    cells = np.concatenate([star, grid + 2 * m + 1]).astype(np.int32)
+    n = 2 * m + 1 + x.shape[0]
+    assert_same(2, n, cells)
+    c = torch.as_tensor(cells, device=DEV)
+    ws = torch.empty(F.ring1_workspace_bytes(2, n, cells.shape[0]), dtype=torch.uint8, device=DEV)
+    ref = oracle.ring1(2, n, cells)
+    for _ in range(2):   # the workspace is reused as it is left
+        rp2, col2 = F.ring1_csr(2, n, c, workspace=ws)
+        assert np.array_equal(rp2.cpu().numpy(), ref.row_ptr) and np.array_equal(col2.cpu().numpy(), ref.col)
+    with pytest.raises(F.FTLEError):
+        F.ring1_csr(2, n, c, workspace=ws[:100])
+    # 3D cells at a 4-byte offset
+    xt, tets = meshes.kuhn_tet_grid(7)
+    flat = torch.empty(tets.size + 1, dtype=torch.int32, device=DEV)
+    flat[1:] = torch.as_tensor(tets.ravel(), device=DEV)
+    shifted = flat[1:].view(-1, 4)
+    assert shifted.data_ptr() % 16 != 0
+    rp3, col3 = F.ring1_csr(3, xt.shape[0], shifted)
+    ref3 = oracle.ring1(3, xt.shape[0], tets)
+    assert np.array_equal(rp3.cpu().numpy(), ref3.row_ptr) and np.array_equal(col3.cpu().numpy(), ref3.col)
+
+
+def test_ring1_csr_too_long_a_row_is_unsupported():
+    """A point in 2100 triangles (4200 candidate entries, over the 4096 a
+    long-row workgroup sorts) is reported, not truncated."""
+    m = 2100
+    star = np.array([[0, 1 + 2 * i, 2 + 2 * i] for i in range(m)], dtype=np.int32)
+    with pytest.raises(F.FTLEError) as e:
+        device_ring1(2, 2 * m + 1, star)
+    assert e.value.status == 4 and "4096" in e.value.message

@@ -495,3 +495,24 @@ def test_axis_list_entries_validation(L):
     assert ax(x=None) == INVALID and ax(rp=None) == INVALID and ax(col=None) == INVALID and ax(ell=None) == INVALID
     assert ax(ell=odd) == INVALID
     assert ax(n=0, x=None, rp=None, col=None, ell=None) == 0
+
+
+def test_ring1_csr_workspace_validation(L):
+    """The workspace size query and the caller-workspace variant validate before
+    any device work (the pointers are never dereferenced)."""
+    INVALID, UNSUP = 1, 4
+    b = ctypes.c_int64()
+    assert L.ftle_ring1_csr_workspace(2, 10, 3, ctypes.byref(b)) == 0 and b.value >= 4 * (3 * 3 + 4 * 11)
+    assert L.ftle_ring1_csr_workspace(3, 10, 3, None) == INVALID
+    assert L.ftle_ring1_csr_workspace(4, 10, 3, ctypes.byref(b)) == INVALID
+    assert L.ftle_ring1_csr_workspace(3, 10, 1 << 31, ctypes.byref(b)) == UNSUP
+    need = b.value
+    fake = ctypes.c_void_p(256)
+    nnz = ctypes.c_int64()
+
+    def ws(workspace=fake, size=need, dim=2):
+        return L.ftle_ring1_csr_ws(dim, 10, 3, fake, fake, fake, 18, ctypes.byref(nnz), workspace, size, None)
+
+    assert ws(workspace=None) == INVALID and ws(size=need - 1) == INVALID
+    assert b"workspace" in L.ftle_last_error()
+    assert ws(dim=5) == INVALID
