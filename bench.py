@@ -495,7 +495,7 @@ def short_kernel_name(name):
     return s[start:].strip()
 
 
-FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "incidence", "scan_tiles", "scan_partials",
+FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "incidence_pass", "scan_tiles", "scan_partials",
                     "add_partials", "ring_rows", "long_rows", "advect")
 
 

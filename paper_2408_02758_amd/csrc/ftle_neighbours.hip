@@ -5,12 +5,14 @@
 // ascending, each once.  Hand-written kernels, no library sort:
 //
 //   1. incidence counts: each cell adds one to the count of each of its K =
-//      dim + 1 points (an index outside [0, n) raises the error flag);
+//      dim + 1 points (an index outside [0, n) raises the error flag),
+//      aggregated per workgroup in LDS first;
 //   2. an exclusive scan of the counts gives each point's incidence offset
 //      (scan_tiles / scan_partials / add_partials: 2048-element tiles, the
 //      tiles' sums scanned by one workgroup, then added back);
 //   3. incidence lists: each cell appends its index to the list of each of its
-//      points (atomic cursors; the order inside a list does not matter);
+//      points (atomic cursors, one per distinct point of a workgroup; the
+//      order inside a list does not matter);
 //   4. rows: one lane per point walks its incident cells and inserts their
 //      other points into a short sorted list of distinct indices in LDS (a
 //      lane's list is interleaved with its workgroup's, so that a list step
@@ -50,39 +52,89 @@ __device__ inline void load_cell(const int32_t* __restrict__ cells, int64_t c, i
     }
 }
 
-// 1. one per (cell, point) occurrence; a cell with an index outside [0, n)
-// sets *err and adds nothing.
-template <int K>
-__global__ void __launch_bounds__(256) count_incidence(const int32_t* __restrict__ cells, int64_t n_cells, int64_t n,
-                                                       uint32_t* __restrict__ cnt, int* __restrict__ err)
-{
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    int32_t v[K];
-    load_cell<K>(cells, c, v);
-    bool bad = false;
-#pragma unroll
-    for (int a = 0; a < K; ++a) bad |= (uint64_t)(int64_t)v[a] >= (uint64_t)n;
-    if (bad) {
-        *err = 1;   // every writer stores the same value
-        return;
-    }
-#pragma unroll
-    for (int a = 0; a < K; ++a) atomicAdd(&cnt[v[a]], 1u);
-}
+// 1 and 3.  A workgroup takes kAggCells cells per lane and first gathers their
+// points' occurrences in an LDS hash table (open addressing, keys inserted by
+// compare-and-swap), so that each distinct point of the workgroup's cells
+// costs one global atomic instead of one per occurrence: cells come in mesh
+// order, and neighbouring cells share most of their points.  A point that
+// finds no slot within kProbes probes goes to global memory directly.
+//   FILL = false: cnt[v] += occurrences of v (a cell with an index outside
+//                 [0, n) sets *err and adds nothing);
+//   FILL = true:  each occurrence of v gets a position from cur[v] (the
+//                 workgroup reserves its block of positions with one atomic)
+//                 and inc[position] = its cell.
+constexpr int kAggThreads = 256, kAggCells = 4, kAggSlots = 4096, kProbes = 32;
 
-// 3. cell c into the incidence list of each of its points (cur: each point's
-// next free position, starting at its offset).
-template <int K>
-__global__ void __launch_bounds__(256) fill_incidence(const int32_t* __restrict__ cells, int64_t n_cells,
-                                                      uint32_t* __restrict__ cur, int32_t* __restrict__ inc)
+__device__ inline uint32_t agg_hash(int32_t v) { return ((uint32_t)v * 2654435761u) >> 20; }   // 12 bits
+
+template <int K, bool FILL>
+__global__ void __launch_bounds__(kAggThreads) incidence_pass(const int32_t* __restrict__ cells, int64_t n_cells,
+                                                              int64_t n, uint32_t* __restrict__ cnt,
+                                                              int32_t* __restrict__ inc, int* __restrict__ err)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    int32_t v[K];
-    load_cell<K>(cells, c, v);
+    static_assert(kAggSlots == 1 << 12, "agg_hash gives 12 bits");
+    __shared__ int32_t key[kAggSlots];
+    __shared__ uint32_t num[kAggSlots];
+    const int t = (int)threadIdx.x;
+    for (int i = t; i < kAggSlots; i += kAggThreads) {
+        key[i] = -1;
+        num[i] = 0;
+    }
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * (kAggThreads * kAggCells);
+    int slot[kAggCells][K];
+    uint32_t local[kAggCells][K];
 #pragma unroll
-    for (int a = 0; a < K; ++a) inc[atomicAdd(&cur[v[a]], 1u)] = (int32_t)c;
+    for (int q = 0; q < kAggCells; ++q) {
+        const int64_t c = c0 + q * kAggThreads + t;
+        int32_t v[K];
+        bool ok = c < n_cells;
+        if (ok) {
+            load_cell<K>(cells, c, v);
+#pragma unroll
+            for (int a = 0; a < K; ++a) ok &= (uint64_t)(int64_t)v[a] < (uint64_t)n;
+            if (!FILL && !ok) *err = 1;   // every writer stores the same value
+        }
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            slot[q][a] = -2;   // nothing to do
+            if (!ok) continue;
+            uint32_t h = agg_hash(v[a]);
+            int s = -1;
+            for (int p = 0; p < kProbes; ++p, h = (h + 1) & (kAggSlots - 1)) {
+                const int32_t k = atomicCAS(&key[h], -1, v[a]);
+                if (k == -1 || k == v[a]) {
+                    s = (int)h;
+                    break;
+                }
+            }
+            slot[q][a] = s;
+            if (s >= 0) {
+                local[q][a] = atomicAdd(&num[s], 1u);
+            } else if (FILL) {
+                inc[atomicAdd(&cnt[v[a]], 1u)] = (int32_t)c;
+            } else {
+                atomicAdd(&cnt[v[a]], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < kAggSlots; i += kAggThreads) {
+        const int32_t k = key[i];
+        if (k < 0) continue;
+        if (FILL)
+            num[i] = atomicAdd(&cnt[k], num[i]);   // the block's first position
+        else
+            atomicAdd(&cnt[k], num[i]);
+    }
+    if constexpr (FILL) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kAggCells; ++q)
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+                if (slot[q][a] >= 0) inc[num[slot[q][a]] + local[q][a]] = (int32_t)(c0 + q * kAggThreads + t);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -189,25 +241,35 @@ __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restri
     int32_t* my = lst + t;   // entry k at my[k * kRowThreads]
     int cnt = 0;
     bool over = false;
-    const uint32_t p1 = off[r + 1];
-    for (uint32_t p = off[r]; p < p1 && !over; ++p) {
-        int32_t v[K];
-        load_cell<K>(cells, inc[p], v);
+    const uint32_t p0 = off[r], p1 = off[r + 1];
+    // incident cells kChunk at a time: their loads are issued together, then
+    // their points are inserted (a cell past the end repeats the last one,
+    // whose points are then found already listed)
+    constexpr int kChunk = 4;
+    for (uint32_t p = p0; p < p1 && !over; p += kChunk) {
+        int32_t v[kChunk][K];
+        int32_t c[kChunk];
 #pragma unroll
-        for (int a = 0; a < K; ++a) {
-            const int32_t u = v[a];
-            if (u == (int32_t)r) continue;
-            int k = cnt;   // insertion point: after every entry below u
-            while (k > 0 && my[(k - 1) * kRowThreads] > u) --k;
-            if (k > 0 && my[(k - 1) * kRowThreads] == u) continue;   // already listed
-            if (cnt == kRowCap) {
-                over = true;
-                break;
+        for (int q = 0; q < kChunk; ++q) c[q] = inc[min(p + q, p1 - 1)];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) load_cell<K>(cells, c[q], v[q]);
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const int32_t u = v[q][a];
+                if (u == (int32_t)r || over) continue;
+                int k = cnt;   // insertion point: after every entry below u
+                while (k > 0 && my[(k - 1) * kRowThreads] > u) --k;
+                if (k > 0 && my[(k - 1) * kRowThreads] == u) continue;   // already listed
+                if (cnt == kRowCap) {
+                    over = true;
+                    continue;
+                }
+                for (int j = cnt; j > k; --j) my[j * kRowThreads] = my[(j - 1) * kRowThreads];
+                my[k * kRowThreads] = u;
+                ++cnt;
             }
-            for (int j = cnt; j > k; --j) my[j * kRowThreads] = my[(j - 1) * kRowThreads];
-            my[k * kRowThreads] = u;
-            ++cnt;
-        }
     }
     if constexpr (!WRITE) {
         if (over) longs[atomicAdd(n_long, 1u)] = (uint32_t)r;
@@ -334,12 +396,11 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
     FTLE_CHECK(hipMemsetAsync(cnt, 0, 4 * (size_t)(n + 1), stream));
     FTLE_CHECK(hipMemsetAsync(err, 0, 8, stream));
     if (n_cells > 0) {
+        const dim3 ag(blocks_for(n_cells, kAggThreads * kAggCells)), ab(kAggThreads);
         if (dim == 2)
-            hipLaunchKernelGGL(count_incidence<3>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, n,
-                               cnt, err);
+            hipLaunchKernelGGL((incidence_pass<3, false>), ag, ab, 0, stream, cells, n_cells, n, cnt, nullptr, err);
         else
-            hipLaunchKernelGGL(count_incidence<4>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, n,
-                               cnt, err);
+            hipLaunchKernelGGL((incidence_pass<4, false>), ag, ab, 0, stream, cells, n_cells, n, cnt, nullptr, err);
         FTLE_CHECK(hipGetLastError());
     }
     int flags = 0;
@@ -354,12 +415,11 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
     // 3. incidence lists
     FTLE_CHECK(hipMemcpyAsync(cur, cnt, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream));
     if (n_cells > 0) {
+        const dim3 ag(blocks_for(n_cells, kAggThreads * kAggCells)), ab(kAggThreads);
         if (dim == 2)
-            hipLaunchKernelGGL(fill_incidence<3>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, cur,
-                               inc);
+            hipLaunchKernelGGL((incidence_pass<3, true>), ag, ab, 0, stream, cells, n_cells, n, cur, inc, nullptr);
         else
-            hipLaunchKernelGGL(fill_incidence<4>, dim3(blocks_for(n_cells)), dim3(256), 0, stream, cells, n_cells, cur,
-                               inc);
+            hipLaunchKernelGGL((incidence_pass<4, true>), ag, ab, 0, stream, cells, n_cells, n, cur, inc, nullptr);
         FTLE_CHECK(hipGetLastError());
     }
     // 4. distinct counts, their offsets, then the lists
