@@ -97,6 +97,36 @@ class Mesh:
         m._init(h, coords.shape[1], coords.shape[0], dtype, host_only)
         return m
 
+    @classmethod
+    def on_device(cls, coords: torch.Tensor, cells: torch.Tensor, reorder: bool = True, tile_log2: int = 0,
+                  stream=None):
+        """Mesh built on the GPU from device tensors (ftle_create_mesh_device):
+        coords (N, dim) float32/float64 (the mesh dtype follows it), cells
+        (ncells, dim+1) int32, both contiguous on the current device.  The
+        one-ring stencil, the Morton order and the tile records all come from
+        kernels; the mesh equals Mesh(coords, cells) built on the host."""
+        if not (isinstance(coords, torch.Tensor) and coords.is_cuda and coords.is_contiguous()
+                and coords.dtype in (torch.float32, torch.float64) and coords.dim() == 2
+                and coords.shape[1] in (2, 3)):
+            raise ValueError("coords must be a contiguous float32/float64 device tensor of shape (N, 2) or (N, 3)")
+        dim = coords.shape[1]
+        if not (isinstance(cells, torch.Tensor) and cells.is_cuda and cells.dtype == torch.int32
+                and cells.is_contiguous() and cells.dim() == 2 and cells.shape[1] == dim + 1):
+            raise ValueError(f"cells must be a contiguous int32 device tensor of shape (ncells, {dim + 1})")
+        dtype = "f64" if coords.dtype == torch.float64 else "f32"
+        flags = _lib.tile_flag(tile_log2)
+        if not reorder:
+            flags |= _lib.NO_REORDER
+        h = ctypes.c_void_p()
+        ncells = cells.shape[0]
+        check(_lib.load().ftle_create_mesh_device(dim, coords.shape[0], ctypes.c_void_p(coords.data_ptr()),
+                                                  _DT[dtype][0], ncells,
+                                                  ctypes.c_void_p(cells.data_ptr()) if ncells else None, flags,
+                                                  _stream_handle(stream), ctypes.byref(h)))
+        m = cls.__new__(cls)
+        m._init(h, dim, coords.shape[0], dtype, False)
+        return m
+
     # -- lifetime ---------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

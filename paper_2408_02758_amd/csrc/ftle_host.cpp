@@ -196,6 +196,7 @@ struct TileSet {
     int max_rec = 0;
     int max_P = 0;
     int64_t halo_total = 0;
+    int64_t rec_bytes = 0;    // records on the device (rec holds a host copy unless built there)
     void* d_meta = nullptr;
     void* d_rec = nullptr;
     void* d_minv = nullptr;   // 3D forward tile set: inverse normal matrices (caller order)
@@ -223,8 +224,13 @@ struct ftle_mesh_s {
     int bwd_block = 256;
     bool symmetric = true;
     bool host_only = false;
+    bool device_built = false;     // perm, csr and tile records live on the device only
+    int64_t nnz = 0;               // stencil entries
     std::vector<int32_t> perm;     // Morton position -> user index
     Csr csr;                       // forward stencil, Morton positions
+    int32_t* d_perm = nullptr;     // device-built: perm, stencil row offsets (int64) and columns
+    int64_t* d_row_ptr = nullptr;
+    int32_t* d_col = nullptr;
     TileSet fwd, bwd;              // bwd empty when symmetric (fwd serves both)
     std::vector<unsigned char> x_user;   // coordinates, user order, dtype
     int device = -1;
@@ -613,6 +619,7 @@ TileSet build_tiles(int dim, bool f64, int64_t n, int tile_points, const Csr& a,
         ts.halo_total += m.H;
     }
     ts.rec.resize(off * 4);
+    ts.rec_bytes = (int64_t)off * 16;
     parallel_for((int64_t)ext.size(), [&](int64_t tb, int64_t te, int) {
         for (int64_t t = tb; t < te; ++t)
             std::copy(recs[t].begin(), recs[t].end(), ts.rec.begin() + (size_t)ts.meta[t].rec_off * 4);
@@ -665,6 +672,12 @@ void release_device(ftle_mesh_s* m)
     if (m->d_hits) (void)hipFree(m->d_hits);
     if (m->d_work) (void)hipFree(m->d_work);
     if (m->work_done) (void)hipEventDestroy(m->work_done);
+    if (m->d_perm) (void)hipFree(m->d_perm);
+    if (m->d_row_ptr) (void)hipFree(m->d_row_ptr);
+    if (m->d_col) (void)hipFree(m->d_col);
+    m->d_perm = nullptr;
+    m->d_row_ptr = nullptr;
+    m->d_col = nullptr;
     m->d_x = nullptr;
     m->d_hits = nullptr;
     m->d_work = nullptr;
@@ -767,19 +780,23 @@ ftle_status ftle_get_eig_threshold(double* tau)
 
 // The axis along which the caller's point order advances, or -1: over a
 // sample of consecutive caller indices the median step is about one spacing
-// along that axis and under a quarter spacing along every other axis.
-int caller_order_axis(int dim, int64_t n, const double* x, const double* unit)
+// along that axis and under a quarter spacing along every other axis.  The
+// sample: m pairs (points k stride and k stride + 1), none below 64 points.
+void order_sample(int64_t n, int64_t* m, int64_t* stride)
 {
-    if (n < 64) return -1;
-    const int64_t m = std::min<int64_t>(n - 1, 1 << 16);
-    const int64_t stride = (n - 1) / m;
+    *m = n < 64 ? 0 : std::min<int64_t>(n - 1, 1 << 16);
+    *stride = *m ? (n - 1) / *m : 0;
+}
+
+// pairs[k * 2 dim + d] and [k * 2 dim + dim + d]: axis d of the two points of sample k.
+int order_axis_from_pairs(int dim, int64_t m, const double* pairs, const double* unit)
+{
+    if (m == 0) return -1;
     double med[3] = {0, 0, 0};
     std::vector<double> v((size_t)m);
     for (int d = 0; d < dim; ++d) {
-        for (int64_t k = 0; k < m; ++k) {
-            const int64_t i = k * stride;
-            v[(size_t)k] = std::fabs(x[(i + 1) * dim + d] - x[i * dim + d]) / unit[d];
-        }
+        for (int64_t k = 0; k < m; ++k)
+            v[(size_t)k] = std::fabs(pairs[k * 2 * dim + dim + d] - pairs[k * 2 * dim + d]) / unit[d];
         std::nth_element(v.begin(), v.begin() + m / 2, v.end());
         med[d] = v[(size_t)(m / 2)];
     }
@@ -792,7 +809,73 @@ int caller_order_axis(int dim, int64_t n, const double* x, const double* unit)
     return f;
 }
 
-}  // extern "C"
+// Quantise each axis in units of the mean point spacing, with `sub`
+// fractional bits.  The unit is the span over n^(1/dim) - 1/2 points and the
+// offset 0.2 unit, so that floor() sends point i of an m-point lattice to i
+// (i (1 + 1/(2m-2)) + 0.2 < i + 1) and also keeps cell-centred points
+// jittered by up to +-0.3 spacing inside their own cell.  On such grids the
+// integer parts are the grid indices, runs of 2^(k*dim) consecutive codes are
+// aligned blocks and tiles have minimal halos; the fractional bits keep
+// irregular meshes finely ordered.  `range`: the largest span in units, plus
+// one.
+void morton_units(int dim, int64_t n, const double* lo, const double* hi, double* unit, double* range)
+{
+    const double per_axis = std::max(2.0, std::pow((double)n, 1.0 / dim));
+    *range = 1.0;
+    for (int d = 0; d < dim; ++d) {
+        const double span = hi[d] - lo[d];
+        unit[d] = span > 0 ? span / (per_axis - 0.5) : 1.0;
+        *range = std::max(*range, span / unit[d] + 1.0);
+    }
+}
+
+// With a caller order that walks one axis (consecutive caller indices one
+// spacing apart along it and fixed along the others, as in a structured grid
+// stored row by row) the other axes' codes move up one bit, so a run of 512
+// codes is a block long along that axis (32 x 16 in 2D, 16 x 8 x 4 instead of
+// 8^3 in 3D) and a tile's points form longer caller-order runs.  (Longer
+// blocks, 64 x 8 in 2D, grow the halo more than they gain.)  The fractional
+// bits shrink until the codes fit 31 bits per axis in 2D, 21 in 3D.
+MortonParams morton_params(int dim, const double* lo, const double* unit, double range, int fast)
+{
+    const int bits = (dim == 2) ? 31 : 21;
+    MortonParams mp{};
+    for (int d = 0; d < dim; ++d) {
+        mp.lo[d] = lo[d];
+        mp.unit[d] = unit[d];
+    }
+    mp.fast = fast;
+    mp.shift_bits = fast >= 0 ? 1 : 0;
+    int sub = 8;
+    while (sub > 0 && std::ldexp(range, sub + mp.shift_bits) >= std::ldexp(1.0, bits)) --sub;
+    mp.scale = std::ldexp(1.0, sub);
+    mp.qmax = std::ldexp(1.0, bits - mp.shift_bits) - 1.0;
+    return mp;
+}
+
+// The low bits that hold every code of these parameters: per axis the
+// quantised value stays below (range + 0.2) scale, shifted by shift_bits.
+int morton_key_bits(int dim, const MortonParams& mp, double range)
+{
+    const double top = std::min(mp.qmax + 1.0, std::ceil((range + 0.2) * mp.scale) + 1.0) * std::ldexp(1.0, mp.shift_bits);
+    int b = 1;
+    while (b < 64 && std::ldexp(1.0, b) < top) ++b;
+    return std::min(64, dim * b);
+}
+
+uint64_t morton_code(int dim, const MortonParams& mp, const double* xi)
+{
+    uint64_t code = 0;
+    for (int d = 0; d < dim; ++d) {
+        const double t = std::floor(((xi[d] - mp.lo[d]) / mp.unit[d] + 0.2) * mp.scale);
+        uint64_t q = (uint64_t)std::min(mp.qmax, std::max(0.0, t));
+        if (mp.fast >= 0 && d != mp.fast) q <<= mp.shift_bits;
+        code |= (dim == 2 ? spread2(q) : spread3(q)) << d;
+    }
+    return code;
+}
+
+}  // namespace
 
 namespace {
 
@@ -825,48 +908,17 @@ ftle_mesh_t build_mesh(int dim, int64_t n, const void* coords, ftle_dtype dtype,
                 lo[d] = std::min(lo[d], xd[i * dim + d]);
                 hi[d] = std::max(hi[d], xd[i * dim + d]);
             }
-        // Quantise each axis in units of the mean point spacing, with
-        // `sub` fractional bits.  The unit is the span over n^(1/dim) - 1/2
-        // points and the offset 0.2 unit, so that floor() sends point i of
-        // an m-point lattice to i (i (1 + 1/(2m-2)) + 0.2 < i + 1) and also
-        // keeps cell-centred points jittered by up to +-0.3 spacing inside
-        // their own cell.  On such grids the integer parts are the grid
-        // indices, runs of 2^(k*dim) consecutive codes are aligned blocks
-        // and tiles have minimal halos; the fractional bits keep irregular
-        // meshes finely ordered.
-        const int bits = (dim == 2) ? 31 : 21;
-        const double per_axis = std::max(2.0, std::pow((double)n, 1.0 / dim));
-        double unit[3] = {1, 1, 1};
-        double range = 1.0;
-        for (int d = 0; d < dim; ++d) {
-            const double span = hi[d] - lo[d];
-            unit[d] = span > 0 ? span / (per_axis - 0.5) : 1.0;
-            range = std::max(range, span / unit[d] + 1.0);
-        }
-        // Caller order that walks one axis (consecutive caller indices one
-        // spacing apart along it and fixed along the others, as in a
-        // structured grid stored row by row): the other axes' codes move up
-        // one bit, so a run of 512 codes is a block long along that axis
-        // (32 x 16 in 2D, 16 x 8 x 4 instead of 8^3 in 3D) and a tile's
-        // points form longer caller-order runs.  (Longer blocks, 64 x 8 in
-        // 2D, grow the halo more than they gain.)
-        const int fast = caller_order_axis(dim, n, xd.data(), unit);
-        const int shift_bits = fast >= 0 ? 1 : 0;
-        int sub = 8;
-        while (sub > 0 && std::ldexp(range, sub + shift_bits) >= std::ldexp(1.0, bits)) --sub;
-        const double qmax = std::ldexp(1.0, bits - shift_bits) - 1.0;
+        double unit[3] = {1, 1, 1}, range = 1.0;
+        morton_units(dim, n, lo, hi, unit, &range);
+        int64_t ms = 0, stride = 0;
+        order_sample(n, &ms, &stride);
+        std::vector<double> pairs((size_t)ms * 2 * dim);
+        for (int64_t k = 0; k < ms; ++k)
+            for (int d = 0; d < 2 * dim; ++d) pairs[(size_t)k * 2 * dim + d] = xd[(size_t)k * stride * dim + d];
+        const MortonParams mp = morton_params(dim, lo, unit, range, order_axis_from_pairs(dim, ms, pairs.data(), unit));
         std::vector<uint64_t> key(n);
         parallel_for(n, [&](int64_t b, int64_t e, int) {
-            for (int64_t i = b; i < e; ++i) {
-                uint64_t code = 0;
-                for (int d = 0; d < dim; ++d) {
-                    const double t = std::floor(((xd[i * dim + d] - lo[d]) / unit[d] + 0.2) * std::ldexp(1.0, sub));
-                    uint64_t q = (uint64_t)std::min(qmax, std::max(0.0, t));
-                    if (fast >= 0 && d != fast) q <<= shift_bits;
-                    code |= (dim == 2 ? spread2(q) : spread3(q)) << d;
-                }
-                key[i] = code;
-            }
+            for (int64_t i = b; i < e; ++i) key[i] = morton_code(dim, mp, &xd[(size_t)i * dim]);
         });
         radix_sort_pairs(key, m->perm);
     }
@@ -874,6 +926,7 @@ ftle_mesh_t build_mesh(int dim, int64_t n, const void* coords, ftle_dtype dtype,
     for (int64_t r = 0; r < n; ++r) inv[m->perm[r]] = (int32_t)r;
 
     m->csr = stencil(m->perm, inv);
+    m->nnz = (int64_t)m->csr.col.size();
     Csr tr = transpose(m->csr, n);
     m->symmetric = csr_equal(tr, m->csr);
     m->fwd = build_tiles(dim, f64, n, m->tile_points, m->csr, m->perm);
@@ -926,6 +979,303 @@ std::vector<double> checked_coords(int dim, int64_t n_points, const void* coords
         xd[i] = v;
     }
     return xd;
+}
+
+// ---------------------------------------------------------------------------
+// The mesh build on the device (ftle_create_mesh_device): the same steps and
+// the same result as build_mesh with the one-ring stencil, with every pass
+// over points, cells or stencil entries in the kernels of ftle_meshbuild.hip
+// and ftle_neighbours.hip.  The host keeps the control: the bounding box
+// reduction over workgroups, the caller-order test on a 2^16-pair sample, the
+// tile-size halving and the record offsets, each from a small download.
+// ---------------------------------------------------------------------------
+
+// A device allocation freed on scope exit unless released.
+struct DevBuf {
+    void* p = nullptr;
+    DevBuf() = default;
+    explicit DevBuf(size_t bytes) { check_hip(hipMalloc(&p, bytes ? bytes : 16), "hipMalloc"); }
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    template <typename T>
+    T* as() const
+    {
+        return static_cast<T*>(p);
+    }
+    void reset()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    void* release()
+    {
+        void* q = p;
+        p = nullptr;
+        return q;
+    }
+};
+
+void to_host(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    if (!bytes) return;
+    check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+void to_device(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    if (!bytes) return;
+    check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+struct Extent {
+    int64_t b, e;
+    uint32_t H, nw;
+};
+
+// Tile extents as build_tiles cuts them: nominal chunks of tile_points,
+// halved until they fit; the halo and word counts of all candidates of one
+// generation come from one launch.
+std::vector<Extent> device_extents(int dim, bool f64, int64_t n, int tile_points, const int64_t* row_ptr,
+                                   const int32_t* col, const int32_t* perm, hipStream_t s)
+{
+    std::vector<std::pair<int64_t, int64_t>> todo, next;
+    for (int64_t b = 0; b < n; b += tile_points) todo.push_back({b, std::min<int64_t>(n, b + tile_points)});
+    std::vector<Extent> out;
+    std::vector<int64_t> ranges;
+    std::vector<uint32_t> hw;
+    while (!todo.empty()) {
+        ranges.resize(2 * todo.size());
+        for (size_t i = 0; i < todo.size(); ++i) {
+            ranges[2 * i] = todo[i].first;
+            ranges[2 * i + 1] = todo[i].second;
+        }
+        DevBuf d_ranges(ranges.size() * 8), d_hw(todo.size() * 8);
+        to_device(d_ranges.p, ranges.data(), ranges.size() * 8, s);
+        check_hip(mb_tile_extent(row_ptr, col, d_ranges.as<int64_t>(), (int64_t)todo.size(), d_hw.as<uint32_t>(), s),
+                  "tile extent kernel");
+        hw.resize(2 * todo.size());
+        to_host(hw.data(), d_hw.p, hw.size() * 4, s);
+        next.clear();
+        for (size_t i = 0; i < todo.size(); ++i) {
+            const auto [b, e] = todo[i];
+            if (tile_fits(dim, f64, e - b, hw[2 * i], hw[2 * i + 1])) {
+                out.push_back({b, e, hw[2 * i], hw[2 * i + 1]});
+            } else if (e - b == 1) {
+                int64_t rp[2];
+                int32_t user = 0;
+                to_host(rp, row_ptr + b, sizeof rp, s);
+                to_host(&user, perm + b, sizeof user, s);
+                fail(FTLE_ERR_UNSUPPORTED, "point " + std::to_string(user) + " has " + std::to_string(rp[1] - rp[0]) +
+                                               " neighbours, more than one tile holds");
+            } else {
+                const int64_t m = b + (e - b) / 2;
+                next.push_back({b, m});
+                next.push_back({m, e});
+            }
+        }
+        todo.swap(next);
+    }
+    std::sort(out.begin(), out.end(), [](const Extent& u, const Extent& v) { return u.b < v.b; });
+    return out;
+}
+
+// The records of the tiles `ext` (two passes: sizes and rows, then the
+// records at their offsets), into ts (meta on host and device, records on
+// the device).
+void device_tiles(const std::vector<Extent>& ext, const int64_t* row_ptr, const int32_t* col, const int32_t* perm,
+                  TileSet& ts, hipStream_t s)
+{
+    const size_t T = ext.size();
+    std::vector<int64_t> ranges(2 * T), row_base(T);
+    int64_t entries = 0;
+    for (size_t t = 0; t < T; ++t) {
+        ranges[2 * t] = ext[t].b;
+        ranges[2 * t + 1] = ext[t].e;
+        row_base[t] = entries;
+        entries += 3 * (int64_t)ext[t].nw;
+    }
+    DevBuf d_ranges(T * 16), d_base(T * 8), d_rows((size_t)entries * 2), d_counts(T * 16);
+    to_device(d_ranges.p, ranges.data(), T * 16, s);
+    to_device(d_base.p, row_base.data(), T * 8, s);
+    const uint32_t* uperm = reinterpret_cast<const uint32_t*>(perm);
+    check_hip(mb_tile_record(false, row_ptr, col, uperm, d_ranges.as<int64_t>(), (int64_t)T, d_base.as<int64_t>(),
+                             d_rows.as<uint16_t>(), d_counts.as<uint32_t>(), nullptr, nullptr, s),
+              "tile record kernel (sizes)");
+    std::vector<uint32_t> counts(4 * T);
+    to_host(counts.data(), d_counts.p, T * 16, s);
+    ts.meta.resize(T);
+    uint64_t off = 0;   // in 16-byte units
+    for (size_t t = 0; t < T; ++t) {
+        const uint32_t* c = &counts[4 * t];
+        if (c[0] > (uint32_t)kMaxTileWords || c[3] != ext[t].nw)
+            fail(FTLE_ERR_DEVICE, "tile " + std::to_string(t) + ": record sizes disagree with its extent");
+        if (off > UINT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "tile records exceed 64 GiB");
+        TileMeta& m = ts.meta[t];
+        m.rec_off = (uint32_t)off;
+        m.P = (uint16_t)(ext[t].e - ext[t].b);
+        m.H = (uint16_t)ext[t].H;
+        m.nw = (uint16_t)c[0];
+        m.nr = (uint16_t)c[1];
+        m.nx = (uint16_t)c[2];
+        m.nwf = (uint16_t)c[3];
+        const uint32_t bytes = rec_layout(m).bytes;
+        off += bytes / 16;
+        ts.max_staged = std::max(ts.max_staged, (int)(m.P + m.H));
+        ts.max_rec = std::max(ts.max_rec, (int)bytes);
+        ts.max_P = std::max(ts.max_P, (int)m.P);
+        ts.halo_total += m.H;
+    }
+    ts.rec_bytes = (int64_t)off * 16;
+    ts.d_meta = dev_upload(ts.meta.data(), T * sizeof(TileMeta));
+    ts.d_rec = dev_upload(nullptr, (size_t)ts.rec_bytes);
+    check_hip(hipMemsetAsync(ts.d_rec, 0, (size_t)ts.rec_bytes, s), "hipMemsetAsync");
+    check_hip(mb_tile_record(true, row_ptr, col, uperm, d_ranges.as<int64_t>(), (int64_t)T, d_base.as<int64_t>(),
+                             d_rows.as<uint16_t>(), nullptr, static_cast<const TileMeta*>(ts.d_meta),
+                             static_cast<unsigned char*>(ts.d_rec), s),
+              "tile record kernel (records)");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype dtype, int64_t n_cells,
+                              const int32_t* cells, unsigned flags, int tile_log2, hipStream_t s)
+{
+    const bool f64 = dtype == FTLE_F64;
+    const size_t eb = f64 ? 8 : 4;
+    const int k = dim + 1;
+    std::unique_ptr<ftle_mesh_s> m(new ftle_mesh_s);
+    m->dim = dim;
+    m->n = n;
+    m->dtype = dtype;
+    m->flags = flags;
+    m->device_built = true;
+    m->tile_points = tile_log2 ? (1 << tile_log2) : 512;
+    m->fwd_block = (dim == 2) ? 256 : 512;
+    m->bwd_block = (dim == 2) ? 256 : 512;
+    check_hip(hipGetDevice(&m->device), "hipGetDevice (no usable GPU?)");
+    struct Release {
+        ftle_mesh_s* m;
+        ~Release()
+        {
+            if (m) release_device(m);
+        }
+    } guard{m.get()};
+
+    // the mesh's own copy of the coordinates; bounds and finiteness
+    m->d_x = dev_upload(nullptr, (size_t)n * dim * eb);
+    check_hip(hipMemcpyAsync(m->d_x, coords, (size_t)n * dim * eb, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    DevBuf part((size_t)nb * 2 * dim * 8 + 8);
+    unsigned long long* first_bad = reinterpret_cast<unsigned long long*>(part.as<double>() + (size_t)nb * 2 * dim);
+    check_hip(hipMemsetAsync(first_bad, 0xff, 8, s), "hipMemsetAsync");
+    check_hip(mb_bbox(dim, f64, m->d_x, n, part.as<double>(), nb, first_bad, s), "bounds kernel");
+    std::vector<double> hp((size_t)nb * 2 * dim + 1);
+    to_host(hp.data(), part.p, hp.size() * 8, s);
+    unsigned long long bad = 0;
+    std::memcpy(&bad, &hp.back(), 8);
+    if (bad != ~0ull) fail(FTLE_ERR_INVALID_ARG, "coordinate " + std::to_string(bad) + " is not finite");
+
+    // Morton order
+    DevBuf perm((size_t)n * 4);
+    if (!(flags & FTLE_NO_REORDER) && n > 1) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int b = 0; b < nb; ++b)
+            for (int d = 0; d < dim; ++d) {
+                lo[d] = std::min(lo[d], hp[(size_t)b * 2 * dim + d]);
+                hi[d] = std::max(hi[d], hp[(size_t)b * 2 * dim + dim + d]);
+            }
+        double unit[3] = {1, 1, 1}, range = 1.0;
+        morton_units(dim, n, lo, hi, unit, &range);
+        int64_t ms = 0, stride = 0;
+        order_sample(n, &ms, &stride);
+        std::vector<double> pairs((size_t)ms * 2 * dim);
+        if (ms) {
+            DevBuf d_pairs(pairs.size() * 8);
+            check_hip(mb_gather_pairs(dim, f64, m->d_x, ms, stride, d_pairs.as<double>(), s), "sample kernel");
+            to_host(pairs.data(), d_pairs.p, pairs.size() * 8, s);
+        }
+        const MortonParams mp = morton_params(dim, lo, unit, range, order_axis_from_pairs(dim, ms, pairs.data(), unit));
+        DevBuf key((size_t)n * 8), scratch(mb_sort_scratch_bytes(n));
+        check_hip(mb_morton(dim, f64, m->d_x, n, mp, key.as<uint64_t>(), perm.as<uint32_t>(), s), "Morton kernel");
+        uint32_t* sorted = nullptr;
+        check_hip(mb_sort(key.as<uint64_t>(), perm.as<uint32_t>(), n, morton_key_bits(dim, mp, range), scratch.p,
+                          &sorted, s),
+                  "radix sort");
+        if (sorted != perm.as<uint32_t>())
+            check_hip(hipMemcpyAsync(perm.p, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+    } else {
+        check_hip(mb_iota(perm.as<uint32_t>(), n, s), "iota kernel");
+    }
+
+    // cells in Morton positions (validated), then the one-ring stencil
+    DevBuf mc((size_t)n_cells * k * 4), row_ptr(((size_t)n + 1) * 8);
+    {
+        DevBuf inv((size_t)n * 4), flag(16);
+        check_hip(hipMemsetAsync(flag.p, 0xff, 8, s), "hipMemsetAsync");
+        check_hip(hipMemsetAsync(flag.as<unsigned char>() + 8, 0, 4, s), "hipMemsetAsync");
+        check_hip(mb_invert(perm.as<uint32_t>(), n, inv.as<int32_t>(), s), "inverse permutation kernel");
+        check_hip(mb_relabel(dim, cells, n_cells, n, inv.as<int32_t>(), mc.as<int32_t>(),
+                             reinterpret_cast<int*>(flag.as<unsigned char>() + 8), flag.as<unsigned long long>(), s),
+                  "cell relabel kernel");
+        unsigned long long hf[2] = {0, 0};
+        to_host(hf, flag.p, 12, s);
+        if (hf[1] & 0xffffffffu) {
+            const int64_t c = (int64_t)hf[0];
+            int32_t v[4] = {0, 0, 0, 0};
+            to_host(v, cells + c * k, (size_t)k * 4, s);
+            int kind = 0;   // the first fault in vertex order, as the host build reports it
+            for (int a = 0; a < k && !kind; ++a) {
+                if (v[a] < 0 || v[a] >= n) kind = 1;
+                for (int q = 0; q < a && !kind; ++q)
+                    if (v[q] == v[a]) kind = 2;
+            }
+            fail(FTLE_ERR_BAD_MESH, std::string(kind == 1 ? "cell index out of range" : "repeated vertex") +
+                                        " in cell " + std::to_string(c));
+        }
+    }
+    int64_t nnz = 0;
+    {
+        DevBuf ws(ring1_workspace_bytes(dim, n, n_cells));
+        int bad_mesh = 0, too_long = 0;
+        check_hip(ring1_build(dim, mc.as<int32_t>(), n_cells, n, ws.p, row_ptr.as<int64_t>(), nullptr, 0, &nnz,
+                              &bad_mesh, &too_long, s),
+                  "one-ring stencil kernels");
+        if (bad_mesh) fail(FTLE_ERR_DEVICE, "relabelled cells failed the stencil's range check");
+        if (too_long) fail(FTLE_ERR_UNSUPPORTED, "a point's incident cells list more than 4096 points");
+        if (nnz > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
+        m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
+        if (nnz)
+            check_hip(ring1_write(dim, mc.as<int32_t>(), n_cells, n, ws.p, row_ptr.as<int64_t>(), m->d_col, s),
+                      "one-ring stencil kernels");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    mc.reset();
+    m->nnz = nnz;
+    m->d_row_ptr = static_cast<int64_t*>(row_ptr.release());
+    m->d_perm = static_cast<int32_t*>(perm.release());
+    // the one-ring relation is symmetric: the forward tiles serve the adjoint
+    m->symmetric = true;
+
+    const std::vector<Extent> ext =
+        device_extents(dim, f64, n, m->tile_points, m->d_row_ptr, m->d_col, m->d_perm, s);
+    device_tiles(ext, m->d_row_ptr, m->d_col, m->d_perm, m->fwd, s);
+    if (dim == 3) {
+        m->fwd.d_minv = dev_upload(nullptr, (size_t)n * 6 * eb);
+        check_hip(mb_normal_inverse(f64, m->d_row_ptr, m->d_col, reinterpret_cast<const uint32_t*>(m->d_perm), m->d_x,
+                                    n, m->fwd.d_minv, s),
+                  "normal matrix kernel");
+    }
+    m->d_hits = static_cast<unsigned long long*>(dev_upload(nullptr, sizeof(unsigned long long)));
+    check_hip(hipMemsetAsync(m->d_hits, 0, sizeof(unsigned long long), s), "hipMemsetAsync");
+    check_hip(hipEventCreateWithFlags(&m->work_done, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    guard.m = nullptr;
+    return m.release();
 }
 
 }  // namespace
@@ -1038,13 +1388,40 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
     });
 }
 
+ftle_status ftle_create_mesh_device(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                                    int64_t n_cells, const int32_t* cells, unsigned flags, ftle_stream_t stream,
+                                    ftle_mesh_t* out)
+{
+    return guarded([&] {
+        if (!out) fail(FTLE_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points must be >= 1");
+        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+        if (!coords) fail(FTLE_ERR_INVALID_ARG, "coords is NULL");
+        if (flags & (FTLE_STENCIL_AXIS | FTLE_HOST_ONLY))
+            fail(FTLE_ERR_UNSUPPORTED, "the device build makes one-ring stencils on the device only");
+        if (flags & ~(unsigned)(FTLE_NO_REORDER | FTLE_TILE(0xff))) fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
+        const int tile_log2 = (int)((flags >> 8) & 0xff);
+        if (tile_log2 != 0 && (tile_log2 < 5 || tile_log2 > 11))
+            fail(FTLE_ERR_INVALID_ARG, "FTLE_TILE(k) needs 5 <= k <= 11");
+        if (n_cells < 0) fail(FTLE_ERR_INVALID_ARG, "n_cells < 0");
+        if (n_cells > 0 && !cells) fail(FTLE_ERR_INVALID_ARG, "cells is NULL");
+        if (n_cells > (int64_t)(UINT32_MAX / (unsigned)(dim + 1)))
+            fail(FTLE_ERR_UNSUPPORTED, "n_cells (dim + 1) must stay below 2^32");
+        const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        *out = build_mesh_device(dim, n_points, coords, dtype, n_cells, cells, flags, tile_log2, s);
+    });
+}
+
 ftle_status ftle_mesh_info(ftle_mesh_t mesh, int* dim, int64_t* n_points, int64_t* nnz, int* dtype)
 {
     return guarded([&] {
         check_mesh(mesh);
         if (dim) *dim = mesh->dim;
         if (n_points) *n_points = mesh->n;
-        if (nnz) *nnz = (int64_t)mesh->csr.col.size();
+        if (nnz) *nnz = mesh->nnz;
         if (dtype) *dtype = (int)mesh->dtype;
     });
 }
@@ -1053,6 +1430,20 @@ ftle_status ftle_mesh_get_csr(ftle_mesh_t mesh, int32_t* row_ptr, int32_t* col, 
 {
     return guarded([&] {
         check_mesh(mesh);
+        if (mesh->device_built) {
+            // copied from the device (row offsets narrowed: nnz <= 2^31 - 1 is checked when built)
+            DeviceScope scope(mesh->device);
+            const int64_t n = mesh->n;
+            if (row_ptr) {
+                std::vector<int64_t> rp((size_t)n + 1);
+                check_hip(hipMemcpy(rp.data(), mesh->d_row_ptr, rp.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+                for (int64_t i = 0; i <= n; ++i) row_ptr[i] = (int32_t)rp[(size_t)i];
+            }
+            if (col && mesh->nnz)
+                check_hip(hipMemcpy(col, mesh->d_col, (size_t)mesh->nnz * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+            if (perm) check_hip(hipMemcpy(perm, mesh->d_perm, (size_t)n * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+            return;
+        }
         if (row_ptr) std::memcpy(row_ptr, mesh->csr.row_ptr.data(), mesh->csr.row_ptr.size() * 4);
         if (col) std::memcpy(col, mesh->csr.col.data(), mesh->csr.col.size() * 4);
         if (perm) std::memcpy(perm, mesh->perm.data(), mesh->perm.size() * 4);
@@ -1067,7 +1458,7 @@ ftle_status ftle_mesh_tile_stats(ftle_mesh_t mesh, int64_t* n_tiles, int64_t* ma
         if (n_tiles) *n_tiles = (int64_t)mesh->fwd.meta.size();
         if (max_tile_points) *max_tile_points = mesh->fwd.max_P;
         if (halo_entries) *halo_entries = mesh->fwd.halo_total;
-        if (record_bytes) *record_bytes = (int64_t)(mesh->fwd.rec.size() * 4 + mesh->fwd.meta.size() * 16);
+        if (record_bytes) *record_bytes = mesh->fwd.rec_bytes + (int64_t)mesh->fwd.meta.size() * 16;
     });
 }
 
@@ -1098,9 +1489,16 @@ ftle_status ftle_mesh_get_tiles(ftle_mesh_t mesh, int adjoint, int64_t* n_tiles,
         check_mesh(mesh);
         const TileSet& ts = adjoint ? mesh->adj_tiles() : mesh->fwd;
         if (n_tiles) *n_tiles = (int64_t)ts.meta.size();
-        if (record_bytes) *record_bytes = (int64_t)ts.rec.size() * 4;
+        if (record_bytes) *record_bytes = ts.rec_bytes;
         if (meta) std::memcpy(meta, ts.meta.data(), ts.meta.size() * sizeof(TileMeta));
-        if (records) std::memcpy(records, ts.rec.data(), ts.rec.size() * 4);
+        if (records && ts.rec_bytes) {
+            if (mesh->device_built) {
+                DeviceScope scope(mesh->device);
+                check_hip(hipMemcpy(records, ts.d_rec, (size_t)ts.rec_bytes, hipMemcpyDeviceToHost), "hipMemcpy");
+            } else {
+                std::memcpy(records, ts.rec.data(), (size_t)ts.rec_bytes);
+            }
+        }
     });
 }
 

@@ -188,10 +188,69 @@ hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, co
 // point whose incident cells list more than 4096 points) may be set;
 // otherwise *nnz holds the entry count, and row_ptr / col are written when it
 // is at most col_capacity.  Synchronises the stream.
+// col = NULL: count only (row_ptr written, nothing else); ring1_write then
+// writes col from the same workspace.
 size_t ring1_workspace_bytes(int dim, int64_t n, int64_t n_cells);
 hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace, int64_t* row_ptr,
                        int32_t* col, int64_t col_capacity, int64_t* nnz, int* bad_mesh, int* too_long,
                        hipStream_t stream);
+hipError_t ring1_write(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace,
+                       const int64_t* row_ptr, int32_t* col, hipStream_t stream);
+// Exclusive scan of m uint32 values into out[0..m), out[m] = their sum
+// (in and out may coincide); partial: scan_partial_bytes(m) of device scratch.
+hipError_t scan_exclusive_u32(const uint32_t* in, int64_t m, uint32_t* out, uint32_t* partial, hipStream_t stream);
+size_t scan_partial_bytes(int64_t m);
+
+// Morton quantisation of the points (both mesh builders): axis d of a point
+// maps to q = clamp(floor(((x_d - lo_d) / unit_d + 0.2) * scale), 0, qmax),
+// shifted up shift_bits when d is not the caller-order axis `fast` (>= 0),
+// and the axes' bits are interleaved (axis d at bit positions d, d + dim, ...).
+struct MortonParams {
+    double lo[3];
+    double unit[3];
+    double scale;   // 2^sub, sub fractional bits per unit
+    double qmax;
+    int fast;       // caller-order axis, or -1
+    int shift_bits;
+};
+
+// The mesh build on the device (ftle_meshbuild.hip).  Each launcher returns
+// hipSuccess or the launch error; none synchronises.
+//   mb_bbox: per-workgroup minima and maxima (part[b * 2 dim + d], then the
+//     maxima at + dim) over nblocks workgroups; *first_bad (set to ~0 before)
+//     gets the lowest point with a coordinate that is not finite
+//   mb_gather_pairs: sample k = points k stride and k stride + 1, as float64
+//   mb_morton: codes key[i] and values val[i] = i
+//   mb_sort: stable sort of (key, val) by the low key_bits bits of key;
+//     *sorted_val is val or a buffer inside scratch (mb_sort_scratch_bytes)
+//   mb_invert: inv[perm[r]] = r
+//   mb_relabel: cells renumbered to Morton positions; a cell with an index
+//     outside [0, n) or a repeated point sets *flag and lowers *first
+//   mb_tile_extent: for ranges [b, e) (int64 pairs) of the Morton order, the
+//     halo size (kMaxStaged + 1 when larger) and the padded stencil words
+//   mb_tile_record: write = false sizes each tile's record (counts[4 t] =
+//     explicit words, runs, explicit rows, all words) and fills the row
+//     buffer; write = true writes the records at 16 meta[t].rec_off bytes
+//   mb_normal_inverse: the 3D inverse normal matrices (caller order)
+hipError_t mb_bbox(int dim, bool f64, const void* x, int64_t n, double* part, int nblocks,
+                   unsigned long long* first_bad, hipStream_t s);
+hipError_t mb_gather_pairs(int dim, bool f64, const void* x, int64_t m, int64_t stride, double* out, hipStream_t s);
+hipError_t mb_morton(int dim, bool f64, const void* x, int64_t n, const MortonParams& mp, uint64_t* key,
+                     uint32_t* val, hipStream_t s);
+size_t mb_sort_scratch_bytes(int64_t n);
+hipError_t mb_sort(uint64_t* key, uint32_t* val, int64_t n, int key_bits, void* scratch, uint32_t** sorted_val,
+                   hipStream_t s);
+hipError_t mb_iota(uint32_t* v, int64_t n, hipStream_t s);
+hipError_t mb_invert(const uint32_t* perm, int64_t n, int32_t* inv, hipStream_t s);
+hipError_t mb_relabel(int dim, const int32_t* cells, int64_t n_cells, int64_t n, const int32_t* inv, int32_t* mc,
+                      int* flag, unsigned long long* first, hipStream_t s);
+hipError_t mb_tile_extent(const int64_t* row_ptr, const int32_t* col, const int64_t* ranges, int64_t n_ranges,
+                          uint32_t* halo_words, hipStream_t s);
+hipError_t mb_tile_record(bool write, const int64_t* row_ptr, const int32_t* col, const uint32_t* perm,
+                          const int64_t* ranges, int64_t n_tiles, const int64_t* row_base, uint16_t* rowbuf,
+                          uint32_t* counts, const TileMeta* meta, unsigned char* rec, hipStream_t s);
+hipError_t mb_normal_inverse(bool f64, const int64_t* row_ptr, const int32_t* col, const uint32_t* perm,
+                             const void* x, int64_t n, void* out, hipStream_t s);
 
 // The paper's fixed-width axis list (ftle_ell.hip): the forward from it (one
 // lane per caller point; staged: each workgroup's block of points in LDS),

@@ -446,7 +446,31 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
         *too_long = 1;
         return hipSuccess;
     }
-    if (total > col_capacity || total == 0) return hipSuccess;
+    if (!col || total > col_capacity || total == 0) return hipSuccess;
+    return ring1_write(dim, cells, n_cells, n, workspace, row_ptr, col, stream);
+#undef FTLE_CHECK
+}
+
+hipError_t ring1_write(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace,
+                       const int64_t* row_ptr, int32_t* col, hipStream_t stream)
+{
+    const int K = dim + 1;
+    unsigned char* w = static_cast<unsigned char*>(workspace);
+    auto carve = [&](size_t bytes) {
+        void* p = w;
+        w += align256(bytes);
+        return p;
+    };
+    uint32_t* cnt = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
+    (void)carve(4 * (size_t)n);
+    int32_t* inc = static_cast<int32_t*>(carve(4 * (size_t)K * n_cells));
+    uint32_t* deg = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
+    uint32_t* longs = static_cast<uint32_t*>(carve(4 * (size_t)n));
+    const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile + 1;
+    (void)carve(8 * (size_t)tiles);
+    int* err = static_cast<int*>(carve(256));
+    uint32_t* n_long = reinterpret_cast<uint32_t*>(err + 1);
+    const dim3 rg(blocks_for(n, kRowThreads)), rb(kRowThreads);
     if (dim == 2) {
         hipLaunchKernelGGL((ring_rows<3, true>), rg, rb, 0, stream, cells, inc, cnt, n, deg, row_ptr, col, longs,
                            n_long);
@@ -458,9 +482,14 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
         hipLaunchKernelGGL((long_rows<4, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
                            n_long, deg, row_ptr, col, err);
     }
-    FTLE_CHECK(hipGetLastError());
-#undef FTLE_CHECK
-    return hipSuccess;
+    return hipGetLastError();
 }
+
+hipError_t scan_exclusive_u32(const uint32_t* in, int64_t m, uint32_t* out, uint32_t* partial, hipStream_t stream)
+{
+    return exclusive_scan<uint32_t>(in, m, out, partial, stream);
+}
+
+size_t scan_partial_bytes(int64_t m) { return 8 * (size_t)((m + kScanTile - 1) / kScanTile + 1); }
 
 }  // namespace ftle

@@ -1,0 +1,239 @@
+"""The mesh built on the GPU (ftle_create_mesh_device) against the host build
+and the oracle.
+
+Integer work with one correct answer, so every comparison is exact: the
+stencil mapped back to caller indices equals the oracle's one-ring stencil
+(the neighbour determination of Section 2.2); the permutation, stencil, tile
+metadata and record bytes equal those of ftle_create_mesh on the same
+arguments; and since every later call reads only those, the FTLE of both
+meshes agrees bit for bit (the 3D tape forward also reads the inverse normal
+matrices, formed on each side in float64 without contraction)."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_02758_amd as F
+from paper_2408_02758_amd import _lib
+from workloads import meshes
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _raw_tiles(m):
+    L = _lib.load()
+    nt, rb = ctypes.c_int64(), ctypes.c_int64()
+    _lib.check(L.ftle_mesh_get_tiles(m.handle, 0, ctypes.byref(nt), ctypes.byref(rb), None, None))
+    meta = np.empty(nt.value * 16, np.uint8)
+    rec = np.empty(max(rb.value, 16), np.uint8)
+    _lib.check(L.ftle_mesh_get_tiles(m.handle, 0, None, None, meta.ctypes.data, rec.ctypes.data))
+    return meta, rec[:rb.value]
+
+
+def _device_mesh(x, cells, dtype, **kw):
+    npdt = np.float64 if dtype == "f64" else np.float32
+    xd = torch.as_tensor(np.ascontiguousarray(x, dtype=npdt), device=DEV)
+    cd = torch.as_tensor(np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, x.shape[1] + 1), device=DEV)
+    return F.Mesh.on_device(xd, cd, **kw)
+
+
+def _oracle_rows(dim, n, cells):
+    st = oracle.ring1(dim, n, cells)
+    return st.row_ptr, st.col
+
+
+def _user_order_csr(m):
+    """The mesh's stencil in caller indices, rows ascending (compare with the oracle's)."""
+    rp, col, perm = m.csr()
+    n = m.n
+    lens = np.diff(rp.astype(np.int64))
+    rows_user = np.repeat(perm.astype(np.int64), lens)
+    cols_user = perm[col].astype(np.int64)
+    order = np.lexsort((cols_user, rows_user))
+    out_rp = np.zeros(n + 1, np.int64)
+    np.add.at(out_rp, rows_user + 1, 1)
+    return np.cumsum(out_rp), cols_user[order].astype(np.int32)
+
+
+def same_bits(a, b):
+    """Equal bit patterns (NaN where a point has no usable FTLE on both sides)."""
+    it = torch.int64 if a.dtype == torch.float64 else torch.int32
+    return a.shape == b.shape and torch.equal(a.contiguous().view(it), b.contiguous().view(it))
+
+
+def _flow(x, seed):
+    g = np.random.default_rng(seed)
+    a = g.normal(size=(x.shape[1], x.shape[1])) * 0.3
+    return x + np.sin(x @ a) * 0.05
+
+
+def assert_same_mesh(x, cells, dtype="f32", tile_log2=0, reorder=True, check_oracle=True, T=2.0):
+    dim = x.shape[1]
+    n = x.shape[0]
+    print(f"[device mesh dim={dim} n={n} cells={len(cells)} {dtype} tile={tile_log2} reorder={reorder}]",
+          flush=True)
+    host = F.Mesh(x, cells, dtype, tile_log2=tile_log2, reorder=reorder)
+    dev = _device_mesh(x, cells, dtype, tile_log2=tile_log2, reorder=reorder)
+    assert dev.info() == host.info()
+    for name, a, b in zip(("row_ptr", "col", "perm"), dev.csr(), host.csr()):
+        assert a.shape == b.shape and np.array_equal(a, b), \
+            f"{name} differs at {np.flatnonzero(a != b)[:8] if a.shape == b.shape else a.shape}"
+    assert dev.tile_stats() == host.tile_stats()
+    dm, dr = _raw_tiles(dev)
+    hm, hr = _raw_tiles(host)
+    assert np.array_equal(dm, hm), "tile metadata differs"
+    assert np.array_equal(dr, hr), "tile record bytes differ"
+    if check_oracle:
+        rp, col = _user_order_csr(dev)
+        orp, ocol = _oracle_rows(dim, n, cells)
+        assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    # every later call reads the same data: bit-identical results
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    phi = torch.as_tensor(_flow(x, 11), dtype=tdt, device=DEV)
+    assert same_bits(dev.forward(phi, T), host.forward(phi, T))
+    if dim == 3:
+        a, _ = dev.forward_tape(phi, T)
+        b, _ = host.forward_tape(phi, T)
+        assert same_bits(a, b)
+    return host, dev
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_tri_grid_row_order(dtype):
+    # points numbered along grid rows: the caller-order axis is detected
+    x, cells = meshes.jittered_tri_grid(97, 61, seed=3)
+    assert_same_mesh(x, cells, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_tet_grid(dtype):
+    x, cells = meshes.kuhn_tet_grid(13, nz=11)
+    assert_same_mesh(x, cells, dtype)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_shuffled_points(dim):
+    x, cells = meshes.jittered_tri_grid(80, 50, seed=2) if dim == 2 else meshes.kuhn_tet_grid(12)
+    xr, cr, _ = meshes.relabel(x, cells, seed=9)
+    assert_same_mesh(xr, cr, "f32")
+
+
+@pytest.mark.parametrize("tile_log2", [5, 8, 11])
+def test_tile_sizes(tile_log2):
+    # 2^11-point chunks exceed the 1024 staged slots: the extents halve them
+    x, cells = meshes.kuhn_tet_grid(14)
+    assert_same_mesh(x, cells, "f32", tile_log2=tile_log2)
+    x, cells = meshes.jittered_tri_grid(70, 66, seed=4)
+    assert_same_mesh(x, cells, "f32", tile_log2=tile_log2)
+
+
+def test_no_reorder():
+    x, cells = meshes.jittered_tri_grid(60, 45, seed=6)
+    assert_same_mesh(x, cells, "f32", reorder=False)
+    x, cells = meshes.kuhn_tet_grid(9)
+    assert_same_mesh(x, cells, "f64", reorder=False)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_delaunay_point_cloud(dim):
+    """Irregular meshes: explicit rows, short runs, uneven degrees."""
+    from scipy.spatial import Delaunay
+    g = np.random.default_rng(40 + dim)
+    n = 6000 if dim == 2 else 3000
+    x = g.random((n, dim))
+    cells = Delaunay(x).simplices.astype(np.int32)
+    assert_same_mesh(x, cells, "f32")
+    assert_same_mesh(x, cells, "f64", tile_log2=7)
+
+
+def test_edge_cases():
+    # one point, no cells
+    x = np.array([[0.5, 0.25]])
+    assert_same_mesh(x, np.zeros((0, 3), np.int32), check_oracle=False)
+    # points in no cell, around a few cells; no cells at all
+    x, cells = meshes.jittered_tri_grid(20, 20, seed=1)
+    assert_same_mesh(x, cells[:7])
+    assert_same_mesh(x, np.zeros((0, 3), np.int32), check_oracle=False)
+    # under 64 points (no caller-order sample), and two points
+    x, cells = meshes.jittered_tri_grid(6, 5, seed=2)
+    assert_same_mesh(x, cells)
+    assert_same_mesh(np.array([[0.0, 0.0, 0.0], [1.0, 0.5, 0.25]]), np.zeros((0, 4), np.int32), check_oracle=False)
+    # all points on a line in one axis (zero spans elsewhere)
+    x = np.stack([np.linspace(0, 1, 300), np.zeros(300)], axis=1)
+    cells = np.array([[i, i + 1, i + 2] for i in range(298)], dtype=np.int32)
+    assert_same_mesh(x, cells)
+
+
+def test_high_degree_fan():
+    """A fan of triangles around one centre: a 900-neighbour row (tiles halve
+    down to few points), then one past a tile's capacity (both builds refuse)."""
+    for k, ok in ((900, True), (1100, False)):
+        t = np.linspace(0, 2 * np.pi, k, endpoint=False)
+        x = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(t), np.sin(t)], 1)])
+        cells = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], dtype=np.int32)
+        if ok:
+            assert_same_mesh(x, cells)
+        else:
+            with pytest.raises(F.FTLEError) as e:
+                F.Mesh(x, cells, "f32")
+            assert e.value.status == 4
+            with pytest.raises(F.FTLEError) as e2:
+                _device_mesh(x, cells, "f32")
+            assert e2.value.status == 4 and "point 0 has 1100 neighbours" in str(e2.value)
+
+
+def test_errors():
+    x, cells = meshes.jittered_tri_grid(10, 8, seed=1)
+    for bad, word in (([0, 1, 200], "out of range"), ([3, -2, 4], "out of range"), ([5, 6, 5], "repeated vertex")):
+        c = cells.copy()
+        c[11] = bad
+        c[17] = bad
+        with pytest.raises(F.FTLEError) as e:
+            _device_mesh(x, c, "f32")
+        assert e.value.status == 2 and word in str(e.value) and "cell 11" in str(e.value)
+    xb = x.copy()
+    xb[33, 1] = np.nan
+    xb[40, 0] = np.inf
+    with pytest.raises(F.FTLEError) as e:
+        _device_mesh(xb, cells, "f64")
+    assert e.value.status == 1 and "coordinate 33" in str(e.value)
+    # the axis stencil is built on the host only
+    L = _lib.load()
+    xd = torch.as_tensor(x, dtype=torch.float32, device=DEV)
+    cd = torch.as_tensor(cells, dtype=torch.int32, device=DEV)
+    h = ctypes.c_void_p()
+    st = L.ftle_create_mesh_device(2, x.shape[0], ctypes.c_void_p(xd.data_ptr()), _lib.F32, cells.shape[0],
+                                   ctypes.c_void_p(cd.data_ptr()), _lib.STENCIL_AXIS, None, ctypes.byref(h))
+    assert st == 4 and not h.value
+
+
+def test_side_stream_and_adjoint():
+    """Built on a side stream; the adjoint (which reuses the forward tiles of the
+    symmetric one-ring stencil) agrees bit for bit too."""
+    x, cells = meshes.kuhn_tet_grid(10)
+    s = torch.cuda.Stream()
+    xd = torch.as_tensor(x.astype(np.float32), device=DEV)
+    cd = torch.as_tensor(cells.astype(np.int32), device=DEV)
+    torch.cuda.synchronize()
+    dev = F.Mesh.on_device(xd, cd, stream=s)
+    host = F.Mesh(x, cells, "f32")
+    phi = torch.as_tensor(_flow(x, 3), dtype=torch.float32, device=DEV)
+    g = torch.as_tensor(np.random.default_rng(5).normal(size=x.shape[0]), dtype=torch.float32, device=DEV)
+    assert same_bits(dev.backward(phi, 1.5, g), host.backward(phi, 1.5, g))
+
+
+def test_full_size_2d_equals_host():
+    """At the benchmark's 2048^2-point triangle grid: permutation, stencil
+    and record bytes equal the host build's."""
+    x, cells = meshes.jittered_tri_grid(2048, 2048, seed=2)
+    print(f"[device mesh full 2D n={x.shape[0]}]", flush=True)
+    host = F.Mesh(x, cells, "f32")
+    dev = _device_mesh(x, cells, "f32")
+    for a, b in zip(dev.csr(), host.csr()):
+        assert np.array_equal(a, b)
+    dm, dr = _raw_tiles(dev)
+    hm, hr = _raw_tiles(host)
+    assert np.array_equal(dm, hm) and np.array_equal(dr, hr)

@@ -516,3 +516,27 @@ def test_ring1_csr_workspace_validation(L):
     assert ws(workspace=None) == INVALID and ws(size=need - 1) == INVALID
     assert b"workspace" in L.ftle_last_error()
     assert ws(dim=5) == INVALID
+
+
+def test_create_mesh_device_validation(L):
+    """ftle_create_mesh_device checks every argument before it touches the
+    device (the pointers here are never dereferenced)."""
+    INVALID, UNSUP = 1, 4
+    fake = ctypes.c_void_p(256)
+    h = ctypes.c_void_p()
+
+    def mk(dim=2, n=10, coords=fake, dtype=0, ncells=3, cells=fake, flags=0, out=True):
+        return L.ftle_create_mesh_device(dim, n, coords, dtype, ncells, cells, flags, None,
+                                         ctypes.byref(h) if out else None)
+
+    assert mk(out=False) == INVALID
+    assert mk(dim=4) == INVALID and mk(dtype=7) == INVALID and mk(n=0) == INVALID
+    assert mk(n=1 << 31) == UNSUP
+    assert mk(coords=None) == INVALID
+    assert mk(ncells=-1) == INVALID and mk(cells=None) == INVALID
+    assert mk(ncells=(1 << 32) // 3 + 1) == UNSUP
+    assert mk(flags=_lib.STENCIL_AXIS) == UNSUP and mk(flags=_lib.HOST_ONLY) == UNSUP
+    assert b"one-ring" in L.ftle_last_error()
+    assert mk(flags=1 << 20) == INVALID
+    assert mk(flags=_lib.tile_flag(4)) == INVALID
+    assert not h.value
