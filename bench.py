@@ -59,11 +59,12 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X float64 vector, published (256 CUs x 1
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions/s: 4 SIMDs per CU, 4 cycles each
 
 # variant groups of --only, and the cached workloads each needs
-GROUPS = ("f16", "fp64", "fwd3d", "fwdbwd", "batched", "axis", "ell", "neighbours", "advect")
+GROUPS = ("f16", "fp64", "fwd3d", "fwdbwd", "batched", "axis", "ell", "neighbours", "meshbuild", "advect")
 GROUP_WORKLOADS = {"headline": ["scale_2d"], "f16": ["scale_2d"], "fp64": ["scale_2d"], "fwd3d": ["abc_3d"],
                    "fwdbwd": ["diff_3d"], "batched": ["batched_2d"], "axis": ["scale_2d", "abc_3d"],
                    "ell": ["scale_2d", "abc_3d"],
-                   "neighbours": ["scale_2d", "abc_3d"], "advect": ["scale_2d", "abc_3d"]}
+                   "neighbours": ["scale_2d", "abc_3d"], "meshbuild": ["scale_2d", "abc_3d"],
+                   "advect": ["scale_2d", "abc_3d"]}
 
 # The commands that made the summaries under profiles/ (run from the
 # repository root; the first fills the workload cache without a profiler).
@@ -678,6 +679,26 @@ def cpu_table(loads, stencils, threads_all, configs_wanted):
     return rows
 
 
+def raw_tiles(m):
+    """A mesh's tile metadata and record bytes, as the library returns them."""
+    import ctypes
+
+    from paper_2408_02758_amd import _lib
+    L = _lib.load()
+    nt, rb = ctypes.c_int64(), ctypes.c_int64()
+    _lib.check(L.ftle_mesh_get_tiles(m.handle, 0, ctypes.byref(nt), ctypes.byref(rb), None, None))
+    meta = ctypes.create_string_buffer(max(1, nt.value * 16))
+    rec = ctypes.create_string_buffer(max(1, rb.value))
+    _lib.check(L.ftle_mesh_get_tiles(m.handle, 0, None, None, meta, rec))
+    return meta.raw[:nt.value * 16], rec.raw[:rb.value]
+
+
+def host_threads():
+    """Threads the host mesh builder runs (FTLE_HOST_THREADS, else the hardware threads, at most 32)."""
+    env = os.environ.get("FTLE_HOST_THREADS")
+    return max(1, int(env)) if env else max(1, min(os.cpu_count() or 1, 32))
+
+
 def stencil_vs_oracle(stencils, w, row_ptr, col):
     """The GPU-built one-ring stencil against the oracle's, entry for entry."""
     import numpy as np
@@ -863,7 +884,7 @@ def main():
         del src, dst
 
     # ---- headline: 2D forward at 2048^2 ------------------------------------
-    w2 = loads.get("scale_2d") if (headline or any(g in groups for g in ("f16", "fp64", "axis", "ell", "neighbours",
+    w2 = loads.get("scale_2d") if (headline or any(g in groups for g in ("f16", "fp64", "axis", "ell", "neighbours", "meshbuild",
                                                                           "advect"))) else None
     copy_gbps = None
     if headline:
@@ -1122,6 +1143,50 @@ def main():
             log(f"{name}: {t:.2f} ms per stencil")
             keep[name] = (wn, rp.cpu().numpy(), col.cpu().numpy())
             del cells_d, rp, col, ws, colbuf
+    if want("meshbuild"):
+        # the whole mesh build on the GPU (ftle_create_mesh_device: Morton
+        # order, one-ring stencil, tile records, 3D normal matrices) beside
+        # the host build of the same mesh with its upload (ftle_create_mesh);
+        # wall time of each call, inputs already where each build takes them
+        for name, wn in (("meshbuild_2d_2048", w2), ("meshbuild_3d_160", loads.get("abc_3d"))):
+            log(f"{name}: mesh build on the GPU and on the host")
+            xd = torch.as_tensor(wn.coords, device=dev).contiguous()
+            cd = torch.as_tensor(wn.cells, dtype=torch.int32, device=dev).contiguous()
+            F.Mesh.on_device(xd, cd).close()
+            torch.cuda.synchronize()
+            td = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                md = F.Mesh.on_device(xd, cd)
+                td.append(time.perf_counter() - t0)
+                md.close()
+            th = []
+            for _ in range(2):
+                t0 = time.perf_counter()
+                mh = F.Mesh(wn.coords, wn.cells, wn.dtype)
+                th.append(time.perf_counter() - t0)
+                if _ == 0:
+                    mh.close()
+            md = F.Mesh.on_device(xd, cd)
+            same = all(np.array_equal(a, b) for a, b in zip(md.csr(), mh.csr())) \
+                and md.tile_stats() == mh.tile_stats() and raw_tiles(md) == raw_tiles(mh)
+            t_dev, t_host = float(np.median(td)) * 1e3, min(th) * 1e3
+            info, stats = md.info(), md.tile_stats()
+            Bm = (4 * cd.numel() + xd.numel() * xd.element_size() + 8 * (wn.n + 1) + 4 * info["nnz"]
+                  + stats["record_bytes"])
+            variants[name] = {
+                "workload": f"mesh of the {'2048^2 triangle' if wn.dim == 2 else '160^3 tetrahedron'} grid built "
+                            "from device coordinates and cells on the GPU (wall time of the call, median of 5)",
+                "points": wn.n, "cells": int(cd.shape[0]), "nnz": info["nnz"], "tiles": stats["n_tiles"],
+                "ms_per_step": round(t_dev, 3), "points_per_s": round(wn.n / (t_dev * 1e-3), 1),
+                "host_build_ms": round(t_host, 1), "host_build_threads": host_threads(),
+                "speedup_vs_host_build": round(t_host / t_dev, 2), "equal_to_host_build": bool(same),
+                "roofline": dict(roofline(Bm, t_dev), alg_bytes_per_launch=Bm,
+                                 alg_model="cells and coordinates read once; stencil and tile records written once")}
+            log(f"{name}: {t_dev:.2f} ms on the GPU, {t_host:.1f} ms on the host, same mesh: {same}")
+            md.close()
+            mh.close()
+            del xd, cd
     if want("advect"):
         # the step before the path: the 2048^2 double-gyre flow map by RK4 on
         # the GPU (float64 arithmetic, float32 output), as the headline's
