@@ -77,6 +77,10 @@ PROFILE_RECIPE = [
     "timeout -k 10 600 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_axis -o kt --output-format csv -- "
     "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 30 --no-cpu-baseline --no-sustained "
     "--no-headline --only axis",
+    # the build kernels: the one-ring stencil and the whole mesh build on the device
+    "timeout -k 10 600 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_build -o kt --output-format csv -- "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 5 --warmup 1 --no-cpu-baseline --no-sustained "
+    "--no-headline --only neighbours,meshbuild",
     # HBM traffic: one counter per run (FETCH_SIZE, then WRITE_SIZE), each run
     # starting with a 256 MiB copy whose counts calibrate the counters
     "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_main -o pmc --output-format csv -- "
@@ -497,7 +501,9 @@ def short_kernel_name(name):
 
 
 FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "incidence_pass", "scan_tiles", "scan_partials",
-                    "add_partials", "ring_rows", "long_rows", "advect")
+                    "add_partials", "ring_rows", "long_rows", "advect", "bbox_partial", "gather_pairs", "morton_keys",
+                    "radix_hist", "radix_scatter", "iota_u32", "invert_perm", "check_relabel", "tile_extent",
+                    "tile_record", "normal_inverse")
 
 
 def summarize_trace(directory, run):
@@ -567,20 +573,24 @@ def profile_header(kind):
     sources it was taken from and the batched launch shape pinned in it."""
     if kind == "trace":
         title = "rocprofv3 --kernel-trace: per-kernel durations (us) of the FTLE kernels, one MI355X (gfx950)"
-        cmds = PROFILE_RECIPE[:3] + ["python bench.py --profile-header trace",
+        cmds = PROFILE_RECIPE[:4] + ["python bench.py --profile-header trace",
                                     "python bench.py --summarize-trace gpurun_out/kt_main main",
-                                    "python bench.py --summarize-trace gpurun_out/kt_axis axis"]
+                                    "python bench.py --summarize-trace gpurun_out/kt_axis axis",
+                                    "python bench.py --summarize-trace gpurun_out/kt_build build"]
     else:
         title = ("rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE: HBM KiB per dispatch of the FTLE kernels, one MI355X "
                  "(gfx950); each counter scaled by the factor that makes a 256 MiB copy (torch.neg) read its size")
-        cmds = [PROFILE_RECIPE[0]] + [c.replace("{counter}", k) for c in PROFILE_RECIPE[3:]
+        cmds = [PROFILE_RECIPE[0]] + [c.replace("{counter}", k) for c in PROFILE_RECIPE[4:]
                                       for k in ("FETCH_SIZE", "WRITE_SIZE")]
         cmds += ["python bench.py --profile-header counters",
                  "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_main gpurun_out/pmc_WRITE_SIZE_main main",
                  "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_axis gpurun_out/pmc_WRITE_SIZE_axis axis"]
     lines = [f"# {title}", "# commands, from the repository root:"] + [f"#   {c}" for c in cmds]
     lines += ["# run 'main': the ring-1, float64, binary16, forward+adjoint, batched and axis-list rows; run 'axis': "
-              "the axis-stencil rows (same kernel names as the ring-1 ones)",
+              "the axis-stencil rows (same kernel names as the ring-1 ones)"
+              + ("; run 'build': the one-ring stencil and the mesh build on the device, 2048^2 and 160^3 (the "
+                 "mesh build's calls include the warm-up builds and the ones beside the host build)"
+                 if kind == "trace" else ""),
               f"kernel_sources_sha256 = {kernel_sources_sha256()}", f"batched_shape = {PROFILE_BATCHED_SHAPE}"]
     return "\n".join(lines)
 
