@@ -501,7 +501,7 @@ def short_kernel_name(name):
 
 
 FTLE_KERNEL_TAGS = ("fwd", "bwd", "batched", "encode16", "ell_", "incidence_pass", "scan_tiles", "scan_partials",
-                    "add_partials", "ring_rows", "long_rows", "advect", "bbox_partial", "gather_pairs", "morton_keys",
+                    "add_partials", "ring_rows", "copy_rows", "long_rows", "advect", "bbox_partial", "gather_pairs", "morton_keys",
                     "radix_hist", "radix_scatter", "iota_u32", "invert_perm", "check_relabel", "tile_extent",
                     "tile_record", "normal_inverse")
 

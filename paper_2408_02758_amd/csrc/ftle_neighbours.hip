@@ -16,11 +16,13 @@
 //   4. rows: one lane per point walks its incident cells and inserts their
 //      other points into a short sorted list of distinct indices in LDS (a
 //      lane's list is interleaved with its workgroup's, so that a list step
-//      is one conflict-free LDS access); the first pass only counts them,
-//      the counts are scanned into the row pointers, and the second pass
-//      writes the lists.  A point with more than kRowCap distinct neighbours
-//      is handed to a workgroup of its own (long_rows: its candidates sorted
-//      by a bitonic network in LDS, duplicates dropped by a flag scan).
+//      is one conflict-free LDS access), then stores its count and the list
+//      (a fixed kRowCap slots per point in the workspace); the counts are
+//      scanned into the row pointers, and a copy moves the lists into place.
+//      A point with more than kRowCap distinct neighbours is handed to a
+//      workgroup of its own (long_rows: its candidates sorted by a bitonic
+//      network in LDS, duplicates dropped by a flag scan), once to count and
+//      once to write.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -221,18 +223,17 @@ hipError_t exclusive_scan(const uint32_t* in, int64_t m, Out* out, Out* partial,
 
 // ---------------------------------------------------------------------------
 // 4. rows.  Lane r (point r) keeps its distinct neighbours, ascending, in
-// lst[k * kRowThreads + lane], k < kRowCap.  WRITE = false: deg[r] = their
-// count; a point with more is appended to longs (deg[r] = 0 for now).
-// WRITE = true: the list goes to col[row_ptr[r] ...]; long points are
-// skipped (long_rows writes them).
+// lst[k * kRowThreads + lane], k < kRowCap, then sets deg[r] to their count
+// and stores them at store[k * n + r] (entry-major, so that each store
+// instruction writes consecutive points).  A point with more is appended to
+// longs (deg[r] = 0 until long_rows counts it).
 // ---------------------------------------------------------------------------
-template <int K, bool WRITE>
+template <int K>
 __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restrict__ cells,
                                                          const int32_t* __restrict__ inc,
                                                          const uint32_t* __restrict__ off, int64_t n,
-                                                         uint32_t* __restrict__ deg, const int64_t* __restrict__ row_ptr,
-                                                         int32_t* __restrict__ col, uint32_t* __restrict__ longs,
-                                                         uint32_t* __restrict__ n_long)
+                                                         uint32_t* __restrict__ deg, int32_t* __restrict__ store,
+                                                         uint32_t* __restrict__ longs, uint32_t* __restrict__ n_long)
 {
     __shared__ int32_t lst[kRowCap * kRowThreads];
     const int t = (int)threadIdx.x;
@@ -271,14 +272,24 @@ __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restri
                 ++cnt;
             }
     }
-    if constexpr (!WRITE) {
-        if (over) longs[atomicAdd(n_long, 1u)] = (uint32_t)r;
-        deg[r] = over ? 0u : (uint32_t)cnt;
-    } else {
-        if (over) return;
-        int32_t* out = col + row_ptr[r];
-        for (int k = 0; k < cnt; ++k) out[k] = my[k * kRowThreads];
-    }
+    if (over) longs[atomicAdd(n_long, 1u)] = (uint32_t)r;
+    deg[r] = over ? 0u : (uint32_t)cnt;
+    if (!over)
+        for (int k = 0; k < cnt; ++k) store[k * n + r] = my[k * kRowThreads];
+}
+
+// The stored lists into place: col[row_ptr[r] + k] = store[k * n + r] for the
+// rows ring_rows kept (a long row's count, set by long_rows, exceeds kRowCap).
+__global__ void __launch_bounds__(256) copy_rows(const int32_t* __restrict__ store, int64_t n,
+                                                 const uint32_t* __restrict__ deg,
+                                                 const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t d = deg[r];
+    if (d > (uint32_t)kRowCap) return;
+    int32_t* out = col + row_ptr[r];
+    for (uint32_t k = 0; k < d; ++k) out[k] = store[(int64_t)k * n + r];
 }
 
 // A long row by a workgroup of 256 lanes: its candidates (the points of its
@@ -357,39 +368,65 @@ constexpr int kLongGrid = 256;
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-}  // namespace
+// Workspace of ring1_build, carved in this order (carve_ring1): incidence
+// counts and offsets (n + 1), cursors (n), incidence lists (K n_cells),
+// distinct counts (n + 1), long rows (n), stored lists (kRowCap n), scan
+// partial sums, error and long-row counters.
+struct Ring1Work {
+    uint32_t *cnt, *cur, *deg, *longs, *n_long;
+    int32_t *inc, *store;
+    void* partial;
+    int* err;
+};
 
-// Workspace of ring1_build, carved in this order: incidence counts and
-// offsets (n + 1), cursors (n), incidence lists (K n_cells), distinct counts
-// (n + 1), long rows (n), scan partial sums, error and long-row counters.
-size_t ring1_workspace_bytes(int dim, int64_t n, int64_t n_cells)
+Ring1Work carve_ring1(void* workspace, int dim, int64_t n, int64_t n_cells, size_t* bytes)
 {
     const int K = dim + 1;
     const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile + 1;
-    return align256(4 * (size_t)(n + 1)) + align256(4 * (size_t)n) + align256(4 * (size_t)K * n_cells) +
-           align256(4 * (size_t)(n + 1)) + align256(4 * (size_t)n) + align256(8 * (size_t)tiles) + 256;
+    unsigned char* base = static_cast<unsigned char*>(workspace);
+    size_t at = 0;
+    auto carve = [&](size_t b) {
+        void* p = base ? base + at : nullptr;
+        at += align256(b);
+        return p;
+    };
+    Ring1Work w;
+    w.cnt = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
+    w.cur = static_cast<uint32_t*>(carve(4 * (size_t)n));
+    w.inc = static_cast<int32_t*>(carve(4 * (size_t)K * n_cells));
+    w.deg = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
+    w.longs = static_cast<uint32_t*>(carve(4 * (size_t)n));
+    w.store = static_cast<int32_t*>(carve(4 * (size_t)kRowCap * n));
+    w.partial = carve(8 * (size_t)tiles);
+    w.err = static_cast<int*>(carve(256));
+    w.n_long = w.err ? reinterpret_cast<uint32_t*>(w.err + 1) : nullptr;
+    if (bytes) *bytes = at;
+    return w;
 }
+
+}  // namespace
+
+size_t ring1_workspace_bytes(int dim, int64_t n, int64_t n_cells)
+{
+    size_t bytes = 0;
+    (void)carve_ring1(nullptr, dim, n, n_cells, &bytes);
+    return bytes;
+}
+
 
 hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace, int64_t* row_ptr,
                        int32_t* col, int64_t col_capacity, int64_t* nnz, int* bad_mesh, int* too_long,
                        hipStream_t stream)
 {
-    const int K = dim + 1;
-    unsigned char* w = static_cast<unsigned char*>(workspace);
-    auto carve = [&](size_t bytes) {
-        void* p = w;
-        w += align256(bytes);
-        return p;
-    };
-    uint32_t* cnt = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
-    uint32_t* cur = static_cast<uint32_t*>(carve(4 * (size_t)n));
-    int32_t* inc = static_cast<int32_t*>(carve(4 * (size_t)K * n_cells));
-    uint32_t* deg = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
-    uint32_t* longs = static_cast<uint32_t*>(carve(4 * (size_t)n));
-    const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile + 1;
-    void* partial = carve(8 * (size_t)tiles);
-    int* err = static_cast<int*>(carve(256));
-    uint32_t* n_long = reinterpret_cast<uint32_t*>(err + 1);
+    const Ring1Work w = carve_ring1(workspace, dim, n, n_cells, nullptr);
+    uint32_t* cnt = w.cnt;
+    uint32_t* cur = w.cur;
+    int32_t* inc = w.inc;
+    uint32_t* deg = w.deg;
+    uint32_t* longs = w.longs;
+    void* partial = w.partial;
+    int* err = w.err;
+    uint32_t* n_long = w.n_long;
     hipError_t e;
 #define FTLE_CHECK(x)                          \
     if ((e = (x)) != hipSuccess) return e;
@@ -425,13 +462,11 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
     // 4. distinct counts, their offsets, then the lists
     const dim3 rg(blocks_for(n, kRowThreads)), rb(kRowThreads);
     if (dim == 2) {
-        hipLaunchKernelGGL((ring_rows<3, false>), rg, rb, 0, stream, cells, inc, cnt, n, deg, nullptr, nullptr, longs,
-                           n_long);
+        hipLaunchKernelGGL((ring_rows<3>), rg, rb, 0, stream, cells, inc, cnt, n, deg, w.store, longs, n_long);
         hipLaunchKernelGGL((long_rows<3, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
                            n_long, deg, nullptr, nullptr, err);
     } else {
-        hipLaunchKernelGGL((ring_rows<4, false>), rg, rb, 0, stream, cells, inc, cnt, n, deg, nullptr, nullptr, longs,
-                           n_long);
+        hipLaunchKernelGGL((ring_rows<4>), rg, rb, 0, stream, cells, inc, cnt, n, deg, w.store, longs, n_long);
         hipLaunchKernelGGL((long_rows<4, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
                            n_long, deg, nullptr, nullptr, err);
     }
@@ -454,34 +489,14 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
 hipError_t ring1_write(int dim, const int32_t* cells, int64_t n_cells, int64_t n, void* workspace,
                        const int64_t* row_ptr, int32_t* col, hipStream_t stream)
 {
-    const int K = dim + 1;
-    unsigned char* w = static_cast<unsigned char*>(workspace);
-    auto carve = [&](size_t bytes) {
-        void* p = w;
-        w += align256(bytes);
-        return p;
-    };
-    uint32_t* cnt = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
-    (void)carve(4 * (size_t)n);
-    int32_t* inc = static_cast<int32_t*>(carve(4 * (size_t)K * n_cells));
-    uint32_t* deg = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
-    uint32_t* longs = static_cast<uint32_t*>(carve(4 * (size_t)n));
-    const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile + 1;
-    (void)carve(8 * (size_t)tiles);
-    int* err = static_cast<int*>(carve(256));
-    uint32_t* n_long = reinterpret_cast<uint32_t*>(err + 1);
-    const dim3 rg(blocks_for(n, kRowThreads)), rb(kRowThreads);
-    if (dim == 2) {
-        hipLaunchKernelGGL((ring_rows<3, true>), rg, rb, 0, stream, cells, inc, cnt, n, deg, row_ptr, col, longs,
-                           n_long);
-        hipLaunchKernelGGL((long_rows<3, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
-                           n_long, deg, row_ptr, col, err);
-    } else {
-        hipLaunchKernelGGL((ring_rows<4, true>), rg, rb, 0, stream, cells, inc, cnt, n, deg, row_ptr, col, longs,
-                           n_long);
-        hipLaunchKernelGGL((long_rows<4, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
-                           n_long, deg, row_ptr, col, err);
-    }
+    const Ring1Work w = carve_ring1(workspace, dim, n, n_cells, nullptr);
+    hipLaunchKernelGGL(copy_rows, dim3(blocks_for(n)), dim3(256), 0, stream, w.store, n, w.deg, row_ptr, col);
+    if (dim == 2)
+        hipLaunchKernelGGL((long_rows<3, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, w.inc, w.cnt, w.longs,
+                           w.n_long, w.deg, row_ptr, col, w.err);
+    else
+        hipLaunchKernelGGL((long_rows<4, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, w.inc, w.cnt, w.longs,
+                           w.n_long, w.deg, row_ptr, col, w.err);
     return hipGetLastError();
 }
 
