@@ -221,8 +221,9 @@ ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const voi
 /* Release a mesh and its device memory (waits for the device).  NULL is a no-op. */
 void ftle_destroy_mesh(ftle_mesh_t mesh);
 
-/* Dimensions of a mesh: dim, number of points, number of stencil entries, dtype.
- * Any output pointer may be NULL. */
+/* Dimensions of a mesh: dim, number of points, number of stencil entries, and
+ * (one output beyond the plain dimensions) the mesh dtype as an ftle_dtype
+ * value.  Any output pointer may be NULL. */
 ftle_status ftle_mesh_info(ftle_mesh_t mesh, int* dim, int64_t* n_points, int64_t* nnz,
                            int* dtype);
 
@@ -399,8 +400,10 @@ ftle_status ftle_backward_tape(ftle_mesh_t mesh, const void* tape, ftle_dtype dt
  * Adjoint without a tape: recomputes the forward quantities from the flow
  * map into a workspace owned by the mesh, then gathers dL/dphi.
  *   flow, dtype, T as in ftle_forward; grad_ftle, grad_flow as in ftle_backward_tape.
- * Calls on one mesh share the workspace: they are ordered on the device
- * (a later call on another stream waits for the previous one).
+ * The workspace (ftle_tape_bytes) is allocated on the mesh's first call and
+ * kept until ftle_destroy_mesh; ftle_backward_noalloc is the variant that
+ * allocates nothing.  Calls on one mesh share the workspace: they are ordered
+ * on the device (a later call on another stream waits for the previous one).
  */
 ftle_status ftle_backward(ftle_mesh_t mesh, const void* flow, ftle_dtype dtype, double T,
                           const void* grad_ftle, void* grad_flow, ftle_stream_t stream);
