@@ -16,9 +16,11 @@
  *
  * Problem statement as in Section 2.2 of the paper: point coordinates, mesh
  * connectivity, the advected flow map and the integration time go in; one
- * FTLE value per point comes out.  The neighbour list is computed once on the
- * host (Section 2.2: neighbours precomputed on the CPU into a list of integer
- * indices) when the mesh is created, and the GPU kernels only stream it.
+ * FTLE value per point comes out.  The neighbour list is computed once, when
+ * the mesh is created: on the host as Section 2.2 does (neighbours precomputed
+ * on the CPU into a list of integer indices; ftle_create_mesh), or on the
+ * device as the Conclusions propose (ftle_create_mesh_device); the FTLE
+ * kernels only stream it.
  *
  * Conventions for every entry point:
  *  - All functions return an ftle_status; none throws or aborts.  On failure
