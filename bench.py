@@ -247,12 +247,14 @@ def time_steps(fns, steps, warmup, torch):
 
 class ClockSampler:
     """Samples the GPU's shader clock while active: the current level of the
-    device's pp_dpm_sclk sysfs file (the line marked '*'), with the board
-    power from its hwmon power1_input, every ~5 ms (file reads, no process).
-    Reports min / median / max, or why nothing was recorded."""
+    device's pp_dpm_sclk sysfs file (the line marked '*'), with the memory and
+    fabric clocks of its pp_dpm_mclk / pp_dpm_fclk files, the board power from
+    its hwmon power1_input and the hwmon temperatures, every ~5 ms (file reads,
+    no process).  Reports min / median / max, or why nothing was recorded."""
 
     def __init__(self, torch):
         self.sclk = self.power = self.reason = None
+        self.clocks, self.temps = {}, {}
         cards = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
         try:
             p = torch.cuda.get_device_properties(0)
@@ -262,11 +264,24 @@ class ClockSampler:
         match = [c for c in cards if bdf and os.path.realpath(os.path.dirname(c)).endswith(bdf)]
         if match or len(cards) == 1:
             self.sclk = (match or cards)[0]
-            pw = sorted(glob.glob(os.path.join(os.path.dirname(self.sclk), "hwmon", "hwmon*", "power1_input")))
+            dev_dir = os.path.dirname(self.sclk)
+            pw = sorted(glob.glob(os.path.join(dev_dir, "hwmon", "hwmon*", "power1_input")))
             self.power = pw[0] if pw else None
+            self.clocks = {k: os.path.join(dev_dir, f"pp_dpm_{k}") for k in ("mclk", "fclk")
+                           if os.path.exists(os.path.join(dev_dir, f"pp_dpm_{k}"))}
+            self.temps = {}
+            for t in sorted(glob.glob(os.path.join(dev_dir, "hwmon", "hwmon*", "temp*_input"))):
+                lab = t[:-len("_input")] + "_label"
+                try:
+                    with open(lab) as f:
+                        name = f.read().strip()
+                except OSError:
+                    name = os.path.basename(t)[:-len("_input")]
+                self.temps[name] = t
         else:
             self.reason = f"{len(cards)} pp_dpm_sclk files, none for PCI device {bdf}"
         self.samples, self.watts = [], []
+        self.other = {}
         self._stop = threading.Event()
         self._thread = None
 
@@ -285,9 +300,16 @@ class ClockSampler:
         if self.power:
             with open(self.power) as f:
                 self.watts.append(int(f.read().strip()) / 1e6)
+        for k, path in self.clocks.items():
+            v = self._read_sclk(path)
+            if v is not None:
+                self.other.setdefault(f"{k}_mhz", []).append(v)
+        for k, path in self.temps.items():
+            with open(path) as f:
+                self.other.setdefault(f"temp_{k}_c", []).append(int(f.read().strip()) / 1000.0)
 
     def __enter__(self):
-        self.samples, self.watts = [], []
+        self.samples, self.watts, self.other = [], [], {}
         if self.sclk:
             try:
                 self._sample()
@@ -321,6 +343,8 @@ class ClockSampler:
                "median_mhz": statistics.median(s), "max_mhz": s[-1]}
         if self.watts:
             out["median_power_w"] = round(statistics.median(self.watts), 1)
+        for k, v in sorted(self.other.items()):
+            out[f"median_{k}"] = round(statistics.median(v), 1)
         return out
 
 
