@@ -265,6 +265,8 @@ __global__ void __launch_bounds__(256) check_relabel(const int32_t* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int kTileThreads = 256;
 constexpr int kHashSlots = 2 * kMaxStaged;   // at most kMaxStaged keys are ever kept
+constexpr int kChunk = 4;                    // stencil entries a lane loads at once
+constexpr int kRowScratch = 32;              // row entries a lane sorts in LDS (longer rows: in global memory)
 
 __device__ inline uint32_t tile_hash(int32_t v) { return ((uint32_t)v * 2654435761u) >> 21; }   // 11 bits
 
@@ -277,18 +279,27 @@ __device__ inline int gather_halo(const int64_t* __restrict__ row_ptr, const int
     static_assert(kHashSlots == 1 << 11, "tile_hash gives 11 bits");
     for (int64_t r = b + t; r < e; r += kTileThreads) {
         if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > kMaxStaged) break;
-        for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
-            const int32_t c = col[p];
-            if (c >= b && c < e) continue;
-            uint32_t h = tile_hash(c);
-            for (int probe = 0; probe < kHashSlots; ++probe, h = (h + 1) & (kHashSlots - 1)) {
-                const int32_t k = atomicCAS(&keys[h], -1, c);
-                if (k == -1) {
-                    const int at = atomicAdd(count, 1);
-                    if (at < kMaxStaged) hlist[at] = c;
-                    break;
+        const int64_t p0 = row_ptr[r], p1 = row_ptr[r + 1];
+        // kChunk entries loaded together, then inserted (a load past the row
+        // end repeats its last entry, which is then found already inserted)
+        for (int64_t p = p0; p < p1; p += kChunk) {
+            int32_t cs[kChunk];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) cs[q] = col[min(p + q, p1 - 1)];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                const int32_t c = cs[q];
+                if (c >= b && c < e) continue;
+                uint32_t h = tile_hash(c);
+                for (int probe = 0; probe < kHashSlots; ++probe, h = (h + 1) & (kHashSlots - 1)) {
+                    const int32_t k = atomicCAS(&keys[h], -1, c);
+                    if (k == -1) {
+                        const int at = atomicAdd(count, 1);
+                        if (at < kMaxStaged) hlist[at] = c;
+                        break;
+                    }
+                    if (k == c) break;
                 }
-                if (k == c) break;
             }
         }
     }
@@ -393,10 +404,15 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
                                                             const TileMeta* __restrict__ meta,
                                                             unsigned char* __restrict__ rec)
 {
-    __shared__ uint64_t srt[kMaxStaged];            // sort keys: (caller index << 32) | payload
+    // srt (sort keys: (caller index << 32) | payload) and hlist (halo in
+    // insertion order) until the halo is sorted, then each lane's row scratch
+    __shared__ __align__(16) unsigned char ubuf[kRowScratch * kTileThreads * 2];
+    static_assert(sizeof(ubuf) >= kMaxStaged * 12, "srt and hlist fit the shared buffer");
+    uint64_t* srt = reinterpret_cast<uint64_t*>(ubuf);
+    int32_t* hlist = reinterpret_cast<int32_t*>(ubuf + 8 * kMaxStaged);
+    uint16_t* rscr = reinterpret_cast<uint16_t*>(ubuf);   // entry k of lane t's row at rscr[k * kTileThreads + t]
     __shared__ int32_t keys[kHashSlots];            // halo hash set (Morton positions)
     __shared__ uint16_t hslot[kHashSlots];          // their slots
-    __shared__ int32_t hlist[kMaxStaged];
     __shared__ uint32_t caller[kMaxStaged];         // caller index of each staged slot
     __shared__ uint16_t own_slot[kMaxStaged];       // slot of own point b + i
     __shared__ int32_t order[kMaxStaged];           // Morton position of own slot l
@@ -406,6 +422,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     __shared__ uint32_t rowoff[kMaxStaged + 1];     // row l's first entry in the tile's row buffer
     __shared__ uint8_t expl[kMaxStaged];
     __shared__ uint8_t start[kMaxStaged];
+    __shared__ uint32_t gmask[kMaxStaged / 32];    // the record's 32-slot group masks
     const int t = (int)threadIdx.x;
     const int64_t b = ranges[2 * blockIdx.x], e = ranges[2 * blockIdx.x + 1];
     const int P = (int)(e - b);
@@ -458,13 +475,22 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     }
     const uint32_t nr = total;
     if (WRITE) {
+        // group masks by one lane each, then their prefix counts by one lane
         for (int g = t; g < (S + 31) / 32; g += kTileThreads) {
-            uint32_t mask = 0, before = 0;
-            for (int l = 0; l < 32 * g; ++l) before += start[l];
+            uint32_t mask = 0;
             for (int i = 0; i < 32 && 32 * g + i < S; ++i) mask |= (uint32_t)start[32 * g + i] << i;
-            reinterpret_cast<uint32_t*>(out + R.smask)[g] = mask;
-            reinterpret_cast<uint16_t*>(out + R.spre)[g] = (uint16_t)before;
+            gmask[g] = mask;
         }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t before = 0;
+            for (int g = 0; g < (S + 31) / 32; ++g) {
+                reinterpret_cast<uint32_t*>(out + R.smask)[g] = gmask[g];
+                reinterpret_cast<uint16_t*>(out + R.spre)[g] = (uint16_t)before;
+                before += (uint32_t)__popc(gmask[g]);
+            }
+        }
+        __syncthreads();
     }
     // rows: padded lengths and their offsets
     {
@@ -490,19 +516,31 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
         for (int l = t; l < P; l += kTileThreads) {
             const int64_t r = order[l];
             uint16_t* row = rows + rowoff[l];
-            int len = 0;
-            for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
-                const int32_t c = col[p];
-                const uint16_t s = (c >= b && c < e) ? own_slot[c - b] : (uint16_t)lookup_halo(keys, hslot, c);
-                int k = len;
-                while (k > 0 && row[k - 1] > s) {
-                    row[k] = row[k - 1];
-                    --k;
-                }
-                row[k] = s;
-                ++len;
-            }
             const int padded = (int)(rowoff[l + 1] - rowoff[l]);
+            // sorted in the lane's LDS scratch when it fits, else in place
+            const bool scratch = padded <= kRowScratch;
+            uint16_t* srow = scratch ? rscr + t : row;
+            const int step = scratch ? kTileThreads : 1;
+            int len = 0;
+            const int64_t p0 = row_ptr[r], p1 = row_ptr[r + 1];
+            for (int64_t p = p0; p < p1; p += kChunk) {
+                int32_t cs[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) cs[q] = col[min(p + q, p1 - 1)];
+                for (int q = 0; q < kChunk && p + q < p1; ++q) {
+                    const int32_t c = cs[q];
+                    const uint16_t s = (c >= b && c < e) ? own_slot[c - b] : (uint16_t)lookup_halo(keys, hslot, c);
+                    int k = len;
+                    while (k > 0 && srow[(k - 1) * step] > s) {
+                        srow[k * step] = srow[(k - 1) * step];
+                        --k;
+                    }
+                    srow[k * step] = s;
+                    ++len;
+                }
+            }
+            if (scratch)
+                for (int k = 0; k < len; ++k) row[k] = srow[k * step];
             for (int k = len; k < padded; ++k) row[k] = (uint16_t)l;
         }
         __syncthreads();
@@ -551,16 +589,21 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     }
     if (WRITE) {
         for (int q = t; q < (P + 31) / 32; q += kTileThreads) {
-            uint32_t mask = 0, before = 0, last = 0;
-            for (int l = 0; l < 32 * q; ++l)
-                if (expl[l]) {
-                    ++before;
-                    last = (uint32_t)l;
-                }
+            uint32_t mask = 0;
             for (int i = 0; i < 32 && 32 * q + i < P; ++i) mask |= (uint32_t)expl[32 * q + i] << i;
-            reinterpret_cast<uint32_t*>(out + R.xmask)[q] = mask;
-            reinterpret_cast<uint16_t*>(out + R.xpre)[q] = (uint16_t)before;
-            reinterpret_cast<uint16_t*>(out + R.xlast)[q] = (uint16_t)last;
+            gmask[q] = mask;
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t before = 0, last = 0;   // explicit rows before group q, and the last of them
+            for (int q = 0; q < (P + 31) / 32; ++q) {
+                const uint32_t mask = gmask[q];
+                reinterpret_cast<uint32_t*>(out + R.xmask)[q] = mask;
+                reinterpret_cast<uint16_t*>(out + R.xpre)[q] = (uint16_t)before;
+                reinterpret_cast<uint16_t*>(out + R.xlast)[q] = (uint16_t)last;
+                before += (uint32_t)__popc(mask);
+                if (mask) last = 32u * (uint32_t)q + 31u - (uint32_t)__clz(mask);
+            }
         }
     } else if (t == 0) {
         counts[4 * blockIdx.x] = nw;

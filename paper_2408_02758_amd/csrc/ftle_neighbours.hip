@@ -280,16 +280,44 @@ __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restri
 
 // The stored lists into place: col[row_ptr[r] + k] = store[k * n + r] for the
 // rows ring_rows kept (a long row's count, set by long_rows, exceeds kRowCap).
+// A workgroup's 256 rows are one contiguous stretch of col: each lane puts its
+// row into that stretch in LDS (long rows' entries marked -1), then the
+// stretch goes out with consecutive lanes writing consecutive entries.  A
+// stretch longer than kCopySeg entries (long rows in the workgroup) is
+// written row by row instead.
+constexpr int kCopySeg = 256 * 24;
+
 __global__ void __launch_bounds__(256) copy_rows(const int32_t* __restrict__ store, int64_t n,
                                                  const uint32_t* __restrict__ deg,
                                                  const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col)
 {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= n) return;
-    const uint32_t d = deg[r];
-    if (d > (uint32_t)kRowCap) return;
-    int32_t* out = col + row_ptr[r];
-    for (uint32_t k = 0; k < d; ++k) out[k] = store[(int64_t)k * n + r];
+    __shared__ int32_t seg[kCopySeg];
+    const int t = (int)threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 256, r = r0 + t;
+    const int64_t r1 = min(r0 + 256, n);
+    const int64_t base = row_ptr[r0], total = row_ptr[r1] - base;
+    const bool live = r < n;
+    const uint32_t d = live ? deg[r] : 0u;
+    const bool kept = d <= (uint32_t)kRowCap;
+    if (total > kCopySeg) {   // workgroup-uniform
+        if (live && kept) {
+            int32_t* out = col + row_ptr[r];
+            for (uint32_t k = 0; k < d; ++k) out[k] = store[(int64_t)k * n + r];
+        }
+        return;
+    }
+    if (live) {
+        int32_t* dst = seg + (row_ptr[r] - base);
+        if (kept)
+            for (uint32_t k = 0; k < d; ++k) dst[k] = store[(int64_t)k * n + r];
+        else
+            for (uint32_t k = 0; k < d; ++k) dst[k] = -1;
+    }
+    __syncthreads();
+    for (int64_t e = t; e < total; e += 256) {
+        const int32_t v = seg[e];
+        if (v >= 0) col[base + e] = v;
+    }
 }
 
 // A long row by a workgroup of 256 lanes: its candidates (the points of its
