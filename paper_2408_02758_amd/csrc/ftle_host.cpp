@@ -1001,6 +1001,11 @@ struct DevBuf {
     }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf& operator=(DevBuf&& o) noexcept
+    {
+        std::swap(p, o.p);
+        return *this;
+    }
     template <typename T>
     T* as() const
     {
@@ -1016,6 +1021,23 @@ struct DevBuf {
         void* q = p;
         p = nullptr;
         return q;
+    }
+};
+
+// The build's temporaries, carved from one allocation: a hipMalloc / hipFree
+// pair per temporary array cost more than the kernels that use them.
+struct Arena {
+    unsigned char* base = nullptr;
+    size_t size = 0, at = 0;
+    static size_t round(size_t b) { return ((b ? b : 1) + 255) & ~(size_t)255; }   // every array takes >= 256 B
+    template <typename T>
+    T* take(size_t bytes)
+    {
+        const size_t b = round(bytes);
+        if (at + b > size) fail(FTLE_ERR_DEVICE, "mesh build: temporary arena exhausted");
+        void* p = base + at;
+        at += b;
+        return static_cast<T*>(p);
     }
 };
 
@@ -1042,7 +1064,7 @@ struct Extent {
 // halved until they fit; the halo and word counts of all candidates of one
 // generation come from one launch.
 std::vector<Extent> device_extents(int dim, bool f64, int64_t n, int tile_points, const int64_t* row_ptr,
-                                   const int32_t* col, const int32_t* perm, hipStream_t s)
+                                   const int32_t* col, const int32_t* perm, Arena& arena, hipStream_t s)
 {
     std::vector<std::pair<int64_t, int64_t>> todo, next;
     for (int64_t b = 0; b < n; b += tile_points) todo.push_back({b, std::min<int64_t>(n, b + tile_points)});
@@ -1055,12 +1077,14 @@ std::vector<Extent> device_extents(int dim, bool f64, int64_t n, int tile_points
             ranges[2 * i] = todo[i].first;
             ranges[2 * i + 1] = todo[i].second;
         }
-        DevBuf d_ranges(ranges.size() * 8), d_hw(todo.size() * 8);
-        to_device(d_ranges.p, ranges.data(), ranges.size() * 8, s);
-        check_hip(mb_tile_extent(row_ptr, col, d_ranges.as<int64_t>(), (int64_t)todo.size(), d_hw.as<uint32_t>(), s),
-                  "tile extent kernel");
+        const size_t mark = arena.at;
+        int64_t* d_ranges = arena.take<int64_t>(ranges.size() * 8);
+        uint32_t* d_hw = arena.take<uint32_t>(todo.size() * 8);
+        to_device(d_ranges, ranges.data(), ranges.size() * 8, s);
+        check_hip(mb_tile_extent(row_ptr, col, d_ranges, (int64_t)todo.size(), d_hw, s), "tile extent kernel");
         hw.resize(2 * todo.size());
-        to_host(hw.data(), d_hw.p, hw.size() * 4, s);
+        to_host(hw.data(), d_hw, hw.size() * 4, s);
+        arena.at = mark;
         next.clear();
         for (size_t i = 0; i < todo.size(); ++i) {
             const auto [b, e] = todo[i];
@@ -1089,7 +1113,7 @@ std::vector<Extent> device_extents(int dim, bool f64, int64_t n, int tile_points
 // records at their offsets), into ts (meta on host and device, records on
 // the device).
 void device_tiles(const std::vector<Extent>& ext, const int64_t* row_ptr, const int32_t* col, const int32_t* perm,
-                  TileSet& ts, hipStream_t s)
+                  TileSet& ts, Arena& arena, hipStream_t s)
 {
     const size_t T = ext.size();
     std::vector<int64_t> ranges(2 * T), row_base(T);
@@ -1100,15 +1124,28 @@ void device_tiles(const std::vector<Extent>& ext, const int64_t* row_ptr, const 
         row_base[t] = entries;
         entries += 3 * (int64_t)ext[t].nw;
     }
-    DevBuf d_ranges(T * 16), d_base(T * 8), d_rows((size_t)entries * 2), d_counts(T * 16);
-    to_device(d_ranges.p, ranges.data(), T * 16, s);
-    to_device(d_base.p, row_base.data(), T * 8, s);
+    // the row buffer from the arena when it fits there, else its own allocation
+    const size_t need = Arena::round(T * 16) * 2 + Arena::round(T * 8) + Arena::round((size_t)entries * 2);
+    DevBuf own;
+    Arena local;
+    if (arena.at + need > arena.size) {
+        own = DevBuf(need);
+        local.base = static_cast<unsigned char*>(own.p);
+        local.size = need;
+    }
+    Arena& a = own.p ? local : arena;
+    int64_t* d_ranges = a.take<int64_t>(T * 16);
+    int64_t* d_base = a.take<int64_t>(T * 8);
+    uint32_t* d_counts = a.take<uint32_t>(T * 16);
+    uint16_t* d_rows = a.take<uint16_t>((size_t)entries * 2);
+    to_device(d_ranges, ranges.data(), T * 16, s);
+    to_device(d_base, row_base.data(), T * 8, s);
     const uint32_t* uperm = reinterpret_cast<const uint32_t*>(perm);
-    check_hip(mb_tile_record(false, row_ptr, col, uperm, d_ranges.as<int64_t>(), (int64_t)T, d_base.as<int64_t>(),
-                             d_rows.as<uint16_t>(), d_counts.as<uint32_t>(), nullptr, nullptr, s),
+    check_hip(mb_tile_record(false, row_ptr, col, uperm, d_ranges, (int64_t)T, d_base, d_rows, d_counts, nullptr,
+                             nullptr, s),
               "tile record kernel (sizes)");
     std::vector<uint32_t> counts(4 * T);
-    to_host(counts.data(), d_counts.p, T * 16, s);
+    to_host(counts.data(), d_counts, T * 16, s);
     ts.meta.resize(T);
     uint64_t off = 0;   // in 16-byte units
     for (size_t t = 0; t < T; ++t) {
@@ -1135,9 +1172,8 @@ void device_tiles(const std::vector<Extent>& ext, const int64_t* row_ptr, const 
     ts.d_meta = dev_upload(ts.meta.data(), T * sizeof(TileMeta));
     ts.d_rec = dev_upload(nullptr, (size_t)ts.rec_bytes);
     check_hip(hipMemsetAsync(ts.d_rec, 0, (size_t)ts.rec_bytes, s), "hipMemsetAsync");
-    check_hip(mb_tile_record(true, row_ptr, col, uperm, d_ranges.as<int64_t>(), (int64_t)T, d_base.as<int64_t>(),
-                             d_rows.as<uint16_t>(), nullptr, static_cast<const TileMeta*>(ts.d_meta),
-                             static_cast<unsigned char*>(ts.d_rec), s),
+    check_hip(mb_tile_record(true, row_ptr, col, uperm, d_ranges, (int64_t)T, d_base, d_rows, nullptr,
+                             static_cast<const TileMeta*>(ts.d_meta), static_cast<unsigned char*>(ts.d_rec), s),
               "tile record kernel (records)");
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
@@ -1166,22 +1202,40 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
         }
     } guard{m.get()};
 
+    // One arena for every temporary: the relabelled cells, then (one phase at
+    // a time above them) the bounds and the sort, the inverse permutation, the
+    // stencil workspace; later the whole arena serves the tile passes.
+    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    int64_t ms = 0, stride = 0;
+    order_sample(n, &ms, &stride);
+    const size_t mc_bytes = Arena::round((size_t)n_cells * k * 4);
+    const size_t phase_sort = Arena::round((size_t)nb * 2 * dim * 8 + 8) + Arena::round((size_t)ms * 2 * dim * 8) +
+                              Arena::round((size_t)n * 8) + Arena::round(mb_sort_scratch_bytes(n));
+    const size_t phase_inv = Arena::round((size_t)n * 4) + Arena::round(16);
+    const size_t phase_ring = Arena::round(ring1_workspace_bytes(dim, n, n_cells));
+    DevBuf arena_buf(mc_bytes + std::max({phase_sort, phase_inv, phase_ring}));
+    Arena arena;
+    arena.base = static_cast<unsigned char*>(arena_buf.p);
+    arena.size = mc_bytes + std::max({phase_sort, phase_inv, phase_ring});
+    int32_t* mc = arena.take<int32_t>((size_t)n_cells * k * 4);
+    const size_t phase_base = arena.at;
+
     // the mesh's own copy of the coordinates; bounds and finiteness
     m->d_x = dev_upload(nullptr, (size_t)n * dim * eb);
     check_hip(hipMemcpyAsync(m->d_x, coords, (size_t)n * dim * eb, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
-    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
-    DevBuf part((size_t)nb * 2 * dim * 8 + 8);
-    unsigned long long* first_bad = reinterpret_cast<unsigned long long*>(part.as<double>() + (size_t)nb * 2 * dim);
+    double* part = arena.take<double>((size_t)nb * 2 * dim * 8 + 8);
+    unsigned long long* first_bad = reinterpret_cast<unsigned long long*>(part + (size_t)nb * 2 * dim);
     check_hip(hipMemsetAsync(first_bad, 0xff, 8, s), "hipMemsetAsync");
-    check_hip(mb_bbox(dim, f64, m->d_x, n, part.as<double>(), nb, first_bad, s), "bounds kernel");
+    check_hip(mb_bbox(dim, f64, m->d_x, n, part, nb, first_bad, s), "bounds kernel");
     std::vector<double> hp((size_t)nb * 2 * dim + 1);
-    to_host(hp.data(), part.p, hp.size() * 8, s);
+    to_host(hp.data(), part, hp.size() * 8, s);
     unsigned long long bad = 0;
     std::memcpy(&bad, &hp.back(), 8);
     if (bad != ~0ull) fail(FTLE_ERR_INVALID_ARG, "coordinate " + std::to_string(bad) + " is not finite");
 
     // Morton order
-    DevBuf perm((size_t)n * 4);
+    m->d_perm = static_cast<int32_t*>(dev_upload(nullptr, (size_t)n * 4));
+    uint32_t* perm = reinterpret_cast<uint32_t*>(m->d_perm);
     if (!(flags & FTLE_NO_REORDER) && n > 1) {
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int b = 0; b < nb; ++b)
@@ -1191,39 +1245,37 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
             }
         double unit[3] = {1, 1, 1}, range = 1.0;
         morton_units(dim, n, lo, hi, unit, &range);
-        int64_t ms = 0, stride = 0;
-        order_sample(n, &ms, &stride);
         std::vector<double> pairs((size_t)ms * 2 * dim);
         if (ms) {
-            DevBuf d_pairs(pairs.size() * 8);
-            check_hip(mb_gather_pairs(dim, f64, m->d_x, ms, stride, d_pairs.as<double>(), s), "sample kernel");
-            to_host(pairs.data(), d_pairs.p, pairs.size() * 8, s);
+            double* d_pairs = arena.take<double>(pairs.size() * 8);
+            check_hip(mb_gather_pairs(dim, f64, m->d_x, ms, stride, d_pairs, s), "sample kernel");
+            to_host(pairs.data(), d_pairs, pairs.size() * 8, s);
         }
         const MortonParams mp = morton_params(dim, lo, unit, range, order_axis_from_pairs(dim, ms, pairs.data(), unit));
-        DevBuf key((size_t)n * 8), scratch(mb_sort_scratch_bytes(n));
-        check_hip(mb_morton(dim, f64, m->d_x, n, mp, key.as<uint64_t>(), perm.as<uint32_t>(), s), "Morton kernel");
+        uint64_t* key = arena.take<uint64_t>((size_t)n * 8);
+        void* scratch = arena.take<void>(mb_sort_scratch_bytes(n));
+        check_hip(mb_morton(dim, f64, m->d_x, n, mp, key, perm, s), "Morton kernel");
         uint32_t* sorted = nullptr;
-        check_hip(mb_sort(key.as<uint64_t>(), perm.as<uint32_t>(), n, morton_key_bits(dim, mp, range), scratch.p,
-                          &sorted, s),
-                  "radix sort");
-        if (sorted != perm.as<uint32_t>())
-            check_hip(hipMemcpyAsync(perm.p, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+        check_hip(mb_sort(key, perm, n, morton_key_bits(dim, mp, range), scratch, &sorted, s), "radix sort");
+        if (sorted != perm)
+            check_hip(hipMemcpyAsync(perm, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
     } else {
-        check_hip(mb_iota(perm.as<uint32_t>(), n, s), "iota kernel");
+        check_hip(mb_iota(perm, n, s), "iota kernel");
     }
 
     // cells in Morton positions (validated), then the one-ring stencil
-    DevBuf mc((size_t)n_cells * k * 4), row_ptr(((size_t)n + 1) * 8);
+    arena.at = phase_base;
     {
-        DevBuf inv((size_t)n * 4), flag(16);
-        check_hip(hipMemsetAsync(flag.p, 0xff, 8, s), "hipMemsetAsync");
-        check_hip(hipMemsetAsync(flag.as<unsigned char>() + 8, 0, 4, s), "hipMemsetAsync");
-        check_hip(mb_invert(perm.as<uint32_t>(), n, inv.as<int32_t>(), s), "inverse permutation kernel");
-        check_hip(mb_relabel(dim, cells, n_cells, n, inv.as<int32_t>(), mc.as<int32_t>(),
-                             reinterpret_cast<int*>(flag.as<unsigned char>() + 8), flag.as<unsigned long long>(), s),
+        int32_t* inv = arena.take<int32_t>((size_t)n * 4);
+        unsigned char* flag = arena.take<unsigned char>(16);
+        check_hip(hipMemsetAsync(flag, 0xff, 8, s), "hipMemsetAsync");
+        check_hip(hipMemsetAsync(flag + 8, 0, 4, s), "hipMemsetAsync");
+        check_hip(mb_invert(perm, n, inv, s), "inverse permutation kernel");
+        check_hip(mb_relabel(dim, cells, n_cells, n, inv, mc, reinterpret_cast<int*>(flag + 8),
+                             reinterpret_cast<unsigned long long*>(flag), s),
                   "cell relabel kernel");
         unsigned long long hf[2] = {0, 0};
-        to_host(hf, flag.p, 12, s);
+        to_host(hf, flag, 12, s);
         if (hf[1] & 0xffffffffu) {
             const int64_t c = (int64_t)hf[0];
             int32_t v[4] = {0, 0, 0, 0};
@@ -1238,32 +1290,30 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
                                         " in cell " + std::to_string(c));
         }
     }
+    arena.at = phase_base;
+    m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
     int64_t nnz = 0;
     {
-        DevBuf ws(ring1_workspace_bytes(dim, n, n_cells));
+        void* ws = arena.take<void>(ring1_workspace_bytes(dim, n, n_cells));
         int bad_mesh = 0, too_long = 0;
-        check_hip(ring1_build(dim, mc.as<int32_t>(), n_cells, n, ws.p, row_ptr.as<int64_t>(), nullptr, 0, &nnz,
-                              &bad_mesh, &too_long, s),
+        check_hip(ring1_build(dim, mc, n_cells, n, ws, m->d_row_ptr, nullptr, 0, &nnz, &bad_mesh, &too_long, s),
                   "one-ring stencil kernels");
         if (bad_mesh) fail(FTLE_ERR_DEVICE, "relabelled cells failed the stencil's range check");
         if (too_long) fail(FTLE_ERR_UNSUPPORTED, "a point's incident cells list more than 4096 points");
         if (nnz > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
         m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
         if (nnz)
-            check_hip(ring1_write(dim, mc.as<int32_t>(), n_cells, n, ws.p, row_ptr.as<int64_t>(), m->d_col, s),
-                      "one-ring stencil kernels");
+            check_hip(ring1_write(dim, mc, n_cells, n, ws, m->d_row_ptr, m->d_col, s), "one-ring stencil kernels");
         check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     }
-    mc.reset();
+    arena.at = 0;   // the cells are no longer needed
     m->nnz = nnz;
-    m->d_row_ptr = static_cast<int64_t*>(row_ptr.release());
-    m->d_perm = static_cast<int32_t*>(perm.release());
     // the one-ring relation is symmetric: the forward tiles serve the adjoint
     m->symmetric = true;
 
     const std::vector<Extent> ext =
-        device_extents(dim, f64, n, m->tile_points, m->d_row_ptr, m->d_col, m->d_perm, s);
-    device_tiles(ext, m->d_row_ptr, m->d_col, m->d_perm, m->fwd, s);
+        device_extents(dim, f64, n, m->tile_points, m->d_row_ptr, m->d_col, m->d_perm, arena, s);
+    device_tiles(ext, m->d_row_ptr, m->d_col, m->d_perm, m->fwd, arena, s);
     if (dim == 3) {
         m->fwd.d_minv = dev_upload(nullptr, (size_t)n * 6 * eb);
         check_hip(mb_normal_inverse(f64, m->d_row_ptr, m->d_col, reinterpret_cast<const uint32_t*>(m->d_perm), m->d_x,
