@@ -129,10 +129,10 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
  * the one-ring neighbour determination of Section 2.2 (which the paper runs
  * on the host and its Conclusions name as future work for the accelerator),
  * the Morton order, the tile cut and the tile records, and in 3D the
- * inverse normal matrices.  The mesh is the one ftle_create_mesh builds from
- * the same arguments with the one-ring stencil: the same permutation,
- * stencil, tiles and record bytes, hence bit-identical results from every
- * call on it.  The host steers the steps from small downloads (bounds,
+ * inverse normal matrices; with FTLE_STENCIL_AXIS also the axis stencil and
+ * its transpose (the adjoint's tiles).  The mesh is the one ftle_create_mesh
+ * builds from the same arguments: the same permutation, stencil, tiles and
+ * record bytes, hence bit-identical results from every call on it.  The host steers the steps from small downloads (bounds,
  * a 2^16-pair sample of the caller's order, tile sizes); the stencil and the
  * records stay on the device, and ftle_mesh_get_csr / ftle_mesh_get_tiles
  * copy them out when asked.
@@ -140,11 +140,11 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
  *            double; copied into the mesh, must be finite
  *   cells    device pointer, n_cells x (dim+1) int32; read during the call
  *   n_cells  >= 0, at most (2^32-1) / (dim+1)
- *   flags    FTLE_NO_REORDER, FTLE_TILE(k)
+ *   flags    FTLE_STENCIL_*, FTLE_NO_REORDER, FTLE_TILE(k)
  *   stream   every kernel and copy of the build runs on it; the call
  *            returns when the mesh is complete (it synchronises the stream)
  * Errors: as ftle_create_mesh (the lowest faulty cell is reported);
- * UNSUPPORTED for FTLE_STENCIL_AXIS or FTLE_HOST_ONLY, a point whose incident
+ * UNSUPPORTED for FTLE_HOST_ONLY, a point whose incident
  * cells list more than 4096 points, or more than 2^31-1 stencil entries.
  */
 ftle_status ftle_create_mesh_device(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,

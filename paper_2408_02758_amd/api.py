@@ -98,13 +98,14 @@ class Mesh:
         return m
 
     @classmethod
-    def on_device(cls, coords: torch.Tensor, cells: torch.Tensor, reorder: bool = True, tile_log2: int = 0,
-                  stream=None):
+    def on_device(cls, coords: torch.Tensor, cells: torch.Tensor, stencil: str = "ring1", reorder: bool = True,
+                  tile_log2: int = 0, stream=None):
         """Mesh built on the GPU from device tensors (ftle_create_mesh_device):
         coords (N, dim) float32/float64 (the mesh dtype follows it), cells
         (ncells, dim+1) int32, both contiguous on the current device.  The
-        one-ring stencil, the Morton order and the tile records all come from
-        kernels; the mesh equals Mesh(coords, cells) built on the host."""
+        stencil ("ring1" or "axis"), the Morton order and the tile records all
+        come from kernels; the mesh equals Mesh(coords, cells, stencil=...)
+        built on the host."""
         if not (isinstance(coords, torch.Tensor) and coords.is_cuda and coords.is_contiguous()
                 and coords.dtype in (torch.float32, torch.float64) and coords.dim() == 2
                 and coords.shape[1] in (2, 3)):
@@ -114,7 +115,7 @@ class Mesh:
                 and cells.is_contiguous() and cells.dim() == 2 and cells.shape[1] == dim + 1):
             raise ValueError(f"cells must be a contiguous int32 device tensor of shape (ncells, {dim + 1})")
         dtype = "f64" if coords.dtype == torch.float64 else "f32"
-        flags = _lib.tile_flag(tile_log2)
+        flags = _lib.tile_flag(tile_log2) | {"ring1": _lib.STENCIL_RING1, "axis": _lib.STENCIL_AXIS}[stencil]
         if not reorder:
             flags |= _lib.NO_REORDER
         h = ctypes.c_void_p()

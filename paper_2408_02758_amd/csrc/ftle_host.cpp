@@ -1291,29 +1291,80 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
         }
     }
     arena.at = phase_base;
-    m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
+    // the one-ring stencil: the mesh's own (RING1), or the input of the axis stencil
+    const bool axis = (flags & FTLE_STENCIL_AXIS) != 0;
+    DevBuf ring_rp, ring_col;
+    int64_t* rp = nullptr;
+    if (axis) {
+        ring_rp = DevBuf(((size_t)n + 1) * 8);
+        rp = ring_rp.as<int64_t>();
+    } else {
+        m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
+        rp = m->d_row_ptr;
+    }
     int64_t nnz = 0;
+    int32_t* colp = nullptr;
     {
         void* ws = arena.take<void>(ring1_workspace_bytes(dim, n, n_cells));
         int bad_mesh = 0, too_long = 0;
-        check_hip(ring1_build(dim, mc, n_cells, n, ws, m->d_row_ptr, nullptr, 0, &nnz, &bad_mesh, &too_long, s),
+        check_hip(ring1_build(dim, mc, n_cells, n, ws, rp, nullptr, 0, &nnz, &bad_mesh, &too_long, s),
                   "one-ring stencil kernels");
         if (bad_mesh) fail(FTLE_ERR_DEVICE, "relabelled cells failed the stencil's range check");
         if (too_long) fail(FTLE_ERR_UNSUPPORTED, "a point's incident cells list more than 4096 points");
         if (nnz > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
-        m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
-        if (nnz)
-            check_hip(ring1_write(dim, mc, n_cells, n, ws, m->d_row_ptr, m->d_col, s), "one-ring stencil kernels");
+        if (axis) {
+            ring_col = DevBuf((size_t)nnz * 4);
+            colp = ring_col.as<int32_t>();
+        } else {
+            m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
+            colp = m->d_col;
+        }
+        if (nnz) check_hip(ring1_write(dim, mc, n_cells, n, ws, rp, colp, s), "one-ring stencil kernels");
         check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     }
     arena.at = 0;   // the cells are no longer needed
-    m->nnz = nnz;
     // the one-ring relation is symmetric: the forward tiles serve the adjoint
     m->symmetric = true;
+    DevBuf t_rp, t_col;   // the axis stencil's transpose, when it differs from the stencil
+    if (axis) {
+        // the axis stencil from the one-ring rows, then its transpose
+        DevBuf slots((size_t)n * 2 * dim * 4), cnt(((size_t)n + 1) * 4), partial(scan_partial_bytes(n + 1) + 16);
+        check_hip(mb_axis_stencil(dim, f64, m->d_x, perm, rp, colp, n, slots.as<int32_t>(), cnt.as<uint32_t>(), s),
+                  "axis stencil kernel");
+        m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
+        check_hip(scan_exclusive_to_i64(cnt.as<uint32_t>(), n, m->d_row_ptr, partial.as<int64_t>(), s), "scan");
+        to_host(&nnz, m->d_row_ptr + n, 8, s);
+        m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
+        check_hip(mb_axis_fill(dim, slots.as<int32_t>(), m->d_row_ptr, n, m->d_col, s), "axis stencil kernel");
+        t_rp = DevBuf(((size_t)n + 1) * 8);
+        t_col = DevBuf((size_t)nnz * 4);
+        int* differ = reinterpret_cast<int*>(slots.p);   // the slots are written out
+        check_hip(hipMemsetAsync(cnt.p, 0, ((size_t)n + 1) * 4, s), "hipMemsetAsync");
+        check_hip(mb_transpose_count(m->d_col, nnz, cnt.as<uint32_t>(), s), "transpose kernel");
+        check_hip(scan_exclusive_to_i64(cnt.as<uint32_t>(), n, t_rp.as<int64_t>(), partial.as<int64_t>(), s), "scan");
+        check_hip(hipMemsetAsync(cnt.p, 0, ((size_t)n + 1) * 4, s), "hipMemsetAsync");
+        check_hip(mb_transpose_fill(m->d_row_ptr, m->d_col, n, t_rp.as<int64_t>(), cnt.as<uint32_t>(),
+                                    t_col.as<int32_t>(), s),
+                  "transpose kernel");
+        check_hip(hipMemsetAsync(differ, 0, 4, s), "hipMemsetAsync");
+        check_hip(mb_csr_compare(m->d_row_ptr, m->d_col, t_rp.as<int64_t>(), t_col.as<int32_t>(), n, nnz, differ, s),
+                  "compare kernel");
+        int hd = 0;
+        to_host(&hd, differ, 4, s);
+        m->symmetric = hd == 0;
+        ring_rp.reset();
+        ring_col.reset();
+    }
+    m->nnz = nnz;
 
     const std::vector<Extent> ext =
         device_extents(dim, f64, n, m->tile_points, m->d_row_ptr, m->d_col, m->d_perm, arena, s);
     device_tiles(ext, m->d_row_ptr, m->d_col, m->d_perm, m->fwd, arena, s);
+    if (!m->symmetric) {
+        const std::vector<Extent> text =
+            device_extents(dim, f64, n, m->tile_points, t_rp.as<int64_t>(), t_col.as<int32_t>(), m->d_perm, arena, s);
+        device_tiles(text, t_rp.as<int64_t>(), t_col.as<int32_t>(), m->d_perm, m->bwd, arena, s);
+    }
     if (dim == 3) {
         m->fwd.d_minv = dev_upload(nullptr, (size_t)n * 6 * eb);
         check_hip(mb_normal_inverse(f64, m->d_row_ptr, m->d_col, reinterpret_cast<const uint32_t*>(m->d_perm), m->d_x,
@@ -1450,9 +1501,9 @@ ftle_status ftle_create_mesh_device(int dim, int64_t n_points, const void* coord
         if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points must be >= 1");
         if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
         if (!coords) fail(FTLE_ERR_INVALID_ARG, "coords is NULL");
-        if (flags & (FTLE_STENCIL_AXIS | FTLE_HOST_ONLY))
-            fail(FTLE_ERR_UNSUPPORTED, "the device build makes one-ring stencils on the device only");
-        if (flags & ~(unsigned)(FTLE_NO_REORDER | FTLE_TILE(0xff))) fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
+        if (flags & FTLE_HOST_ONLY) fail(FTLE_ERR_UNSUPPORTED, "a device-built mesh lives on the device");
+        if (flags & ~(unsigned)(FTLE_STENCIL_AXIS | FTLE_NO_REORDER | FTLE_HOST_ONLY | FTLE_TILE(0xff)))
+            fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
         const int tile_log2 = (int)((flags >> 8) & 0xff);
         if (tile_log2 != 0 && (tile_log2 < 5 || tile_log2 > 11))
             fail(FTLE_ERR_INVALID_ARG, "FTLE_TILE(k) needs 5 <= k <= 11");

@@ -251,6 +251,24 @@ hipError_t mb_tile_record(bool write, const int64_t* row_ptr, const int32_t* col
                           uint32_t* counts, const TileMeta* meta, unsigned char* rec, hipStream_t s);
 hipError_t mb_normal_inverse(bool f64, const int64_t* row_ptr, const int32_t* col, const uint32_t* perm,
                              const void* x, int64_t n, void* out, hipStream_t s);
+//   mb_axis_stencil: the axis stencil's slots (n x 2 dim, -1 absent) and
+//     counts per Morton row from the one-ring CSR; mb_axis_fill: its CSR
+//   mb_transpose_count / mb_transpose_fill: column counts (tcnt zeroed
+//     before), then, with trp their exclusive scan and cur zeroed, the
+//     transposed rows, each sorted ascending
+//   mb_csr_compare: *differ = 1 (set to 0 before) where two CSRs differ
+hipError_t mb_axis_stencil(int dim, bool f64, const void* x, const uint32_t* perm, const int64_t* ring_rp,
+                           const int32_t* ring_col, int64_t n, int32_t* slots, uint32_t* cnt, hipStream_t s);
+hipError_t mb_axis_fill(int dim, const int32_t* slots, const int64_t* row_ptr, int64_t n, int32_t* col,
+                        hipStream_t s);
+hipError_t mb_transpose_count(const int32_t* col, int64_t nnz, uint32_t* tcnt, hipStream_t s);
+hipError_t mb_transpose_fill(const int64_t* row_ptr, const int32_t* col, int64_t n, const int64_t* trp,
+                             uint32_t* cur, int32_t* tcol, hipStream_t s);
+hipError_t mb_csr_compare(const int64_t* rp_a, const int32_t* col_a, const int64_t* rp_b, const int32_t* col_b,
+                          int64_t n, int64_t nnz, int* differ, hipStream_t s);
+// Exclusive scan of m uint32 values into int64 out[0..m), out[m] = their sum;
+// partial: scan_partial_bytes(m) of device scratch.
+hipError_t scan_exclusive_to_i64(const uint32_t* in, int64_t m, int64_t* out, int64_t* partial, hipStream_t stream);
 
 // The paper's fixed-width axis list (ftle_ell.hip): the forward from it (one
 // lane per caller point; staged: each workgroup's block of points in LDS),

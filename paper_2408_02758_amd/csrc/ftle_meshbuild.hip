@@ -29,6 +29,7 @@
 //   normal_inverse  the 3D normal matrix inverse per point (float64)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "ftle_internal.h"
@@ -648,6 +649,133 @@ __global__ void __launch_bounds__(256) normal_inverse(const int64_t* __restrict_
     for (int k = 0; k < 6; ++k) out[i * 6 + k] = (T)v[k];
 }
 
+// ---------------------------------------------------------------------------
+// The axis stencil over Morton positions (FTLE_STENCIL_AXIS), as the host
+// builds it: per signed axis direction the one-ring neighbour on that side
+// with the largest cosine to the axis (float64, no contraction, ties to the
+// smaller caller index), in slot order (-x, +x, -y, +y[, -z, +z]), absent
+// sides dropped, a neighbour chosen twice listed twice.
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+__global__ void __launch_bounds__(256) axis_slots(const T* __restrict__ x, const uint32_t* __restrict__ perm,
+                                                  const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                  int64_t n, int32_t* __restrict__ slots, uint32_t* __restrict__ cnt)
+{
+#pragma clang fp contract(off)
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int64_t i = perm[r];
+    double xi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xi[d] = (double)x[i * D + d];
+    int32_t best[2 * D];
+    uint32_t best_u[2 * D];
+    double best_c[2 * D];
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        best[k] = -1;
+        best_u[k] = 0;
+        best_c[k] = 0.0;
+    }
+    for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
+        const int32_t c = col[p];
+        const uint32_t j = perm[c];
+        double dx[D];
+        double nrm2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            dx[d] = (double)x[(int64_t)j * D + d] - xi[d];
+            nrm2 = nrm2 + dx[d] * dx[d];
+        }
+        const double nrm = sqrt(nrm2);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const double along = sg ? dx[d] : -dx[d];
+                if (!(along > 0.0)) continue;
+                const double cs = along / nrm;
+                const int k = 2 * d + sg;
+                if (best[k] < 0 || cs > best_c[k] || (cs == best_c[k] && j < best_u[k])) {
+                    best_c[k] = cs;
+                    best[k] = c;
+                    best_u[k] = j;
+                }
+            }
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        slots[r * 2 * D + k] = best[k];
+        m += best[k] >= 0 ? 1u : 0u;
+    }
+    cnt[r] = m;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) axis_fill(const int32_t* __restrict__ slots, const int64_t* __restrict__ row_ptr,
+                                                 int64_t n, int32_t* __restrict__ col)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    int64_t q = row_ptr[r];
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) {
+        const int32_t c = slots[r * 2 * D + k];
+        if (c >= 0) col[q++] = c;
+    }
+}
+
+// Transpose of a CSR over Morton positions: column counts, then (after their
+// scan) each entry placed by an atomic cursor, then each row sorted (rows
+// ascend, as the host's counting transpose leaves them).
+__global__ void __launch_bounds__(256) transpose_count(const int32_t* __restrict__ col, int64_t nnz,
+                                                       uint32_t* __restrict__ tcnt)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < nnz) atomicAdd(&tcnt[col[p]], 1u);
+}
+
+__global__ void __launch_bounds__(256) transpose_fill(const int64_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col, int64_t n,
+                                                      const int64_t* __restrict__ trp, uint32_t* __restrict__ cur,
+                                                      int32_t* __restrict__ tcol)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
+        const int32_t c = col[p];
+        tcol[trp[c] + atomicAdd(&cur[c], 1u)] = (int32_t)r;
+    }
+}
+
+__global__ void __launch_bounds__(256) sort_rows(const int64_t* __restrict__ row_ptr, int64_t n,
+                                                 int32_t* __restrict__ col)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    int32_t* row = col + row_ptr[r];
+    const int64_t len = row_ptr[r + 1] - row_ptr[r];
+    for (int64_t a = 1; a < len; ++a) {
+        const int32_t v = row[a];
+        int64_t k = a;
+        while (k > 0 && row[k - 1] > v) {
+            row[k] = row[k - 1];
+            --k;
+        }
+        row[k] = v;
+    }
+}
+
+// *differ = 1 where two CSRs of n rows and nnz entries differ
+__global__ void __launch_bounds__(256) csr_compare(const int64_t* __restrict__ rp_a, const int32_t* __restrict__ col_a,
+                                                   const int64_t* __restrict__ rp_b, const int32_t* __restrict__ col_b,
+                                                   int64_t n, int64_t nnz, int* __restrict__ differ)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((i <= n && rp_a[i] != rp_b[i]) || (i < nnz && col_a[i] != col_b[i])) *differ = 1;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -782,6 +910,60 @@ hipError_t mb_normal_inverse(bool f64, const int64_t* row_ptr, const int32_t* co
     else
         hipLaunchKernelGGL(normal_inverse<float>, dim3(blocks_of(n, 256)), dim3(256), 0, s, row_ptr, col, perm,
                            static_cast<const float*>(x), n, 1e-5, static_cast<float*>(out));
+    return hipGetLastError();
+}
+
+hipError_t mb_axis_stencil(int dim, bool f64, const void* x, const uint32_t* perm, const int64_t* ring_rp,
+                           const int32_t* ring_col, int64_t n, int32_t* slots, uint32_t* cnt, hipStream_t s)
+{
+    const dim3 g(blocks_of(n, 256)), b(256);
+    if (dim == 2) {
+        if (f64)
+            hipLaunchKernelGGL((axis_slots<2, double>), g, b, 0, s, static_cast<const double*>(x), perm, ring_rp,
+                               ring_col, n, slots, cnt);
+        else
+            hipLaunchKernelGGL((axis_slots<2, float>), g, b, 0, s, static_cast<const float*>(x), perm, ring_rp,
+                               ring_col, n, slots, cnt);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL((axis_slots<3, double>), g, b, 0, s, static_cast<const double*>(x), perm, ring_rp,
+                               ring_col, n, slots, cnt);
+        else
+            hipLaunchKernelGGL((axis_slots<3, float>), g, b, 0, s, static_cast<const float*>(x), perm, ring_rp,
+                               ring_col, n, slots, cnt);
+    }
+    return hipGetLastError();
+}
+
+hipError_t mb_axis_fill(int dim, const int32_t* slots, const int64_t* row_ptr, int64_t n, int32_t* col, hipStream_t s)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL(axis_fill<2>, dim3(blocks_of(n, 256)), dim3(256), 0, s, slots, row_ptr, n, col);
+    else
+        hipLaunchKernelGGL(axis_fill<3>, dim3(blocks_of(n, 256)), dim3(256), 0, s, slots, row_ptr, n, col);
+    return hipGetLastError();
+}
+
+hipError_t mb_transpose_count(const int32_t* col, int64_t nnz, uint32_t* tcnt, hipStream_t s)
+{
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(transpose_count, dim3(blocks_of(nnz, 256)), dim3(256), 0, s, col, nnz, tcnt);
+    return hipGetLastError();
+}
+
+hipError_t mb_transpose_fill(const int64_t* row_ptr, const int32_t* col, int64_t n, const int64_t* trp, uint32_t* cur,
+                             int32_t* tcol, hipStream_t s)
+{
+    hipLaunchKernelGGL(transpose_fill, dim3(blocks_of(n, 256)), dim3(256), 0, s, row_ptr, col, n, trp, cur, tcol);
+    hipLaunchKernelGGL(sort_rows, dim3(blocks_of(n, 256)), dim3(256), 0, s, trp, n, tcol);
+    return hipGetLastError();
+}
+
+hipError_t mb_csr_compare(const int64_t* rp_a, const int32_t* col_a, const int64_t* rp_b, const int32_t* col_b,
+                          int64_t n, int64_t nnz, int* differ, hipStream_t s)
+{
+    const int64_t m = std::max<int64_t>(n + 1, nnz);
+    hipLaunchKernelGGL(csr_compare, dim3(blocks_of(m, 256)), dim3(256), 0, s, rp_a, col_a, rp_b, col_b, n, nnz, differ);
     return hipGetLastError();
 }
 

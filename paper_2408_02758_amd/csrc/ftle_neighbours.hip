@@ -533,6 +533,11 @@ hipError_t scan_exclusive_u32(const uint32_t* in, int64_t m, uint32_t* out, uint
     return exclusive_scan<uint32_t>(in, m, out, partial, stream);
 }
 
+hipError_t scan_exclusive_to_i64(const uint32_t* in, int64_t m, int64_t* out, int64_t* partial, hipStream_t stream)
+{
+    return exclusive_scan<int64_t>(in, m, out, partial, stream);
+}
+
 size_t scan_partial_bytes(int64_t m) { return 8 * (size_t)((m + kScanTile - 1) / kScanTile + 1); }
 
 }  // namespace ftle

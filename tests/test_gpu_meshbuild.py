@@ -23,21 +23,21 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def _raw_tiles(m):
+def _raw_tiles(m, adjoint=0):
     L = _lib.load()
     nt, rb = ctypes.c_int64(), ctypes.c_int64()
-    _lib.check(L.ftle_mesh_get_tiles(m.handle, 0, ctypes.byref(nt), ctypes.byref(rb), None, None))
+    _lib.check(L.ftle_mesh_get_tiles(m.handle, adjoint, ctypes.byref(nt), ctypes.byref(rb), None, None))
     meta = np.empty(nt.value * 16, np.uint8)
     rec = np.empty(max(rb.value, 16), np.uint8)
-    _lib.check(L.ftle_mesh_get_tiles(m.handle, 0, None, None, meta.ctypes.data, rec.ctypes.data))
+    _lib.check(L.ftle_mesh_get_tiles(m.handle, adjoint, None, None, meta.ctypes.data, rec.ctypes.data))
     return meta, rec[:rb.value]
 
 
-def _device_mesh(x, cells, dtype, **kw):
+def _device_mesh(x, cells, dtype, stencil="ring1", **kw):
     npdt = np.float64 if dtype == "f64" else np.float32
     xd = torch.as_tensor(np.ascontiguousarray(x, dtype=npdt), device=DEV)
     cd = torch.as_tensor(np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, x.shape[1] + 1), device=DEV)
-    return F.Mesh.on_device(xd, cd, **kw)
+    return F.Mesh.on_device(xd, cd, stencil=stencil, **kw)
 
 
 def _oracle_rows(dim, n, cells):
@@ -70,30 +70,41 @@ def _flow(x, seed):
     return x + np.sin(x @ a) * 0.05
 
 
-def assert_same_mesh(x, cells, dtype="f32", tile_log2=0, reorder=True, check_oracle=True, T=2.0):
+def assert_same_mesh(x, cells, dtype="f32", tile_log2=0, reorder=True, check_oracle=True, T=2.0, stencil="ring1"):
     dim = x.shape[1]
     n = x.shape[0]
-    print(f"[device mesh dim={dim} n={n} cells={len(cells)} {dtype} tile={tile_log2} reorder={reorder}]",
-          flush=True)
-    host = F.Mesh(x, cells, dtype, tile_log2=tile_log2, reorder=reorder)
-    dev = _device_mesh(x, cells, dtype, tile_log2=tile_log2, reorder=reorder)
+    print(f"[device mesh dim={dim} n={n} cells={len(cells)} {dtype} tile={tile_log2} reorder={reorder} "
+          f"stencil={stencil}]", flush=True)
+    host = F.Mesh(x, cells, dtype, tile_log2=tile_log2, reorder=reorder, stencil=stencil)
+    dev = _device_mesh(x, cells, dtype, tile_log2=tile_log2, reorder=reorder, stencil=stencil)
     assert dev.info() == host.info()
     for name, a, b in zip(("row_ptr", "col", "perm"), dev.csr(), host.csr()):
         assert a.shape == b.shape and np.array_equal(a, b), \
             f"{name} differs at {np.flatnonzero(a != b)[:8] if a.shape == b.shape else a.shape}"
     assert dev.tile_stats() == host.tile_stats()
-    dm, dr = _raw_tiles(dev)
-    hm, hr = _raw_tiles(host)
-    assert np.array_equal(dm, hm), "tile metadata differs"
-    assert np.array_equal(dr, hr), "tile record bytes differ"
+    for adjoint in (0, 1):
+        dm, dr = _raw_tiles(dev, adjoint)
+        hm, hr = _raw_tiles(host, adjoint)
+        assert np.array_equal(dm, hm), f"tile metadata differs (adjoint={adjoint})"
+        assert np.array_equal(dr, hr), f"tile record bytes differ (adjoint={adjoint})"
     if check_oracle:
         rp, col = _user_order_csr(dev)
-        orp, ocol = _oracle_rows(dim, n, cells)
+        if stencil == "ring1":
+            orp, ocol = _oracle_rows(dim, n, cells)
+        else:
+            xx = np.asarray(x, np.float32 if dtype == "f32" else np.float64).astype(np.float64)
+            st = oracle.axis(dim, xx, oracle.ring1(dim, n, cells))
+            sl = st.col.reshape(n, 2 * dim)
+            keep = sl >= 0
+            orp = np.concatenate([[0], np.cumsum(keep.sum(1))]).astype(np.int64)
+            ocol = np.concatenate([np.sort(r[r >= 0]) for r in sl]).astype(np.int32) if n else np.zeros(0, np.int32)
         assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
     # every later call reads the same data: bit-identical results
     tdt = torch.float64 if dtype == "f64" else torch.float32
     phi = torch.as_tensor(_flow(x, 11), dtype=tdt, device=DEV)
     assert same_bits(dev.forward(phi, T), host.forward(phi, T))
+    g = torch.as_tensor(np.random.default_rng(7).normal(size=n), dtype=tdt, device=DEV)
+    assert same_bits(dev.backward(phi, T, g), host.backward(phi, T, g))
     if dim == 3:
         a, _ = dev.forward_tape(phi, T)
         b, _ = host.forward_tape(phi, T)
@@ -200,13 +211,13 @@ def test_errors():
     with pytest.raises(F.FTLEError) as e:
         _device_mesh(xb, cells, "f64")
     assert e.value.status == 1 and "coordinate 33" in str(e.value)
-    # the axis stencil is built on the host only
+    # a device-built mesh cannot be host-only
     L = _lib.load()
     xd = torch.as_tensor(x, dtype=torch.float32, device=DEV)
     cd = torch.as_tensor(cells, dtype=torch.int32, device=DEV)
     h = ctypes.c_void_p()
     st = L.ftle_create_mesh_device(2, x.shape[0], ctypes.c_void_p(xd.data_ptr()), _lib.F32, cells.shape[0],
-                                   ctypes.c_void_p(cd.data_ptr()), _lib.STENCIL_AXIS, None, ctypes.byref(h))
+                                   ctypes.c_void_p(cd.data_ptr()), _lib.HOST_ONLY, None, ctypes.byref(h))
     assert st == 4 and not h.value
 
 
@@ -237,3 +248,23 @@ def test_full_size_2d_equals_host():
     dm, dr = _raw_tiles(dev)
     hm, hr = _raw_tiles(host)
     assert np.array_equal(dm, hm) and np.array_equal(dr, hr)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_axis_stencil(dim, dtype):
+    """The paper's axis stencil built on the device: slot order, repeats kept,
+    its transpose for the adjoint tiles, all equal to the host build."""
+    x, cells = meshes.jittered_tri_grid(71, 53, seed=8) if dim == 2 else meshes.kuhn_tet_grid(12, nz=10)
+    assert_same_mesh(x, cells, dtype, stencil="axis")
+    xr, cr, _ = meshes.relabel(x, cells, seed=4)
+    assert_same_mesh(xr, cr, dtype, stencil="axis", tile_log2=7)
+
+
+def test_axis_stencil_irregular():
+    from scipy.spatial import Delaunay
+    g = np.random.default_rng(12)
+    for dim, n in ((2, 4000), (3, 2500)):
+        x = g.random((n, dim))
+        cells = Delaunay(x).simplices.astype(np.int32)
+        assert_same_mesh(x, cells, "f32", stencil="axis")
