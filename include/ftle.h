@@ -152,6 +152,27 @@ ftle_status ftle_create_mesh_device(int dim, int64_t n_points, const void* coord
                                     ftle_mesh_t* out);
 
 /*
+ * ftle_create_mesh_from_csr with the stencil on the device, and every step of
+ * the build there (the Morton order, the rows moved to Morton positions and
+ * sorted, the transpose for the adjoint when the stencil is not symmetric,
+ * the tiles and records): the same mesh, byte for byte.  Takes the output of
+ * ftle_ring1_csr, or the paper's fixed-width list as it stands (row_ptr[i] =
+ * 2 dim i; its -1 entries are dropped).
+ *   coords   device pointer, n_points x dim, float or double; copied
+ *   row_ptr  device, n_points+1 int64, row_ptr[0] = 0, non-decreasing; read
+ *            during the call (row_ptr[n_points] is copied to the host first)
+ *   col      device, row_ptr[n_points] int32 in [-1, n_points); read during
+ *            the call
+ *   flags    FTLE_NO_REORDER, FTLE_TILE(k)
+ *   stream   as ftle_create_mesh_device
+ * Errors: as ftle_create_mesh_from_csr (the lowest faulty row or entry is
+ * reported); UNSUPPORTED for FTLE_HOST_ONLY.
+ */
+ftle_status ftle_create_mesh_device_from_csr(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                                             const int64_t* row_ptr, const int32_t* col, unsigned flags,
+                                             ftle_stream_t stream, ftle_mesh_t* out);
+
+/*
  * The one-ring stencil of a cell mesh, built on the device: row i lists, in
  * ascending order and once each, every other point that shares a cell with
  * point i (the neighbour determination that Section 2.2 keeps off the

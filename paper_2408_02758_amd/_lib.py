@@ -40,6 +40,7 @@ SIGNATURES = {
     "ftle_create_mesh": (_int, [_int, _i64, _vp, _int, _i64, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_create_mesh_from_csr": (_int, [_int, _i64, _vp, _int, _vp, _vp, ctypes.c_uint, _P(_vp)]),
     "ftle_create_mesh_device": (_int, [_int, _i64, _vp, _int, _i64, _vp, ctypes.c_uint, _vp, _P(_vp)]),
+    "ftle_create_mesh_device_from_csr": (_int, [_int, _i64, _vp, _int, _vp, _vp, ctypes.c_uint, _vp, _P(_vp)]),
     "ftle_ring1_csr": (_int, [_int, _i64, _i64, _vp, _vp, _vp, _i64, _P(_i64), _vp]),
     "ftle_ring1_csr_workspace": (_int, [_int, _i64, _i64, _P(_i64)]),
     "ftle_ring1_csr_ws": (_int, [_int, _i64, _i64, _vp, _vp, _vp, _i64, _P(_i64), _vp, _i64, _vp]),

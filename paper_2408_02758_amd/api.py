@@ -128,6 +128,37 @@ class Mesh:
         m._init(h, dim, coords.shape[0], dtype, False)
         return m
 
+    @classmethod
+    def from_csr_on_device(cls, coords: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, reorder: bool = True,
+                           tile_log2: int = 0, stream=None):
+        """Mesh.from_csr built on the GPU (ftle_create_mesh_device_from_csr):
+        coords (N, dim) float32/float64, row_ptr (N+1,) int64 and col int32
+        device tensors (caller indices; -1 and self entries dropped, repeats
+        kept), e.g. ring1_csr's output or the paper's list with
+        row_ptr = 2*dim*arange(N+1)."""
+        if not (isinstance(coords, torch.Tensor) and coords.is_cuda and coords.is_contiguous()
+                and coords.dtype in (torch.float32, torch.float64) and coords.dim() == 2
+                and coords.shape[1] in (2, 3)):
+            raise ValueError("coords must be a contiguous float32/float64 device tensor of shape (N, 2) or (N, 3)")
+        n, dim = coords.shape
+        if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.is_contiguous()
+                and tuple(row_ptr.shape) == (n + 1,)):
+            raise ValueError("row_ptr must be a contiguous int64 device tensor of N+1 entries")
+        if not (col.is_cuda and col.dtype == torch.int32 and col.is_contiguous()):
+            raise ValueError("col must be a contiguous int32 device tensor")
+        dtype = "f64" if coords.dtype == torch.float64 else "f32"
+        flags = _lib.tile_flag(tile_log2)
+        if not reorder:
+            flags |= _lib.NO_REORDER
+        h = ctypes.c_void_p()
+        check(_lib.load().ftle_create_mesh_device_from_csr(
+            dim, n, ctypes.c_void_p(coords.data_ptr()), _DT[dtype][0], ctypes.c_void_p(row_ptr.data_ptr()),
+            ctypes.c_void_p(col.data_ptr()) if col.numel() else None, flags, _stream_handle(stream),
+            ctypes.byref(h)))
+        m = cls.__new__(cls)
+        m._init(h, dim, n, dtype, False)
+        return m
+
     # -- lifetime ---------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

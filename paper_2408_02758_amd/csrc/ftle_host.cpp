@@ -1178,12 +1178,19 @@ void device_tiles(const std::vector<Extent>& ext, const int64_t* row_ptr, const 
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype dtype, int64_t n_cells,
-                              const int32_t* cells, unsigned flags, int tile_log2, hipStream_t s)
+// The skeleton shared by both device builds: the mesh's coordinates, the
+// bounds, the Morton order; then `stencil(m, perm, arena)` sets the forward
+// stencil over Morton positions (m->d_row_ptr, m->d_col, m->nnz); then, unless
+// the stencil is known to be symmetric, its transpose is formed and compared
+// (the host build's test); then the tiles (and the transpose's tiles when it
+// differs), the 3D inverse normal matrices and the mesh's counters.
+// stencil_bytes: the arena the stencil step needs.
+template <typename Stencil>
+ftle_mesh_t build_device(int dim, int64_t n, const void* coords, ftle_dtype dtype, unsigned flags, int tile_log2,
+                         size_t stencil_bytes, bool known_symmetric, hipStream_t s, Stencil&& stencil)
 {
     const bool f64 = dtype == FTLE_F64;
     const size_t eb = f64 ? 8 : 4;
-    const int k = dim + 1;
     std::unique_ptr<ftle_mesh_s> m(new ftle_mesh_s);
     m->dim = dim;
     m->n = n;
@@ -1202,23 +1209,17 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
         }
     } guard{m.get()};
 
-    // One arena for every temporary: the relabelled cells, then (one phase at
-    // a time above them) the bounds and the sort, the inverse permutation, the
-    // stencil workspace; later the whole arena serves the tile passes.
+    // One arena for every temporary: the bounds and the sort first, then the
+    // stencil step's arrays, later the tile passes.
     const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
     int64_t ms = 0, stride = 0;
     order_sample(n, &ms, &stride);
-    const size_t mc_bytes = Arena::round((size_t)n_cells * k * 4);
     const size_t phase_sort = Arena::round((size_t)nb * 2 * dim * 8 + 8) + Arena::round((size_t)ms * 2 * dim * 8) +
                               Arena::round((size_t)n * 8) + Arena::round(mb_sort_scratch_bytes(n));
-    const size_t phase_inv = Arena::round((size_t)n * 4) + Arena::round(16);
-    const size_t phase_ring = Arena::round(ring1_workspace_bytes(dim, n, n_cells));
-    DevBuf arena_buf(mc_bytes + std::max({phase_sort, phase_inv, phase_ring}));
+    DevBuf arena_buf(std::max(phase_sort, stencil_bytes));
     Arena arena;
     arena.base = static_cast<unsigned char*>(arena_buf.p);
-    arena.size = mc_bytes + std::max({phase_sort, phase_inv, phase_ring});
-    int32_t* mc = arena.take<int32_t>((size_t)n_cells * k * 4);
-    const size_t phase_base = arena.at;
+    arena.size = std::max(phase_sort, stencil_bytes);
 
     // the mesh's own copy of the coordinates; bounds and finiteness
     m->d_x = dev_upload(nullptr, (size_t)n * dim * eb);
@@ -1263,82 +1264,20 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
         check_hip(mb_iota(perm, n, s), "iota kernel");
     }
 
-    // cells in Morton positions (validated), then the one-ring stencil
-    arena.at = phase_base;
-    {
-        int32_t* inv = arena.take<int32_t>((size_t)n * 4);
-        unsigned char* flag = arena.take<unsigned char>(16);
-        check_hip(hipMemsetAsync(flag, 0xff, 8, s), "hipMemsetAsync");
-        check_hip(hipMemsetAsync(flag + 8, 0, 4, s), "hipMemsetAsync");
-        check_hip(mb_invert(perm, n, inv, s), "inverse permutation kernel");
-        check_hip(mb_relabel(dim, cells, n_cells, n, inv, mc, reinterpret_cast<int*>(flag + 8),
-                             reinterpret_cast<unsigned long long*>(flag), s),
-                  "cell relabel kernel");
-        unsigned long long hf[2] = {0, 0};
-        to_host(hf, flag, 12, s);
-        if (hf[1] & 0xffffffffu) {
-            const int64_t c = (int64_t)hf[0];
-            int32_t v[4] = {0, 0, 0, 0};
-            to_host(v, cells + c * k, (size_t)k * 4, s);
-            int kind = 0;   // the first fault in vertex order, as the host build reports it
-            for (int a = 0; a < k && !kind; ++a) {
-                if (v[a] < 0 || v[a] >= n) kind = 1;
-                for (int q = 0; q < a && !kind; ++q)
-                    if (v[q] == v[a]) kind = 2;
-            }
-            fail(FTLE_ERR_BAD_MESH, std::string(kind == 1 ? "cell index out of range" : "repeated vertex") +
-                                        " in cell " + std::to_string(c));
-        }
-    }
-    arena.at = phase_base;
-    // the one-ring stencil: the mesh's own (RING1), or the input of the axis stencil
-    const bool axis = (flags & FTLE_STENCIL_AXIS) != 0;
-    DevBuf ring_rp, ring_col;
-    int64_t* rp = nullptr;
-    if (axis) {
-        ring_rp = DevBuf(((size_t)n + 1) * 8);
-        rp = ring_rp.as<int64_t>();
-    } else {
-        m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
-        rp = m->d_row_ptr;
-    }
-    int64_t nnz = 0;
-    int32_t* colp = nullptr;
-    {
-        void* ws = arena.take<void>(ring1_workspace_bytes(dim, n, n_cells));
-        int bad_mesh = 0, too_long = 0;
-        check_hip(ring1_build(dim, mc, n_cells, n, ws, rp, nullptr, 0, &nnz, &bad_mesh, &too_long, s),
-                  "one-ring stencil kernels");
-        if (bad_mesh) fail(FTLE_ERR_DEVICE, "relabelled cells failed the stencil's range check");
-        if (too_long) fail(FTLE_ERR_UNSUPPORTED, "a point's incident cells list more than 4096 points");
-        if (nnz > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
-        if (axis) {
-            ring_col = DevBuf((size_t)nnz * 4);
-            colp = ring_col.as<int32_t>();
-        } else {
-            m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
-            colp = m->d_col;
-        }
-        if (nnz) check_hip(ring1_write(dim, mc, n_cells, n, ws, rp, colp, s), "one-ring stencil kernels");
-        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    }
-    arena.at = 0;   // the cells are no longer needed
-    // the one-ring relation is symmetric: the forward tiles serve the adjoint
+    // the stencil over Morton positions
+    arena.at = 0;
+    stencil(m.get(), perm, arena);
+    arena.at = 0;
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const int64_t nnz = m->nnz;
+
+    // its transpose, when the stencil is not known to be symmetric
+    DevBuf t_rp, t_col;
     m->symmetric = true;
-    DevBuf t_rp, t_col;   // the axis stencil's transpose, when it differs from the stencil
-    if (axis) {
-        // the axis stencil from the one-ring rows, then its transpose
-        DevBuf slots((size_t)n * 2 * dim * 4), cnt(((size_t)n + 1) * 4), partial(scan_partial_bytes(n + 1) + 16);
-        check_hip(mb_axis_stencil(dim, f64, m->d_x, perm, rp, colp, n, slots.as<int32_t>(), cnt.as<uint32_t>(), s),
-                  "axis stencil kernel");
-        m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
-        check_hip(scan_exclusive_to_i64(cnt.as<uint32_t>(), n, m->d_row_ptr, partial.as<int64_t>(), s), "scan");
-        to_host(&nnz, m->d_row_ptr + n, 8, s);
-        m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
-        check_hip(mb_axis_fill(dim, slots.as<int32_t>(), m->d_row_ptr, n, m->d_col, s), "axis stencil kernel");
+    if (!known_symmetric) {
+        DevBuf cnt(((size_t)n + 1) * 4), partial(scan_partial_bytes(n + 1) + 16), flag(16);
         t_rp = DevBuf(((size_t)n + 1) * 8);
         t_col = DevBuf((size_t)nnz * 4);
-        int* differ = reinterpret_cast<int*>(slots.p);   // the slots are written out
         check_hip(hipMemsetAsync(cnt.p, 0, ((size_t)n + 1) * 4, s), "hipMemsetAsync");
         check_hip(mb_transpose_count(m->d_col, nnz, cnt.as<uint32_t>(), s), "transpose kernel");
         check_hip(scan_exclusive_to_i64(cnt.as<uint32_t>(), n, t_rp.as<int64_t>(), partial.as<int64_t>(), s), "scan");
@@ -1346,16 +1285,14 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
         check_hip(mb_transpose_fill(m->d_row_ptr, m->d_col, n, t_rp.as<int64_t>(), cnt.as<uint32_t>(),
                                     t_col.as<int32_t>(), s),
                   "transpose kernel");
-        check_hip(hipMemsetAsync(differ, 0, 4, s), "hipMemsetAsync");
-        check_hip(mb_csr_compare(m->d_row_ptr, m->d_col, t_rp.as<int64_t>(), t_col.as<int32_t>(), n, nnz, differ, s),
+        check_hip(hipMemsetAsync(flag.p, 0, 4, s), "hipMemsetAsync");
+        check_hip(mb_csr_compare(m->d_row_ptr, m->d_col, t_rp.as<int64_t>(), t_col.as<int32_t>(), n, nnz,
+                                 flag.as<int>(), s),
                   "compare kernel");
-        int hd = 0;
-        to_host(&hd, differ, 4, s);
-        m->symmetric = hd == 0;
-        ring_rp.reset();
-        ring_col.reset();
+        int differ = 0;
+        to_host(&differ, flag.p, 4, s);
+        m->symmetric = differ == 0;
     }
-    m->nnz = nnz;
 
     const std::vector<Extent> ext =
         device_extents(dim, f64, n, m->tile_points, m->d_row_ptr, m->d_col, m->d_perm, arena, s);
@@ -1367,8 +1304,7 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
     }
     if (dim == 3) {
         m->fwd.d_minv = dev_upload(nullptr, (size_t)n * 6 * eb);
-        check_hip(mb_normal_inverse(f64, m->d_row_ptr, m->d_col, reinterpret_cast<const uint32_t*>(m->d_perm), m->d_x,
-                                    n, m->fwd.d_minv, s),
+        check_hip(mb_normal_inverse(f64, m->d_row_ptr, m->d_col, perm, m->d_x, n, m->fwd.d_minv, s),
                   "normal matrix kernel");
     }
     m->d_hits = static_cast<unsigned long long*>(dev_upload(nullptr, sizeof(unsigned long long)));
@@ -1377,6 +1313,129 @@ ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     guard.m = nullptr;
     return m.release();
+}
+
+// From device cells: the cells relabelled and checked, the one-ring stencil,
+// and with FTLE_STENCIL_AXIS the axis stencil from it.
+ftle_mesh_t build_mesh_device(int dim, int64_t n, const void* coords, ftle_dtype dtype, int64_t n_cells,
+                              const int32_t* cells, unsigned flags, int tile_log2, hipStream_t s)
+{
+    const int k = dim + 1;
+    const bool axis = (flags & FTLE_STENCIL_AXIS) != 0;
+    const size_t mc_bytes = Arena::round((size_t)n_cells * k * 4);
+    const size_t need = mc_bytes + std::max(Arena::round((size_t)n * 4) + Arena::round(16),
+                                            Arena::round(ring1_workspace_bytes(dim, n, n_cells)));
+    return build_device(dim, n, coords, dtype, flags, tile_log2, need, !axis, s,
+                        [&](ftle_mesh_s* m, const uint32_t* perm, Arena& arena) {
+        const bool f64 = dtype == FTLE_F64;
+        int32_t* mc = arena.take<int32_t>((size_t)n_cells * k * 4);
+        const size_t phase_base = arena.at;
+        {
+            int32_t* inv = arena.take<int32_t>((size_t)n * 4);
+            unsigned char* flag = arena.take<unsigned char>(16);
+            check_hip(hipMemsetAsync(flag, 0xff, 8, s), "hipMemsetAsync");
+            check_hip(hipMemsetAsync(flag + 8, 0, 4, s), "hipMemsetAsync");
+            check_hip(mb_invert(perm, n, inv, s), "inverse permutation kernel");
+            check_hip(mb_relabel(dim, cells, n_cells, n, inv, mc, reinterpret_cast<int*>(flag + 8),
+                                 reinterpret_cast<unsigned long long*>(flag), s),
+                      "cell relabel kernel");
+            unsigned long long hf[2] = {0, 0};
+            to_host(hf, flag, 12, s);
+            if (hf[1] & 0xffffffffu) {
+                const int64_t c = (int64_t)hf[0];
+                int32_t v[4] = {0, 0, 0, 0};
+                to_host(v, cells + c * k, (size_t)k * 4, s);
+                int kind = 0;   // the first fault in vertex order, as the host build reports it
+                for (int a = 0; a < k && !kind; ++a) {
+                    if (v[a] < 0 || v[a] >= n) kind = 1;
+                    for (int q = 0; q < a && !kind; ++q)
+                        if (v[q] == v[a]) kind = 2;
+                }
+                fail(FTLE_ERR_BAD_MESH, std::string(kind == 1 ? "cell index out of range" : "repeated vertex") +
+                                            " in cell " + std::to_string(c));
+            }
+        }
+        arena.at = phase_base;
+        // the one-ring stencil: the mesh's own (RING1), or the input of the axis stencil
+        DevBuf ring_rp, ring_col;
+        int64_t* rp = nullptr;
+        if (axis) {
+            ring_rp = DevBuf(((size_t)n + 1) * 8);
+            rp = ring_rp.as<int64_t>();
+        } else {
+            m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
+            rp = m->d_row_ptr;
+        }
+        int64_t nnz = 0;
+        int32_t* colp = nullptr;
+        {
+            void* ws = arena.take<void>(ring1_workspace_bytes(dim, n, n_cells));
+            int bad_mesh = 0, too_long = 0;
+            check_hip(ring1_build(dim, mc, n_cells, n, ws, rp, nullptr, 0, &nnz, &bad_mesh, &too_long, s),
+                      "one-ring stencil kernels");
+            if (bad_mesh) fail(FTLE_ERR_DEVICE, "relabelled cells failed the stencil's range check");
+            if (too_long) fail(FTLE_ERR_UNSUPPORTED, "a point's incident cells list more than 4096 points");
+            if (nnz > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
+            if (axis) {
+                ring_col = DevBuf((size_t)nnz * 4);
+                colp = ring_col.as<int32_t>();
+            } else {
+                m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
+                colp = m->d_col;
+            }
+            if (nnz) check_hip(ring1_write(dim, mc, n_cells, n, ws, rp, colp, s), "one-ring stencil kernels");
+            check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
+        if (axis) {
+            // the axis stencil from the one-ring rows
+            DevBuf slots((size_t)n * 2 * dim * 4), cnt(((size_t)n + 1) * 4), partial(scan_partial_bytes(n + 1) + 16);
+            check_hip(mb_axis_stencil(dim, f64, m->d_x, perm, rp, colp, n, slots.as<int32_t>(), cnt.as<uint32_t>(),
+                                      s),
+                      "axis stencil kernel");
+            m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
+            check_hip(scan_exclusive_to_i64(cnt.as<uint32_t>(), n, m->d_row_ptr, partial.as<int64_t>(), s), "scan");
+            to_host(&nnz, m->d_row_ptr + n, 8, s);
+            m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
+            check_hip(mb_axis_fill(dim, slots.as<int32_t>(), m->d_row_ptr, n, m->d_col, s), "axis stencil kernel");
+            check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
+        m->nnz = nnz;
+    });
+}
+
+// From a caller's device CSR over caller indices (rows in any order, -1 and
+// self entries dropped, repeats kept): rows moved to Morton positions and
+// sorted, as ftle_create_mesh_from_csr does on the host.
+ftle_mesh_t build_mesh_device_csr(int dim, int64_t n, const void* coords, ftle_dtype dtype, const int64_t* row_ptr,
+                                  const int32_t* col, int64_t nnz_in, unsigned flags, int tile_log2, hipStream_t s)
+{
+    const size_t need = Arena::round((size_t)n * 4) * 2 + Arena::round(scan_partial_bytes(n + 1)) + Arena::round(32);
+    return build_device(dim, n, coords, dtype, flags, tile_log2, need, false, s,
+                        [&](ftle_mesh_s* m, const uint32_t* perm, Arena& arena) {
+        int32_t* inv = arena.take<int32_t>((size_t)n * 4);
+        uint32_t* cnt = arena.take<uint32_t>((size_t)n * 4);
+        int64_t* partial = arena.take<int64_t>(scan_partial_bytes(n + 1));
+        unsigned long long* err = arena.take<unsigned long long>(32);   // [0]: lowest bad row, [1]: lowest bad entry
+        check_hip(hipMemsetAsync(err, 0xff, 16, s), "hipMemsetAsync");
+        check_hip(mb_invert(perm, n, inv, s), "inverse permutation kernel");
+        check_hip(mb_csr_in_count(row_ptr, col, n, nnz_in, perm, cnt, err, s), "stencil count kernel");
+        unsigned long long he[2] = {0, 0};
+        to_host(he, err, 16, s);
+        if (he[0] != ~0ull) {
+            if (he[0] == 0) fail(FTLE_ERR_BAD_MESH, "row_ptr[0] must be 0");
+            fail(FTLE_ERR_BAD_MESH, "row_ptr decreases at row " + std::to_string(he[0] - 1));
+        }
+        if (he[1] != ~0ull) fail(FTLE_ERR_BAD_MESH, "col[" + std::to_string(he[1]) + "] out of range");
+        m->d_row_ptr = static_cast<int64_t*>(dev_upload(nullptr, ((size_t)n + 1) * 8));
+        check_hip(scan_exclusive_to_i64(cnt, n, m->d_row_ptr, partial, s), "scan");
+        int64_t nnz = 0;
+        to_host(&nnz, m->d_row_ptr + n, 8, s);
+        if (nnz > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "stencil has more than 2^31-1 entries");
+        m->d_col = static_cast<int32_t*>(dev_upload(nullptr, (size_t)nnz * 4));
+        check_hip(mb_csr_in_fill(row_ptr, col, n, perm, inv, m->d_row_ptr, m->d_col, s), "stencil fill kernel");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+        m->nnz = nnz;
+    });
 }
 
 }  // namespace
@@ -1486,6 +1545,34 @@ ftle_status ftle_create_mesh_from_csr(int dim, int64_t n_points, const void* coo
                               });
                               return c;
                           });
+    });
+}
+
+ftle_status ftle_create_mesh_device_from_csr(int dim, int64_t n_points, const void* coords, ftle_dtype dtype,
+                                             const int64_t* row_ptr, const int32_t* col, unsigned flags,
+                                             ftle_stream_t stream, ftle_mesh_t* out)
+{
+    return guarded([&] {
+        if (!out) fail(FTLE_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (dtype != FTLE_F32 && dtype != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        if (n_points < 1) fail(FTLE_ERR_INVALID_ARG, "n_points must be >= 1");
+        if (n_points > INT32_MAX) fail(FTLE_ERR_UNSUPPORTED, "n_points > 2^31-1");
+        if (!coords) fail(FTLE_ERR_INVALID_ARG, "coords is NULL");
+        if (!row_ptr) fail(FTLE_ERR_INVALID_ARG, "row_ptr is NULL");
+        if (flags & FTLE_HOST_ONLY) fail(FTLE_ERR_UNSUPPORTED, "a device-built mesh lives on the device");
+        if (flags & ~(unsigned)(FTLE_NO_REORDER | FTLE_HOST_ONLY | FTLE_TILE(0xff)))
+            fail(FTLE_ERR_INVALID_ARG, "unknown flag bits");
+        const int tile_log2 = (int)((flags >> 8) & 0xff);
+        if (tile_log2 != 0 && (tile_log2 < 5 || tile_log2 > 11))
+            fail(FTLE_ERR_INVALID_ARG, "FTLE_TILE(k) needs 5 <= k <= 11");
+        const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        int64_t nnz_in = 0;
+        to_host(&nnz_in, row_ptr + n_points, 8, s);
+        if (nnz_in < 0) fail(FTLE_ERR_BAD_MESH, "row_ptr[n_points] < 0");
+        if (nnz_in > 0 && !col) fail(FTLE_ERR_INVALID_ARG, "col is NULL");
+        *out = build_mesh_device_csr(dim, n_points, coords, dtype, row_ptr, col, nnz_in, flags, tile_log2, s);
     });
 }
 

@@ -266,6 +266,16 @@ hipError_t mb_transpose_fill(const int64_t* row_ptr, const int32_t* col, int64_t
                              uint32_t* cur, int32_t* tcol, hipStream_t s);
 hipError_t mb_csr_compare(const int64_t* rp_a, const int32_t* col_a, const int64_t* rp_b, const int32_t* col_b,
                           int64_t n, int64_t nnz, int* differ, hipStream_t s);
+//   mb_csr_in_count / mb_csr_in_fill: a caller's CSR over caller indices
+//     (nnz_in = row_ptr[n] entries) moved to Morton positions: per Morton row
+//     the count of entries that are neither -1 nor the point itself (err[0]
+//     and err[1], set to ~0 before, lower to a faulty row + 1, 0 for
+//     row_ptr[0] != 0, and to a faulty entry), then the rows, renumbered by
+//     inv and sorted ascending
+hipError_t mb_csr_in_count(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz_in, const uint32_t* perm,
+                           uint32_t* cnt, unsigned long long* err, hipStream_t s);
+hipError_t mb_csr_in_fill(const int64_t* row_ptr, const int32_t* col, int64_t n, const uint32_t* perm,
+                          const int32_t* inv, const int64_t* out_rp, int32_t* out, hipStream_t s);
 // Exclusive scan of m uint32 values into int64 out[0..m), out[m] = their sum;
 // partial: scan_partial_bytes(m) of device scratch.
 hipError_t scan_exclusive_to_i64(const uint32_t* in, int64_t m, int64_t* out, int64_t* partial, hipStream_t stream);

@@ -776,6 +776,63 @@ __global__ void __launch_bounds__(256) csr_compare(const int64_t* __restrict__ r
     if ((i <= n && rp_a[i] != rp_b[i]) || (i < nnz && col_a[i] != col_b[i])) *differ = 1;
 }
 
+// ---------------------------------------------------------------------------
+// A caller's CSR over caller indices moved to Morton positions: per Morton
+// row r (caller row perm[r]) the entries that are neither -1 nor the point
+// itself, renumbered and sorted ascending (repeats kept).  The count pass also
+// checks the input: err[0] lowers to 0 for row_ptr[0] != 0 and to i + 1 for a
+// row i whose end precedes its start; err[1] lowers to the position of an
+// entry outside [-1, n).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) csr_in_count(const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col, int64_t n, int64_t nnz_in,
+                                                    const uint32_t* __restrict__ perm, uint32_t* __restrict__ cnt,
+                                                    unsigned long long* __restrict__ err)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    if (r == 0 && row_ptr[0] != 0) atomicMin(&err[0], 0ull);
+    const int64_t i = perm[r];
+    const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
+    uint32_t c = 0;
+    if (p1 < p0) {
+        atomicMin(&err[0], (unsigned long long)(i + 1));
+    } else if (p0 >= 0 && p1 <= nnz_in) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const int32_t v = col[p];
+            if (v < -1 || v >= n)
+                atomicMin(&err[1], (unsigned long long)p);
+            else if (v >= 0 && v != (int32_t)i)
+                ++c;
+        }
+    }
+    cnt[r] = c;
+}
+
+__global__ void __launch_bounds__(256) csr_in_fill(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, int64_t n,
+                                                   const uint32_t* __restrict__ perm, const int32_t* __restrict__ inv,
+                                                   const int64_t* __restrict__ out_rp, int32_t* __restrict__ out)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const int64_t i = perm[r];
+    int32_t* row = out + out_rp[r];
+    int64_t len = 0;
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        const int32_t v = col[p];
+        if (v < 0 || v == (int32_t)i) continue;
+        const int32_t u = inv[v];
+        int64_t k = len;
+        while (k > 0 && row[k - 1] > u) {
+            row[k] = row[k - 1];
+            --k;
+        }
+        row[k] = u;
+        ++len;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -964,6 +1021,20 @@ hipError_t mb_csr_compare(const int64_t* rp_a, const int32_t* col_a, const int64
 {
     const int64_t m = std::max<int64_t>(n + 1, nnz);
     hipLaunchKernelGGL(csr_compare, dim3(blocks_of(m, 256)), dim3(256), 0, s, rp_a, col_a, rp_b, col_b, n, nnz, differ);
+    return hipGetLastError();
+}
+
+hipError_t mb_csr_in_count(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz_in, const uint32_t* perm,
+                           uint32_t* cnt, unsigned long long* err, hipStream_t s)
+{
+    hipLaunchKernelGGL(csr_in_count, dim3(blocks_of(n, 256)), dim3(256), 0, s, row_ptr, col, n, nnz_in, perm, cnt, err);
+    return hipGetLastError();
+}
+
+hipError_t mb_csr_in_fill(const int64_t* row_ptr, const int32_t* col, int64_t n, const uint32_t* perm,
+                          const int32_t* inv, const int64_t* out_rp, int32_t* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(csr_in_fill, dim3(blocks_of(n, 256)), dim3(256), 0, s, row_ptr, col, n, perm, inv, out_rp, out);
     return hipGetLastError();
 }
 

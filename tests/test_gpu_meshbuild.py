@@ -268,3 +268,96 @@ def test_axis_stencil_irregular():
         x = g.random((n, dim))
         cells = Delaunay(x).simplices.astype(np.int32)
         assert_same_mesh(x, cells, "f32", stencil="axis")
+
+
+def assert_same_csr_mesh(x, row_ptr, col, dtype="f32", tile_log2=0, reorder=True, T=2.0):
+    """ftle_create_mesh_device_from_csr against ftle_create_mesh_from_csr on the
+    same list: permutation, stencil, both tile sets byte for byte, forward and
+    adjoint bit for bit."""
+    n, dim = x.shape
+    print(f"[device csr mesh dim={dim} n={n} nnz={len(col)} {dtype} tile={tile_log2}]", flush=True)
+    host = F.Mesh.from_csr(x, row_ptr, col, dtype, tile_log2=tile_log2, reorder=reorder)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    dev = F.Mesh.from_csr_on_device(torch.as_tensor(np.ascontiguousarray(x, dtype=npdt), device=DEV),
+                                    torch.as_tensor(np.asarray(row_ptr, np.int64), device=DEV),
+                                    torch.as_tensor(np.asarray(col, np.int32), device=DEV),
+                                    tile_log2=tile_log2, reorder=reorder)
+    assert dev.info() == host.info()
+    for name, a, b in zip(("row_ptr", "col", "perm"), dev.csr(), host.csr()):
+        assert a.shape == b.shape and np.array_equal(a, b), name
+    for adjoint in (0, 1):
+        dm, dr = _raw_tiles(dev, adjoint)
+        hm, hr = _raw_tiles(host, adjoint)
+        assert np.array_equal(dm, hm) and np.array_equal(dr, hr), f"tiles differ (adjoint={adjoint})"
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    phi = torch.as_tensor(_flow(x, 5), dtype=tdt, device=DEV)
+    g = torch.as_tensor(np.random.default_rng(9).normal(size=n), dtype=tdt, device=DEV)
+    assert same_bits(dev.forward(phi, T), host.forward(phi, T))
+    assert same_bits(dev.backward(phi, T, g), host.backward(phi, T, g))
+    return host, dev
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_from_csr_knn_with_repeats_self_and_absent(dim):
+    """A non-symmetric k-nearest-neighbour list in shuffled caller order, with
+    -1 entries, self entries and repeated entries planted."""
+    from scipy.spatial import cKDTree
+    x, _ = meshes.jittered_tri_grid(60, 41, seed=3) if dim == 2 else meshes.kuhn_tet_grid(11)
+    k = 6 if dim == 2 else 10
+    _, nb = cKDTree(x).query(x, k + 1)
+    nb = np.ascontiguousarray(nb[:, 1:], dtype=np.int32)
+    g = np.random.default_rng(dim)
+    nb = g.permuted(nb, axis=1)
+    rows = g.choice(x.shape[0], 200, replace=False)
+    nb[rows[:80], 0] = -1
+    nb[rows[80:140], 1] = rows[80:140]          # self
+    nb[rows[140:], 2] = nb[rows[140:], 3]        # a repeat
+    row_ptr = np.arange(x.shape[0] + 1, dtype=np.int64) * k
+    assert_same_csr_mesh(x, row_ptr, nb.ravel(), "f32")
+    assert_same_csr_mesh(x, row_ptr, nb.ravel(), "f64", tile_log2=6)
+
+
+def test_from_csr_paper_list_and_ring1_output():
+    """The paper's fixed-width list straight from ftle_axis_ell, and the one-ring
+    CSR straight from ftle_ring1_csr, each into a device-built mesh."""
+    x, cells = meshes.jittered_tri_grid(90, 70, seed=5)
+    n = x.shape[0]
+    xd = torch.as_tensor(x.astype(np.float32), device=DEV)
+    rp, col = F.ring1_csr(2, n, torch.as_tensor(cells, dtype=torch.int32, device=DEV))
+    ell = F.axis_ell(xd, rp, col)
+    ell_rp = torch.arange(n + 1, dtype=torch.int64, device=DEV) * 4
+    assert_same_csr_mesh(x, ell_rp.cpu().numpy(), ell.cpu().numpy().ravel(), "f32")
+    dev = F.Mesh.from_csr_on_device(xd, ell_rp, ell.reshape(-1).contiguous())
+    host = F.Mesh(x, cells, "f32", stencil="axis")
+    phi = torch.as_tensor(_flow(x, 2), dtype=torch.float32, device=DEV)
+    # the same neighbours as the axis mesh (its rows in slot order, these ascending): equal to rounding
+    a, b = dev.forward(phi, 3.0).cpu().numpy(), host.forward(phi, 3.0).cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b)) and np.nanmax(np.abs(a - b)) <= 1e-5
+    assert_same_csr_mesh(x, rp.cpu().numpy(), col.cpu().numpy(), "f32")
+
+
+def test_from_csr_errors():
+    x, _ = meshes.jittered_tri_grid(10, 8, seed=1)
+    n = x.shape[0]
+    xd = torch.as_tensor(x.astype(np.float32), device=DEV)
+    rp = np.arange(n + 1, dtype=np.int64) * 3
+    col = np.tile(np.array([1, 2, 3], np.int32), n)
+
+    def mk(r, c):
+        return F.Mesh.from_csr_on_device(xd, torch.as_tensor(r, device=DEV), torch.as_tensor(c, device=DEV))
+
+    bad = rp.copy()
+    bad[0] = 1
+    with pytest.raises(F.FTLEError) as e:
+        mk(bad, col)
+    assert e.value.status == 2 and "row_ptr[0]" in str(e.value)
+    bad = rp.copy()
+    bad[20], bad[30] = bad[22], bad[33]          # rows 20 and 30 decrease; the lowest is reported
+    with pytest.raises(F.FTLEError) as e:
+        mk(bad, col)
+    assert e.value.status == 2 and "decreases at row 20" in str(e.value)
+    c = col.copy()
+    c[[50, 71]] = [n, -2]
+    with pytest.raises(F.FTLEError) as e:
+        mk(rp, c)
+    assert e.value.status == 2 and "col[50]" in str(e.value)

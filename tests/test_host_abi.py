@@ -539,3 +539,23 @@ def test_create_mesh_device_validation(L):
     assert mk(flags=1 << 20) == INVALID
     assert mk(flags=_lib.tile_flag(4)) == INVALID
     assert not h.value
+
+
+def test_create_mesh_device_from_csr_validation(L):
+    """Argument checks of ftle_create_mesh_device_from_csr before any device work."""
+    INVALID, UNSUP = 1, 4
+    fake = ctypes.c_void_p(256)
+    h = ctypes.c_void_p()
+
+    def mk(dim=2, n=10, coords=fake, dtype=0, rp=fake, col=fake, flags=0, out=True):
+        return L.ftle_create_mesh_device_from_csr(dim, n, coords, dtype, rp, col, flags, None,
+                                                  ctypes.byref(h) if out else None)
+
+    assert mk(out=False) == INVALID
+    assert mk(dim=1) == INVALID and mk(dtype=2) == INVALID and mk(n=0) == INVALID
+    assert mk(n=1 << 31) == UNSUP
+    assert mk(coords=None) == INVALID and mk(rp=None) == INVALID
+    assert mk(flags=_lib.HOST_ONLY) == UNSUP
+    assert mk(flags=_lib.STENCIL_AXIS) == INVALID and mk(flags=_lib.tile_flag(12)) == INVALID
+    assert not h.value
+
