@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "ftle_device_math.h"
 #include "ftle_internal.h"
 
 namespace ftle {
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(256) check_relabel(const int32_t* __restrict__
                                                      const int32_t* __restrict__ inv, int32_t* __restrict__ mc,
                                                      int* __restrict__ flag, unsigned long long* __restrict__ first)
 {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
     if (c >= n_cells) return;
     int32_t v[K];
 #pragma unroll
@@ -328,7 +329,8 @@ __global__ void __launch_bounds__(kTileThreads) tile_extent(const int64_t* __res
     __shared__ int count;
     __shared__ unsigned long long words;
     const int t = (int)threadIdx.x;
-    const int64_t b = ranges[2 * blockIdx.x], e = ranges[2 * blockIdx.x + 1];
+    const int tb = xcd_tile((int)blockIdx.x, (int)gridDim.x);   // XCD-contiguous ranges
+    const int64_t b = ranges[2 * tb], e = ranges[2 * tb + 1];
     for (int i = t; i < kHashSlots; i += kTileThreads) keys[i] = -1;
     if (t == 0) {
         count = 0;
@@ -342,8 +344,8 @@ __global__ void __launch_bounds__(kTileThreads) tile_extent(const int64_t* __res
     if (e - b <= kMaxStaged) H = gather_halo(row_ptr, col, b, e, keys, hlist, &count, t);
     __syncthreads();
     if (t == 0) {
-        halo_words[2 * blockIdx.x] = (uint32_t)H;
-        halo_words[2 * blockIdx.x + 1] = (uint32_t)(words > 0xffffffffull ? 0xffffffffull : words);
+        halo_words[2 * tb] = (uint32_t)H;
+        halo_words[2 * tb + 1] = (uint32_t)(words > 0xffffffffull ? 0xffffffffull : words);
     }
 }
 
@@ -425,7 +427,8 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     __shared__ uint8_t start[kMaxStaged];
     __shared__ uint32_t gmask[kMaxStaged / 32];    // the record's 32-slot group masks
     const int t = (int)threadIdx.x;
-    const int64_t b = ranges[2 * blockIdx.x], e = ranges[2 * blockIdx.x + 1];
+    const int tb = xcd_tile((int)blockIdx.x, (int)gridDim.x);   // XCD-contiguous tiles
+    const int64_t b = ranges[2 * tb], e = ranges[2 * tb + 1];
     const int P = (int)(e - b);
     for (int i = t; i < kHashSlots; i += kTileThreads) keys[i] = -1;
     if (t == 0) count = 0;
@@ -444,7 +447,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     const int H = gather_halo(row_ptr, col, b, e, keys, hlist, &count, t);
     if (P + H > kMaxStaged) {
         if (!WRITE && t == 0)
-            for (int q = 0; q < 4; ++q) counts[4 * blockIdx.x + q] = ~0u;
+            for (int q = 0; q < 4; ++q) counts[4 * tb + q] = ~0u;
         return;
     }
     for (int h = t; h < H; h += kTileThreads) srt[h] = ((uint64_t)perm[hlist[h]] << 32) | (uint32_t)hlist[h];
@@ -458,7 +461,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     }
     __syncthreads();
     const int S = P + H;
-    const TileMeta m = WRITE ? meta[blockIdx.x] : TileMeta{};
+    const TileMeta m = WRITE ? meta[tb] : TileMeta{};
     const RecLayout R = WRITE ? rec_layout(m) : RecLayout{};
     unsigned char* out = WRITE ? rec + (size_t)16 * m.rec_off : nullptr;
     // runs of consecutive caller indices
@@ -511,7 +514,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
     }
     __syncthreads();
     const uint32_t nwf = rowoff[P] / 3;
-    uint16_t* rows = rowbuf + row_base[blockIdx.x];
+    uint16_t* rows = rowbuf + row_base[tb];
     if (!WRITE) {
         // each row: its neighbours' slots, insertion-sorted, then the padding
         for (int l = t; l < P; l += kTileThreads) {
@@ -607,10 +610,10 @@ __global__ void __launch_bounds__(kTileThreads) tile_record(const int64_t* __res
             }
         }
     } else if (t == 0) {
-        counts[4 * blockIdx.x] = nw;
-        counts[4 * blockIdx.x + 1] = nr;
-        counts[4 * blockIdx.x + 2] = nx;
-        counts[4 * blockIdx.x + 3] = nwf;
+        counts[4 * tb] = nw;
+        counts[4 * tb + 1] = nr;
+        counts[4 * tb + 2] = nx;
+        counts[4 * tb + 3] = nwf;
     }
 }
 
@@ -623,7 +626,7 @@ __global__ void __launch_bounds__(256) normal_inverse(const int64_t* __restrict_
                                                       int64_t n, double tau, T* __restrict__ out)
 {
 #pragma clang fp contract(off)
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
     if (r >= n) return;
     const int64_t i = perm[r];
     const double xi0 = (double)x[i * 3], xi1 = (double)x[i * 3 + 1], xi2 = (double)x[i * 3 + 2];
@@ -662,7 +665,7 @@ __global__ void __launch_bounds__(256) axis_slots(const T* __restrict__ x, const
                                                   int64_t n, int32_t* __restrict__ slots, uint32_t* __restrict__ cnt)
 {
 #pragma clang fp contract(off)
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
     if (r >= n) return;
     const int64_t i = perm[r];
     double xi[D];
@@ -789,7 +792,7 @@ __global__ void __launch_bounds__(256) csr_in_count(const int64_t* __restrict__ 
                                                     const uint32_t* __restrict__ perm, uint32_t* __restrict__ cnt,
                                                     unsigned long long* __restrict__ err)
 {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
     if (r >= n) return;
     if (r == 0 && row_ptr[0] != 0) atomicMin(&err[0], 0ull);
     const int64_t i = perm[r];
@@ -814,7 +817,7 @@ __global__ void __launch_bounds__(256) csr_in_fill(const int64_t* __restrict__ r
                                                    const uint32_t* __restrict__ perm, const int32_t* __restrict__ inv,
                                                    const int64_t* __restrict__ out_rp, int32_t* __restrict__ out)
 {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
     if (r >= n) return;
     const int64_t i = perm[r];
     int32_t* row = out + out_rp[r];

@@ -27,6 +27,7 @@
 
 #include <cstdint>
 
+#include "ftle_device_math.h"
 #include "ftle_internal.h"
 
 namespace ftle {
@@ -83,7 +84,8 @@ __global__ void __launch_bounds__(kAggThreads) incidence_pass(const int32_t* __r
         num[i] = 0;
     }
     __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * (kAggThreads * kAggCells);
+    // each XCD takes a contiguous stretch of cells (its L2 then holds their points' counters)
+    const int64_t c0 = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * (kAggThreads * kAggCells);
     int slot[kAggCells][K];
     uint32_t local[kAggCells][K];
 #pragma unroll
@@ -237,7 +239,7 @@ __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restri
 {
     __shared__ int32_t lst[kRowCap * kRowThreads];
     const int t = (int)threadIdx.x;
-    const int64_t r = (int64_t)blockIdx.x * kRowThreads + t;
+    const int64_t r = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * kRowThreads + t;   // XCD-contiguous rows
     if (r >= n) return;
     int32_t* my = lst + t;   // entry k at my[k * kRowThreads]
     int cnt = 0;
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(256) copy_rows(const int32_t* __restrict__ sto
 {
     __shared__ int32_t seg[kCopySeg];
     const int t = (int)threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * 256, r = r0 + t;
+    const int64_t r0 = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256, r = r0 + t;
     const int64_t r1 = min(r0 + 256, n);
     const int64_t base = row_ptr[r0], total = row_ptr[r1] - base;
     const bool live = r < n;
