@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) axis_ell_kernel(const T* __restrict__ x, 
                                                          int32_t* __restrict__ ell)
 {
 #pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;   // XCD-contiguous
     if (i >= n) return;
     double xi[D];
 #pragma unroll

@@ -361,3 +361,18 @@ def test_from_csr_errors():
     with pytest.raises(F.FTLEError) as e:
         mk(rp, c)
     assert e.value.status == 2 and "col[50]" in str(e.value)
+
+
+def test_edge_cases_axis_and_lists():
+    # the axis stencil of a mesh without cells, of one point, and of a tiny 3D mesh
+    x, cells = meshes.jittered_tri_grid(9, 7, seed=3)
+    assert_same_mesh(x, np.zeros((0, 3), np.int32), stencil="axis", check_oracle=False)
+    assert_same_mesh(np.array([[0.25, 0.5]]), np.zeros((0, 3), np.int32), stencil="axis", check_oracle=False)
+    x3, c3 = meshes.kuhn_tet_grid(3)
+    assert_same_mesh(x3, c3, stencil="axis")
+    # lists with no entries, and lists of -1 and self entries only
+    n = x.shape[0]
+    assert_same_csr_mesh(x, np.zeros(n + 1, np.int64), np.zeros(0, np.int32))
+    rp = np.arange(n + 1, dtype=np.int64) * 2
+    col = np.stack([np.full(n, -1), np.arange(n)], 1).astype(np.int32).ravel()
+    assert_same_csr_mesh(x, rp, col)
