@@ -348,8 +348,10 @@ class ClockSampler:
         return out
 
 
-def sustained(fns, torch, alg_bytes, clock, steps=200, warmup=50):
-    """ms per launch over `steps` launches after `warmup`, with the clock samples."""
+def sustained(fns, torch, alg_bytes, clock, steps=1000, warmup=100):
+    """ms per launch over `steps` launches after `warmup` (a few tens of ms of
+    back-to-back work, against the fraction of a millisecond a default burst
+    takes), with the clock samples."""
     with clock:
         ms = time_steps(fns, steps, warmup, torch)
     gbps = alg_bytes / (ms * 1e-3) / 1e9
