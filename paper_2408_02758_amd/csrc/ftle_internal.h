@@ -1,5 +1,5 @@
 // Internal declarations shared by the host side (ftle_host.cpp) and the HIP
-// kernels (ftle_kernels.hip) of the FTLE library.  Not part of the C ABI.
+// kernels (ftle_*.hip) of the FTLE library.  Not part of the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

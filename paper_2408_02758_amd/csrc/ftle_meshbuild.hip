@@ -1,7 +1,9 @@
-// The whole mesh build on the GPU (ftle_create_mesh_device): the Morton
-// order of the points, the one-ring stencil over Morton positions, the tile
-// cut and the compressed tile records, and (3D) the inverse normal matrices,
-// from device coordinates and cells.  The host-side builder in ftle_host.cpp
+// The whole mesh build on the GPU (ftle_create_mesh_device and
+// ftle_create_mesh_device_from_csr): the Morton order of the points, the
+// stencil over Morton positions (the one-ring stencil from the cells, the
+// axis stencil from it, or a caller's list moved to Morton positions), its
+// transpose when it is not symmetric, the tile cut and the compressed tile
+// records, and (3D) the inverse normal matrices.  The host-side builder in ftle_host.cpp
 // does the same on the CPU, following Section 2.2 (neighbours determined
 // once, before the FTLE kernels); the Conclusions name moving that step to
 // the accelerator as future work.  Every kernel here reproduces the host's
@@ -27,6 +29,13 @@
 //                   sorted local slots, shift rows; a first pass sizes the
 //                   records, a second writes them
 //   normal_inverse  the 3D normal matrix inverse per point (float64)
+//   axis_slots / axis_fill
+//                   the axis stencil from the one-ring rows, then its CSR
+//   csr_in_count / csr_in_fill
+//                   a caller's list checked, moved to Morton positions, sorted
+//   transpose_count / transpose_fill / sort_rows / csr_compare
+//                   the transpose for the adjoint's tiles, and the test
+//                   whether it equals the stencil
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
