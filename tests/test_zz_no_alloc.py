@@ -37,3 +37,29 @@ def test_backward_noalloc_matches_backward(dtype):
     m2, fl2, g2, T2 = _case(configs.tri2d(61, 47, seed=3, t0=0.0, T=9.0, dtype=dtype, device=DEV), 3)
     got2 = m2.backward_noalloc(fl2, T2, g2, torch.empty_like(fl2))
     assert torch.equal(got2, m2.backward(fl2, T2, g2))
+
+
+def test_backward_noalloc_replayed_from_a_captured_graph():
+    """The callers it is for: captured once into a HIP graph (no allocation
+    happens inside), replayed three times with eager work and synchronisation
+    between the replays, each replay equal to ftle_backward bit for bit."""
+    m, fl, g, T = _case(configs.abc3d(14, 8.0, "f32", DEV), 4)
+    out = torch.empty_like(fl)
+    ref = m.backward(fl, T, g)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        m.backward_noalloc(fl, T, g, out, stream=side)   # first use on this device, outside the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        m.backward_noalloc(fl, T, g, out, stream=side)
+    torch.cuda.synchronize()
+    for k in range(3):
+        out.fill_(float("nan"))
+        scratch_user = m.backward_noalloc(fl * 1.01, T, g, torch.empty_like(fl))   # the shared scratch rewritten
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {k}"
+        assert not torch.equal(scratch_user, ref)
