@@ -1,7 +1,6 @@
 """The oracle's pins have teeth: plant plausible mistakes in copies of the
 oracle source (on the CPU), rebuild, and require at least one pin to fail for
 every planted mistake.  The real oracle is never modified."""
-import os
 
 import pytest
 
