@@ -1307,7 +1307,24 @@ def main():
         if "f16" in keep:
             # against the oracle on the original float32 flow map: the accuracy
             # the binary16 storage gives up (its parity on the decoded map is tested)
-            err["f16flow_2d_2048_vs_float32_flow"] = error_vs_oracle(stencils, w2, keep["f16"])
+            import oracle
+            e16 = error_vs_oracle(stencils, w2, keep["f16"])
+            # and against the stated bound of that storage (oracle.ftle_perturbation_bound of
+            # the binary16 rounding, oracle.flow_error_f16), on a sample
+            sel = np.sort(rng.choice(w2.n, 200000, replace=False))
+            x32, p32 = w2.coords.astype(np.float32), w2.flow_numpy().astype(np.float32)
+            ref = oracle.ftle(2, x32.astype(np.float64), p32.astype(np.float64), stencils.get(w2), w2.T, sel=sel)
+            bd = oracle.ftle_perturbation_bound(2, x32, p32, stencils.get(w2), w2.T, oracle.flow_error_f16(x32, p32),
+                                                sel=sel)
+            fin = np.isfinite(ref) & np.isfinite(bd)
+            diff = np.abs(np.asarray(keep["f16"], np.float64)[sel] - ref)
+            tol = 2e-5 / (2 * abs(w2.T))
+            e16["stated_bound"] = {
+                "points": int(sel.size), "finite_fraction": round(float(fin.mean()), 4),
+                "within_where_finite": bool(np.all(diff[fin] <= bd[fin] + tol)),
+                "median_bound": float(np.median(bd[fin])) if fin.any() else None,
+                "max_diff_over_bound": float((diff[fin] / (bd[fin] + tol)).max()) if fin.any() else None}
+            err["f16flow_2d_2048_vs_float32_flow"] = e16
         for name in ("ring1_csr_2d_2048", "ring1_csr_3d_160"):
             if name in keep:
                 err[name] = stencil_vs_oracle(stencils, *keep[name])

@@ -9,7 +9,11 @@ code with the GPU library and does not import it.
 
 It also holds the two steps around the path that the library offers on the
 GPU: RK4 flow maps of analytic flows, and the binary16 storage of a flow map
-(numpy).  What pins each function is in the test modules
+(numpy), with the error bound that storage carries: the storage's rounding
+per point (flow_error_f16) and the FTLE change any flow-map error within given
+per-point limits can cause (ftle_perturbation_bound, from the least squares'
+linearity in phi and Weyl's inequality).  What pins each function is in the
+test modules
 ``tests/test_oracle_pins.py``, ``tests/test_oracle_advect.py`` and
 ``tests/test_oracle_f16.py``.
 """
@@ -236,3 +240,68 @@ def decode_flow_f16(coords, delta):
     """The flow map the stored displacements stand for: x + d in float32 (one
     rounding), d widened exactly from binary16."""
     return np.asarray(coords, dtype=np.float32) + np.asarray(delta, dtype=np.float16).astype(np.float32)
+
+
+def flow_error_f16(coords, flow):
+    """Per point, a bound on max_k |phi'_k - phi_k| for the binary16 storage
+    above, phi' = decode_flow_f16(coords, encode_flow_f16(coords, flow)), with
+    coords and flow the float32 values stored: the float32 difference
+    (<= 2^-24 |phi - x|), its rounding to binary16 (<= 2^-11 of its magnitude
+    in the normal range, <= 2^-25 in the subnormal range) and the float32 sum
+    x + d (<= 2^-24 |x + d|).  inf where the displacement overflows binary16."""
+    x = np.asarray(coords, dtype=np.float32).astype(np.float64)
+    p = np.asarray(flow, dtype=np.float32).astype(np.float64)
+    a = np.abs(p - x)
+    e1 = 2.0 ** -24 * a
+    e2 = np.maximum(2.0 ** -11 * (a + e1), 2.0 ** -25)
+    e3 = 2.0 ** -24 * (np.abs(p) + e1 + e2)
+    e = e1 + e2 + e3
+    e[a + e1 > 65504.0] = np.inf
+    return e.max(axis=1)
+
+
+def ftle_perturbation_bound(dim: int, coords, flow, st: Stencil, T: float, delta, sel=None):
+    """For each point i, a bound on |FTLE_i(phi') - FTLE_i(phi)| over every
+    flow map phi' with max_k |phi'_jk - phi_jk| <= delta_j at each point j
+    (numpy, float64).  In the least squares of ftle(), J = B M^-1 and phi'
+    changes B by sum_j (e_j - e_i)(x_j - x_i)^T, hence J by sum_j (e_j - e_i)
+    w_j^T with w_j = M^-1 (x_j - x_i); its Frobenius norm is at most
+    eps_i = sum_j sqrt(D) (delta_j + delta_i) |w_j|.  The largest singular value
+    of J moves by at most eps_i (Weyl's inequality), so FTLE = ln(sigma_max)/|T|
+    moves by at most -ln(1 - eps_i / sigma_max) / |T| while eps_i < sigma_max,
+    and without bound beyond.  NaN where ftle() gives NaN for the stencil
+    (det M <= 1e-12 (tr M / D)^D).  sel: optional point indices (the result
+    then holds only those points)."""
+    x = _f64(coords).reshape(-1, dim)
+    p = _f64(flow).reshape(-1, dim)
+    delta = np.asarray(delta, dtype=np.float64)
+    pts = np.arange(x.shape[0]) if sel is None else np.asarray(sel, dtype=np.int64)
+    n = pts.shape[0]
+    lens = st.row_ptr[pts + 1] - st.row_ptr[pts]
+    rows = np.repeat(np.arange(n), lens)                      # local row of each entry
+    starts = np.repeat(st.row_ptr[pts] - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    cols = st.col[np.arange(rows.shape[0]) + starts].astype(np.int64)
+    keep = cols >= 0
+    rows, cols = rows[keep], cols[keep]
+    owner = pts[rows]                                         # global index of each entry's point
+    dx = x[cols] - x[owner]
+    dp = p[cols] - p[owner]
+    M = np.empty((n, dim, dim))
+    B = np.empty((n, dim, dim))
+    for a in range(dim):
+        for b in range(dim):
+            M[:, a, b] = np.bincount(rows, weights=dx[:, a] * dx[:, b], minlength=n)
+            B[:, a, b] = np.bincount(rows, weights=dp[:, a] * dx[:, b], minlength=n)
+    tr = np.trace(M, axis1=1, axis2=2) / dim
+    ok = np.linalg.det(M) > 1e-12 * tr ** dim
+    Msafe = np.where(ok[:, None, None], M, np.eye(dim))
+    Minv = np.linalg.inv(Msafe)
+    sigma = np.linalg.svd(B @ Minv, compute_uv=False)[:, 0]
+    w = np.einsum("nab,nb->na", Minv[rows], dx)
+    eps = np.sqrt(dim) * np.bincount(rows, weights=(delta[cols] + delta[owner]) * np.linalg.norm(w, axis=1),
+                                     minlength=n)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out = np.where(eps < sigma, -np.log1p(-eps / sigma) / abs(T), np.inf)
+    out[eps == 0] = 0.0
+    out[~ok] = np.nan
+    return out

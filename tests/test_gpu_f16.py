@@ -50,6 +50,30 @@ def test_f16_flow_2048_sampled():
     check_f32("f16 flow 2048^2 sampled", got[sel], ref, gap, w.T)
 
 
+def test_f16_flow_2048_within_stated_bound():
+    """Against the FTLE of the float32 flow map itself: at sampled points of the
+    2048^2 map the binary16 storage's FTLE stays within the stated bound (the
+    oracle's ftle_perturbation_bound for the storage error flow_error_f16)
+    plus the float32 path's own tolerance, wherever that bound is finite."""
+    w = configs.scale_2d(DEV)
+    m = F.Mesh(w.coords, w.cells, "f32")
+    flow = w.flow.to(DEV).float().contiguous()
+    got = m.forward_f16(m.encode_flow_f16(flow), w.T).cpu().numpy().astype(np.float64)
+    x32 = np.asarray(w.coords, dtype=np.float32)
+    p32 = w.flow_numpy().astype(np.float32)
+    st = oracle.ring1(2, w.n, w.cells)
+    sel = _sample(w.n, 20000, 13)
+    ref = oracle.ftle(2, x32.astype(np.float64), p32.astype(np.float64), st, w.T, sel=sel)
+    bd = oracle.ftle_perturbation_bound(2, x32, p32, st, w.T, oracle.flow_error_f16(x32, p32), sel=sel)
+    fin = np.isfinite(ref) & np.isfinite(bd)
+    tol = 2e-5 / (2 * abs(w.T))
+    diff = np.abs(got[sel] - ref)
+    print(f"[f16 2048^2] bound finite at {fin.mean():.4f} of the sample, median {np.median(bd[fin]):.3e}, "
+          f"max |diff| {diff[fin].max():.3e}, max diff/bound {(diff[fin] / (bd[fin] + tol)).max():.3f}", flush=True)
+    assert np.all(diff[fin] <= bd[fin] + tol)
+    assert fin.mean() > 0.5
+
+
 def test_f16_flow_rejects_3d_and_f64():
     w3 = configs.abc_3d(DEV, n=6)
     m3 = F.Mesh(w3.coords, w3.cells, "f32")
