@@ -244,7 +244,8 @@ def decode_flow_f16(coords, delta):
 
 def flow_error_f16(coords, flow):
     """Per point, a bound on max_k |phi'_k - phi_k| for the binary16 storage
-    above, phi' = decode_flow_f16(coords, encode_flow_f16(coords, flow)), with
+    above (the precision-for-bandwidth trade of Section 1.1),
+    phi' = decode_flow_f16(coords, encode_flow_f16(coords, flow)), with
     coords and flow the float32 values stored: the float32 difference
     (<= 2^-24 |phi - x|), its rounding to binary16 (<= 2^-11 of its magnitude
     in the normal range, <= 2^-25 in the subnormal range) and the float32 sum
