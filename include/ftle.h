@@ -192,7 +192,7 @@ ftle_status ftle_create_mesh_device_from_csr(int dim, int64_t n_points, const vo
  *   nnz          host, receives the entry count (also when it exceeds
  *                col_capacity)
  * ftle_ring1_csr allocates its workspace (ftle_ring1_csr_workspace bytes,
- * about 4 bytes per cell corner and 16 per point) for the duration of the
+ * about 4 bytes per cell corner and 144 per point) for the duration of the
  * call; ftle_ring1_csr_ws takes it from the caller (device memory of at
  * least that size, overwritten).  Both return after the stream has finished
  * the work.

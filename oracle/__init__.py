@@ -71,6 +71,9 @@ class _Lib:
                                          vp, vp]
         lib.oracle_advect_rk4.restype = None
         lib.oracle_advect_rk4.argtypes = [ctypes.c_int, vp, i64, vp, vp, vp, ctypes.c_double, vp]
+        lib.oracle_advect_rk4_grid.restype = None
+        lib.oracle_advect_rk4_grid.argtypes = [ctypes.c_int, vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp,
+                                               i64, vp, vp, vp, ctypes.c_double, vp]
         lib.oracle_jacobi_eig3.restype = None
         lib.oracle_jacobi_eig3.argtypes = [vp, vp, vp]
         lib.oracle_set_threads.restype = None
@@ -222,6 +225,28 @@ def advect_rk4(flow: str, x0, t0, T, dt: float, params=None, lib=None):
     Ta = _f64(np.broadcast_to(np.asarray(T, dtype=np.float64), (n,)))
     out = np.empty_like(x)
     lib.oracle_advect_rk4(kind, _p(prm), n, _p(x), _p(t0a), _p(Ta), float(dt), _p(out))
+    return out
+
+
+def advect_rk4_grid(vel, origin, spacing, t_first, t_step, x0, t0, T, dt: float, lib=None):
+    """advect_rk4 in a velocity field sampled on a regular grid: vel of shape
+    (n_times, [nz,] ny, nx, dim) holds the velocity at node origin + index *
+    spacing (x fastest) and time t_first + k * t_step; multilinear in space,
+    linear in time, the nearest point of the grid's box (and the nearest
+    slice) outside it."""
+    lib = _load(lib)
+    v = _f64(vel)
+    dim = v.shape[-1]
+    nt = v.shape[0]
+    shape = np.ascontiguousarray(v.shape[1:-1][::-1], dtype=np.int64)   # nx, ny[, nz]
+    assert shape.size == dim and np.all(shape >= 2)
+    x = _f64(x0).reshape(-1, dim)
+    n = x.shape[0]
+    t0a = _f64(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
+    Ta = _f64(np.broadcast_to(np.asarray(T, dtype=np.float64), (n,)))
+    out = np.empty_like(x)
+    lib.oracle_advect_rk4_grid(dim, _p(shape), _p(_f64(origin)), _p(_f64(spacing)), nt, float(t_first),
+                               float(t_step), _p(v), n, _p(x), _p(t0a), _p(Ta), float(dt), _p(out))
     return out
 
 

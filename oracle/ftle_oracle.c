@@ -499,3 +499,83 @@ void oracle_advect_rk4(int kind, const double* prm, int64_t n, const double* x0,
         for (int d = 0; d < D; ++d) phi[i * D + d] = p[d];
     }
 }
+
+/*
+ * A velocity field sampled on a regular grid (the form simulation data
+ * comes in): nodes origin[d] + i spacing[d], i = 0 .. shape[d] - 1, along
+ * each axis, at times t_first + k t_step, k = 0 .. nt - 1; vel holds the dim
+ * components of node (x, y[, z]) at slice k at
+ * ((k * nz + z) * ny + y) * nx + x (x fastest).  Between nodes the velocity
+ * is multilinear in space (bilinear, trilinear) and linear in time; a point
+ * outside the grid's box takes the value at the nearest point of the box, a
+ * time before the first slice or after the last that slice's value.
+ */
+static void grid_velocity(int D, const int64_t* shape, const double* origin, const double* spacing, int64_t nt,
+                          double t_first, double t_step, const double* vel, const double* p, double t, double* v)
+{
+    int64_t cell[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < D; ++d) {
+        double u = (p[d] - origin[d]) / spacing[d];
+        const double top = (double)(shape[d] - 1);
+        if (!(u > 0.0)) u = 0.0;   /* also NaN */
+        if (u > top) u = top;
+        int64_t c = (int64_t)floor(u);
+        if (c > shape[d] - 2) c = shape[d] - 2;
+        cell[d] = c;
+        f[d] = u - (double)c;
+    }
+    int64_t k = 0;
+    double g = 0.0;
+    if (nt > 1) {
+        double s = (t - t_first) / t_step;
+        if (!(s > 0.0)) s = 0.0;
+        if (s > (double)(nt - 1)) s = (double)(nt - 1);
+        k = (int64_t)floor(s);
+        if (k > nt - 2) k = nt - 2;
+        g = s - (double)k;
+    }
+    const int64_t nx = shape[0], ny = shape[1], nz = D == 3 ? shape[2] : 1;
+    for (int c = 0; c < D; ++c) v[c] = 0.0;
+    for (int slice = 0; slice < (nt > 1 ? 2 : 1); ++slice) {
+        const double ws = nt > 1 ? (slice ? g : 1.0 - g) : 1.0;
+        for (int corner = 0; corner < (1 << D); ++corner) {
+            double w = ws;
+            int64_t at[3] = {0, 0, 0};
+            for (int d = 0; d < D; ++d) {
+                const int bit = (corner >> d) & 1;
+                w *= bit ? f[d] : 1.0 - f[d];
+                at[d] = cell[d] + bit;
+            }
+            const int64_t node = (((k + slice) * nz + at[2]) * ny + at[1]) * nx + at[0];
+            for (int c = 0; c < D; ++c) v[c] += w * vel[node * D + c];
+        }
+    }
+}
+
+/* oracle_advect_rk4 in a gridded velocity field (grid_velocity above). */
+void oracle_advect_rk4_grid(int D, const int64_t* shape, const double* origin, const double* spacing, int64_t nt,
+                            double t_first, double t_step, const double* vel, int64_t n, const double* x0,
+                            const double* t0, const double* T, double dt, double* phi)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double p[3], q[3], k1[3], k2[3], k3[3], k4[3];
+        for (int d = 0; d < D; ++d) p[d] = x0[i * D + d];
+        double steps = ceil(fabs(T[i]) / dt - 1e-9);
+        if (steps < 1.0) steps = 1.0;
+        const double h = T[i] / steps;
+        for (int64_t s = 0; s < (int64_t)steps; ++s) {
+            const double t = t0[i] + (double)s * h;
+            grid_velocity(D, shape, origin, spacing, nt, t_first, t_step, vel, p, t, k1);
+            for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k1[d];
+            grid_velocity(D, shape, origin, spacing, nt, t_first, t_step, vel, q, t + 0.5 * h, k2);
+            for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k2[d];
+            grid_velocity(D, shape, origin, spacing, nt, t_first, t_step, vel, q, t + 0.5 * h, k3);
+            for (int d = 0; d < D; ++d) q[d] = p[d] + h * k3[d];
+            grid_velocity(D, shape, origin, spacing, nt, t_first, t_step, vel, q, t + h, k4);
+            for (int d = 0; d < D; ++d) p[d] += h / 6.0 * (k1[d] + 2.0 * k2[d] + 2.0 * k3[d] + k4[d]);
+        }
+        for (int d = 0; d < D; ++d) phi[i * D + d] = p[d];
+    }
+}
