@@ -50,6 +50,9 @@ SIGNATURES = {
     "ftle_forward_f16": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp]),
     "ftle_advect_rk4": (_int, [_int, _vp, _i64, _vp, _int, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, _vp, _vp]),
+    "ftle_advect_rk4_grid": (_int, [_int, _vp, _vp, _vp, _i64, ctypes.c_double, ctypes.c_double, _vp, _int, _i64,
+                                    _vp, _int, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
+                                    _vp]),
     "ftle_destroy_mesh": (None, [_vp]),
     "ftle_mesh_info": (_int, [_vp, _P(_int), _P(_i64), _P(_i64), _P(_int)]),
     "ftle_mesh_get_csr": (_int, [_vp, _vp, _vp, _vp]),

@@ -492,6 +492,47 @@ def advect_rk4(flow: str, x0: torch.Tensor, t0, T, dt: float, params=None, out: 
     return out
 
 
+def advect_rk4_grid(velocity: torch.Tensor, origin, spacing, t_first: float, t_step: float, x0: torch.Tensor, t0, T,
+                    dt: float, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Flow map x(t0 + T) of particles at x0 by RK4 on the GPU in a velocity
+    field sampled on a regular grid (ftle_advect_rk4_grid): velocity is a
+    contiguous float32/float64 device tensor (n_times, [nz,] ny, nx, dim) of
+    the velocity at node origin + index * spacing (x fastest) and time
+    t_first + k * t_step; multilinear in space, linear in time, the nearest box
+    point and slice outside.  x0 (N, dim), t0 and T as in advect_rk4."""
+    if not (isinstance(velocity, torch.Tensor) and velocity.is_cuda and velocity.is_contiguous()
+            and velocity.dtype in (torch.float32, torch.float64) and velocity.dim() in (4, 5)):
+        raise ValueError("velocity must be a contiguous float32/float64 device tensor (n_times, [nz,] ny, nx, dim)")
+    dim = velocity.shape[-1]
+    if velocity.dim() != dim + 2:
+        raise ValueError("velocity's last axis must hold dim components for a dim-dimensional grid")
+    if not (x0.is_cuda and x0.is_contiguous() and x0.dim() == 2 and x0.shape[1] == dim
+            and x0.dtype in (torch.float32, torch.float64)):
+        raise ValueError(f"x0 must be a contiguous float32/float64 device tensor of shape (N, {dim})")
+    n = x0.shape[0]
+
+    def per_point(v, name):
+        if isinstance(v, torch.Tensor):
+            if not (v.is_cuda and v.dtype == torch.float64 and v.is_contiguous() and v.shape == (n,)):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of {n} values")
+            return ctypes.c_void_p(v.data_ptr()), 0.0
+        return None, float(v)
+
+    t0p, t0s = per_point(t0, "t0")
+    Tp, Ts = per_point(T, "T")
+    if out is None:
+        out = torch.empty_like(x0)
+    shape = (ctypes.c_int64 * dim)(*[int(v) for v in velocity.shape[1:-1][::-1]])
+    org = (ctypes.c_double * dim)(*[float(v) for v in origin])
+    spc = (ctypes.c_double * dim)(*[float(v) for v in spacing])
+    check(_lib.load().ftle_advect_rk4_grid(
+        dim, shape, org, spc, velocity.shape[0], float(t_first), float(t_step), ctypes.c_void_p(velocity.data_ptr()),
+        1 if velocity.dtype == torch.float64 else 0, n, ctypes.c_void_p(x0.data_ptr()),
+        1 if x0.dtype == torch.float64 else 0, t0p, Tp, t0s, Ts, float(dt), ctypes.c_void_p(out.data_ptr()),
+        _stream_handle(stream)))
+    return out
+
+
 def ring1_workspace_bytes(dim: int, n_points: int, n_cells: int) -> int:
     """Device workspace bytes of ring1_csr(..., workspace=...) (ftle_ring1_csr_workspace)."""
     b = ctypes.c_int64()

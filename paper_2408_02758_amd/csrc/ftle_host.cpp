@@ -2187,6 +2187,53 @@ ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const voi
     });
 }
 
+ftle_status ftle_advect_rk4_grid(int dim, const int64_t* shape, const double* origin, const double* spacing,
+                                 int64_t n_times, double t_first, double t_step, const void* velocity,
+                                 ftle_dtype velocity_dtype, int64_t n, const void* x0, ftle_dtype dtype,
+                                 const double* t0s, const double* Ts, double t0, double T, double dt, void* phi,
+                                 ftle_stream_t stream)
+{
+    return guarded([&] {
+        if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
+        if (!shape || !origin || !spacing) fail(FTLE_ERR_INVALID_ARG, "shape, origin or spacing is NULL");
+        if (n_times < 1) fail(FTLE_ERR_INVALID_ARG, "n_times must be >= 1");
+        if (!velocity) fail(FTLE_ERR_INVALID_ARG, "velocity is NULL");
+        for (ftle_dtype d : {velocity_dtype, dtype})
+            if (d != FTLE_F32 && d != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
+        GridField g{};
+        double values = (double)n_times * dim;
+        for (int d = 0; d < dim; ++d) {
+            if (shape[d] < 2) fail(FTLE_ERR_INVALID_ARG, "every axis needs >= 2 grid nodes");
+            if (!std::isfinite(origin[d])) fail(FTLE_ERR_INVALID_ARG, "origin must be finite");
+            if (!(spacing[d] > 0.0) || !std::isfinite(spacing[d]))
+                fail(FTLE_ERR_INVALID_ARG, "spacing must be positive and finite");
+            g.shape[d] = shape[d];
+            g.origin[d] = origin[d];
+            g.spacing[d] = spacing[d];
+            values *= (double)shape[d];
+        }
+        if (values > 9.0e15) fail(FTLE_ERR_INVALID_ARG, "grid too large");
+        if (!std::isfinite(t_first)) fail(FTLE_ERR_INVALID_ARG, "t_first must be finite");
+        if (n_times > 1 && (!(t_step > 0.0) || !std::isfinite(t_step)))
+            fail(FTLE_ERR_INVALID_ARG, "t_step must be positive and finite");
+        g.nt = n_times;
+        g.t_first = t_first;
+        g.t_step = n_times > 1 ? t_step : 1.0;
+        if (n < 0) fail(FTLE_ERR_INVALID_ARG, "n < 0");
+        if (n > 0 && (!x0 || !phi)) fail(FTLE_ERR_INVALID_ARG, "x0 or phi is NULL");
+        if (!(dt > 0.0) || !std::isfinite(dt)) fail(FTLE_ERR_INVALID_ARG, "dt must be positive and finite");
+        if (!std::isfinite(t0) || !std::isfinite(T)) fail(FTLE_ERR_INVALID_ARG, "t0 and T must be finite");
+        if (!Ts && !(std::ceil(std::fabs(T) / dt - 1e-9) <= (double)kMaxAdvectSteps))
+            fail(FTLE_ERR_INVALID_ARG, "|T| / dt exceeds the step limit (10^7 steps per particle)");
+        if (n == 0) return;
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
+        check_hip(launch_advect_grid(dim, g, velocity, velocity_dtype == FTLE_F64, dtype == FTLE_F64, n, x0, t0s, Ts,
+                                     t0, T, dt, phi, static_cast<hipStream_t>(stream)),
+                  "advect launch");
+    });
+}
+
 namespace {
 
 void check_ring1_args(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, const int64_t* row_ptr,

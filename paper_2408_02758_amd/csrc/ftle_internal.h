@@ -177,6 +177,18 @@ inline bool supported_block(int b) { return b == 128 || b == 256 || b == 512; }
 // per-point t0s / Ts when not null, else t0 / T for every particle.  At most
 // kMaxAdvectSteps steps per particle.
 constexpr int64_t kMaxAdvectSteps = 10000000;
+// A velocity field sampled on a regular grid: shape[d] nodes at origin[d] +
+// i spacing[d] per axis (x fastest), nt slices at t_first + k t_step.
+struct GridField {
+    int64_t shape[3];
+    double origin[3];
+    double spacing[3];
+    int64_t nt;
+    double t_first, t_step;
+};
+hipError_t launch_advect_grid(int dim, const GridField& g, const void* vel, bool vel_f64, bool f64, int64_t n,
+                              const void* x0, const double* t0s, const double* Ts, double t0, double T, double dt,
+                              void* phi, hipStream_t stream);
 hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, const void* x0, const double* t0s,
                          const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream);
 

@@ -105,3 +105,94 @@ def test_advect_full_2048_sampled():
     err = np.abs(phi[sel].astype(np.float64) - ref)
     print(f"[advect 2048^2 sampled] max |d| = {err.max():.3e}", flush=True)
     assert np.all(err <= 1e-9 + 2.0 ** -23 * np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# ftle_advect_rk4_grid: a velocity field sampled on a regular grid
+# ---------------------------------------------------------------------------
+def _gyre_grid(nx, ny, times):
+    """The double gyre (A = 0.1, eps = 0.25, omega = 2 pi / 10) at the nodes of
+    an nx x ny grid over [0, 2] x [0, 1]: (n_times, ny, nx, 2), float64."""
+    A, eps, om = 0.1, 0.25, 2.0 * np.pi / 10.0
+    xs, ys = np.linspace(0.0, 2.0, nx), np.linspace(0.0, 1.0, ny)
+    yy, xx = np.meshgrid(ys, xs, indexing="ij")
+    out = []
+    for t in times:
+        s = np.sin(om * t)
+        a, b = eps * s, 1 - 2 * eps * s
+        f = a * xx ** 2 + b * xx
+        out.append(np.stack([-np.pi * A * np.sin(np.pi * f) * np.cos(np.pi * yy),
+                             np.pi * A * np.cos(np.pi * f) * np.sin(np.pi * yy) * (2 * a * xx + b)], -1))
+    return np.stack(out)
+
+
+def _abc_grid(n):
+    a, b, c = np.sqrt(3.0), np.sqrt(2.0), 1.0
+    ax = np.linspace(0.0, 2 * np.pi, n)
+    zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+    v = np.stack([a * np.sin(zz) + c * np.cos(yy), b * np.sin(xx) + a * np.cos(zz), c * np.sin(yy) + b * np.cos(xx)],
+                 -1)
+    return v[None], 2 * np.pi / (n - 1)
+
+
+@pytest.mark.parametrize("vel_dtype", [np.float32, np.float64])
+def test_advect_grid_vs_oracle(vel_dtype):
+    """Both sides step the same RK4 through the same stored field in float64:
+    they differ by rounding only (the summation order of the corner weights),
+    amplified by the flow's stretching: 1e-9 over T = 15 as for the analytic flows."""
+    times = np.arange(0.0, 20.0 + 1e-9, 0.5)
+    vel = _gyre_grid(201, 101, times).astype(vel_dtype)
+    x, _ = meshes.jittered_tri_grid(64, 48, seed=5)
+    g = np.random.default_rng(2)
+    t0s = g.uniform(0.0, 5.0, x.shape[0])
+    Ts = g.uniform(-4.0, 15.0, x.shape[0])
+    Ts[:7] = 0.0
+    ref = oracle.advect_rk4_grid(vel.astype(np.float64), [0.0, 0.0], [0.01, 0.01], 0.0, 0.5, x, t0s, Ts, 0.02)
+    vd = torch.as_tensor(vel, device=DEV)
+    x64 = torch.as_tensor(x, dtype=torch.float64, device=DEV)
+    got = F.advect_rk4_grid(vd, [0.0, 0.0], [0.01, 0.01], 0.0, 0.5, x64, torch.as_tensor(t0s, device=DEV),
+                            torch.as_tensor(Ts, device=DEV), 0.02).cpu().numpy()
+    err = np.abs(got - ref).max()
+    print(f"[advect grid gyre vel={np.dtype(vel_dtype).name}] max |d| = {err:.3e}", flush=True)
+    assert err < 1e-9
+    assert np.array_equal(got[:7], x[:7])
+    # float32 particles: the same up to the output's rounding
+    got32 = F.advect_rk4_grid(vd, [0.0, 0.0], [0.01, 0.01], 0.0, 0.5, x64.float().contiguous(), 1.5, 9.0,
+                              0.02).cpu().numpy().astype(np.float64)
+    ref32 = oracle.advect_rk4_grid(vel.astype(np.float64), [0.0, 0.0], [0.01, 0.01], 0.0, 0.5,
+                                   x.astype(np.float32).astype(np.float64), 1.5, 9.0, 0.02)
+    assert np.all(np.abs(got32 - ref32) <= 1e-9 + 2 ** -23 * np.abs(ref32))
+
+
+def test_advect_grid_3d_clamping_and_steady():
+    """A sampled ABC field (one slice: steady) in 3D, with particles starting
+    outside the grid's box (the nearest box point's velocity), against the oracle."""
+    vel, h = _abc_grid(33)
+    g = np.random.default_rng(4)
+    x = np.concatenate([g.uniform(0.0, 2 * np.pi, size=(3000, 3)), g.uniform(-2.0, 9.0, size=(500, 3))])
+    ref = oracle.advect_rk4_grid(vel, [0.0] * 3, [h] * 3, 0.0, 1.0, x, 0.0, 5.0, 0.05)
+    got = F.advect_rk4_grid(torch.as_tensor(vel, device=DEV), [0.0] * 3, [h] * 3, 0.0, 1.0,
+                            torch.as_tensor(x, device=DEV), 0.0, 5.0, 0.05).cpu().numpy()
+    err = np.abs(got - ref).max()
+    print(f"[advect grid abc] max |d| = {err:.3e}", flush=True)
+    assert err < 1e-9
+    assert F.advect_rk4_grid(torch.as_tensor(vel, device=DEV), [0.0] * 3, [h] * 3, 0.0, 1.0,
+                             torch.empty(0, 3, dtype=torch.float64, device=DEV), 0.0, 5.0, 0.05).numel() == 0
+
+
+def test_advect_grid_full_2048_sampled():
+    """The headline's 2048^2 particles through a double gyre sampled on a
+    513 x 257 grid at 61 slices (float32 field, T = 15, dt = 0.01, float32
+    output), against the oracle on 20,000 sampled particles."""
+    times = np.arange(0.0, 15.0 + 1e-9, 0.25)
+    vel = _gyre_grid(513, 257, times).astype(np.float32)
+    x, _ = meshes.jittered_tri_grid(2048, 2048, seed=2)
+    x32 = torch.as_tensor(x, dtype=torch.float32, device=DEV)
+    got = F.advect_rk4_grid(torch.as_tensor(vel, device=DEV), [0.0, 0.0], [2.0 / 512, 1.0 / 256], 0.0, 0.25, x32,
+                            0.0, 15.0, 0.01).cpu().numpy().astype(np.float64)
+    sel = np.sort(np.random.default_rng(8).choice(x.shape[0], 20000, replace=False))
+    ref = oracle.advect_rk4_grid(vel.astype(np.float64), [0.0, 0.0], [2.0 / 512, 1.0 / 256], 0.0, 0.25,
+                                 x[sel].astype(np.float32).astype(np.float64), 0.0, 15.0, 0.01)
+    err = np.abs(got[sel] - ref) - 2 ** -23 * np.abs(ref)
+    print(f"[advect grid 2048^2] max |d| beyond output rounding = {err.max():.3e}", flush=True)
+    assert np.all(err <= 1e-9)

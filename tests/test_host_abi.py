@@ -559,3 +559,27 @@ def test_create_mesh_device_from_csr_validation(L):
     assert mk(flags=_lib.STENCIL_AXIS) == INVALID and mk(flags=_lib.tile_flag(12)) == INVALID
     assert not h.value
 
+
+
+def test_advect_grid_validation(L):
+    """ftle_advect_rk4_grid checks every argument before any device work."""
+    INVALID = 1
+    fake = ctypes.c_void_p(256)
+    shape = (ctypes.c_int64 * 3)(4, 5, 6)
+    org = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    spc = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+
+    def adv(dim=2, shp=shape, o=org, sp=spc, nt=3, t_first=0.0, t_step=0.5, vel=fake, vdt=0, n=10, x0=fake, dt_=0,
+            T=1.0, dt=0.1, phi=fake):
+        return L.ftle_advect_rk4_grid(dim, shp, o, sp, nt, t_first, t_step, vel, vdt, n, x0, dt_, None, None, 0.0, T,
+                                      dt, phi, None)
+
+    assert adv(dim=4) == INVALID and adv(shp=None) == INVALID and adv(nt=0) == INVALID
+    assert adv(vel=None) == INVALID and adv(vdt=5) == INVALID and adv(dt_=5) == INVALID
+    assert adv(shp=(ctypes.c_int64 * 3)(1, 5, 6)) == INVALID
+    assert adv(sp=(ctypes.c_double * 3)(1.0, 0.0, 1.0)) == INVALID
+    assert adv(o=(ctypes.c_double * 3)(float("nan"), 0.0, 0.0)) == INVALID
+    assert adv(t_step=0.0) == INVALID and adv(t_first=float("inf")) == INVALID
+    assert adv(n=-1) == INVALID and adv(x0=None) == INVALID and adv(phi=None) == INVALID
+    assert adv(dt=0.0) == INVALID and adv(T=float("nan")) == INVALID and adv(T=1e9, dt=1e-3) == INVALID
+    assert adv(n=0) == 0 and adv(n=0, nt=1, t_step=0.0) == 0
