@@ -95,7 +95,23 @@ KERNEL_TRACE = os.path.join(ROOT, "profiles", "ftle_kernel_trace_stats.txt")
 COUNTERS = os.path.join(ROOT, "profiles", "ftle_counters_fetch_write.txt")
 CSRC = os.path.join(ROOT, "paper_2408_02758_amd", "csrc")
 ADVECT_PROFILE = os.path.join(ROOT, "profiles", "ftle_advect_rk4.txt")
-ADVECT_SRC = os.path.join(CSRC, "ftle_advect.hip")
+# the RK4 kernels: profile key -> (kernel name, source file, particles, steps per particle)
+ADVECT_KERNELS = {"dg": ("advect_kernel<0, float>", "ftle_advect.hip", 2048 * 2048, 1500),
+                  "abc": ("advect_kernel<1, float>", "ftle_advect.hip", 160 ** 3, 500),
+                  "grid_dg": ("advect_grid_kernel<2, float, float>", "ftle_advect_grid.hip", 2048 * 2048, 1500)}
+ADVECT_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP64_TRANS",
+                   "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")
+# the commands that made profiles/ftle_advect_rk4.txt (from the repository root)
+ADVECT_RECIPE = [
+    "python -u bench.py --fill-cache --cache /tmp/ftle_wc --only advect",
+    "timeout -k 10 300 rocprofv3 --kernel-trace --stats -d gpurun_out/kt_advect -o kt --output-format csv -- "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --no-cpu-baseline --no-sustained --no-headline "
+    "--only advect",
+    "timeout -s KILL 300 rocprofv3 --pmc " + " ".join(ADVECT_COUNTERS) + " -d gpurun_out/pmc_advect -o pmc "
+    "--output-format csv -- python -u bench.py --require-cache --cache /tmp/ftle_wc --no-cpu-baseline "
+    "--no-sustained --no-headline --only advect",
+    "python bench.py --summarize-advect gpurun_out/kt_advect gpurun_out/pmc_advect",
+]
 
 
 def log(msg):
@@ -415,27 +431,32 @@ def traced_durations(path=KERNEL_TRACE):
     return out
 
 
-def advect_counts(flow="double_gyre"):
-    """Float64 FLOPs and VALU instructions per launch of the measured flow map
-    ("double_gyre": the 2048^2 grid; "abc": the 160^3 grid), from the committed
-    rocprofv3 summary, or {} when that summary was taken from another version
-    of the kernel source."""
-    if not os.path.exists(ADVECT_PROFILE):
-        return {}
-    meta = {}
-    with open(ADVECT_PROFILE) as f:
-        for ln in f:
-            ln = ln.strip()
-            if ln and not ln.startswith("#") and "=" in ln:
-                k, v = ln.split("=", 1)
-                meta[k.strip()] = v.strip()
-    with open(ADVECT_SRC, "rb") as f:
-        if meta.get("advect_source_sha256") != hashlib.sha256(f.read()).hexdigest():
+def advect_counts(key="dg"):
+    """Float64 FLOPs and VALU instructions per launch of a measured flow map
+    ("dg": the 2048^2 double gyre; "abc": the 160^3 ABC flow; "grid_dg": the
+    2048^2 double gyre sampled on a grid), from the committed rocprofv3
+    summary, or {} when that summary was taken from another version of the
+    kernel's source."""
+    meta = _profile_meta(ADVECT_PROFILE)
+    src = ADVECT_KERNELS[key][1]
+    with open(os.path.join(CSRC, src), "rb") as f:
+        if meta.get(f"sha256 {src}") != hashlib.sha256(f.read()).hexdigest():
             return {}
-    key = "dg" if flow == "double_gyre" else "abc"
     if f"{key}_fp64_flops_per_launch" not in meta:
         return {}
     return {"flops": float(meta[f"{key}_fp64_flops_per_launch"]), "valu": float(meta[f"{key}_valu_insts_per_launch"])}
+
+
+def _profile_meta(path):
+    meta = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for ln in f:
+                ln = ln.strip()
+                if ln and not ln.startswith("#") and "=" in ln:
+                    k, v = ln.split("=", 1)
+                    meta[k.strip()] = v.strip()
+    return meta
 
 
 def alu_roofline(counts, ms):
@@ -587,6 +608,51 @@ def summarize_counters(fetch_dir, write_dir, run, probe_mib=256):
         lines.append(f"run: {run} | kernel: {name} | dispatches: {len(fetch[name])} | fetch_kib: {fe:.1f} | "
                      f"write_kib: {wr:.1f} | fetch_factor: {ff:.4f} | write_factor: {wf:.4f} | "
                      f"hbm_mb: {(fe * ff + wr * wf) * 1024 / 1e6:.1f}")
+    return lines
+
+
+def summarize_advect(trace_dir, pmc_dir):
+    """The RK4 flow-map profile: per kernel of ADVECT_KERNELS its kernel-trace
+    durations and the median of each SQ counter over its dispatches, with the
+    float64 FLOPs (64 per wave-level count of SQ_INSTS_VALU_FLOPS_FP64) and VALU
+    instructions per launch that the ALU rooflines use."""
+    durs = {}
+    for r in _csv_rows(trace_dir, "kernel_trace.csv"):
+        name = short_kernel_name(_field(r, "Kernel_Name", "Kernel-Name"))
+        durs.setdefault(name, []).append((int(_field(r, "End_Timestamp")) - int(_field(r, "Start_Timestamp"))) / 1e6)
+    counts = {}
+    for r in _csv_rows(pmc_dir, "counter_collection.csv"):
+        name = short_kernel_name(_field(r, "Kernel_Name"))
+        per = counts.setdefault(name, {}).setdefault(_field(r, "Counter_Name"), {})
+        disp = int(_field(r, "Dispatch_Id"))
+        per[disp] = per.get(disp, 0.0) + float(_field(r, "Counter_Value"))
+    lines = ["# rocprofv3 profile of the RK4 flow-map kernels on one MI355X (gfx950): the 2048^2 double gyre "
+             "(dg: 4194304 particles, 1500 steps), the 160^3 ABC flow (abc: 4096000 particles, 500 steps) and the "
+             "2048^2 double gyre sampled on a 513 x 257 grid at 61 slices (grid_dg: float32 field, 1500 steps); "
+             "float64 arithmetic, float32 in and out",
+             "# commands, from the repository root:"] + [f"#   {c}" for c in ADVECT_RECIPE]
+    for src in sorted({v[1] for v in ADVECT_KERNELS.values()}):
+        with open(os.path.join(CSRC, src), "rb") as f:
+            lines.append(f"sha256 {src} = {hashlib.sha256(f.read()).hexdigest()}")
+    lines.append("# kernel                                    calls    avg_ms    min_ms    max_ms")
+    for key, (kname, _, _, _) in ADVECT_KERNELS.items():
+        ts = durs.get(kname, [])
+        if ts:
+            lines.append(f"#   {kname:<40} {len(ts):5d} {statistics.mean(ts):9.3f} {min(ts):9.3f} {max(ts):9.3f}")
+    for key, (kname, _, n, steps) in ADVECT_KERNELS.items():
+        c = counts.get(kname)
+        if not c or any(k not in c for k in ADVECT_COUNTERS):
+            continue
+        med = {k: statistics.median(c[k].values()) for k in ADVECT_COUNTERS}
+        lines.append(f"# {kname}: {len(c['SQ_WAVES'])} dispatches; median counters per dispatch (per wave "
+                     "instruction, summed over waves; SQ_INSTS_VALU_FLOPS_FP64 = ADD + MUL + 2 FMA + TRANS, so "
+                     "FLOPs = 64 x it):")
+        lines += [f"#   {k:<32} {med[k]:.6g}" for k in ADVECT_COUNTERS]
+        flops, valu = 64.0 * med["SQ_INSTS_VALU_FLOPS_FP64"], med["SQ_INSTS_VALU"]
+        lines += [f"{key}_fp64_flops_per_launch = {flops:.6g}",
+                  f"{key}_fp64_flops_per_particle_step = {flops / (n * steps):.2f}",
+                  f"{key}_valu_insts_per_launch = {valu:.6g}",
+                  f"{key}_valu_per_particle_step = {64.0 * valu / (n * steps):.2f}"]
     return lines
 
 
@@ -793,6 +859,13 @@ def oracle_advect(x0, t0, T, flow="double_gyre", dt=0.01):
     return oracle.advect_rk4(flow, x0, t0, T, dt)
 
 
+def oracle_advect_grid(vel, spacing, t_step, x0, t0, T, dt):
+    """The FP64 oracle's RK4 flow map of the given particles in a sampled field
+    whose nodes start at the origin and whose slices start at time 0."""
+    import oracle
+    return oracle.advect_rk4_grid(vel, [0.0] * len(spacing), list(spacing), 0.0, t_step, x0, t0, T, dt)
+
+
 def copy_probe_gbps(torch, dev, mib=1024, reps=10):
     """Bandwidth of a plain elementwise kernel (torch.neg: mib MiB read + mib MiB written)."""
     src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
@@ -851,6 +924,8 @@ def main():
                     help="print the kernel-trace summary lines of rocprofv3 CSV output in DIR and exit")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "RUN"),
                     help="print the FETCH_SIZE / WRITE_SIZE summary lines of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-advect", nargs=2, metavar=("TRACE_DIR", "PMC_DIR"),
+                    help="print the RK4 flow-map profile from a kernel-trace and an SQ-counter run and exit")
     ap.add_argument("--profile-header", choices=("trace", "counters"),
                     help="print the header of a profile summary (commands, source hash) and exit")
     args = ap.parse_args()
@@ -867,6 +942,9 @@ def main():
         return
     if args.profile_header:
         print(profile_header(args.profile_header))
+        return
+    if args.summarize_advect:
+        print("\n".join(summarize_advect(*args.summarize_advect)))
         return
 
     only = [g for g in args.only.split(",") if g]
@@ -899,6 +977,7 @@ def main():
         return
 
     import paper_2408_02758_amd as F
+    from workloads import flows
 
     torch.cuda.set_device(0)
     want = lambda k: k in groups  # noqa: E731
@@ -1262,6 +1341,35 @@ def main():
         log(f"advect_3d_160: {t:.2f} ms per flow map")
         keep["advect_abc"] = (w3a, x0.cpu().numpy(), phi.cpu().numpy())
         del x0, phi
+        # the same 2048^2 particles and steps through the double gyre sampled
+        # on a grid, as simulation output comes: 513 x 257 nodes over
+        # [0, 2] x [0, 1], 61 slices 0.25 apart (float32, 64 MB), bilinear in
+        # space and linear in time
+        log("advect_grid_2d_2048: RK4 flow map in a sampled field on the GPU")
+        gshape, gspacing, gtimes = (513, 257), (2.0 / 512, 1.0 / 256), np.arange(61) * 0.25
+        vel = torch.as_tensor(flows.sampled_field(flows.double_gyre_velocity, (0.0, 0.0), gspacing, gshape, gtimes)
+                              .astype(np.float32), device=dev)
+        x0 = torch.as_tensor(w2.coords, dtype=torch.float32, device=dev).contiguous()
+        phi = torch.empty_like(x0)
+
+        def grid_map():
+            F.advect_rk4_grid(vel, (0.0, 0.0), gspacing, 0.0, 0.25, x0, t0, w2.T, 0.01, out=phi)
+        grid_map()
+        t = time_steps([grid_map], 3, 1, torch)
+        nsteps = math.ceil(abs(w2.T) / 0.01 - 1e-9)
+        variants["advect_grid_2d_2048"] = {
+            "workload": "RK4 flow map of the 2048^2 jittered grid in the double gyre sampled on a 513 x 257 grid "
+                        "over [0, 2] x [0, 1] at 61 slices 0.25 apart (float32 field, bilinear in space, linear in "
+                        "time), t0 = 0, T = 15, dt = 0.01 (float64 arithmetic, float32 output)",
+            "points": w2.n, "steps_per_point": nsteps, "ms_per_step": round(t, 4),
+            "points_per_s": round(w2.n / (t * 1e-3), 1),
+            "particle_steps_per_s": round(w2.n * nsteps / (t * 1e-3), 1),
+            "field_bytes": int(vel.numel() * vel.element_size()),
+            "roofline": alu_roofline(advect_counts("grid_dg"), t)}
+        log(f"advect_grid_2d_2048: {t:.2f} ms per flow map")
+        keep["advect_grid"] = (w2, vel.cpu().numpy().astype(np.float64), gspacing, x0.cpu().numpy(), t0,
+                               phi.cpu().numpy())
+        del x0, phi, vel
     if copy_gbps:
         for v in variants.values():
             if v["roofline"]["bound"] == "hbm":
@@ -1340,6 +1448,12 @@ def main():
             ref = oracle_advect(x0[sel].astype(np.float64), 0.0, wa.T, "abc", 0.02)
             err["advect_3d_160_sample"] = {"points": int(sel.size),
                                            "max_abs_err": float(np.abs(phi[sel].astype(np.float64) - ref).max())}
+        if "advect_grid" in keep:
+            wa, vel, gspacing, x0, t0, phi = keep["advect_grid"]
+            sel = np.sort(rng.choice(wa.n, 20000, replace=False))
+            ref = oracle_advect_grid(vel, gspacing, 0.25, x0[sel].astype(np.float64), t0, wa.T, 0.01)
+            err["advect_grid_2d_2048_sample"] = {
+                "points": int(sel.size), "max_abs_err": float(np.abs(phi[sel].astype(np.float64) - ref).max())}
         for key in ("ell_2d_2048_direct", "ell_2d_2048_staged", "ell_3d_160_direct", "ell_3d_160_staged"):
             if key in keep:
                 we, got, lst = keep[key]

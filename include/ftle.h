@@ -250,17 +250,18 @@ ftle_status ftle_advect_rk4(int flow, const double* params, int64_t n, const voi
  * slice or after the last that slice's value.  Same steps, step limit and
  * per-particle windows as ftle_advect_rk4; float64 arithmetic.
  *   dim           2 or 3
- *   shape         host, dim node counts (x first), each >= 2
+ *   shape         host, dim node counts (x first), each in [2, 2^31)
  *   origin        host, dim: coordinates of node 0
  *   spacing       host, dim: node spacing per axis (> 0)
- *   n_times       slices (>= 1; one slice is a steady field), at times
+ *   n_times       slices (in [1, 2^31); one slice is a steady field), at times
  *                 t_first + k t_step (t_step > 0 when n_times > 1)
  *   velocity      device, n_times x [nz x] ny x nx x dim of velocity_dtype
  *                 (x fastest: slice k, node (i, j[, l]) at
  *                 ((k nz + l) ny + j) nx + i), read during the call
  *   x0, dtype, t0s, Ts, t0, T, dt, phi, stream   as ftle_advect_rk4
- * Errors: INVALID_ARG (dim, a null pointer, shape < 2, non-finite origin,
- * spacing <= 0, n_times < 1, t_step <= 0, and as ftle_advect_rk4), DEVICE.
+ * Errors: INVALID_ARG (dim, a null pointer, a shape or n_times out of range,
+ * non-finite origin, spacing <= 0, t_step <= 0, and as ftle_advect_rk4),
+ * DEVICE.
  */
 ftle_status ftle_advect_rk4_grid(int dim, const int64_t* shape, const double* origin, const double* spacing,
                                  int64_t n_times, double t_first, double t_step, const void* velocity,

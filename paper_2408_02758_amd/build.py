@@ -12,6 +12,7 @@ LIB = os.path.join(HERE, "libftle.so")
 SOURCES = [os.path.join(CSRC, "ftle_kernels.hip"), os.path.join(CSRC, "ftle_advect.hip"),
            os.path.join(CSRC, "ftle_neighbours.hip"), os.path.join(CSRC, "ftle_noalloc.hip"),
            os.path.join(CSRC, "ftle_ell.hip"), os.path.join(CSRC, "ftle_meshbuild.hip"),
+           os.path.join(CSRC, "ftle_advect_grid.hip"),
            os.path.join(CSRC, "ftle_host.cpp")]
 ARCH = "gfx950"
 

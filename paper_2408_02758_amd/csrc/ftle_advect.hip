@@ -14,8 +14,7 @@
 // particle whose duration is not finite or needs more than kMaxAdvectSteps
 // steps gets NaN without stepping (the host rejects such a common T).
 // The work is arithmetic (transcendentals) on registers: one 2-3 value load
-// and one store per particle.  A velocity field sampled on a regular grid
-// takes the same steps (advect_grid_kernel).
+// and one store per particle.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -128,131 +127,7 @@ hipError_t advect_launch(const FlowParams& pr, int64_t n, const void* x0, const 
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// A velocity field sampled on a regular grid (the form simulation output
-// comes in): nodes origin + i spacing per axis (x fastest), slices at
-// t_first + k t_step; multilinear in space, linear in time, the nearest point
-// of the grid's box and the nearest slice outside them.  The same steps as the
-// analytic flows; the field is read through the caches (neighbouring
-// particles share cells), in its stored precision, the arithmetic in float64.
-// ---------------------------------------------------------------------------
-template <int D, typename V>
-__device__ inline void grid_velocity(const GridField& g, const V* __restrict__ vel, const double* p, double t,
-                                     double* v)
-{
-    int64_t cell[3] = {0, 0, 0};
-    double f[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        double u = (p[d] - g.origin[d]) / g.spacing[d];
-        const double top = (double)(g.shape[d] - 1);
-        u = (u > 0.0) ? u : 0.0;   // also NaN
-        u = (u > top) ? top : u;
-        int64_t c = (int64_t)floor(u);
-        c = (c > g.shape[d] - 2) ? g.shape[d] - 2 : c;
-        cell[d] = c;
-        f[d] = u - (double)c;
-    }
-    int64_t k = 0;
-    double gw = 0.0;
-    if (g.nt > 1) {
-        double s = (t - g.t_first) / g.t_step;
-        s = (s > 0.0) ? s : 0.0;
-        s = (s > (double)(g.nt - 1)) ? (double)(g.nt - 1) : s;
-        k = (int64_t)floor(s);
-        k = (k > g.nt - 2) ? g.nt - 2 : k;
-        gw = s - (double)k;
-    }
-    const int64_t nx = g.shape[0], ny = g.shape[1], nz = D == 3 ? g.shape[2] : 1;
-#pragma unroll
-    for (int c = 0; c < D; ++c) v[c] = 0.0;
-    const int slices = g.nt > 1 ? 2 : 1;
-    for (int slice = 0; slice < slices; ++slice) {
-        const double ws = g.nt > 1 ? (slice ? gw : 1.0 - gw) : 1.0;
-#pragma unroll
-        for (int corner = 0; corner < (1 << D); ++corner) {
-            double w = ws;
-            int64_t at[3] = {0, 0, 0};
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const int bit = (corner >> d) & 1;
-                w *= bit ? f[d] : 1.0 - f[d];
-                at[d] = cell[d] + bit;
-            }
-            const int64_t node = (((k + slice) * nz + at[2]) * ny + at[1]) * nx + at[0];
-#pragma unroll
-            for (int c = 0; c < D; ++c) v[c] += w * (double)vel[node * D + c];
-        }
-    }
-}
-
-template <int D, typename T, typename V>
-__global__ void __launch_bounds__(256) advect_grid_kernel(GridField g, const V* __restrict__ vel, int64_t n,
-                                                          const T* __restrict__ x0, const double* __restrict__ t0s,
-                                                          const double* __restrict__ Ts, double t0, double Tall,
-                                                          double dt, T* __restrict__ phi)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double p[D], q[D], k1[D], k2[D], k3[D], k4[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) p[d] = (double)x0[i * D + d];
-    const double ti = t0s ? t0s[i] : t0;
-    const double Ti = Ts ? Ts[i] : Tall;
-    const double steps = fmax(1.0, ceil(fabs(Ti) / dt - 1e-9));
-    if (!(steps <= (double)kMaxAdvectSteps)) {   // also NaN and inf
-#pragma unroll
-        for (int d = 0; d < D; ++d) phi[i * D + d] = (T)NAN;
-        return;
-    }
-    const double h = Ti / steps;
-    const int64_t ns = (int64_t)steps;
-    for (int64_t s = 0; s < ns; ++s) {
-        const double t = ti + (double)s * h;
-        grid_velocity<D>(g, vel, p, t, k1);
-#pragma unroll
-        for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k1[d];
-        grid_velocity<D>(g, vel, q, t + 0.5 * h, k2);
-#pragma unroll
-        for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k2[d];
-        grid_velocity<D>(g, vel, q, t + 0.5 * h, k3);
-#pragma unroll
-        for (int d = 0; d < D; ++d) q[d] = p[d] + h * k3[d];
-        grid_velocity<D>(g, vel, q, t + h, k4);
-#pragma unroll
-        for (int d = 0; d < D; ++d) p[d] += h / 6.0 * (k1[d] + 2.0 * k2[d] + 2.0 * k3[d] + k4[d]);
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) phi[i * D + d] = (T)p[d];
-}
-
-template <int D, typename T, typename V>
-hipError_t advect_grid_launch(const GridField& g, const void* vel, int64_t n, const void* x0, const double* t0s,
-                              const double* Ts, double t0, double T_, double dt, void* phi, hipStream_t stream)
-{
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL((advect_grid_kernel<D, T, V>), dim3((unsigned)blocks), dim3(256), 0, stream, g,
-                       static_cast<const V*>(vel), n, static_cast<const T*>(x0), t0s, Ts, t0, T_, dt,
-                       static_cast<T*>(phi));
-    return hipGetLastError();
-}
-
 }  // namespace
-
-hipError_t launch_advect_grid(int dim, const GridField& g, const void* vel, bool vel_f64, bool f64, int64_t n,
-                              const void* x0, const double* t0s, const double* Ts, double t0, double T, double dt,
-                              void* phi, hipStream_t stream)
-{
-    if (n == 0) return hipSuccess;
-#define FTLE_GRID(D, TT, VV) advect_grid_launch<D, TT, VV>(g, vel, n, x0, t0s, Ts, t0, T, dt, phi, stream)
-    if (dim == 2) {
-        if (f64) return vel_f64 ? FTLE_GRID(2, double, double) : FTLE_GRID(2, double, float);
-        return vel_f64 ? FTLE_GRID(2, float, double) : FTLE_GRID(2, float, float);
-    }
-    if (f64) return vel_f64 ? FTLE_GRID(3, double, double) : FTLE_GRID(3, double, float);
-    return vel_f64 ? FTLE_GRID(3, float, double) : FTLE_GRID(3, float, float);
-#undef FTLE_GRID
-}
 
 hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, const void* x0, const double* t0s,
                          const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream)

@@ -2196,14 +2196,15 @@ ftle_status ftle_advect_rk4_grid(int dim, const int64_t* shape, const double* or
     return guarded([&] {
         if (dim != 2 && dim != 3) fail(FTLE_ERR_INVALID_ARG, "dim must be 2 or 3");
         if (!shape || !origin || !spacing) fail(FTLE_ERR_INVALID_ARG, "shape, origin or spacing is NULL");
-        if (n_times < 1) fail(FTLE_ERR_INVALID_ARG, "n_times must be >= 1");
+        if (n_times < 1 || n_times > INT32_MAX) fail(FTLE_ERR_INVALID_ARG, "n_times must be in [1, 2^31)");
         if (!velocity) fail(FTLE_ERR_INVALID_ARG, "velocity is NULL");
         for (ftle_dtype d : {velocity_dtype, dtype})
             if (d != FTLE_F32 && d != FTLE_F64) fail(FTLE_ERR_INVALID_ARG, "unknown dtype");
         GridField g{};
         double values = (double)n_times * dim;
         for (int d = 0; d < dim; ++d) {
-            if (shape[d] < 2) fail(FTLE_ERR_INVALID_ARG, "every axis needs >= 2 grid nodes");
+            if (shape[d] < 2 || shape[d] > INT32_MAX)
+                fail(FTLE_ERR_INVALID_ARG, "every axis needs between 2 and 2^31 - 1 grid nodes");
             if (!std::isfinite(origin[d])) fail(FTLE_ERR_INVALID_ARG, "origin must be finite");
             if (!(spacing[d] > 0.0) || !std::isfinite(spacing[d]))
                 fail(FTLE_ERR_INVALID_ARG, "spacing must be positive and finite");

@@ -82,3 +82,35 @@ def test_profile_summaries_from_rocprof_csv(tmp_path):
     row = dict(p.split(": ", 1) for p in lines[0].split(" | "))
     assert float(row["fetch_factor"]) == 2.0 and float(row["write_factor"]) == 1.0
     assert row["dispatches"] == "2" and float(row["fetch_kib"]) == 50000.0
+
+
+def test_advect_profile_from_rocprof_csv(tmp_path, monkeypatch):
+    """The RK4 flow-map profile: median SQ counters per dispatch become FLOPs
+    and VALU instructions per launch (64 per wave-level count), which
+    advect_counts reads back only while the kernel source hashes match."""
+    kname = bench.ADVECT_KERNELS["grid_dg"][0]
+    kt = tmp_path / "kt" / "h" / "1"
+    kt.mkdir(parents=True)
+    with open(kt / "kt_kernel_trace.csv", "w") as f:
+        f.write('"Kind","Kernel_Name","Start_Timestamp","End_Timestamp"\n')
+        f.write(f'"KERNEL_DISPATCH","void ftle::(anonymous namespace)::{kname}(ftle::GridField)","0","2000000"\n')
+        f.write(f'"KERNEL_DISPATCH","void ftle::(anonymous namespace)::{kname}(ftle::GridField)","0","4000000"\n')
+    pm = tmp_path / "pmc" / "h" / "2"
+    pm.mkdir(parents=True)
+    with open(pm / "pmc_counter_collection.csv", "w") as f:
+        f.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+        for disp, scale in ((1, 1.0), (2, 3.0), (3, 2.0)):
+            for c in bench.ADVECT_COUNTERS:
+                f.write(f'"{disp}","{kname}","{c}","{100.0 * scale}"\n')
+    lines = bench.summarize_advect(str(tmp_path / "kt"), str(tmp_path / "pmc"))
+    text = "\n".join(lines)
+    assert "grid_dg_fp64_flops_per_launch = 12800" in text      # 64 x median 200
+    assert "grid_dg_valu_insts_per_launch = 200" in text
+    assert f"{kname:<40}     2     3.000     2.000     4.000" in text
+    prof = tmp_path / "advect.txt"
+    prof.write_text(text + "\n")
+    monkeypatch.setattr(bench, "ADVECT_PROFILE", str(prof))
+    assert bench.advect_counts("grid_dg") == {"flops": 12800.0, "valu": 200.0}
+    assert bench.advect_counts("dg") == {}          # no counters for that kernel in the summary
+    prof.write_text(text.replace("sha256 ftle_advect_grid.hip = ", "sha256 ftle_advect_grid.hip = 0") + "\n")
+    assert bench.advect_counts("grid_dg") == {}     # taken from another source

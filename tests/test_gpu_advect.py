@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import paper_2408_02758_amd as F
-from workloads import meshes
+from workloads import flows, meshes
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -111,28 +111,15 @@ def test_advect_full_2048_sampled():
 # ftle_advect_rk4_grid: a velocity field sampled on a regular grid
 # ---------------------------------------------------------------------------
 def _gyre_grid(nx, ny, times):
-    """The double gyre (A = 0.1, eps = 0.25, omega = 2 pi / 10) at the nodes of
-    an nx x ny grid over [0, 2] x [0, 1]: (n_times, ny, nx, 2), float64."""
-    A, eps, om = 0.1, 0.25, 2.0 * np.pi / 10.0
-    xs, ys = np.linspace(0.0, 2.0, nx), np.linspace(0.0, 1.0, ny)
-    yy, xx = np.meshgrid(ys, xs, indexing="ij")
-    out = []
-    for t in times:
-        s = np.sin(om * t)
-        a, b = eps * s, 1 - 2 * eps * s
-        f = a * xx ** 2 + b * xx
-        out.append(np.stack([-np.pi * A * np.sin(np.pi * f) * np.cos(np.pi * yy),
-                             np.pi * A * np.cos(np.pi * f) * np.sin(np.pi * yy) * (2 * a * xx + b)], -1))
-    return np.stack(out)
+    """The double gyre at the nodes of an nx x ny grid over [0, 2] x [0, 1]."""
+    return flows.sampled_field(flows.double_gyre_velocity, [0.0, 0.0], [2.0 / (nx - 1), 1.0 / (ny - 1)], (nx, ny),
+                               times)
 
 
 def _abc_grid(n):
-    a, b, c = np.sqrt(3.0), np.sqrt(2.0), 1.0
-    ax = np.linspace(0.0, 2 * np.pi, n)
-    zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
-    v = np.stack([a * np.sin(zz) + c * np.cos(yy), b * np.sin(xx) + a * np.cos(zz), c * np.sin(yy) + b * np.cos(xx)],
-                 -1)
-    return v[None], 2 * np.pi / (n - 1)
+    """The ABC flow at the nodes of an n^3 grid over [0, 2 pi]^3, and the spacing."""
+    h = 2 * np.pi / (n - 1)
+    return flows.sampled_field(flows.abc_velocity, [0.0] * 3, [h] * 3, (n, n, n)), h
 
 
 @pytest.mark.parametrize("vel_dtype", [np.float32, np.float64])

@@ -577,6 +577,7 @@ def test_advect_grid_validation(L):
     assert adv(dim=4) == INVALID and adv(shp=None) == INVALID and adv(nt=0) == INVALID
     assert adv(vel=None) == INVALID and adv(vdt=5) == INVALID and adv(dt_=5) == INVALID
     assert adv(shp=(ctypes.c_int64 * 3)(1, 5, 6)) == INVALID
+    assert adv(dim=2, shp=(ctypes.c_int64 * 3)(2 ** 31, 2, 6), nt=1) == INVALID and adv(nt=2 ** 31) == INVALID
     assert adv(sp=(ctypes.c_double * 3)(1.0, 0.0, 1.0)) == INVALID
     assert adv(o=(ctypes.c_double * 3)(float("nan"), 0.0, 0.0)) == INVALID
     assert adv(t_step=0.0) == INVALID and adv(t_first=float("inf")) == INVALID

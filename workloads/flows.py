@@ -79,3 +79,20 @@ def advect_rk4(velocity, p0, t0, T, dt: float, device=None) -> torch.Tensor:
         else:
             p += torch.where((s < nsteps)[:, None], incr, torch.zeros_like(incr))
     return p
+
+
+@torch.no_grad()
+def sampled_field(velocity, origin, spacing, shape, times=(0.0,)) -> "numpy.ndarray":
+    """A velocity field sampled on a regular grid, the gridded input of
+    ftle_advect_rk4_grid: nodes origin[d] + i spacing[d] for i < shape[d]
+    (x fastest) at each of ``times``.  Returns a float64 array of shape
+    (len(times), [nz,] ny, nx, D)."""
+    D = len(shape)
+    axes = [torch.arange(shape[d], dtype=torch.float64) * spacing[d] + origin[d] for d in range(D)]
+    grids = torch.meshgrid(*axes[::-1], indexing="ij")          # slowest axis first
+    pts = torch.stack([g.reshape(-1) for g in grids[::-1]], dim=1)
+    out = []
+    for t in times:
+        v = velocity(pts, torch.tensor(float(t), dtype=torch.float64))
+        out.append(v.reshape(*[shape[d] for d in range(D)][::-1], D))
+    return torch.stack(out).numpy()
