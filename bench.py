@@ -98,7 +98,7 @@ ADVECT_PROFILE = os.path.join(ROOT, "profiles", "ftle_advect_rk4.txt")
 # the RK4 kernels: profile key -> (kernel name, source file, particles, steps per particle)
 ADVECT_KERNELS = {"dg": ("advect_kernel<0, float>", "ftle_advect.hip", 2048 * 2048, 1500),
                   "abc": ("advect_kernel<1, float>", "ftle_advect.hip", 160 ** 3, 500),
-                  "grid_dg": ("advect_grid_kernel<2, float, float>", "ftle_advect_grid.hip", 2048 * 2048, 1500)}
+                  "grid_dg": ("advect_grid_kernel<2, true, float, float>", "ftle_advect_grid.hip", 2048 * 2048, 1500)}
 ADVECT_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP64_TRANS",
                    "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")
 # the commands that made profiles/ftle_advect_rk4.txt (from the repository root)

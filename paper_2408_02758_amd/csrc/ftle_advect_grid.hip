@@ -8,13 +8,16 @@
 // lane, the classical fourth-order Runge-Kutta method in float64 with the
 // steps of the analytic flows (ftle_advect.hip).
 //
-// The reads, not the arithmetic, bound this kernel: every evaluation needs
-// its cell's corner values in two slices (64 bytes per particle in 2D),
-// gathered lane by lane.  A particle moves less than a cell per step and
-// stays between the same two slices for many steps, so each lane keeps its
-// current cell's corner values in registers and reads the field only when
-// its cell or slice pair changes; the values, and so the results, are the
-// same as when every evaluation reads them.
+// Read plainly, every evaluation gathers its cell's corner values in two
+// slices (64 bytes per particle in 2D) lane by lane, and those gathers bound
+// the kernel.  A particle moves less than a cell per step and stays between
+// the same two slices for many steps, so each lane keeps its current cell's
+// interpolant in registers (float64 polynomial coefficients, slice 0 and the
+// change to slice 1) and reads the field only when its cell or slice pair
+// changes; an evaluation is then 2^D fused multiply-adds per component for
+// the time and 2^D - 1 for the cell.  Against the definition's weighted sum
+// of corner values, this and the reciprocal spacings reorder the arithmetic
+// at the level of a rounding.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,48 +42,61 @@ struct GridArgs {
     int two;                                     // more than one slice
 };
 
-// The pair of slices bracketing time t: the first one's index and both
-// weights (the nearest slice outside the sampled times).
+// The pair of slices bracketing time t: the first one's index and the
+// second one's weight (the nearest slice outside the sampled times).
 struct SliceWeights {
     int k;
-    double w0, w1;
+    double w;
 };
 
 __device__ inline SliceWeights slice_weights(const GridArgs& g, double t)
 {
-    SliceWeights r{0, 1.0, 0.0};
+    SliceWeights r{0, 0.0};
     if (g.two) {
         double s = (t - g.t_first) * g.inv_t_step;
         s = (s > 0.0) ? s : 0.0;   // also NaN
         s = (s > g.t_top) ? g.t_top : s;
         int k = (int)s;            // 0 <= s < 2^31: truncation is the floor
         k = (k > g.kmax) ? g.kmax : k;
-        const double gw = s - (double)k;
         r.k = k;
-        r.w0 = 1.0 - gw;
-        r.w1 = gw;
+        r.w = s - (double)k;
     }
     return r;
 }
 
-// A lane's current cell and slice pair, with the corner values read for it:
-// per slice and cell row along x (the (y[, z]) corners), the row's two x
-// neighbours' components (2 D consecutive values of the field).
-template <int D, typename V>
+// A lane's current cell and slice pair, with the interpolant read for it.
+// In a cell the multilinear interpolant of one component is the polynomial
+// sum over corner sets m of a_m prod_{d in m} f_d in the cell fractions f;
+// between two slices it is a0 + w (a1 - a0) coefficient by coefficient.  The
+// cache holds a0 and a1 - a0 per component, in float64.
+template <int D>
 struct CellCache {
-    static constexpr int kRows = 1 << (D - 1);
+    static constexpr int kCorners = 1 << D;
     int cell[D];
     int k;
-    V val[2][kRows][2 * D];
+    double a0[D][kCorners], da[D][kCorners];
 };
+
+// A cell's corner values (corner m = x bit | y bit << 1 [| z bit << 2]) into
+// the polynomial's coefficients: along each axis, the upper corners' values
+// less the lower ones'.
+template <int D>
+__device__ inline void corners_to_coefficients(double* a)
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int m = 0; m < (1 << D); ++m)
+            if (m & (1 << d)) a[m] -= a[m ^ (1 << d)];
+}
 
 // Multilinear velocity at p between the slices of sw, reading the field only
 // when p's cell or the slice pair differs from the cached one.
-template <int D, typename V>
+template <int D, bool TWO, typename V>
 __device__ inline void grid_velocity(const GridArgs& g, const V* __restrict__ vel, const double* p,
-                                     const SliceWeights& sw, CellCache<D, V>& cc, double* v)
+                                     const SliceWeights& sw, CellCache<D>& cc, double* v)
 {
-    constexpr int kRows = CellCache<D, V>::kRows;
+    constexpr int kCorners = CellCache<D>::kCorners;
     double f[3] = {0.0, 0.0, 0.0};
     int c[3] = {0, 0, 0};
     bool miss = sw.k != cc.k;
@@ -103,46 +119,48 @@ __device__ inline void grid_velocity(const GridArgs& g, const V* __restrict__ ve
             cc.cell[d] = c[d];
         }
         cc.k = sw.k;
+        // each cell row along x: the two x neighbours' components, 2 D
+        // consecutive values of the field
+        int64_t row[kCorners / 2];
 #pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            if (sl == 1 && !g.two) break;
+        for (int r = 0; r < kCorners / 2; ++r)
+            row[r] = base + ((r & 1) ? g.stride[1] : 0) + ((D == 3 && (r & 2)) ? g.stride[2] : 0);
 #pragma unroll
-            for (int r = 0; r < kRows; ++r) {
-                const int64_t at = base + (sl ? g.slice : 0) + ((r & 1) ? g.stride[1] : 0) +
-                                   ((D == 3 && (r & 2)) ? g.stride[2] : 0);
+        for (int r = 0; r < kCorners / 2; ++r)
 #pragma unroll
-                for (int e = 0; e < 2 * D; ++e) cc.val[sl][r][e] = vel[at + e];
+            for (int e = 0; e < 2 * D; ++e) cc.a0[e % D][2 * r + e / D] = (double)vel[row[r] + e];
+        if (TWO) {
+#pragma unroll
+            for (int r = 0; r < kCorners / 2; ++r)
+#pragma unroll
+                for (int e = 0; e < 2 * D; ++e) cc.da[e % D][2 * r + e / D] = (double)vel[row[r] + g.slice + e];
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            corners_to_coefficients<D>(cc.a0[d]);
+            if (TWO) {
+                corners_to_coefficients<D>(cc.da[d]);
+#pragma unroll
+                for (int m = 0; m < kCorners; ++m) cc.da[d][m] -= cc.a0[d][m];
             }
         }
     }
-    double wr[kRows];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        double w = (r & 1) ? f[1] : 1.0 - f[1];
-        if (D == 3) w *= (r & 2) ? f[2] : 1.0 - f[2];
-        wr[r] = w;
-    }
-    const double wx[2] = {1.0 - f[0], f[0]};
+    for (int d = 0; d < D; ++d) {
+        double a[kCorners];
 #pragma unroll
-    for (int d = 0; d < D; ++d) v[d] = 0.0;
+        for (int m = 0; m < kCorners; ++m) a[m] = TWO ? cc.a0[d][m] + sw.w * cc.da[d][m] : cc.a0[d][m];
+        // the polynomial in f, the highest axis folded first
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-        if (sl == 1 && !g.two) break;
-        const double ws = sl ? sw.w1 : sw.w0;
+        for (int e = D - 1; e >= 0; --e)
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const double w = ws * wr[r];
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                const double wc = w * wx[x];
-#pragma unroll
-                for (int d = 0; d < D; ++d) v[d] += wc * (double)cc.val[sl][r][x * D + d];
-            }
-        }
+            for (int m = 0; m < kCorners; ++m)
+                if (!(m & (1 << e)) && m < (1 << e)) a[m] += f[e] * a[m | (1 << e)];
+        v[d] = a[0];
     }
 }
 
-template <int D, typename T, typename V>
+template <int D, bool TWO, typename T, typename V>
 __global__ void __launch_bounds__(256) advect_grid_kernel(GridArgs g, const V* __restrict__ vel, int64_t n,
                                                           const T* __restrict__ x0, const double* __restrict__ t0s,
                                                           const double* __restrict__ Ts, double t0, double Tall,
@@ -163,7 +181,7 @@ __global__ void __launch_bounds__(256) advect_grid_kernel(GridArgs g, const V* _
     }
     const double h = Ti / steps;
     const int64_t ns = (int64_t)steps;
-    CellCache<D, V> cc;
+    CellCache<D> cc;
     cc.k = -1;   // no cell read yet
 #pragma unroll
     for (int d = 0; d < D; ++d) cc.cell[d] = -1;
@@ -171,16 +189,16 @@ __global__ void __launch_bounds__(256) advect_grid_kernel(GridArgs g, const V* _
         const double t = ti + (double)s * h;
         const SliceWeights w0 = slice_weights(g, t), wh = slice_weights(g, t + 0.5 * h),
                            w1 = slice_weights(g, t + h);
-        grid_velocity<D>(g, vel, p, w0, cc, k1);
+        grid_velocity<D, TWO>(g, vel, p, w0, cc, k1);
 #pragma unroll
         for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k1[d];
-        grid_velocity<D>(g, vel, q, wh, cc, k2);
+        grid_velocity<D, TWO>(g, vel, q, wh, cc, k2);
 #pragma unroll
         for (int d = 0; d < D; ++d) q[d] = p[d] + 0.5 * h * k2[d];
-        grid_velocity<D>(g, vel, q, wh, cc, k3);
+        grid_velocity<D, TWO>(g, vel, q, wh, cc, k3);
 #pragma unroll
         for (int d = 0; d < D; ++d) q[d] = p[d] + h * k3[d];
-        grid_velocity<D>(g, vel, q, w1, cc, k4);
+        grid_velocity<D, TWO>(g, vel, q, w1, cc, k4);
 #pragma unroll
         for (int d = 0; d < D; ++d) p[d] += h / 6.0 * (k1[d] + 2.0 * k2[d] + 2.0 * k3[d] + k4[d]);
     }
@@ -209,7 +227,8 @@ hipError_t advect_grid_launch(const GridField& g, const void* vel, int64_t n, co
     a.t_top = (double)(g.nt - 1);
     a.kmax = (int)(g.nt - 2);
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL((advect_grid_kernel<D, T, V>), dim3((unsigned)blocks), dim3(256), 0, stream, a,
+    auto kernel = a.two ? advect_grid_kernel<D, true, T, V> : advect_grid_kernel<D, false, T, V>;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a,
                        static_cast<const V*>(vel), n, static_cast<const T*>(x0), t0s, Ts, t0, T_, dt,
                        static_cast<T*>(phi));
     return hipGetLastError();
