@@ -379,9 +379,9 @@ def sustained(fns, torch, alg_bytes, clock, steps=1000, warmup=100):
 # committed profile summaries
 # ---------------------------------------------------------------------------
 def kernel_sources_sha256():
-    """SHA-256 over every kernel source (the .hip files and the shared header)."""
+    """SHA-256 over every kernel source (the .hip files and the headers they include)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + [os.path.join(CSRC, "ftle_internal.h")]):
+    for p in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h"))):
         h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
             h.update(f.read())
