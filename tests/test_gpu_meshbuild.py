@@ -178,6 +178,22 @@ def test_edge_cases():
     assert_same_mesh(x, cells)
 
 
+def test_duplicate_points_and_far_offset():
+    """Equal Morton codes (every point twice, the copies in no cell, shuffled)
+    keep the stable order on both builds; a mesh far from the origin (offset
+    10^6, float64) quantises to the same codes on both."""
+    x, cells = meshes.jittered_tri_grid(24, 17, seed=5)
+    n = x.shape[0]
+    perm = np.random.default_rng(7).permutation(2 * n)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(2 * n)
+    xx = np.concatenate([x, x])[perm]
+    assert_same_mesh(xx, inv[cells].astype(np.int32))
+    x3, c3 = meshes.kuhn_tet_grid(7)
+    assert_same_mesh(x3 + 1.0e6, c3, dtype="f64")
+    assert_same_mesh(x3 + 1.0e6, c3, dtype="f64", stencil="axis")
+
+
 def test_high_degree_fan():
     """A fan of triangles around one centre: a 900-neighbour row (tiles halve
     down to few points), then one past a tile's capacity (both builds refuse)."""
