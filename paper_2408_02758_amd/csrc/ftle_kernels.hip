@@ -157,7 +157,8 @@ __device__ inline void rec_put(P* base, uint32_t i, uint32_t bytes, const V v)
 // step: the words' LDS loads, then the neighbours' slot loads, then the
 // arithmetic; a final single word.  visit(pad, l...) gets the local indices
 // and the padding count of the step's last word (its bits 30-31): a zero
-// constant except for the row's last word, visited first when PAD.
+// constant except for the row's last word, visited first when PAD and as the
+// final single word otherwise.
 template <int K> using IntK = std::integral_constant<int, K>;
 
 template <int WPS, bool PAD, typename F>
@@ -195,7 +196,15 @@ __device__ inline void walk_row(uint32_t words, int s, int e, F&& visit)
     }
     for (; a < end; a += 4u) {
         const uint32_t w0 = lds_ld<uint32_t>(a);
-        visit(Zero{}, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
+        if constexpr (PAD) {
+            visit(Zero{}, ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
+        } else {
+            // with two words a step this single word, when there is one, is
+            // the row's last: its padding is skipped when the active lanes'
+            // rows all end in padding there (the 2D rows of 7 and 8 entries)
+            // (at most 2 padding entries: the first entry is always live)
+            visit(min(w0 >> 30, 2u), ix(w0, IntK<0>{}), ix(w0, IntK<1>{}), ix(w0, IntK<2>{}));
+        }
     }
 }
 
