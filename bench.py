@@ -830,6 +830,7 @@ def error_vs_oracle(stencils, w, got, sel=None, stencil="ring1"):
             "masked_max_rel_err": float(rel.max(initial=0)),
             "masked_p99_rel_err": float(np.percentile(rel, 99)) if rel.size else 0.0,
             "mask_fraction": round(float(mask.mean()), 4),
+            "nan_count": int(np.isnan(g).sum()),
             "nan_masks_equal": bool(np.array_equal(np.isnan(g), np.isnan(ref)))}
 
 
