@@ -386,7 +386,8 @@ def _handles(meshes: Sequence[Mesh]):
 
 
 def batched(meshes: Sequence[Mesh], flows: Sequence[torch.Tensor], Ts: Sequence[float], outs=None, stream=None):
-    """One persistent launch (replayed from a cached HIP graph) over many meshes."""
+    """One launch over many meshes (a persistent grid draining a queue or a
+    flat grid, as autotuned or pinned), replayed from a cached HIP graph."""
     n = len(meshes)
     if not (len(flows) == n == len(Ts)):
         raise ValueError("meshes, flows and Ts must have the same length")
@@ -462,6 +463,16 @@ class FTLEFunction(torch.autograd.Function):
 _FLOWS = {"double_gyre": (0, 2), "abc": (1, 3)}
 
 
+def _check_out(out, shape, dtype, name="out", not_alias=None):
+    """out must be a contiguous device tensor of the given shape and dtype (and
+    not the input not_alias): the kernels write exactly that many values."""
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == dtype and out.is_contiguous()
+            and tuple(out.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor of shape {tuple(shape)}")
+    if not_alias is not None and out.numel() and out.data_ptr() == not_alias.data_ptr():
+        raise ValueError(f"{name} must not be the input tensor")
+
+
 def advect_rk4(flow: str, x0: torch.Tensor, t0, T, dt: float, params=None, out: torch.Tensor | None = None,
                stream=None) -> torch.Tensor:
     """Flow map x(t0 + T) of particles at x0 (device tensor, (N, 2) for
@@ -486,6 +497,7 @@ def advect_rk4(flow: str, x0: torch.Tensor, t0, T, dt: float, params=None, out: 
     Tp, Ts = per_point(T, "T")
     if out is None:
         out = torch.empty_like(x0)
+    _check_out(out, x0.shape, x0.dtype, not_alias=x0)
     prm = None if params is None else (ctypes.c_double * 3)(*[float(v) for v in params])
     check(_lib.load().ftle_advect_rk4(kind, prm, n, ctypes.c_void_p(x0.data_ptr()), code, t0p, Tp, t0s, Ts,
                                       float(dt), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
@@ -522,6 +534,9 @@ def advect_rk4_grid(velocity: torch.Tensor, origin, spacing, t_first: float, t_s
     Tp, Ts = per_point(T, "T")
     if out is None:
         out = torch.empty_like(x0)
+    _check_out(out, x0.shape, x0.dtype, not_alias=x0)
+    if len(origin) != dim or len(spacing) != dim:
+        raise ValueError(f"origin and spacing need {dim} values each")
     shape = (ctypes.c_int64 * dim)(*[int(v) for v in velocity.shape[1:-1][::-1]])
     org = (ctypes.c_double * dim)(*[float(v) for v in origin])
     spc = (ctypes.c_double * dim)(*[float(v) for v in spacing])
@@ -611,6 +626,7 @@ def forward_ell(coords: torch.Tensor, ell: torch.Tensor, flow: torch.Tensor, T: 
         raise ValueError(f"ell must be a contiguous int32 device tensor of shape ({n}, {2 * dim})")
     if out is None:
         out = torch.empty(n, dtype=coords.dtype, device=coords.device)
+    _check_out(out, (n,), coords.dtype)
     code = _lib.F64 if coords.dtype == torch.float64 else _lib.F32
     check(_lib.load().ftle_forward_ell(dim, n, ctypes.c_void_p(coords.data_ptr()), code,
                                        ctypes.c_void_p(ell.data_ptr()), ctypes.c_void_p(flow.data_ptr()), float(T),

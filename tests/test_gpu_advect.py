@@ -242,3 +242,21 @@ def test_advect_grid_full_2048_sampled():
     err = np.abs(got[sel] - ref) - 2 ** -23 * np.abs(ref)
     print(f"[advect grid 2048^2] max |d| beyond output rounding = {err.max():.3e}", flush=True)
     assert np.all(err <= 1e-9)
+
+
+def test_wrappers_reject_bad_outputs():
+    """The Python wrappers check the output tensor (shape, dtype, device, not
+    the input) and the grid's origin and spacing lengths before any launch."""
+    x = torch.zeros(10, 2, dtype=torch.float64, device=DEV)
+    vel = torch.zeros(2, 3, 4, 2, dtype=torch.float32, device=DEV)
+    bad = [torch.empty(9, 2, dtype=torch.float64, device=DEV), torch.empty(10, 2, dtype=torch.float32, device=DEV),
+           torch.empty(10, 2, dtype=torch.float64), x]
+    for out in bad:
+        with pytest.raises(ValueError):
+            F.advect_rk4("double_gyre", x, 0.0, 1.0, 0.1, out=out)
+        with pytest.raises(ValueError):
+            F.advect_rk4_grid(vel, [0.0, 0.0], [1.0, 1.0], 0.0, 1.0, x, 0.0, 1.0, 0.1, out=out)
+    with pytest.raises(ValueError):
+        F.advect_rk4_grid(vel, [0.0, 0.0, 0.0], [1.0, 1.0], 0.0, 1.0, x, 0.0, 1.0, 0.1)
+    ok = F.advect_rk4_grid(vel, [0.0, 0.0], [1.0, 1.0], 0.0, 1.0, x, 0.0, 1.0, 0.1)
+    assert torch.equal(ok, x)   # a zero field leaves every particle in place

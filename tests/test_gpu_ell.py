@@ -97,6 +97,10 @@ def test_forward_ell_tiny_and_empty():
         assert np.allclose(out, np.log(3.0) / 2.0, rtol=1e-6)
     e = torch.empty(0, 2, device=DEV)
     assert F.forward_ell(e, torch.empty(0, 4, dtype=torch.int32, device=DEV), e, 1.0).numel() == 0
+    # an output of the wrong size, dtype or device is refused before the launch
+    for out in (torch.empty(2, device=DEV), torch.empty(3, dtype=torch.float64, device=DEV), torch.empty(3)):
+        with pytest.raises(ValueError):
+            F.forward_ell(x, ell, phi, 2.0, out=out)
 
 
 @pytest.mark.parametrize("which", ["scale_2d", "abc_3d"])
