@@ -8,7 +8,9 @@ smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
 code with the GPU library and does not import it.
 
 It also holds the two steps around the path that the library offers on the
-GPU: RK4 flow maps of analytic flows, and the binary16 storage of a flow map
+GPU: RK4 flow maps (of analytic flows, and in a velocity field sampled on a
+regular grid, multilinear in space and linear in time), and the binary16
+storage of a flow map
 (numpy), with the error bound that storage carries: the storage's rounding
 per point (flow_error_f16) and the FTLE change any flow-map error within given
 per-point limits can cause (ftle_perturbation_bound, from the least squares'
