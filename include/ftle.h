@@ -191,8 +191,9 @@ ftle_status ftle_create_mesh_device_from_csr(int dim, int64_t n_points, const vo
  *   col_capacity n_cells * dim * (dim+1) always suffices
  *   nnz          host, receives the entry count (also when it exceeds
  *                col_capacity)
- * ftle_ring1_csr allocates its workspace (ftle_ring1_csr_workspace bytes,
- * about 4 bytes per cell corner and 144 per point) for the duration of the
+ * ftle_ring1_csr allocates its workspace (ftle_ring1_csr_workspace bytes:
+ * the larger of 4 bytes per cell corner and 64 (2D) or 128 (3D) bytes per
+ * point, plus about 144 bytes per point) for the duration of the
  * call; ftle_ring1_csr_ws takes it from the caller (device memory of at
  * least that size, overwritten).  Both return after the stream has finished
  * the work.

@@ -4,15 +4,18 @@
 // Every point's neighbours are the other points sharing a cell with it,
 // ascending, each once.  Hand-written kernels, no library sort:
 //
-//   1. incidence counts: each cell adds one to the count of each of its K =
-//      dim + 1 points (an index outside [0, n) raises the error flag),
-//      aggregated per workgroup in LDS first;
-//   2. an exclusive scan of the counts gives each point's incidence offset
-//      (scan_tiles / scan_partials / add_partials: 2048-element tiles, the
-//      tiles' sums scanned by one workgroup, then added back);
-//   3. incidence lists: each cell appends its index to the list of each of its
-//      points (atomic cursors, one per distinct point of a workgroup; the
-//      order inside a list does not matter);
+//   1. incidence lists in one pass: each cell appends its index to the list
+//      of each of its K = dim + 1 points, a list of at most kIncCap entries
+//      per point at a fixed place (atomic cursors, one per distinct point of
+//      a workgroup, aggregated in LDS first; the order inside a list does not
+//      matter; an index outside [0, n) raises the error flag).  When a point
+//      has more incident cells than that, or the fixed lists would not be
+//      addressable in 32 bits, the lists are packed instead:
+//   2. the counts (from the first pass, or from a counting pass) are scanned
+//      into each point's incidence offset (scan_tiles / scan_partials /
+//      add_partials: 2048-element tiles, the tiles' sums scanned by one
+//      workgroup, then added back), and
+//   3. a second pass appends each cell's index to its points' packed lists;
 //   4. rows: one lane per point walks its incident cells and inserts their
 //      other points into a short sorted list of distinct indices in LDS (a
 //      lane's list is interleaved with its workgroup's, so that a list step
@@ -25,6 +28,7 @@
 //      once to write.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "ftle_device_math.h"
@@ -37,6 +41,7 @@ constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kSc
 constexpr int kRowThreads = 128;   // lanes per workgroup of the row passes
 constexpr int kRowCap = 32;        // distinct neighbours a lane keeps in LDS
 constexpr int kLongCap = 4096;     // candidates (with repeats) of a long row
+constexpr uint32_t kIncCap2 = 16, kIncCap3 = 32;   // fixed incidence list length (triangles, tetrahedra)
 
 inline unsigned blocks_for(int64_t m, int per = 256) { return (unsigned)((m + per - 1) / per); }
 
@@ -61,20 +66,26 @@ __device__ inline void load_cell(const int32_t* __restrict__ cells, int64_t c, i
 // costs one global atomic instead of one per occurrence: cells come in mesh
 // order, and neighbouring cells share most of their points.  A point that
 // finds no slot within kProbes probes goes to global memory directly.
-//   FILL = false: cnt[v] += occurrences of v (a cell with an index outside
-//                 [0, n) sets *err and adds nothing);
-//   FILL = true:  each occurrence of v gets a position from cur[v] (the
-//                 workgroup reserves its block of positions with one atomic)
-//                 and inc[position] = its cell.
+//   kCount:  cnt[v] += occurrences of v (a cell with an index outside [0, n)
+//            sets bit 1 of *err and adds nothing);
+//   kPacked: each occurrence of v gets a position from cur[v] (the workgroup
+//            reserves its block of positions with one atomic) and
+//            inc[position] = its cell;
+//   kFixed:  as kCount, and each occurrence of v also gets list position
+//            k = the count before it, inc[v cap + k] = its cell while k < cap
+//            (beyond it, bit 4 of *err and no store).
 constexpr int kAggThreads = 256, kAggCells = 4, kAggSlots = 4096, kProbes = 32;
+enum IncMode { kCount, kPacked, kFixed };
 
 __device__ inline uint32_t agg_hash(int32_t v) { return ((uint32_t)v * 2654435761u) >> 20; }   // 12 bits
 
-template <int K, bool FILL>
+template <int K, int MODE>
 __global__ void __launch_bounds__(kAggThreads) incidence_pass(const int32_t* __restrict__ cells, int64_t n_cells,
                                                               int64_t n, uint32_t* __restrict__ cnt,
-                                                              int32_t* __restrict__ inc, int* __restrict__ err)
+                                                              int32_t* __restrict__ inc, int* __restrict__ err,
+                                                              uint32_t cap)
 {
+    constexpr bool FILL = MODE != kCount;
     static_assert(kAggSlots == 1 << 12, "agg_hash gives 12 bits");
     __shared__ int32_t key[kAggSlots];
     __shared__ uint32_t num[kAggSlots];
@@ -97,7 +108,7 @@ __global__ void __launch_bounds__(kAggThreads) incidence_pass(const int32_t* __r
             load_cell<K>(cells, c, v);
 #pragma unroll
             for (int a = 0; a < K; ++a) ok &= (uint64_t)(int64_t)v[a] < (uint64_t)n;
-            if (!FILL && !ok) *err = 1;   // every writer stores the same value
+            if (MODE != kPacked && !ok) atomicOr(err, 1);
         }
 #pragma unroll
         for (int a = 0; a < K; ++a) {
@@ -115,8 +126,14 @@ __global__ void __launch_bounds__(kAggThreads) incidence_pass(const int32_t* __r
             slot[q][a] = s;
             if (s >= 0) {
                 local[q][a] = atomicAdd(&num[s], 1u);
-            } else if (FILL) {
+            } else if (MODE == kPacked) {
                 inc[atomicAdd(&cnt[v[a]], 1u)] = (int32_t)c;
+            } else if (MODE == kFixed) {
+                const uint32_t k = atomicAdd(&cnt[v[a]], 1u);
+                if (k < cap)
+                    inc[(uint32_t)v[a] * cap + k] = (int32_t)c;
+                else
+                    atomicOr(err, 4);
             } else {
                 atomicAdd(&cnt[v[a]], 1u);
             }
@@ -131,13 +148,28 @@ __global__ void __launch_bounds__(kAggThreads) incidence_pass(const int32_t* __r
         else
             atomicAdd(&cnt[k], num[i]);
     }
-    if constexpr (FILL) {
+    if constexpr (MODE == kPacked) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kAggCells; ++q)
 #pragma unroll
             for (int a = 0; a < K; ++a)
                 if (slot[q][a] >= 0) inc[num[slot[q][a]] + local[q][a]] = (int32_t)(c0 + q * kAggThreads + t);
+    } else if constexpr (MODE == kFixed) {
+        __syncthreads();
+        bool over = false;
+#pragma unroll
+        for (int q = 0; q < kAggCells; ++q)
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+                if (slot[q][a] >= 0) {
+                    const uint32_t k = num[slot[q][a]] + local[q][a];
+                    if (k < cap)
+                        inc[(uint32_t)key[slot[q][a]] * cap + k] = (int32_t)(c0 + q * kAggThreads + t);
+                    else
+                        over = true;
+                }
+        if (over) atomicOr(err, 4);
     }
 }
 
@@ -230,10 +262,26 @@ hipError_t exclusive_scan(const uint32_t* in, int64_t m, Out* out, Out* partial,
 // instruction writes consecutive points).  A point with more is appended to
 // longs (deg[r] = 0 until long_rows counts it).
 // ---------------------------------------------------------------------------
+// Point r's incidence list: inc[p0, p1).  *capp = 0: packed lists at the
+// offsets off[r], off[r + 1]; otherwise fixed lists of *capp entries, off[r]
+// of them used.
+struct IncRange {
+    uint32_t p0, p1;
+};
+__device__ inline IncRange inc_range(const uint32_t* __restrict__ off, uint32_t cap, int64_t r)
+{
+    if (cap) {
+        const uint32_t p0 = (uint32_t)r * cap;
+        return IncRange{p0, p0 + off[r]};
+    }
+    return IncRange{off[r], off[r + 1]};
+}
+
 template <int K>
 __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restrict__ cells,
                                                          const int32_t* __restrict__ inc,
-                                                         const uint32_t* __restrict__ off, int64_t n,
+                                                         const uint32_t* __restrict__ off,
+                                                         const uint32_t* __restrict__ capp, int64_t n,
                                                          uint32_t* __restrict__ deg, int32_t* __restrict__ store,
                                                          uint32_t* __restrict__ longs, uint32_t* __restrict__ n_long)
 {
@@ -244,7 +292,8 @@ __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restri
     int32_t* my = lst + t;   // entry k at my[k * kRowThreads]
     int cnt = 0;
     bool over = false;
-    const uint32_t p0 = off[r], p1 = off[r + 1];
+    const IncRange ir = inc_range(off, *capp, r);
+    const uint32_t p0 = ir.p0, p1 = ir.p1;
     // incident cells kChunk at a time: their loads are issued together, then
     // their points are inserted (a cell past the end repeats the last one,
     // whose points are then found already listed)
@@ -330,7 +379,8 @@ __global__ void __launch_bounds__(256) copy_rows(const int32_t* __restrict__ sto
 // device).
 template <int K, bool WRITE>
 __global__ void __launch_bounds__(256) long_rows(const int32_t* __restrict__ cells, const int32_t* __restrict__ inc,
-                                                 const uint32_t* __restrict__ off, const uint32_t* __restrict__ longs,
+                                                 const uint32_t* __restrict__ off, const uint32_t* __restrict__ capp,
+                                                 const uint32_t* __restrict__ longs,
                                                  const uint32_t* __restrict__ n_long, uint32_t* __restrict__ deg,
                                                  const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                                                  int* __restrict__ err)
@@ -343,7 +393,8 @@ __global__ void __launch_bounds__(256) long_rows(const int32_t* __restrict__ cel
     const uint32_t nl = *n_long;
     for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
         const int64_t r = longs[li];
-        const uint32_t p0 = off[r], m = (off[r + 1] - p0) * K;
+        const IncRange ir = inc_range(off, *capp, r);
+        const uint32_t p0 = ir.p0, m = (ir.p1 - p0) * K;
         if (m > (uint32_t)kLongCap) {
             if (t == 0) atomicOr(err, 2);
             continue;
@@ -398,12 +449,21 @@ constexpr int kLongGrid = 256;
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Length of the fixed incidence lists, 0 where n of them would not be
+// addressable with 32-bit positions (then only packed lists are built).
+uint32_t inc_cap(int dim, int64_t n)
+{
+    const uint32_t cap = dim == 2 ? kIncCap2 : kIncCap3;
+    return (uint64_t)n * cap <= 0xffffffffull ? cap : 0u;
+}
+
 // Workspace of ring1_build, carved in this order (carve_ring1): incidence
-// counts and offsets (n + 1), cursors (n), incidence lists (K n_cells),
-// distinct counts (n + 1), long rows (n), stored lists (kRowCap n), scan
-// partial sums, error and long-row counters.
+// counts and offsets (n + 1), cursors (n), incidence lists (the larger of
+// K n_cells packed and n fixed lists), distinct counts (n + 1), long rows
+// (n), stored lists (kRowCap n), scan partial sums, then the error flags,
+// the long-row count and the fixed list length in use (0: packed lists).
 struct Ring1Work {
-    uint32_t *cnt, *cur, *deg, *longs, *n_long;
+    uint32_t *cnt, *cur, *deg, *longs, *n_long, *cap;
     int32_t *inc, *store;
     void* partial;
     int* err;
@@ -423,13 +483,14 @@ Ring1Work carve_ring1(void* workspace, int dim, int64_t n, int64_t n_cells, size
     Ring1Work w;
     w.cnt = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
     w.cur = static_cast<uint32_t*>(carve(4 * (size_t)n));
-    w.inc = static_cast<int32_t*>(carve(4 * (size_t)K * n_cells));
+    w.inc = static_cast<int32_t*>(carve(4 * std::max((size_t)K * n_cells, (size_t)n * inc_cap(dim, n))));
     w.deg = static_cast<uint32_t*>(carve(4 * (size_t)(n + 1)));
     w.longs = static_cast<uint32_t*>(carve(4 * (size_t)n));
     w.store = static_cast<int32_t*>(carve(4 * (size_t)kRowCap * n));
     w.partial = carve(8 * (size_t)tiles);
     w.err = static_cast<int*>(carve(256));
     w.n_long = w.err ? reinterpret_cast<uint32_t*>(w.err + 1) : nullptr;
+    w.cap = w.err ? reinterpret_cast<uint32_t*>(w.err + 2) : nullptr;
     if (bytes) *bytes = at;
     return w;
 }
@@ -461,43 +522,55 @@ hipError_t ring1_build(int dim, const int32_t* cells, int64_t n_cells, int64_t n
 #define FTLE_CHECK(x)                          \
     if ((e = (x)) != hipSuccess) return e;
     FTLE_CHECK(hipMemsetAsync(cnt, 0, 4 * (size_t)(n + 1), stream));
-    FTLE_CHECK(hipMemsetAsync(err, 0, 8, stream));
+    FTLE_CHECK(hipMemsetAsync(err, 0, 12, stream));   // flags, long rows, fixed list length
+    const dim3 ag(blocks_for(n_cells, kAggThreads * kAggCells)), ab(kAggThreads);
+    // 1. fixed lists (with the counts), or the counts alone
+    const uint32_t cap = n_cells > 0 ? inc_cap(dim, n) : 0u;
     if (n_cells > 0) {
-        const dim3 ag(blocks_for(n_cells, kAggThreads * kAggCells)), ab(kAggThreads);
-        if (dim == 2)
-            hipLaunchKernelGGL((incidence_pass<3, false>), ag, ab, 0, stream, cells, n_cells, n, cnt, nullptr, err);
-        else
-            hipLaunchKernelGGL((incidence_pass<4, false>), ag, ab, 0, stream, cells, n_cells, n, cnt, nullptr, err);
+        if (cap) {
+            if (dim == 2)
+                hipLaunchKernelGGL((incidence_pass<3, kFixed>), ag, ab, 0, stream, cells, n_cells, n, cnt, inc, err, cap);
+            else
+                hipLaunchKernelGGL((incidence_pass<4, kFixed>), ag, ab, 0, stream, cells, n_cells, n, cnt, inc, err, cap);
+        } else {
+            if (dim == 2)
+                hipLaunchKernelGGL((incidence_pass<3, kCount>), ag, ab, 0, stream, cells, n_cells, n, cnt, nullptr, err, 0u);
+            else
+                hipLaunchKernelGGL((incidence_pass<4, kCount>), ag, ab, 0, stream, cells, n_cells, n, cnt, nullptr, err, 0u);
+        }
         FTLE_CHECK(hipGetLastError());
     }
     int flags = 0;
     FTLE_CHECK(hipMemcpyAsync(&flags, err, sizeof(int), hipMemcpyDeviceToHost, stream));
     FTLE_CHECK(hipStreamSynchronize(stream));
-    if (flags) {
+    if (flags & 1) {
         *bad_mesh = 1;
         return hipSuccess;
     }
-    // 2. offsets (cnt becomes off, in place: the tile scan reads a value before writing it)
-    FTLE_CHECK(exclusive_scan<uint32_t>(cnt, n, cnt, static_cast<uint32_t*>(partial), stream));
-    // 3. incidence lists
-    FTLE_CHECK(hipMemcpyAsync(cur, cnt, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream));
-    if (n_cells > 0) {
-        const dim3 ag(blocks_for(n_cells, kAggThreads * kAggCells)), ab(kAggThreads);
+    if (cap && !(flags & 4)) {
+        // every list fits: the rows read them in place
+        FTLE_CHECK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(w.cap), (int)cap, 1, stream));
+    } else if (n_cells > 0) {
+        // packed lists: 2. offsets from the counts (cnt becomes off, in place:
+        // the tile scan reads a value before writing it), 3. the second pass
+        FTLE_CHECK(hipMemsetAsync(err, 0, sizeof(int), stream));
+        FTLE_CHECK(exclusive_scan<uint32_t>(cnt, n, cnt, static_cast<uint32_t*>(partial), stream));
+        FTLE_CHECK(hipMemcpyAsync(cur, cnt, 4 * (size_t)n, hipMemcpyDeviceToDevice, stream));
         if (dim == 2)
-            hipLaunchKernelGGL((incidence_pass<3, true>), ag, ab, 0, stream, cells, n_cells, n, cur, inc, nullptr);
+            hipLaunchKernelGGL((incidence_pass<3, kPacked>), ag, ab, 0, stream, cells, n_cells, n, cur, inc, nullptr, 0u);
         else
-            hipLaunchKernelGGL((incidence_pass<4, true>), ag, ab, 0, stream, cells, n_cells, n, cur, inc, nullptr);
+            hipLaunchKernelGGL((incidence_pass<4, kPacked>), ag, ab, 0, stream, cells, n_cells, n, cur, inc, nullptr, 0u);
         FTLE_CHECK(hipGetLastError());
     }
     // 4. distinct counts, their offsets, then the lists
     const dim3 rg(blocks_for(n, kRowThreads)), rb(kRowThreads);
     if (dim == 2) {
-        hipLaunchKernelGGL((ring_rows<3>), rg, rb, 0, stream, cells, inc, cnt, n, deg, w.store, longs, n_long);
-        hipLaunchKernelGGL((long_rows<3, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
+        hipLaunchKernelGGL((ring_rows<3>), rg, rb, 0, stream, cells, inc, cnt, w.cap, n, deg, w.store, longs, n_long);
+        hipLaunchKernelGGL((long_rows<3, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, w.cap, longs,
                            n_long, deg, nullptr, nullptr, err);
     } else {
-        hipLaunchKernelGGL((ring_rows<4>), rg, rb, 0, stream, cells, inc, cnt, n, deg, w.store, longs, n_long);
-        hipLaunchKernelGGL((long_rows<4, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, longs,
+        hipLaunchKernelGGL((ring_rows<4>), rg, rb, 0, stream, cells, inc, cnt, w.cap, n, deg, w.store, longs, n_long);
+        hipLaunchKernelGGL((long_rows<4, false>), dim3(kLongGrid), dim3(256), 0, stream, cells, inc, cnt, w.cap, longs,
                            n_long, deg, nullptr, nullptr, err);
     }
     FTLE_CHECK(hipGetLastError());
@@ -522,10 +595,10 @@ hipError_t ring1_write(int dim, const int32_t* cells, int64_t n_cells, int64_t n
     const Ring1Work w = carve_ring1(workspace, dim, n, n_cells, nullptr);
     hipLaunchKernelGGL(copy_rows, dim3(blocks_for(n)), dim3(256), 0, stream, w.store, n, w.deg, row_ptr, col);
     if (dim == 2)
-        hipLaunchKernelGGL((long_rows<3, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, w.inc, w.cnt, w.longs,
+        hipLaunchKernelGGL((long_rows<3, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, w.inc, w.cnt, w.cap, w.longs,
                            w.n_long, w.deg, row_ptr, col, w.err);
     else
-        hipLaunchKernelGGL((long_rows<4, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, w.inc, w.cnt, w.longs,
+        hipLaunchKernelGGL((long_rows<4, true>), dim3(kLongGrid), dim3(256), 0, stream, cells, w.inc, w.cnt, w.cap, w.longs,
                            w.n_long, w.deg, row_ptr, col, w.err);
     return hipGetLastError();
 }
