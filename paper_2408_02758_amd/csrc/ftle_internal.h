@@ -192,9 +192,10 @@ hipError_t launch_advect_grid(int dim, const GridField& g, const void* vel, bool
 hipError_t launch_advect(int kind, const double* params, bool f64, int64_t n, const void* x0, const double* t0s,
                          const double* Ts, double t0, double T, double dt, void* phi, hipStream_t stream);
 
-// One-ring stencil on the device (ftle_neighbours.hip): incidence counts,
-// their scan, incidence lists, then each point's distinct neighbours counted,
-// scanned into row_ptr and written to col.  The workspace
+// One-ring stencil on the device (ftle_neighbours.hip): incidence lists (in
+// one pass at fixed places, or packed after a count and its scan), then each
+// point's distinct neighbours counted, scanned into row_ptr and written to
+// col.  The workspace
 // (ring1_workspace_bytes) is device memory the call may overwrite.  On return
 // *bad_mesh (a cell index outside [0, n): nothing written) or *too_long (a
 // point whose incident cells list more than 4096 points) may be set;
