@@ -54,6 +54,8 @@ SIGNATURES = {
                                     _vp, _int, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp,
                                     _vp]),
     "ftle_destroy_mesh": (None, [_vp]),
+    "ftle_cached_memory_bytes": (_int, [_P(_i64)]),
+    "ftle_release_cached_memory": (_int, []),
     "ftle_mesh_info": (_int, [_vp, _P(_int), _P(_i64), _P(_i64), _P(_int)]),
     "ftle_mesh_get_csr": (_int, [_vp, _vp, _vp, _vp]),
     "ftle_mesh_tile_stats": (_int, [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)]),

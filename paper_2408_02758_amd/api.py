@@ -635,6 +635,18 @@ def forward_ell(coords: torch.Tensor, ell: torch.Tensor, flow: torch.Tensor, T: 
     return out
 
 
+def cached_memory_bytes() -> int:
+    """Device memory the mesh builds keep between calls (all devices)."""
+    v = ctypes.c_int64(0)
+    check(_lib.load().ftle_cached_memory_bytes(ctypes.byref(v)))
+    return v.value
+
+
+def release_cached_memory() -> None:
+    """Free the device memory the mesh builds keep between calls."""
+    check(_lib.load().ftle_release_cached_memory())
+
+
 def force_wide_offsets(on: bool) -> None:
     """Testing aid: make every later launch take the 64-bit offset path (see ftle_force_wide_offsets)."""
     check(_lib.load().ftle_force_wide_offsets(int(bool(on))))

@@ -1026,6 +1026,65 @@ struct DevBuf {
 
 // The build's temporaries, carved from one allocation: a hipMalloc / hipFree
 // pair per temporary array cost more than the kernels that use them.
+// Scratch device memory of the device mesh builds, kept per device between
+// builds and grown when a build needs more, so that a build does not pay for
+// allocating and releasing its temporaries each time.  One build at a time
+// holds it (a concurrent build on the same device takes memory of its own);
+// ftle_release_cached_memory frees it.  Never freed by a static destructor:
+// the runtime may be gone by then, and the process's end returns it anyway.
+struct BuildScratch {
+    std::mutex m;
+    void* p = nullptr;
+    size_t bytes = 0;
+    bool busy = false;
+};
+constexpr int kMaxCachedDevices = 64;
+BuildScratch g_build_scratch[kMaxCachedDevices];
+
+class ScratchLease {
+  public:
+    ScratchLease(size_t need, hipStream_t s) : s_(s)
+    {
+        int dev = -1;
+        check_hip(hipGetDevice(&dev), "hipGetDevice");
+        if (dev >= 0 && dev < kMaxCachedDevices) {
+            BuildScratch& c = g_build_scratch[dev];
+            std::lock_guard<std::mutex> lk(c.m);
+            if (!c.busy) {
+                if (c.bytes < need) {
+                    if (c.p) (void)hipFree(c.p);
+                    c.p = nullptr;
+                    c.bytes = 0;
+                    check_hip(hipMalloc(&c.p, need ? need : 16), "hipMalloc (mesh build scratch)");
+                    c.bytes = need;
+                }
+                c.busy = true;
+                cache_ = &c;
+                p_ = c.p;
+                return;
+            }
+        }
+        own_ = DevBuf(need);
+        p_ = own_.p;
+    }
+    ~ScratchLease()
+    {
+        if (!cache_) return;
+        (void)hipStreamSynchronize(s_);   // the build's kernels are done with it (also after a failure)
+        std::lock_guard<std::mutex> lk(cache_->m);
+        cache_->busy = false;
+    }
+    ScratchLease(const ScratchLease&) = delete;
+    ScratchLease& operator=(const ScratchLease&) = delete;
+    void* get() const { return p_; }
+
+  private:
+    hipStream_t s_;
+    BuildScratch* cache_ = nullptr;
+    DevBuf own_;
+    void* p_ = nullptr;
+};
+
 struct Arena {
     unsigned char* base = nullptr;
     size_t size = 0, at = 0;
@@ -1216,9 +1275,9 @@ ftle_mesh_t build_device(int dim, int64_t n, const void* coords, ftle_dtype dtyp
     order_sample(n, &ms, &stride);
     const size_t phase_sort = Arena::round((size_t)nb * 2 * dim * 8 + 8) + Arena::round((size_t)ms * 2 * dim * 8) +
                               Arena::round((size_t)n * 8) + Arena::round(mb_sort_scratch_bytes(n));
-    DevBuf arena_buf(std::max(phase_sort, stencil_bytes));
+    ScratchLease arena_buf(std::max(phase_sort, stencil_bytes), s);
     Arena arena;
-    arena.base = static_cast<unsigned char*>(arena_buf.p);
+    arena.base = static_cast<unsigned char*>(arena_buf.get());
     arena.size = std::max(phase_sort, stencil_bytes);
 
     // the mesh's own copy of the coordinates; bounds and finiteness
@@ -2093,6 +2152,38 @@ void ftle_destroy_mesh(ftle_mesh_t mesh)
     }
     release_device(mesh);
     delete mesh;
+}
+
+ftle_status ftle_release_cached_memory(void)
+{
+    return guarded([&] {
+        int cur = -1;   // the current device, read once something is to be freed
+        for (int dev = 0; dev < kMaxCachedDevices; ++dev) {
+            BuildScratch& c = g_build_scratch[dev];
+            std::lock_guard<std::mutex> lk(c.m);
+            if (!c.p || c.busy) continue;
+            if (cur < 0) check_hip(hipGetDevice(&cur), "hipGetDevice");
+            check_hip(hipSetDevice(dev), "hipSetDevice");
+            (void)hipFree(c.p);
+            c.p = nullptr;
+            c.bytes = 0;
+        }
+        if (cur >= 0) check_hip(hipSetDevice(cur), "hipSetDevice");
+    });
+}
+
+ftle_status ftle_cached_memory_bytes(int64_t* bytes)
+{
+    return guarded([&] {
+        if (!bytes) fail(FTLE_ERR_INVALID_ARG, "bytes is NULL");
+        int64_t total = 0;
+        for (int dev = 0; dev < kMaxCachedDevices; ++dev) {
+            BuildScratch& c = g_build_scratch[dev];
+            std::lock_guard<std::mutex> lk(c.m);
+            total += (int64_t)c.bytes;
+        }
+        *bytes = total;
+    });
 }
 
 ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* flows, const double* T,

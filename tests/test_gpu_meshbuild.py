@@ -392,3 +392,23 @@ def test_edge_cases_axis_and_lists():
     rp = np.arange(n + 1, dtype=np.int64) * 2
     col = np.stack([np.full(n, -1), np.arange(n)], 1).astype(np.int32).ravel()
     assert_same_csr_mesh(x, rp, col)
+
+
+def test_build_scratch_is_kept_and_released():
+    """A device build keeps its scratch for the next one; the builds before and
+    after a release give byte-identical meshes."""
+    x, cells = meshes.kuhn_tet_grid(9)
+    F.release_cached_memory()
+    a = _device_mesh(x, cells, "f32")
+    held = F.cached_memory_bytes()
+    assert held > 0
+    b = _device_mesh(x, cells, "f32")
+    assert F.cached_memory_bytes() == held          # reused, not grown
+    F.release_cached_memory()
+    assert F.cached_memory_bytes() == 0
+    c = _device_mesh(x, cells, "f32")
+    for m in (b, c):
+        for adjoint in (0, 1):
+            ma, ra = _raw_tiles(a, adjoint)
+            mm, rm = _raw_tiles(m, adjoint)
+            assert np.array_equal(ma, mm) and np.array_equal(ra, rm)

@@ -584,3 +584,12 @@ def test_advect_grid_validation(L):
     assert adv(n=-1) == INVALID and adv(x0=None) == INVALID and adv(phi=None) == INVALID
     assert adv(dt=0.0) == INVALID and adv(T=float("nan")) == INVALID and adv(T=1e9, dt=1e-3) == INVALID
     assert adv(n=0) == 0 and adv(n=0, nt=1, t_step=0.0) == 0
+
+
+def test_cached_memory_calls(L):
+    """Nothing is cached before a device build: zero bytes, and releasing
+    nothing succeeds without a device; a NULL output is refused."""
+    v = ctypes.c_int64(-1)
+    assert L.ftle_cached_memory_bytes(ctypes.byref(v)) == 0 and v.value == 0
+    assert L.ftle_cached_memory_bytes(None) == 1
+    assert L.ftle_release_cached_memory() == 0
