@@ -2212,6 +2212,7 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         // the previous launch of this plan may still use the queue counters
+        // (only a persistent launch records that it used them)
         if (p->launched && p->done_stream != s) check_hip(hipStreamWaitEvent(s, p->done, 0), "hipStreamWaitEvent");
         if (g_pin.block)
             apply_pin(p, g_pin);
@@ -2239,9 +2240,11 @@ ftle_status ftle_batched(int n, const ftle_mesh_t* meshes, const void* const* fl
             p->last_tau = tau;
         }
         check_hip(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
-        check_hip(hipEventRecord(p->done, s), "hipEventRecord");
-        p->done_stream = s;
-        p->launched = true;
+        if (p->tiles_per_pop > 0) {
+            check_hip(hipEventRecord(p->done, s), "hipEventRecord");
+            p->done_stream = s;
+            p->launched = true;
+        }
     });
 }
 
