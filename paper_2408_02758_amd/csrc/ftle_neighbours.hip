@@ -311,9 +311,17 @@ __global__ void __launch_bounds__(kRowThreads) ring_rows(const int32_t* __restri
             for (int a = 0; a < K; ++a) {
                 const int32_t u = v[q][a];
                 if (u == (int32_t)r || over) continue;
-                int k = cnt;   // insertion point: after every entry below u
-                while (k > 0 && my[(k - 1) * kRowThreads] > u) --k;
-                if (k > 0 && my[(k - 1) * kRowThreads] == u) continue;   // already listed
+                // insertion point k: the number of listed entries below u, by
+                // binary search (at most 6 steps for 32 entries)
+                int k = 0, hi = cnt;
+                while (k < hi) {
+                    const int mid = (k + hi) >> 1;
+                    if (my[mid * kRowThreads] < u)
+                        k = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (k < cnt && my[k * kRowThreads] == u) continue;   // already listed
                 if (cnt == kRowCap) {
                     over = true;
                     continue;
