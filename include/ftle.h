@@ -191,11 +191,12 @@ ftle_status ftle_create_mesh_device_from_csr(int dim, int64_t n_points, const vo
  *   col_capacity n_cells * dim * (dim+1) always suffices
  *   nnz          host, receives the entry count (also when it exceeds
  *                col_capacity)
- * ftle_ring1_csr allocates its workspace (ftle_ring1_csr_workspace bytes:
- * the larger of 4 bytes per cell corner and 64 (2D) or 128 (3D) bytes per
- * point, plus about 144 bytes per point) for the duration of the
- * call; ftle_ring1_csr_ws takes it from the caller (device memory of at
- * least that size, overwritten).  Both return after the stream has finished
+ * ftle_ring1_csr takes its workspace (ftle_ring1_csr_workspace bytes: the
+ * larger of 4 bytes per cell corner and 64 (2D) or 128 (3D) bytes per point,
+ * plus about 144 bytes per point) from the device memory the mesh builds keep
+ * between calls (ftle_release_cached_memory), growing it if needed;
+ * ftle_ring1_csr_ws takes it from the caller (device memory of at least that
+ * size, overwritten).  Both return after the stream has finished
  * the work.
  * Errors: INVALID_ARG (dim, n_points < 1, n_cells < 0, null pointer, too
  * small a workspace), BAD_MESH (a cell index outside [0, n_points), found on
@@ -274,10 +275,10 @@ ftle_status ftle_advect_rk4_grid(int dim, const int64_t* shape, const double* or
 void ftle_destroy_mesh(ftle_mesh_t mesh);
 
 /*
- * The device mesh builds (ftle_create_mesh_device*) keep their temporary
- * device memory per device between calls, grown when a build needs more, so
- * that repeated builds do not allocate and free it each time (a few hundred
- * bytes per point: 1.5 GB for a 4.1 M-point tetrahedral mesh).
+ * The device mesh builds (ftle_create_mesh_device*) and ftle_ring1_csr keep
+ * their temporary device memory per device between calls, grown when a call
+ * needs more, so that repeated calls do not allocate and free it each time (a
+ * few hundred bytes per point: 1.5 GB for a 4.1 M-point tetrahedral mesh).
  * ftle_cached_memory_bytes reports how much is held (all devices);
  * ftle_release_cached_memory frees what no build is using.
  * Errors: INVALID_ARG (bytes NULL), DEVICE.

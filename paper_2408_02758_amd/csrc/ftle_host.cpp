@@ -2391,21 +2391,14 @@ ftle_status ftle_ring1_csr_ws(int dim, int64_t n_points, int64_t n_cells, const 
 ftle_status ftle_ring1_csr(int dim, int64_t n_points, int64_t n_cells, const int32_t* cells, int64_t* row_ptr,
                            int32_t* col, int64_t col_capacity, int64_t* nnz, ftle_stream_t stream)
 {
-    struct Scratch {   // released on every exit
-        void* p = nullptr;
-        ~Scratch()
-        {
-            if (p) (void)hipFree(p);
-        }
-    };
     return guarded([&] {
         check_ring1_args(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz);
         int dev = 0;
         check_hip(hipGetDevice(&dev), "hipGetDevice (no usable GPU?)");
-        Scratch w;
-        check_hip(hipMalloc(&w.p, ring1_workspace_bytes(dim, n_points, n_cells)), "hipMalloc (stencil workspace)");
-        ring1_run(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz, w.p,
-                  static_cast<hipStream_t>(stream));
+        // the device builds' cached scratch (or memory of its own while a build holds it)
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        ScratchLease w(ring1_workspace_bytes(dim, n_points, n_cells), s);
+        ring1_run(dim, n_points, n_cells, cells, row_ptr, col, col_capacity, nnz, w.get(), s);
     });
 }
 
