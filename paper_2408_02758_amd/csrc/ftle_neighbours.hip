@@ -5,23 +5,25 @@
 // ascending, each once.  Hand-written kernels, no library sort:
 //
 //   1. incidence lists in one pass: each cell appends its index to the list
-//      of each of its K = dim + 1 points, a list of at most kIncCap entries
-//      per point at a fixed place (atomic cursors, one per distinct point of
-//      a workgroup, aggregated in LDS first; the order inside a list does not
-//      matter; an index outside [0, n) raises the error flag).  When a point
-//      has more incident cells than that, or the fixed lists would not be
-//      addressable in 32 bits, the lists are packed instead:
+//      of each of its K = dim + 1 points, a list of at most 16 (triangles)
+//      or 32 (tetrahedra) entries per point at a fixed place (atomic
+//      cursors, one per distinct point of a workgroup, aggregated in LDS
+//      first; the order inside a list does not matter; an index outside
+//      [0, n) raises the error flag).  When a point has more incident cells
+//      than that, or the fixed lists would not be addressable in 32 bits,
+//      the lists are packed instead:
 //   2. the counts (from the first pass, or from a counting pass) are scanned
 //      into each point's incidence offset (scan_tiles / scan_partials /
 //      add_partials: 2048-element tiles, the tiles' sums scanned by one
 //      workgroup, then added back), and
 //   3. a second pass appends each cell's index to its points' packed lists;
 //   4. rows: one lane per point walks its incident cells and inserts their
-//      other points into a short sorted list of distinct indices in LDS (a
-//      lane's list is interleaved with its workgroup's, so that a list step
-//      is one conflict-free LDS access), then stores its count and the list
-//      (a fixed kRowCap slots per point in the workspace); the counts are
-//      scanned into the row pointers, and a copy moves the lists into place.
+//      other points into a short sorted list of distinct indices in LDS, each
+//      one's place found by binary search (a lane's list is interleaved with
+//      its workgroup's, so that a list step is one conflict-free LDS access),
+//      then stores its count and the list (a fixed kRowCap slots per point in
+//      the workspace); the counts are scanned into the row pointers, and a
+//      copy moves the lists into place.
 //      A point with more than kRowCap distinct neighbours is handed to a
 //      workgroup of its own (long_rows: its candidates sorted by a bitonic
 //      network in LDS, duplicates dropped by a flag scan), once to count and
