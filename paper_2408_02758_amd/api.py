@@ -678,4 +678,5 @@ def ftle(mesh: Mesh, flow: torch.Tensor, T: float) -> torch.Tensor:
 
 __all__ = ["Mesh", "batched", "BatchedCall", "batched_config", "FTLEFunction", "ftle", "FTLEError",
            "force_wide_offsets", "set_eig_threshold", "eig_threshold", "pin_batched_config", "advect_rk4",
-           "ring1_csr", "ring1_workspace_bytes", "axis_ell", "forward_ell"]
+           "advect_rk4_grid", "ring1_csr", "ring1_workspace_bytes", "axis_ell", "forward_ell",
+           "cached_memory_bytes", "release_cached_memory"]
