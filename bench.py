@@ -89,6 +89,10 @@ PROFILE_RECIPE = [
     "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_axis -o pmc --output-format csv -- "
     "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 3 --warmup 1 --copies 1 --no-cpu-baseline "
     "--no-sustained --no-headline --copy-probe-mib 256 --only axis",
+    # the one-ring stencil's kernels (2048^2 and 160^3; the scan and copy kernels serve both)
+    "timeout -s KILL 300 rocprofv3 --pmc {counter} -d gpurun_out/pmc_{counter}_build -o pmc --output-format csv -- "
+    "python -u bench.py --require-cache --cache /tmp/ftle_wc --steps 2 --warmup 1 --copies 1 --no-cpu-baseline "
+    "--no-sustained --no-headline --copy-probe-mib 256 --only neighbours",
 ]
 
 KERNEL_TRACE = os.path.join(ROOT, "profiles", "ftle_kernel_trace_stats.txt")
@@ -676,13 +680,15 @@ def profile_header(kind):
                                       for k in ("FETCH_SIZE", "WRITE_SIZE")]
         cmds += ["python bench.py --profile-header counters",
                  "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_main gpurun_out/pmc_WRITE_SIZE_main main",
-                 "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_axis gpurun_out/pmc_WRITE_SIZE_axis axis"]
+                 "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_axis gpurun_out/pmc_WRITE_SIZE_axis axis",
+                 "python bench.py --summarize-counters gpurun_out/pmc_FETCH_SIZE_build gpurun_out/pmc_WRITE_SIZE_build build"]
     lines = [f"# {title}", "# commands, from the repository root:"] + [f"#   {c}" for c in cmds]
     lines += ["# run 'main': the ring-1, float64, binary16, forward+adjoint, batched and axis-list rows; run 'axis': "
               "the axis-stencil rows (same kernel names as the ring-1 ones)"
               + ("; run 'build': the one-ring stencil and the mesh build on the device, 2048^2 and 160^3 (the "
                  "mesh build's calls include the warm-up builds and the ones beside the host build)"
-                 if kind == "trace" else ""),
+                 if kind == "trace" else "; run 'build': the one-ring stencil's kernels, 2048^2 and 160^3 (the "
+                 "scan and copy kernels' figures are means over both)"),
               f"kernel_sources_sha256 = {kernel_sources_sha256()}", f"batched_shape = {PROFILE_BATCHED_SHAPE}"]
     return "\n".join(lines)
 
